@@ -1,0 +1,584 @@
+/*
+ * Plain FP64 CPU oracle of the explicit-implicit scheme of arXiv 1408.5853.
+ *
+ * TEST INFRASTRUCTURE ONLY: it exists to check the GPU library, and only the
+ * tests, the smoke check and the benchmark's CPU-baseline leg load it.
+ *
+ * Readings of the paper taken here (each also listed in the design notes):
+ *  - Face conductivities are the layer law evaluated at the mean of the two
+ *    node temperatures (Sec. 3, definitions after eq. (11)), all at the old
+ *    time level (the scheme is linear per step, no iterations, Sec. 3.1).
+ *  - An r-face takes the layer holding that interval; z-faces take the node's
+ *    layer (layers are stacked along r).
+ *  - Interface rows come from eq. (18) with the flux quotients on the new
+ *    level and lambda* at the old interface temperature; they carry no heat
+ *    capacity, no z-conduction and no source.  Eq. (12) applied to this row
+ *    reproduces eq. (20).
+ *  - Boundary rows in r follow eq. (15) (insulated) or hold the wall value
+ *    (fixed).  The z-boundary lines are not solved: after all interior lines
+ *    they copy their neighbour line (insulated) or hold the wall value.
+ *  - The pulse gate of eq. (4) enters each step as its average over
+ *    [t_k, t_k + dt); pulse times are taken in step units and snapped to the
+ *    nearest integer when within 1e-9 relative.  The source is the amplitude
+ *    times that average on the heater layer's capacity nodes (p(t) = 1).
+ *  - Axial spacing is uniform, eta = height / (nz - 1).
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { ROW_BC = 0, ROW_CAP = 1, ROW_IFACE = 2 };
+
+typedef struct {
+    int nr, L;
+    double *r;    /* node radii */
+    double *h;    /* h[i] = r_i - r_{i-1}, i >= 1 (eq. (9)) */
+    int *lay;     /* layer of interval i (i >= 1) */
+    int *kind;    /* row class of node i */
+    int *mat;     /* capacity: its layer; interface: the inner layer */
+    double *dr;   /* [nr][L]  d r_i / d thick_m */
+    double *dh;   /* [nr][L]  d h_i / d thick_m */
+} geom;
+
+static void geom_free(geom *g)
+{
+    free(g->r); free(g->h); free(g->lay); free(g->kind); free(g->mat);
+    free(g->dr); free(g->dh);
+}
+
+static int check_cell(const ocell *c)
+{
+    if (c->nr < 3 || c->nz < 3 || c->n_layers < 1) return 1;
+    if (!(c->dt > 0) || !(c->height > 0) || !(c->r_inner >= 0)) return 1;
+    if (c->heater < 0 || c->heater >= c->n_layers) return 1;
+    if (c->width < 0 || c->period <= 0 || c->width > c->period) return 1;
+    long tot = 0;
+    for (int m = 0; m < c->n_layers; m++) {
+        if (c->intervals[m] < 2 || !(c->thick[m] > 0)) return 1;
+        tot += c->intervals[m];
+    }
+    if (tot != c->nr - 1) return 1;
+    if (c->r_inner == 0 && c->bc_kind[0] != 0) return 1;
+    return 0;
+}
+
+/* eq. (9): r_{i+1} = r_i + h_{i+1}, with layer m cut into equal intervals */
+static int geom_build(const ocell *c, geom *g)
+{
+    int nr = c->nr, L = c->n_layers;
+    memset(g, 0, sizeof(*g));
+    g->nr = nr; g->L = L;
+    g->r = calloc(nr, sizeof(double));
+    g->h = calloc(nr + 1, sizeof(double));
+    g->lay = calloc(nr + 1, sizeof(int));
+    g->kind = calloc(nr, sizeof(int));
+    g->mat = calloc(nr, sizeof(int));
+    g->dr = calloc((size_t)nr * L, sizeof(double));
+    g->dh = calloc((size_t)(nr + 1) * L, sizeof(double));
+    if (!g->r || !g->h || !g->lay || !g->kind || !g->mat || !g->dr || !g->dh) {
+        geom_free(g);
+        return 1;
+    }
+    int i = 0;
+    for (int m = 0; m < L; m++)
+        for (int k = 0; k < c->intervals[m]; k++) {
+            i++;
+            g->lay[i] = m;
+            g->h[i] = c->thick[m] / c->intervals[m];
+            g->dh[(size_t)i * L + m] = 1.0 / c->intervals[m];
+        }
+    g->r[0] = c->r_inner;
+    for (i = 1; i < nr; i++) {
+        g->r[i] = g->r[i - 1] + g->h[i];
+        for (int m = 0; m < L; m++)
+            g->dr[(size_t)i * L + m] = g->dr[(size_t)(i - 1) * L + m] + g->dh[(size_t)i * L + m];
+    }
+    g->kind[0] = g->kind[nr - 1] = ROW_BC;
+    for (i = 1; i < nr - 1; i++) {
+        g->mat[i] = g->lay[i];
+        g->kind[i] = (g->lay[i] != g->lay[i + 1]) ? ROW_IFACE : ROW_CAP;
+    }
+    return 0;
+}
+
+/* material laws of the workloads: lambda_m(T), c_m(T) and their T-derivatives */
+static double lam(const ocell *c, int m, double T)
+{
+    return c->kscale[m] * c->k0[m] * pow(T / c->tref[m], c->p[m]);
+}
+static double dlam(const ocell *c, int m, double T)
+{
+    return c->p[m] * lam(c, m, T) / T;
+}
+static double cap(const ocell *c, int m, double T)
+{
+    return c->c0[m] * pow(T / c->tref[m], c->q[m]);
+}
+static double dcap(const ocell *c, int m, double T)
+{
+    return c->q[m] * cap(c, m, T) / T;
+}
+
+int oc_radii(const ocell *c, double *r)
+{
+    geom g;
+    if (check_cell(c) || geom_build(c, &g)) return 1;
+    memcpy(r, g.r, sizeof(double) * c->nr);
+    geom_free(&g);
+    return 0;
+}
+
+static double snap(double x)
+{
+    double n = nearbyint(x);
+    return fabs(x - n) <= 1e-9 * fmax(1.0, fabs(x)) ? n : x;
+}
+
+/* eq. (4): nu(t) = 1 on [t_on + nP, t_on + nP + w), averaged over one step */
+double oc_source_fraction(const ocell *c, long k)
+{
+    if (!(c->width > 0)) return 0.0;
+    double b0 = snap(c->t_on / c->dt), W = snap(c->width / c->dt);
+    double P = snap(c->period / c->dt);
+    double lo = (double)k, hi = (double)k + 1.0, s = 0.0;
+    long n = (long)floor((lo - b0 - W) / P);
+    if (n < 0) n = 0;
+    for (;; n++) {
+        double b = b0 + n * P, e = b + W;
+        if (b >= hi) break;
+        double o = fmin(hi, e) - fmax(lo, b);
+        if (o > 0) s += o;
+    }
+    return s;
+}
+
+/* d/d(width) of the step average: 1/dt while a pulse ends inside the step,
+ * half of that on each side when it ends exactly on a step boundary (the
+ * mean of the one-sided derivatives, which a central difference sees) */
+double oc_source_fraction_dwidth(const ocell *c, long k)
+{
+    if (!(c->width > 0)) return 0.0;
+    double b0 = snap(c->t_on / c->dt), W = snap(c->width / c->dt);
+    double P = snap(c->period / c->dt);
+    double lo = (double)k, hi = (double)k + 1.0, d = 0.0;
+    long n = (long)floor((lo - b0 - W) / P);
+    if (n < 0) n = 0;
+    for (;; n++) {
+        double b = b0 + n * P, e = b + W;
+        if (b >= hi) break;
+        if (e > lo && e < hi) d += 1.0;
+        else if (e == lo || e == hi) d += 0.5;
+    }
+    return d / c->dt;
+}
+
+/* Rows of eq. (13) for line j (capacity), eq. (18) (interface), eq. (15)
+ * (r boundaries); the explicit z operator eq. (11) sits in F. */
+static void line_rows(const ocell *c, const geom *g, const double *T, double s,
+                      int j, double *A, double *B, double *C, double *F)
+{
+    int nr = c->nr;
+    double tau = c->dt, eta = c->height / (c->nz - 1);
+    const double *Tj = T + (size_t)j * nr;
+    const double *Tn = Tj + nr, *Ts = Tj - nr;
+    const double *r = g->r, *h = g->h;
+    for (int i = 1; i < nr - 1; i++) {
+        if (g->kind[i] == ROW_CAP) {
+            int m = g->mat[i];
+            double lw = lam(c, m, 0.5 * (Tj[i] + Tj[i - 1]));   /* lambda_{i-1/2,j} */
+            double le = lam(c, m, 0.5 * (Tj[i] + Tj[i + 1]));   /* lambda_{i+1/2,j} */
+            double rw = 0.5 * (r[i] + r[i - 1]);                 /* r_{i-1/2} */
+            double re = 0.5 * (r[i] + r[i + 1]);                 /* r_{i+1/2} */
+            double hb = 0.5 * (h[i + 1] + h[i]);                 /* hbar_i */
+            double rc = c->rho[m] * cap(c, m, Tj[i]) / tau;
+            A[i] = -rw * lw / (r[i] * hb * h[i]);
+            C[i] = -re * le / (r[i] * hb * h[i + 1]);
+            B[i] = (rw * lw / h[i] + re * le / h[i + 1]) / (r[i] * hb) + rc;
+            double ln = lam(c, m, 0.5 * (Tj[i] + Tn[i]));       /* lambda_{i,j+1/2} */
+            double ls = lam(c, m, 0.5 * (Tj[i] + Ts[i]));       /* lambda_{i,j-1/2} */
+            double Lz = (ln * (Tn[i] - Tj[i]) / eta - ls * (Tj[i] - Ts[i]) / eta) / eta;
+            double X = (m == c->heater) ? c->amplitude * s : 0.0;
+            F[i] = rc * Tj[i] + Lz + X;
+        } else {
+            int a = g->mat[i], b = a + 1;
+            double la = lam(c, a, Tj[i]), lb = lam(c, b, Tj[i]);  /* lambda*_m, lambda*_{m+1} */
+            A[i] = -la * h[i + 1];
+            B[i] = la * h[i + 1] + lb * h[i];
+            C[i] = -lb * h[i];
+            F[i] = 0.0;
+        }
+    }
+    A[0] = 0.0; B[0] = 1.0;
+    if (c->bc_kind[0] == 0) { C[0] = -1.0; F[0] = 0.0; }
+    else { C[0] = 0.0; F[0] = c->bc_value[0]; }
+    C[nr - 1] = 0.0; B[nr - 1] = 1.0;
+    if (c->bc_kind[1] == 0) { A[nr - 1] = -1.0; F[nr - 1] = 0.0; }
+    else { A[nr - 1] = 0.0; F[nr - 1] = c->bc_value[1]; }
+}
+
+int oc_line_rows(const ocell *c, const double *T, long k, int j,
+                 double *A, double *B, double *C, double *F)
+{
+    geom g;
+    if (check_cell(c) || j < 1 || j > c->nz - 2 || geom_build(c, &g)) return 1;
+    line_rows(c, &g, T, oc_source_fraction(c, k), j, A, B, C, F);
+    geom_free(&g);
+    return 0;
+}
+
+/* eq. (12) forward sweep, eq. (14) back substitution */
+static void thomas(int n, const double *A, const double *B, const double *C,
+                   const double *F, double *al, double *be, double *x)
+{
+    double ap = 0.0, bp = 0.0;
+    for (int i = 0; i < n; i++) {
+        double den = B[i] + A[i] * ap;
+        al[i] = -C[i] / den;
+        be[i] = (F[i] - A[i] * bp) / den;
+        ap = al[i];
+        bp = be[i];
+    }
+    x[n - 1] = be[n - 1];
+    for (int i = n - 2; i >= 0; i--) x[i] = al[i] * x[i + 1] + be[i];
+}
+
+int oc_thomas(int n, const double *A, const double *B, const double *C,
+              const double *F, double *x)
+{
+    if (n < 1) return 1;
+    double *w = malloc(sizeof(double) * 2 * n);
+    if (!w) return 1;
+    thomas(n, A, B, C, F, w, w + n, x);
+    free(w);
+    return 0;
+}
+
+int oc_line_paper_sweep(const ocell *c, const double *T, long k, int j, double *x)
+{
+    geom g;
+    if (check_cell(c) || c->bc_kind[0] != 0 || c->bc_kind[1] != 0) return 1;
+    if (j < 1 || j > c->nz - 2 || geom_build(c, &g)) return 1;
+    int nr = c->nr;
+    double *A = malloc(sizeof(double) * 6 * nr);
+    if (!A) { geom_free(&g); return 1; }
+    double *B = A + nr, *C = B + nr, *F = C + nr, *al = F + nr, *be = al + nr;
+    line_rows(c, &g, T, oc_source_fraction(c, k), j, A, B, C, F);
+    const double *Tj = T + (size_t)j * nr;
+    al[0] = 1.0; be[0] = 0.0;                                   /* eq. (16) */
+    for (int i = 1; i < nr - 1; i++) {
+        if (g.kind[i] == ROW_IFACE) {                           /* eq. (20) */
+            int a = g.mat[i], b = a + 1;
+            double la = lam(c, a, Tj[i]), lb = lam(c, b, Tj[i]);
+            double D = lb * g.h[i] + la * g.h[i + 1] * (1.0 - al[i - 1]);
+            al[i] = lb * g.h[i] / D;
+            be[i] = la * g.h[i + 1] * be[i - 1] / D;
+        } else {                                                /* eq. (12) */
+            double den = B[i] + A[i] * al[i - 1];
+            al[i] = -C[i] / den;
+            be[i] = (F[i] - A[i] * be[i - 1]) / den;
+        }
+    }
+    x[nr - 1] = be[nr - 2] / (1.0 - al[nr - 2]);                /* eq. (17) */
+    for (int i = nr - 2; i >= 1; i--) x[i] = al[i] * x[i + 1] + be[i];  /* (14),(19) */
+    x[0] = x[1];                                                /* eq. (15) */
+    free(A);
+    geom_free(&g);
+    return 0;
+}
+
+/* z-boundary lines after the interior solve: copy (insulated) or hold */
+static void z_boundaries(const ocell *c, double *T)
+{
+    int nr = c->nr, nz = c->nz;
+    if (c->bc_kind[2] == 0) memcpy(T, T + nr, sizeof(double) * nr);
+    else for (int i = 0; i < nr; i++) T[i] = c->bc_value[2];
+    double *top = T + (size_t)(nz - 1) * nr;
+    if (c->bc_kind[3] == 0) memcpy(top, top - nr, sizeof(double) * nr);
+    else for (int i = 0; i < nr; i++) top[i] = c->bc_value[3];
+}
+
+/* trapezoid weights along the outer surface r = r_max, normalised to 1 */
+static double surface_mean(const ocell *c, const double *T)
+{
+    int nr = c->nr, nz = c->nz;
+    double s = 0.0;
+    for (int j = 0; j < nz; j++) {
+        double w = (j == 0 || j == nz - 1) ? 0.5 : 1.0;
+        s += w * T[(size_t)j * nr + nr - 1];
+    }
+    return s / (nz - 1);
+}
+
+typedef struct { double *A, *B, *C, *F, *al, *be, *wa, *wb; } rows_t;
+
+static int nthreads_of(int n)
+{
+#ifdef _OPENMP
+    return n > 0 ? n : omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
+static int thread_id(void)
+{
+#ifdef _OPENMP
+    return omp_get_thread_num();
+#else
+    return 0;
+#endif
+}
+
+/* one step of eq. (8): T (old, step k) -> Tn (new); scratch per thread */
+static void step(const ocell *c, const geom *g, const double *T, double *Tn,
+                 long k, rows_t *scr, int nth)
+{
+    int nr = c->nr, nz = c->nz;
+    double s = oc_source_fraction(c, k);
+#pragma omp parallel for num_threads(nth) schedule(static)
+    for (int j = 1; j < nz - 1; j++) {
+        rows_t *w = &scr[thread_id()];
+        line_rows(c, g, T, s, j, w->A, w->B, w->C, w->F);
+        thomas(nr, w->A, w->B, w->C, w->F, w->al, w->be, Tn + (size_t)j * nr);
+    }
+    z_boundaries(c, Tn);
+}
+
+static rows_t *scratch_alloc(int nth, int nr)
+{
+    rows_t *s = calloc(nth, sizeof(rows_t));
+    if (!s) return NULL;
+    for (int t = 0; t < nth; t++) {
+        double *p = malloc(sizeof(double) * 8 * nr);
+        if (!p) return NULL;
+        s[t].A = p; s[t].B = p + nr; s[t].C = p + 2 * nr; s[t].F = p + 3 * nr;
+        s[t].al = p + 4 * nr; s[t].be = p + 5 * nr;
+        s[t].wa = p + 6 * nr; s[t].wb = p + 7 * nr;
+    }
+    return s;
+}
+
+static void scratch_free(rows_t *s, int nth)
+{
+    if (!s) return;
+    for (int t = 0; t < nth; t++) free(s[t].A);
+    free(s);
+}
+
+int oc_forward(const ocell *c, double *T, long k0, long nsteps, double *surf,
+               int nthreads)
+{
+    geom g;
+    if (check_cell(c) || nsteps < 0 || geom_build(c, &g)) return 1;
+    size_t n = (size_t)c->nr * c->nz;
+    int nth = nthreads_of(nthreads);
+    double *Tn = malloc(sizeof(double) * n);
+    rows_t *scr = scratch_alloc(nth, c->nr);
+    if (!Tn || !scr) { free(Tn); scratch_free(scr, nth); geom_free(&g); return 1; }
+    for (long s = 0; s < nsteps; s++) {
+        step(c, &g, T, Tn, k0 + s, scr, nth);
+        memcpy(T, Tn, sizeof(double) * n);
+        if (surf) surf[s] = surface_mean(c, T);
+    }
+    free(Tn);
+    scratch_free(scr, nth);
+    geom_free(&g);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Discrete adjoint.  The step maps T^n -> T^{n+1} through, per interior line,
+ * the residual r = A(T^n) T^{n+1} - F(T^n) = 0, plus the z-boundary copies.
+ * J = sum_{n=1..N} (S_n - target_n)^2 with S the surface mean.
+ * With lam^{n+1} = dJ/dT^{n+1}:
+ *   mu   = lam^{n+1} on interior lines, plus the boundary lines' entries
+ *          moved onto the lines they copy,
+ *   y_j  = A_j^{-T} mu_j (transposed tridiagonal solve per line),
+ *   lam^n = dJ_n/dT^n - sum_j (dr_j/dT^n)^T y_j,
+ *   dJ/dtheta -= sum_j y_j^T dr_j/dtheta.
+ * ---------------------------------------------------------------------- */
+
+typedef struct {
+    const ocell *c;
+    const geom *g;
+    int L, ng;
+} adj_ctx;
+
+/* contributions of line j's rows; lamn rows j-1..j+1 updated; gl = grad part */
+static void adjoint_line(const adj_ctx *x, const double *T, const double *Tn,
+                         double s, double sd, int j, const double *y,
+                         double *lamn, double *gl)
+{
+    const ocell *c = x->c;
+    const geom *g = x->g;
+    int nr = c->nr, L = x->L;
+    double tau = c->dt, eta = c->height / (c->nz - 1), e2 = eta * eta;
+    const double *Tj = T + (size_t)j * nr, *Tnn = Tj + nr, *Tss = Tj - nr;
+    const double *X = Tn + (size_t)j * nr;   /* new values of line j */
+    double *lj = lamn + (size_t)j * nr, *ln_ = lj + nr, *ls_ = lj - nr;
+    const double *r = g->r, *h = g->h;
+    for (int i = 1; i < nr - 1; i++) {
+        double yi = y[i];
+        if (yi == 0.0) continue;
+        double Dw = X[i] - X[i - 1], De = X[i] - X[i + 1];
+        if (g->kind[i] == ROW_CAP) {
+            int m = g->mat[i];
+            double Tw = 0.5 * (Tj[i] + Tj[i - 1]), Te = 0.5 * (Tj[i] + Tj[i + 1]);
+            double lw = lam(c, m, Tw), le = lam(c, m, Te);
+            double dlw = dlam(c, m, Tw), dle = dlam(c, m, Te);
+            double rw = 0.5 * (r[i] + r[i - 1]), re = 0.5 * (r[i] + r[i + 1]);
+            double hb = 0.5 * (h[i + 1] + h[i]);
+            double aw = rw / (r[i] * hb * h[i]), ae = re / (r[i] * hb * h[i + 1]);
+            double rc = c->rho[m] * cap(c, m, Tj[i]) / tau;
+            double drc = c->rho[m] * dcap(c, m, Tj[i]) / tau;
+            double Tzn = 0.5 * (Tj[i] + Tnn[i]), Tzs = 0.5 * (Tj[i] + Tss[i]);
+            double lzn = lam(c, m, Tzn), lzs = lam(c, m, Tzs);
+            double dlzn = dlam(c, m, Tzn), dlzs = dlam(c, m, Tzs);
+            double gn = Tnn[i] - Tj[i], gs = Tj[i] - Tss[i];
+            double Lz = (lzn * gn - lzs * gs) / e2;
+            double dLn = (0.5 * dlzn * gn + lzn) / e2;               /* dLz/dT_{j+1} */
+            double dLc = (0.5 * dlzn * gn - lzn - 0.5 * dlzs * gs - lzs) / e2;
+            double dLs = (-0.5 * dlzs * gs + lzs) / e2;              /* dLz/dT_{j-1} */
+            /* residual r = aw lw Dw + ae le De + rc (X_i - T_i) - Lz - Q s */
+            lj[i - 1] -= yi * aw * Dw * 0.5 * dlw;
+            lj[i + 1] -= yi * ae * De * 0.5 * dle;
+            lj[i] -= yi * (aw * Dw * 0.5 * dlw + ae * De * 0.5 * dle
+                           + drc * (X[i] - Tj[i]) - rc - dLc);
+            ln_[i] -= yi * (-dLn);
+            ls_[i] -= yi * (-dLs);
+            if (m == c->heater) {
+                gl[0] += yi * s;
+                gl[1] += yi * c->amplitude * sd;
+            }
+            gl[2 + L + m] -= yi * (aw * lw * Dw + ae * le * De - Lz) / c->kscale[m];
+            for (int l = 0; l < L; l++) {
+                double dri = g->dr[(size_t)i * L + l];
+                double drw = 0.5 * (dri + g->dr[(size_t)(i - 1) * L + l]);
+                double dre = 0.5 * (dri + g->dr[(size_t)(i + 1) * L + l]);
+                double dhi = g->dh[(size_t)i * L + l], dhe = g->dh[(size_t)(i + 1) * L + l];
+                double dhb = 0.5 * (dhi + dhe);
+                double daw = aw * (drw / rw - dri / r[i] - dhb / hb - dhi / h[i]);
+                double dae = ae * (dre / re - dri / r[i] - dhb / hb - dhe / h[i + 1]);
+                gl[2 + l] -= yi * (daw * lw * Dw + dae * le * De);
+            }
+        } else {
+            int a = g->mat[i], b = a + 1;
+            double la = lam(c, a, Tj[i]), lb = lam(c, b, Tj[i]);
+            double dla = dlam(c, a, Tj[i]), dlb = dlam(c, b, Tj[i]);
+            /* residual r = la h_{i+1} Dw + lb h_i De */
+            lj[i] -= yi * (dla * h[i + 1] * Dw + dlb * h[i] * De);
+            gl[2 + L + a] -= yi * la * h[i + 1] * Dw / c->kscale[a];
+            gl[2 + L + b] -= yi * lb * h[i] * De / c->kscale[b];
+            for (int l = 0; l < L; l++)
+                gl[2 + l] -= yi * (la * g->dh[(size_t)(i + 1) * L + l] * Dw
+                                   + lb * g->dh[(size_t)i * L + l] * De);
+        }
+    }
+}
+
+int oc_gradient(const ocell *c, const double *T0, long N, const double *target,
+                long ckpt, double *J, double *grad, double *surf, double *lam0,
+                int nthreads)
+{
+    geom g;
+    if (check_cell(c) || N < 1 || geom_build(c, &g)) return 1;
+    int nr = c->nr, nz = c->nz, L = c->n_layers, ng = 2 + 2 * L;
+    size_t n = (size_t)nr * nz;
+    long K = ckpt > 0 ? ckpt : N;
+    long nseg = (N + K - 1) / K;
+    int nth = nthreads_of(nthreads);
+    int rc_ = 1;
+    double *ck = malloc(sizeof(double) * n * nseg);
+    double *seg = malloc(sizeof(double) * n * (K + 1));
+    double *S = malloc(sizeof(double) * (N + 1));
+    double *lam_ = calloc(n, sizeof(double)), *lamn = calloc(n, sizeof(double));
+    double *mu = calloc(n, sizeof(double)), *Y = calloc(n, sizeof(double));
+    double *gl = calloc((size_t)nz * ng, sizeof(double));
+    rows_t *scr = scratch_alloc(nth, nr);
+    if (!ck || !seg || !S || !lam_ || !lamn || !mu || !Y || !gl || !scr) goto out;
+
+    /* forward sweep with checkpoints */
+    double *Tc = seg, *Tt = seg + n;
+    memcpy(Tc, T0, sizeof(double) * n);
+    double Jv = 0.0;
+    for (long k = 0; k < N; k++) {
+        if (k % K == 0) memcpy(ck + n * (k / K), Tc, sizeof(double) * n);
+        step(c, &g, Tc, Tt, k, scr, nth);
+        memcpy(Tc, Tt, sizeof(double) * n);
+        S[k + 1] = surface_mean(c, Tc);
+        if (surf) surf[k] = S[k + 1];
+        double d = S[k + 1] - target[k];
+        Jv += d * d;
+    }
+    *J = Jv;
+    for (int q = 0; q < ng; q++) grad[q] = 0.0;
+
+    /* lam^N = dJ_N / dT^N */
+    for (int j = 0; j < nz; j++) {
+        double w = ((j == 0 || j == nz - 1) ? 0.5 : 1.0) / (nz - 1);
+        lam_[(size_t)j * nr + nr - 1] = 2.0 * (S[N] - target[N - 1]) * w;
+    }
+    adj_ctx ax = { c, &g, L, ng };
+    for (long sg = nseg - 1; sg >= 0; sg--) {
+        long a = sg * K, b = (a + K < N) ? a + K : N;
+        memcpy(seg, ck + n * sg, sizeof(double) * n);
+        for (long k = a; k < b; k++)
+            step(c, &g, seg + n * (k - a), seg + n * (k - a + 1), k, scr, nth);
+        for (long k = b - 1; k >= a; k--) {
+            const double *T = seg + n * (k - a), *Tn = seg + n * (k - a + 1);
+            double s = oc_source_fraction(c, k), sd = oc_source_fraction_dwidth(c, k);
+            /* move the copied boundary lines' sensitivities onto their sources */
+            memcpy(mu, lam_, sizeof(double) * n);
+            if (c->bc_kind[2] == 0)
+                for (int i = 0; i < nr; i++) mu[nr + i] += lam_[i];
+            if (c->bc_kind[3] == 0)
+                for (int i = 0; i < nr; i++)
+                    mu[(size_t)(nz - 2) * nr + i] += lam_[(size_t)(nz - 1) * nr + i];
+            /* transposed line solves */
+#pragma omp parallel for num_threads(nth) schedule(static)
+            for (int j = 1; j < nz - 1; j++) {
+                rows_t *w = &scr[thread_id()];
+                line_rows(c, &g, T, s, j, w->A, w->B, w->C, w->F);
+                /* A^T: sub-diagonal C_{i-1}, diagonal B_i, super-diagonal A_{i+1} */
+                double *sub = w->F, *sup = w->al;
+                sub[0] = 0.0;
+                for (int i = 1; i < nr; i++) sub[i] = w->C[i - 1];
+                for (int i = 0; i < nr - 1; i++) sup[i] = w->A[i + 1];
+                sup[nr - 1] = 0.0;
+                thomas(nr, sub, w->B, sup, mu + (size_t)j * nr, w->wa, w->wb,
+                       Y + (size_t)j * nr);
+            }
+            memset(lamn, 0, sizeof(double) * n);
+            if (k >= 1)
+                for (int j = 0; j < nz; j++) {
+                    double w = ((j == 0 || j == nz - 1) ? 0.5 : 1.0) / (nz - 1);
+                    lamn[(size_t)j * nr + nr - 1] = 2.0 * (S[k] - target[k - 1]) * w;
+                }
+            memset(gl, 0, sizeof(double) * nz * ng);
+            /* lines three apart touch disjoint rows of lamn */
+            for (int phase = 0; phase < 3; phase++) {
+#pragma omp parallel for num_threads(nth) schedule(static)
+                for (int j = 1 + phase; j < nz - 1; j += 3)
+                    adjoint_line(&ax, T, Tn, s, sd, j, Y + (size_t)j * nr, lamn,
+                                 gl + (size_t)j * ng);
+            }
+            for (int j = 1; j < nz - 1; j++)
+                for (int q = 0; q < ng; q++) grad[q] += gl[(size_t)j * ng + q];
+            double *t = lam_; lam_ = lamn; lamn = t;
+        }
+    }
+    if (lam0) memcpy(lam0, lam_, sizeof(double) * n);
+    rc_ = 0;
+out:
+    free(ck); free(seg); free(S); free(lam_); free(lamn); free(mu); free(Y);
+    free(gl);
+    scratch_free(scr, nth);
+    geom_free(&g);
+    return rc_;
+}
