@@ -1,0 +1,178 @@
+/*
+ * cryocell — time stepping of the pulsed, nonlinear heat equation in a
+ * multilayer cylindrical (r, z) cell on one AMD Instinct MI355X (gfx950),
+ * with the explicit-implicit finite-difference scheme of
+ *   A. Ayriyan, J. Busa Jr., E. E. Donets, H. Grigorian, J. Pribis,
+ *   "Algorithm and Simulation of Heat Conduction Process for Design of a
+ *   Thin Multilayer Technical Device", arXiv:1408.5853.
+ *
+ * The problem is the paper's Sec. 2: eq. (1) with layer-wise material laws,
+ * a periodic rectangular heating pulse (eqs. (2)-(4)), a uniform initial
+ * temperature (eq. (5)), insulated or held boundaries (eq. (6)) and ideal
+ * contact between layers (eq. (7)).  The scheme is Sec. 3: eq. (8) with the
+ * r operator (10) implicit and the z operator (11) explicit, coefficients at
+ * the old time level, one tridiagonal system per axial line (eqs. (12)-(14),
+ * (16), (17)), interface rows from eqs. (18)-(20), and the explicit stability
+ * bound (21).
+ *
+ * Units are SI throughout (m, s, K, W/m/K, J/kg/K, kg/m^3, W/m^3).
+ *
+ * Conventions shared by every call:
+ *  - Status: every call returns cryo_status; CRYO_OK is 0.  On failure
+ *    cryo_last_error() returns a thread-local message; nothing is thrown.
+ *  - Ownership: descriptors are copied at create time.  The library owns only
+ *    its opaque plan/batch objects, their host tables and a small read-only
+ *    device copy of the per-radius tables (O(nr) bytes), made by the first
+ *    call that runs on the device, on the device current then.  The
+ *    temperature fields, the workspace and all outputs are device memory
+ *    owned by the caller; the library allocates nothing on the step path.
+ *  - Streams: `stream` is a hipStream_t passed as void*; NULL is the null
+ *    stream.  All device work of a call is enqueued on that stream and the
+ *    call returns without waiting, except where noted.  Buffers must stay
+ *    alive until the stream reaches the end of the call's work.
+ *  - Field layout: a CRYO_F64 temperature field is a dense row-major double
+ *    array [nz][nr], r contiguous, so one radial line (one tridiagonal
+ *    system) is one row.  A CRYO_F32 field is a compensated pair of such
+ *    planes, float [2][nz][nr]: plane 0 holds T rounded to float and plane 1
+ *    the residual T - plane0 (at most half an ulp of plane 0).  Arithmetic of
+ *    an F32 plan is FP32; the pair only carries the state, because a lone
+ *    float cannot accumulate per-step increments far below its ulp.
+ */
+#ifndef CRYOCELL_H
+#define CRYOCELL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CRYO_OK = 0,
+    CRYO_ERR_ARG = 1,          /* malformed descriptor or argument */
+    CRYO_ERR_UNSTABLE = 2,     /* dt violates the explicit bound, eq. (21) */
+    CRYO_ERR_DEVICE = 3,       /* a HIP runtime call failed */
+    CRYO_ERR_NONFINITE = 4,    /* a non-finite temperature was produced */
+    CRYO_ERR_WORKSPACE = 5,    /* workspace missing or too small */
+    CRYO_ERR_UNSUPPORTED = 6   /* valid problem outside the built kernels' range */
+} cryo_status;
+
+typedef enum { CRYO_F64 = 0, CRYO_F32 = 1 } cryo_dtype;
+
+/* Boundary kinds of eq. (6): zero normal derivative, or a held temperature. */
+typedef enum { CRYO_INSULATED = 0, CRYO_HELD = 1 } cryo_bc_kind;
+
+/* Material laws of one layer (the workloads' power-law families standing in
+ * for the paper's polynomial fits, eqs. (23)-(24)):
+ *   lambda(T) = k_scale * k0 * (T / tref)^p     [W/m/K]
+ *   c(T)      = c0 * (T / tref)^q               [J/kg/K],  rho constant. */
+typedef struct {
+    double k0, p, k_scale;
+    double c0, q;
+    double rho, tref;
+} cryo_material;
+
+/* One radial layer, listed inner to outer (Sec. 2: cooler, insulator,
+ * heater, outer insulator, ...).  `intervals` >= 2 equal radial intervals. */
+typedef struct {
+    double thickness;
+    int32_t intervals;
+    cryo_material mat;
+} cryo_layer;
+
+/* The cell (eq. (9) grid): radial nodes r_0 = r_inner, then each layer cut
+ * into equal intervals, nr = 1 + sum(intervals); axial nodes uniform over
+ * [0, height], nz of them.  Node counts include the boundary nodes. */
+typedef struct {
+    double r_inner;            /* >= 0; 0 only with an insulated inner side */
+    double height;
+    int32_t nr, nz;            /* 3 <= nr <= 2048, nz >= 3 */
+    int32_t n_layers;          /* 1..16 */
+    const cryo_layer *layers;  /* n_layers entries, copied */
+} cryo_geometry;
+
+/* Heating pulse (eqs. (2)-(4) with p(t) = 1): volumetric source `amplitude`
+ * on the heater layer's interior nodes while t - t_on lies in
+ * [n period, n period + width) for some integer n >= 0.  Each step uses the
+ * gate's average over [t_k, t_k + dt); t_k = k dt. */
+typedef struct {
+    int32_t layer;
+    double amplitude, width, period, t_on;
+} cryo_pulse;
+
+/* Sides in the order r_inner, r_outer, z_low, z_high. */
+typedef struct {
+    int32_t kind[4];
+    double value[4];
+} cryo_boundary;
+
+typedef struct {
+    cryo_geometry geom;
+    cryo_pulse pulse;
+    cryo_boundary bc;
+    double dt;                 /* time step tau */
+    double T_init;             /* eq. (5) */
+} cryo_problem;
+
+typedef struct cryo_plan cryo_plan;
+typedef struct cryo_batch cryo_batch;
+
+/* Thread-local text of the last failure (never NULL). */
+const char *cryo_last_error(void);
+
+/* Library version string. */
+const char *cryo_version(void);
+
+/* Host-only check of a descriptor: geometry, layer counts, laws, pulse and
+ * boundary kinds.  Does not test stability.  No device calls. */
+cryo_status cryo_validate(const cryo_problem *prob);
+
+/* Largest dt allowed by the explicit z half, eq. (21):
+ *   dt_max = (eta^2 / 2) * min over layers of rho c(T) / lambda(T)
+ * evaluated at temperature T_min (> 0).  No device calls. */
+cryo_status cryo_stability_dt_max(const cryo_problem *prob, double T_min,
+                                  double *dt_max);
+
+/* Create a plan: validates `prob`, rejects dt above eq. (21)'s bound at the
+ * coldest prescribed temperature (min of T_init and held wall values) with
+ * CRYO_ERR_UNSTABLE, and builds the grid tables.  Host only.  `dtype`
+ * selects the field type (double or float). */
+cryo_status cryo_plan_create(const cryo_problem *prob, cryo_dtype dtype,
+                             cryo_plan **out);
+void cryo_plan_destroy(cryo_plan *plan);
+
+/* Host copy of the node radii r_0..r_{nr-1} (eq. (9)). */
+cryo_status cryo_grid_radii(const cryo_plan *plan, double *r);
+
+/* Host copy of the per-step pulse averages s_k, k = k0..k0+n-1 (eq. (4)). */
+cryo_status cryo_source_fraction(const cryo_plan *plan, int64_t k0, int64_t n,
+                                 double *s);
+
+/* Device workspace needed by cryo_forward for runs of up to `nsteps` steps
+ * per call (bytes, 256-aligned base expected). */
+cryo_status cryo_workspace_bytes(const cryo_plan *plan, int64_t nsteps,
+                                 size_t *bytes);
+
+/* Fill the field T (device, see Field layout) with T_init (eq. (5)); an F32
+ * field's residual plane is set to zero. */
+cryo_status cryo_init(const cryo_plan *plan, void *T, void *stream);
+
+/* Advance T (device, [nz][nr], in: state after step k0, out: after step
+ * k0 + nsteps) by nsteps steps of eq. (8).  `ws` is the workspace
+ * (cryo_workspace_bytes).  `surf` (device double[nsteps], nullable) receives
+ * the surface mean S after each step: the trapezoid mean of T over z on the
+ * outer radius r = r_max.  Asynchronous on `stream`. */
+cryo_status cryo_forward(const cryo_plan *plan, void *T, int64_t k0,
+                         int64_t nsteps, void *ws, size_t ws_bytes,
+                         double *surf, void *stream);
+
+/* After the stream has finished a cryo_forward that used `ws`: returns
+ * CRYO_ERR_NONFINITE if that call produced a non-finite temperature, else
+ * CRYO_OK.  Synchronises `stream`. */
+cryo_status cryo_poll(const cryo_plan *plan, const void *ws, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

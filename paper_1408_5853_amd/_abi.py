@@ -1,0 +1,133 @@
+"""ctypes declarations of the cryocell C ABI (include/cryocell.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Loading fails loudly when libcryocell.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcryocell.so")
+
+CRYO_OK = 0
+STATUS = {0: "CRYO_OK", 1: "CRYO_ERR_ARG", 2: "CRYO_ERR_UNSTABLE", 3: "CRYO_ERR_DEVICE",
+          4: "CRYO_ERR_NONFINITE", 5: "CRYO_ERR_WORKSPACE", 6: "CRYO_ERR_UNSUPPORTED"}
+F64, F32 = 0, 1
+
+# every exported symbol the header declares
+SYMBOLS = [
+    "cryo_last_error", "cryo_version", "cryo_validate", "cryo_stability_dt_max",
+    "cryo_plan_create", "cryo_plan_destroy", "cryo_grid_radii", "cryo_source_fraction",
+    "cryo_workspace_bytes", "cryo_init", "cryo_forward", "cryo_poll",
+]
+
+
+class CryoError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class Material(C.Structure):
+    _fields_ = [("k0", C.c_double), ("p", C.c_double), ("k_scale", C.c_double),
+                ("c0", C.c_double), ("q", C.c_double), ("rho", C.c_double),
+                ("tref", C.c_double)]
+
+
+class Layer(C.Structure):
+    _fields_ = [("thickness", C.c_double), ("intervals", C.c_int32), ("mat", Material)]
+
+
+class Geometry(C.Structure):
+    _fields_ = [("r_inner", C.c_double), ("height", C.c_double), ("nr", C.c_int32),
+                ("nz", C.c_int32), ("n_layers", C.c_int32), ("layers", C.POINTER(Layer))]
+
+
+class Pulse(C.Structure):
+    _fields_ = [("layer", C.c_int32), ("amplitude", C.c_double), ("width", C.c_double),
+                ("period", C.c_double), ("t_on", C.c_double)]
+
+
+class Boundary(C.Structure):
+    _fields_ = [("kind", C.c_int32 * 4), ("value", C.c_double * 4)]
+
+
+class Problem(C.Structure):
+    _fields_ = [("geom", Geometry), ("pulse", Pulse), ("bc", Boundary), ("dt", C.c_double),
+                ("T_init", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libcryocell.so is not built; run paper_1408_5853_amd/build.py "
+                              "(or __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        vp, dp, i64 = C.c_void_p, C.POINTER(C.c_double), C.c_int64
+        pp = C.POINTER(Problem)
+        L.cryo_last_error.restype = C.c_char_p
+        L.cryo_version.restype = C.c_char_p
+        L.cryo_validate.argtypes = [pp]
+        L.cryo_stability_dt_max.argtypes = [pp, C.c_double, dp]
+        L.cryo_plan_create.argtypes = [pp, C.c_int, C.POINTER(vp)]
+        L.cryo_plan_destroy.argtypes = [vp]
+        L.cryo_plan_destroy.restype = None
+        L.cryo_grid_radii.argtypes = [vp, dp]
+        L.cryo_source_fraction.argtypes = [vp, i64, i64, dp]
+        L.cryo_workspace_bytes.argtypes = [vp, i64, C.POINTER(C.c_size_t)]
+        L.cryo_init.argtypes = [vp, vp, vp]
+        L.cryo_forward.argtypes = [vp, vp, i64, i64, vp, C.c_size_t, vp, vp]
+        L.cryo_poll.argtypes = [vp, vp, vp]
+        for name in SYMBOLS:
+            if name not in ("cryo_last_error", "cryo_version", "cryo_plan_destroy"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def check(status):
+    if status != CRYO_OK:
+        raise CryoError(status, lib().cryo_last_error().decode())
+
+
+class ProblemStruct:
+    """A Problem structure built from a problem dictionary; keeps its layer
+    array alive."""
+
+    def __init__(self, cell):
+        Ls = cell["layers"]
+        self.layers = (Layer * len(Ls))()
+        for m, l in enumerate(Ls):
+            self.layers[m].thickness = float(l["thickness"])
+            self.layers[m].intervals = int(l["intervals"])
+            mt = self.layers[m].mat
+            mt.k0, mt.p, mt.k_scale = float(l["k0"]), float(l["p"]), float(l["k_scale"])
+            mt.c0, mt.q = float(l["c0"]), float(l["q"])
+            mt.rho, mt.tref = float(l["rho"]), float(l["tref"])
+        s = Problem()
+        s.geom.r_inner = float(cell["r_inner"])
+        s.geom.height = float(cell["height"])
+        s.geom.nr, s.geom.nz = int(cell["nr"]), int(cell["nz"])
+        s.geom.n_layers = len(Ls)
+        s.geom.layers = C.cast(self.layers, C.POINTER(Layer))
+        s.pulse.layer = int(cell["heater"])
+        s.pulse.amplitude = float(cell["amplitude"])
+        s.pulse.width = float(cell["width"])
+        s.pulse.period = float(cell["period"])
+        s.pulse.t_on = float(cell["t_on"])
+        for q in range(4):
+            s.bc.kind[q] = int(cell["bc"][q][0])
+            s.bc.value[q] = float(cell["bc"][q][1])
+        s.dt = float(cell["dt"])
+        s.T_init = float(cell["T_init"])
+        self.s = s
+
+    def ref(self):
+        return C.byref(self.s)

@@ -1,0 +1,39 @@
+"""Build libcryocell.so (HIP, gfx950) in-tree with hipcc."""
+from __future__ import annotations
+
+import glob
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+LIB = os.path.join(HERE, "libcryocell.so")
+
+# Packed FP32 instructions are switched off for all device code.
+HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-Wall", "-Wno-unused-result"]
+
+
+def build(verbose=False):
+    srcs = sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
+    objs = []
+    for s in srcs:
+        o = os.path.join(HERE, "csrc", os.path.basename(s) + ".o")
+        cmd = ["hipcc", "-c", *HIP_FLAGS, "-I", os.path.join(ROOT, "include"),
+               "-I", os.path.join(HERE, "csrc"), "-o", o, s]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        objs.append(o)
+    tmp = LIB + ".tmp"
+    cmd = ["hipcc", "-shared", "--offload-arch=gfx950", "-o", tmp, *objs]
+    subprocess.check_call(cmd)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose="-v" in sys.argv)
+    print(LIB)

@@ -1,0 +1,96 @@
+"""Host-side checks of the C ABI (no device calls): the library loads and
+exports every declared symbol, descriptors are validated, the explicit
+stability bound (eq. (21)) is enforced, and the library's own grid and pulse
+schedule agree with the oracle's."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import cellgen
+import oracle
+import paper_1408_5853_amd as P
+from paper_1408_5853_amd import _abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "cryocell.h")).read()
+    return sorted(set(re.findall(r"\b(cryo_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(_abi.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_abi.SYMBOLS)
+
+
+def test_validation_rejects_bad_descriptors():
+    good = cellgen.config1(0)
+    P.validate(good)
+    bad = []
+    c = cellgen.scaled(good); c["layers"] = [dict(l) for l in c["layers"]]
+    c["layers"][0]["intervals"] = 1; bad.append(c)
+    c = cellgen.scaled(good, nr=good["nr"] + 1); bad.append(c)
+    c = cellgen.scaled(good, heater=7); bad.append(c)
+    c = cellgen.scaled(good, width=2.0 * good["period"]); bad.append(c)
+    c = cellgen.scaled(good, nz=2); bad.append(c)
+    c = cellgen.scaled(good, bc=[[2, 0.0]] * 4); bad.append(c)
+    c = cellgen.scaled(good, r_inner=0.0); bad.append(c)    # held axis
+    for c in bad:
+        with pytest.raises(P.CryoError) as e:
+            P.validate(c)
+        assert e.value.status == 1
+
+
+def test_unstable_dt_is_refused():
+    c = cellgen.config1(0)
+    dmax = P.stability_dt_max(c, 28.0)
+    assert c["dt"] <= dmax
+    P.Plan(cellgen.scaled(c, dt=0.999 * dmax))
+    with pytest.raises(P.CryoError) as e:
+        P.Plan(cellgen.scaled(c, dt=1.01 * dmax))
+    assert e.value.status == 2
+
+
+def test_stability_bound_formula():
+    # eq. (21): tau <= eta^2/2 * min rho c / lambda, here at T = tref
+    c = cellgen.config1(1)
+    eta = c["height"] / (c["nz"] - 1)
+    want = min(l["rho"] * l["c0"] / (l["k_scale"] * l["k0"]) for l in c["layers"])
+    assert P.stability_dt_max(c, 30.0) == pytest.approx(0.5 * eta * eta * want, rel=1e-14)
+
+
+def test_nr_above_limit_unsupported():
+    c = cellgen.config1(0)
+    c = cellgen.scaled(c, nr=4097)
+    c["layers"] = [dict(l) for l in c["layers"]]
+    c["layers"][0]["intervals"] += 4097 - 64
+    with pytest.raises(P.CryoError) as e:
+        P.validate(c)
+    assert e.value.status == 6
+
+
+@pytest.mark.parametrize("make", [lambda: cellgen.config1(0), lambda: cellgen.config2(0),
+                                  lambda: cellgen.config3(0, 3)[2],
+                                  lambda: cellgen.tiny(1)])
+def test_library_grid_and_schedule_match_oracle(make):
+    c = make()
+    pl = P.Plan(c)
+    assert np.allclose(pl.radii(), oracle.radii(c), rtol=1e-15, atol=0)
+    n = 5000
+    s = pl.source_fraction(0, n)
+    so = np.array([oracle.source_fraction(c, k) for k in range(n)])
+    assert np.max(np.abs(s - so)) < 1e-9
+
+
+def test_workspace_grows_with_grid():
+    a = P.Plan(cellgen.config1(0)).workspace_bytes(100)
+    b = P.Plan(cellgen.config2(0, nz=64)).workspace_bytes(100)
+    assert 0 < a < b
