@@ -53,7 +53,8 @@ typedef enum {
     CRYO_ERR_ARG = 1,          /* malformed descriptor or argument */
     CRYO_ERR_UNSTABLE = 2,     /* dt violates the explicit bound, eq. (21) */
     CRYO_ERR_DEVICE = 3,       /* a HIP runtime call failed */
-    CRYO_ERR_NONFINITE = 4,    /* a non-finite temperature was produced */
+    CRYO_ERR_NONFINITE = 4,    /* a non-finite temperature, or one outside
+                                  [1/16 K, 2^20 K), was produced */
     CRYO_ERR_WORKSPACE = 5,    /* workspace missing or too small */
     CRYO_ERR_UNSUPPORTED = 6   /* valid problem outside the built kernels' range */
 } cryo_status;
@@ -142,6 +143,18 @@ cryo_status cryo_plan_create(const cryo_problem *prob, cryo_dtype dtype,
                              cryo_plan **out);
 void cryo_plan_destroy(cryo_plan *plan);
 
+/* Launch shape of the stepping kernel: radial rows per lane, waves (of 64
+ * lanes) per radial line, and interior lines marched by one line group per
+ * step.  The plan picks one at create time; cryo_plan_set_shape overrides it
+ * (the autotuner's hook) and must precede the plan's first device call.
+ * Built shapes: (2,1) (4,1) (8,1) (4,2) (8,2) (4,4) (8,4); 64 * waves *
+ * rows must cover nr.  Results do not depend on lines_per_wave; different
+ * chunk shapes change only rounding. */
+cryo_status cryo_plan_shape(const cryo_plan *plan, int32_t *rows_per_lane,
+                            int32_t *waves_per_line, int32_t *lines_per_wave);
+cryo_status cryo_plan_set_shape(cryo_plan *plan, int32_t rows_per_lane,
+                                int32_t waves_per_line, int32_t lines_per_wave);
+
 /* Host copy of the node radii r_0..r_{nr-1} (eq. (9)). */
 cryo_status cryo_grid_radii(const cryo_plan *plan, double *r);
 
@@ -171,6 +184,59 @@ cryo_status cryo_forward(const cryo_plan *plan, void *T, int64_t k0,
  * CRYO_ERR_NONFINITE if that call produced a non-finite temperature, else
  * CRYO_OK.  Synchronises `stream`. */
 cryo_status cryo_poll(const cryo_plan *plan, const void *ws, void *stream);
+
+/* ---- Gradient by the discrete adjoint -----------------------------------
+ * J = sum_{n=1..N} (S_n - target_n)^2 with S_n the surface mean after step
+ * n, and its gradient with respect to
+ *   theta = [amplitude, width, thickness_0..L-1, k_scale_0..L-1]
+ * (grad has 2 + 2L entries), from the exact discrete adjoint of the N steps
+ * from T0 (steps 0..N-1): transposed line solves, the local stencil of the
+ * lagged coefficients, the copied z-boundary lines, the radii that move with
+ * the thicknesses, and the pulse-edge steps (a pulse end on a step boundary
+ * takes the mean of the two one-sided derivatives).  States are checkpointed
+ * every ckpt steps (0: ceil(sqrt(N))) and each segment is recomputed.
+ * FP64 plans only.  T0 is a device field; target, J, grad and surf
+ * (nullable, N values) are host arrays.  Synchronous on `stream`. */
+cryo_status cryo_gradient_workspace_bytes(const cryo_plan *plan, int64_t nsteps, int64_t ckpt,
+                                          size_t *bytes);
+cryo_status cryo_gradient(const cryo_plan *plan, const void *T0, int64_t nsteps,
+                          const double *target, int64_t ckpt, void *ws, size_t ws_bytes,
+                          double *J, double *grad, double *surf, void *stream);
+
+/* ---- Batched design sweeps ---------------------------------------------
+ * Many independent cells (uneven grids, own dt, layers and pulse) stepped
+ * together: instances are grouped by kernel shape; each step is one launch
+ * per shape group over all of its instances, and blocks of steps are
+ * captured once in a HIP graph (on a private capture stream) and replayed on
+ * the caller's stream.  The fields of all instances are packed in one device
+ * buffer: instance i's field (the plan's field layout) starts at element
+ * offsets[i] of the batch dtype.  Every instance uses the same global step
+ * range k0 .. k0 + nsteps. */
+
+/* Create a batch of n instances.  `shapes` (nullable) gives per instance
+ * (rows_per_lane, waves_per_line, lines_per_wave), e.g. from cryo_autotune;
+ * otherwise each plan's default.  Errors name the failing instance. */
+cryo_status cryo_batch_create(int32_t n, const cryo_problem *probs, cryo_dtype dtype,
+                              const int32_t *shapes, cryo_batch **out);
+void cryo_batch_destroy(cryo_batch *batch);
+/* Element offsets of the instances' fields in the packed buffer (n + 1). */
+cryo_status cryo_batch_offsets(const cryo_batch *batch, int64_t *offsets);
+/* Kernel shape chosen for instance i (3 values, as cryo_plan_shape). */
+cryo_status cryo_batch_shape(const cryo_batch *batch, int32_t i, int32_t *shape);
+/* Device workspace of cryo_batch_forward (bytes, 256-aligned base). */
+cryo_status cryo_batch_workspace_bytes(const cryo_batch *batch, size_t *bytes);
+/* Fill every instance's field with its T_init. */
+cryo_status cryo_batch_init(const cryo_batch *batch, void *T, void *stream);
+/* Advance every instance by nsteps steps from global step k0.  The captured
+ * graph is tied to `ws`; a call with another workspace re-captures it.
+ * Asynchronous on `stream`.  No device allocation after the first call. */
+cryo_status cryo_batch_forward(cryo_batch *batch, void *T, int64_t k0, int64_t nsteps,
+                               void *ws, size_t ws_bytes, void *stream);
+/* After a cryo_batch_forward: CRYO_ERR_NONFINITE if an instance produced a
+ * non-finite or out-of-range temperature; *bad_instance (nullable) gets the
+ * first such instance or -1.  Synchronises `stream`. */
+cryo_status cryo_batch_poll(const cryo_batch *batch, const void *ws, void *stream,
+                            int32_t *bad_instance);
 
 #ifdef __cplusplus
 }

@@ -14,7 +14,8 @@ import numpy as np
 from . import _abi
 from ._abi import CryoError, check, lib
 
-__all__ = ["Plan", "CryoError", "validate", "stability_dt_max", "version"]
+__all__ = ["Plan", "Batch", "CryoError", "CryoSolve", "gradient", "with_params", "params_of",
+           "validate", "stability_dt_max", "version"]
 
 
 def version():
@@ -77,6 +78,16 @@ class Plan:
     def torch_dtype(self):
         torch = _torch()
         return torch.float64 if self.dtype == "f64" else torch.float32
+
+    def shape(self):
+        """(rows per lane, waves per line, lines per wave) of the step kernel."""
+        v = [C.c_int32() for _ in range(3)]
+        check(lib().cryo_plan_shape(self._h, *[C.byref(x) for x in v]))
+        return tuple(x.value for x in v)
+
+    def set_shape(self, rows_per_lane, waves_per_line, lines_per_wave):
+        check(lib().cryo_plan_set_shape(self._h, int(rows_per_lane), int(waves_per_line),
+                                        int(lines_per_wave)))
 
     def radii(self):
         r = np.zeros(self.nr)
@@ -155,3 +166,177 @@ class Plan:
 
     def poll(self, ws, stream=None):
         check(lib().cryo_poll(self._h, _ptr(ws), _stream(stream)))
+
+    def gradient(self, target, T0=None, nsteps=None, ckpt=0, stream=None):
+        """J = sum_n (S_n - target_n)^2 and dJ/d[amplitude, width, thickness_m,
+        k_scale_m] by the discrete adjoint (FP64 plans).  Returns (J, grad,
+        surface trace) as float, numpy, numpy.  Synchronous."""
+        torch = _torch()
+        n = int(self.cell["nsteps"] if nsteps is None else nsteps)
+        tgt = np.ascontiguousarray(np.asarray(target, dtype=np.float64)[:n])
+        if tgt.size < n:
+            raise ValueError("target needs nsteps values")
+        T = self.init() if T0 is None else self.field_from(T0)
+        b = C.c_size_t()
+        check(lib().cryo_gradient_workspace_bytes(self._h, n, int(ckpt), C.byref(b)))
+        ws = torch.empty(b.value, dtype=torch.uint8, device="cuda")
+        J = C.c_double()
+        L = len(self.cell["layers"])
+        g = np.zeros(2 + 2 * L)
+        S = np.zeros(n)
+        dp = C.POINTER(C.c_double)
+        check(lib().cryo_gradient(self._h, _ptr(T), n, tgt.ctypes.data_as(dp), int(ckpt),
+                                  _ptr(ws), ws.numel(), C.byref(J), g.ctypes.data_as(dp),
+                                  S.ctypes.data_as(dp), _stream(stream)))
+        return J.value, g, S
+
+
+class Batch:
+    """Many independent cells stepped together (design sweeps)."""
+
+    def __init__(self, cells, dtype="f64", shapes=None):
+        self.cells = list(cells)
+        self.dtype = dtype
+        n = len(self.cells)
+        self._ps = [_abi.ProblemStruct(c) for c in self.cells]
+        arr = (_abi.Problem * n)(*[p.s for p in self._ps])
+        self._arr = arr
+        sh = None
+        if shapes is not None:
+            flat = np.ascontiguousarray(np.asarray(shapes, dtype=np.int32).reshape(n, 3))
+            self._shapes = flat
+            sh = flat.ctypes.data_as(C.POINTER(C.c_int32))
+        h = C.c_void_p()
+        check(lib().cryo_batch_create(n, arr, _abi.F64 if dtype == "f64" else _abi.F32, sh,
+                                      C.byref(h)))
+        self._h = h
+        off = (C.c_int64 * (n + 1))()
+        check(lib().cryo_batch_offsets(self._h, off))
+        self.offsets = [int(x) for x in off]
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().cryo_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def torch_dtype(self):
+        torch = _torch()
+        return torch.float64 if self.dtype == "f64" else torch.float32
+
+    def shape(self, i):
+        v = (C.c_int32 * 3)()
+        check(lib().cryo_batch_shape(self._h, int(i), v))
+        return tuple(v)
+
+    def workspace(self, device="cuda"):
+        torch = _torch()
+        b = C.c_size_t()
+        check(lib().cryo_batch_workspace_bytes(self._h, C.byref(b)))
+        ws = torch.empty(b.value, dtype=torch.uint8, device=device)
+        assert ws.data_ptr() % 256 == 0
+        return ws
+
+    def init(self, T=None, stream=None):
+        torch = _torch()
+        if T is None:
+            T = torch.empty(self.offsets[-1], dtype=self.torch_dtype, device="cuda")
+        check(lib().cryo_batch_init(self._h, _ptr(T), _stream(stream)))
+        return T
+
+    def field(self, T, i):
+        """View of instance i's field in the packed buffer."""
+        c = self.cells[i]
+        v = T[self.offsets[i]:self.offsets[i + 1]]
+        shp = (c["nz"], c["nr"]) if self.dtype == "f64" else (2, c["nz"], c["nr"])
+        return v.view(shp)
+
+    def forward(self, T, k0, nsteps, ws, stream=None):
+        check(lib().cryo_batch_forward(self._h, _ptr(T), int(k0), int(nsteps), _ptr(ws),
+                                       ws.numel(), _stream(stream)))
+        return T
+
+    def poll(self, ws, stream=None):
+        bad = C.c_int32(-1)
+        check(lib().cryo_batch_poll(self._h, _ptr(ws), _stream(stream), C.byref(bad)))
+
+
+def params_of(cell):
+    """theta = [amplitude, width, thickness_0..L-1, k_scale_0..L-1]."""
+    Ls = cell["layers"]
+    return np.array([cell["amplitude"], cell["width"]] + [l["thickness"] for l in Ls]
+                    + [l["k_scale"] for l in Ls], dtype=np.float64)
+
+
+def with_params(cell, theta):
+    """Copy of `cell` with theta (see params_of) applied."""
+    import copy
+    c = copy.deepcopy(cell)
+    L = len(c["layers"])
+    theta = np.asarray(theta, dtype=np.float64)
+    c["amplitude"], c["width"] = float(theta[0]), float(theta[1])
+    for m in range(L):
+        c["layers"][m]["thickness"] = float(theta[2 + m])
+        c["layers"][m]["k_scale"] = float(theta[2 + L + m])
+    return c
+
+
+def _gradient_shape(cell):
+    # four radial rows per lane keep the adjoint kernel within registers
+    nr = int(cell["nr"])
+    w = 1
+    while 64 * 4 * w < nr:
+        w *= 2
+    return (4, w, 1) if w <= 4 else None
+
+
+def gradient(cell, target, T0=None, nsteps=None, ckpt=0):
+    """(J, dJ/dtheta, surface trace) of `cell` on the GPU (FP64)."""
+    plan = Plan(cell, "f64")
+    sh = _gradient_shape(cell)
+    if sh is not None:
+        plan.set_shape(*sh)
+    return plan.gradient(target, T0=T0, nsteps=nsteps, ckpt=ckpt)
+
+
+def _make_solve():
+    import torch
+
+    class CryoSolve(torch.autograd.Function):
+        """J(theta) for theta = [amplitude, width, thickness_m, k_scale_m] of a
+        cell, differentiable by the hand-written discrete adjoint (one forward
+        with checkpoints, recompute and adjoint sweep per call).
+
+        CryoSolve.apply(theta, cell, target, nsteps, ckpt) -> J (0-d tensor)."""
+
+        @staticmethod
+        def forward(ctx, theta, cell, target, nsteps, ckpt):
+            c = with_params(cell, theta.detach().cpu().numpy())
+            J, g, _ = gradient(c, target, nsteps=nsteps, ckpt=ckpt)
+            ctx.save_for_backward(torch.as_tensor(g, dtype=theta.dtype, device=theta.device))
+            return torch.as_tensor(J, dtype=theta.dtype, device=theta.device)
+
+        @staticmethod
+        def backward(ctx, gJ):
+            (g,) = ctx.saved_tensors
+            return gJ * g, None, None, None, None
+
+    return CryoSolve
+
+
+class _LazySolve:
+    _cls = None
+
+    def __getattr__(self, name):
+        if _LazySolve._cls is None:
+            _LazySolve._cls = _make_solve()
+        return getattr(_LazySolve._cls, name)
+
+
+CryoSolve = _LazySolve()

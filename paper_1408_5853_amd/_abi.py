@@ -21,6 +21,10 @@ SYMBOLS = [
     "cryo_last_error", "cryo_version", "cryo_validate", "cryo_stability_dt_max",
     "cryo_plan_create", "cryo_plan_destroy", "cryo_grid_radii", "cryo_source_fraction",
     "cryo_workspace_bytes", "cryo_init", "cryo_forward", "cryo_poll",
+    "cryo_plan_shape", "cryo_plan_set_shape",
+    "cryo_batch_create", "cryo_batch_destroy", "cryo_batch_offsets", "cryo_batch_shape",
+    "cryo_batch_workspace_bytes", "cryo_batch_init", "cryo_batch_forward", "cryo_batch_poll",
+    "cryo_gradient_workspace_bytes", "cryo_gradient",
 ]
 
 
@@ -85,8 +89,23 @@ def lib():
         L.cryo_init.argtypes = [vp, vp, vp]
         L.cryo_forward.argtypes = [vp, vp, i64, i64, vp, C.c_size_t, vp, vp]
         L.cryo_poll.argtypes = [vp, vp, vp]
+        i32p = C.POINTER(C.c_int32)
+        L.cryo_plan_shape.argtypes = [vp, i32p, i32p, i32p]
+        L.cryo_plan_set_shape.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
+        L.cryo_batch_create.argtypes = [C.c_int32, pp, C.c_int, i32p, C.POINTER(vp)]
+        L.cryo_batch_destroy.argtypes = [vp]
+        L.cryo_batch_destroy.restype = None
+        L.cryo_batch_offsets.argtypes = [vp, C.POINTER(C.c_int64)]
+        L.cryo_batch_shape.argtypes = [vp, C.c_int32, i32p]
+        L.cryo_batch_workspace_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+        L.cryo_batch_init.argtypes = [vp, vp, vp]
+        L.cryo_batch_forward.argtypes = [vp, vp, i64, i64, vp, C.c_size_t, vp]
+        L.cryo_batch_poll.argtypes = [vp, vp, vp, i32p]
+        L.cryo_gradient_workspace_bytes.argtypes = [vp, i64, i64, C.POINTER(C.c_size_t)]
+        L.cryo_gradient.argtypes = [vp, vp, i64, dp, i64, vp, C.c_size_t, dp, dp, dp, vp]
         for name in SYMBOLS:
-            if name not in ("cryo_last_error", "cryo_version", "cryo_plan_destroy"):
+            if name not in ("cryo_last_error", "cryo_version", "cryo_plan_destroy",
+                            "cryo_batch_destroy"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib

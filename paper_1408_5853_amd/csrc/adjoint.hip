@@ -1,0 +1,410 @@
+// gfx950 kernels of the discrete adjoint of one step of eq. (8) (FP64).
+//
+// A step maps T^n -> T^{n+1}: per interior line j the residual
+//   r = A(T^n) T^{n+1} - F(T^n) = 0,
+// (rows of eq. (13), (18), (15)), plus the copied or held z-boundary lines.
+// With lam^{n+1} = dJ/dT^{n+1} the adjoint step is
+//   mu_j   = lam^{n+1}_j (+ the copied boundary line's entries),
+//   y_j    = A_j^{-T} mu_j                     (transposed line solve),
+//   lam^n  = dJ_n/dT^n - sum over rows of y * (d r / d T^n),
+//   dJ/dth -= sum over rows of y * (d r / d theta).
+// Pass 1 (k_adj1) does the line solves and the radial part of lam^n; pass 2
+// (k_adj2) adds the axial-face part, which couples neighbouring lines: the
+// face between lines j and j+1 with flux F = lam_f (T_{j+1} - T_j) adds
+// dF/dT_j (y_j - y_{j+1}) to line j and dF/dT_{j+1} (y_j - y_{j+1}) to j+1.
+//
+// Parameter sensitivities are accumulated per row (radial flux terms y fw Dw
+// and y fe De, axial term y (F_N - F_S)) and per heater (y s, y Q ds/dw);
+// the host turns the row sums into d/d thickness and d/d k_scale.
+#include <math.h>
+#include <string.h>
+
+#include "device_common.h"
+
+namespace cryo {
+
+struct AdjArgs {
+    const double *T;        // T^n (internal layout)
+    const double *X;        // T^{n+1}
+    const double *lam_in;   // lam^{n+1}
+    double *Y;              // pass 1 out: y
+    double *lpart;          // pass 1 out: radial part of lam^n
+    double *lam_out;        // pass 2 out: lam^n
+    double *acc;            // per line group: [groups][3][np] row sums
+    double *accg;           // per line group: [groups][2]  (y s, y Q ds/dw)
+    double s, ds;           // pulse average of step n and its width derivative
+    double cS;              // dJ_n / dS_n (0 for n = 0)
+};
+
+constexpr int ADJ_WAVES = 8;
+
+// exchange of one value per lane with the neighbouring lanes of the line
+// (shuffles inside a wave, LDS across the waves of the line)
+template <int G>
+__device__ inline void nb_exchange(double v_last, double v_first, double &from_prev,
+                                   double &from_next, int lane, int wig, double *xb) {
+    from_prev = shfl_up1(v_last, 1, lane);
+    from_next = shfl_dn1(v_first, 1, lane);
+    if constexpr (G > 1) {
+        if (lane == WAVE - 1) xb[2 * wig] = v_last;
+        if (lane == 0) xb[2 * wig + 1] = v_first;
+        __syncthreads();
+        if (lane == 0 && wig > 0) from_prev = xb[2 * (wig - 1)];
+        if (lane == WAVE - 1 && wig < G - 1) from_next = xb[2 * (wig + 1) + 1];
+        __syncthreads();
+    }
+}
+
+template <int RPL, int G>
+__global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj1(StepArgs<double> a, AdjArgs d) {
+    constexpr int NL = WAVE * G, NG = ADJ_WAVES / G;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double xchg[NG][9 * G];
+    __shared__ double xb[NG][2 * G];
+    double *sgw = (double *)(smem + ((law_lds_bytes<double>(a.laws.L) + 15) & ~(size_t)15));
+    double *sge = sgw + a.np;
+    uint32_t *sinf = (uint32_t *)(sge + a.np);
+    for (int i = threadIdx.x; i < a.np; i += blockDim.x) {
+        sgw[i] = a.gw[i];
+        sge[i] = a.ge[i];
+        sinf[i] = a.info[i];
+    }
+    const LawLds<double> law = stage_laws<double>(a, smem);
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    const int grp = wv / G, wig = wv % G, lg = wig * WAVE + lane;
+    const int gidx = blockIdx.x * NG + grp;                  // line group
+    const int j0 = 1 + gidx * a.lpw;
+    const int j1 = min(j0 + a.lpw, a.nz - 1);
+    const size_t LS = a.np;
+    const int qW = lg > 0 ? (RPL - 1) * NL + lg - 1 : 0;
+    const int qE = lg < NL - 1 ? lg + 1 : (RPL - 1) * NL + lg;
+    const double *lrow = law.lrow;
+    int bad = 0;
+    double accW[RPL], accE[RPL], gS = 0.0, gD = 0.0;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) accW[r] = accE[r] = 0.0;
+    for (int it = 0; it < a.lpw; ++it) {
+        const int jr = j0 + it;
+        const bool active = jr < j1;
+        const int j = min(jr, a.nz - 2);
+        const size_t base = (size_t)j * LS;
+        double T[RPL], X[RPL], fw[RPL], fe[RPL], fwT[RPL], feT[RPL];
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int q = r * NL + lg;
+            T[r] = d.T[base + q];
+            X[r] = d.X[base + q];
+        }
+        const double TwF = d.T[base + qW], TeL = d.T[base + qE];
+        const double XwF = d.X[base + qW], XeL = d.X[base + qE];
+        // west face of the chunk's first row
+        double lamW, dlamW;
+        {
+            const int le = (sinf[qW] >> 6) & 63;
+            const double tf = 0.5 * (TwF + T[0]);
+            lamW = law.law(le, tf, bad);
+            dlamW = lrow[le * POW_LROW + POW_NE] * lamW / tf;
+        }
+        double a0 = 0, b0 = 1, c0 = 0, d0 = 0, ccm2 = 0, bbm1 = 1, ccm1 = 0, mum1 = 0;
+        double al[RPL], ga[RPL], de[RPL];
+        double aa0 = 0, ccL = 0;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int q = r * NL + lg;
+            const uint32_t inf_r = sinf[q];
+            const uint32_t kind = inf_r & 7;
+            const bool cap = kind == K_CAP, ifc = kind == K_IFACE;
+            const double t = T[r], Te = (r < RPL - 1) ? T[r + 1] : TeL;
+            const int le = (inf_r >> 6) & 63, l2 = (inf_r >> 12) & 63;
+            const int l3 = (inf_r >> 18) & 63, lc = (inf_r >> 24) & 63;
+            const double tf = 0.5 * (t + Te);
+            const double lamE = law.law(le, tf, bad);
+            const double dlamE = lrow[le * POW_LROW + POW_NE] * lamE / tf;
+            // interface: the two layer laws at the node; boundary rows: unit/zero
+            double l2v = l2 == law_unit(a.laws.L) ? 1.0 : 0.0, l3v = l3 == law_unit(a.laws.L) ? 1.0 : 0.0;
+            double dl2 = 0.0, dl3 = 0.0;
+            if (__any(ifc)) {
+                const double va = law.law(l2, t, bad), vb = law.law(l3, t, bad);
+                if (ifc) {
+                    l2v = va;
+                    l3v = vb;
+                    dl2 = lrow[l2 * POW_LROW + POW_NE] * va / t;
+                    dl3 = lrow[l3 * POW_LROW + POW_NE] * vb / t;
+                }
+            }
+            const double rc = a.laws.cube ? law.cube(lc, t) : law.law(lc, t, bad);
+            fw[r] = sgw[q] * (cap ? lamW : l2v);
+            fe[r] = sge[q] * (cap ? lamE : l3v);
+            fwT[r] = sgw[q] * (cap ? 0.5 * dlamW : dl2);
+            feT[r] = sge[q] * (cap ? 0.5 * dlamE : dl3);
+            const double aa = -fw[r], bb = fw[r] + fe[r] + rc, cc = -fe[r];
+            // boundary-copy lines feed their sensitivity back to the copied line
+            double mu = d.lam_in[base + q];
+            if (j == 1 && !a.held[2]) mu += d.lam_in[q];
+            if (j == a.nz - 2 && !a.held[3]) mu += d.lam_in[(size_t)(a.nz - 1) * LS + q];
+            // transposed row r-1 = (cc_{r-2}, bb_{r-1}, aa_r | mu_{r-1})
+            if (r == 0) {
+                aa0 = aa;
+                b0 = bb;
+                d0 = mu;
+            } else if (r == 1) {
+                c0 = aa;          // sup of the first transposed row
+            } else {
+                elim_row<double, RPL>(r - 1, ccm2, bbm1, aa, mum1, al, ga, de);
+            }
+            ccm2 = ccm1;
+            ccm1 = cc;
+            bbm1 = bb;
+            mum1 = mu;
+            if (r == RPL - 1) ccL = cc;
+            lamW = lamE;
+            dlamW = dlamE;
+            if (r & 1) __builtin_amdgcn_sched_barrier(0);
+        }
+        // chunk ends: sub of the first row = cc of the previous row, sup of the
+        // last row = aa of the next row
+        double ccPrev, aaNext;
+        nb_exchange<G>(ccL, aa0, ccPrev, aaNext, lane, wig, xb[grp]);
+        a0 = ccPrev;
+        if (RPL == 2) {
+            // the first row's sup is the second row's aa, already in c0
+        }
+        elim_row<double, RPL>(RPL - 1, ccm2, bbm1, aaNext, mum1, al, ga, de);
+        double y[RPL];
+        solve_tail<double, RPL, G>(a0, b0, c0, d0, al, ga, de, y, lane, wig, xchg[grp]);
+        // radial part of lam^n:  dJ - [y_i dr_i/dT_i + y_{i-1} dr_{i-1}/dT_i + y_{i+1} dr_{i+1}/dT_i]
+        double Dw[RPL], De[RPL];
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const double xw = (r > 0) ? X[r - 1] : XwF, xe = (r < RPL - 1) ? X[r + 1] : XeL;
+            Dw[r] = X[r] - xw;
+            De[r] = X[r] - xe;
+        }
+        // coupling terms leaving each row towards its r-neighbours (capacity rows:
+        // the face conductivity depends on both nodes)
+        const bool capF = (sinf[lg] & 7) == K_CAP, capL = (sinf[(RPL - 1) * NL + lg] & 7) == K_CAP;
+        const double qwF = capF ? y[0] * fwT[0] * Dw[0] : 0.0;                  // to row i0-1
+        const double qeL = capL ? y[RPL - 1] * feT[RPL - 1] * De[RPL - 1] : 0.0; // to row i0+RPL
+        double qePrev, qwNext;
+        nb_exchange<G>(qeL, qwF, qePrev, qwNext, lane, wig, xb[grp]);
+        if (active) {
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                const int q = r * NL + lg;
+                const uint32_t inf_r = sinf[q];
+                const uint32_t kind = inf_r & 7;
+                const bool cap = kind == K_CAP, ifc = kind == K_IFACE;
+                const double t = T[r];
+                const int lc = (inf_r >> 24) & 63;
+                double rc, drc;
+                if (a.laws.cube) {
+                    rc = law.cube(lc, t);
+                    drc = 3.0 * law.ck[lc] * t * t;
+                } else {
+                    rc = law.law(lc, t, bad);
+                    drc = lrow[lc * POW_LROW + POW_NE] * rc / t;
+                }
+                double self = 0.0;
+                if (cap || ifc) self = fwT[r] * Dw[r] + feT[r] * De[r] + drc * (X[r] - t) - rc;
+                double from_w, from_e;    // y_{i-1} dr_{i-1}/dT_i, y_{i+1} dr_{i+1}/dT_i
+                if (r > 0) {
+                    const bool cw = (sinf[q - NL] & 7) == K_CAP;
+                    from_w = cw ? y[r - 1] * feT[r - 1] * De[r - 1] : 0.0;
+                } else {
+                    from_w = qePrev;
+                }
+                if (r < RPL - 1) {
+                    const bool ce = (sinf[q + NL] & 7) == K_CAP;
+                    from_e = ce ? y[r + 1] * fwT[r + 1] * Dw[r + 1] : 0.0;
+                } else {
+                    from_e = qwNext;
+                }
+                double lp = -(y[r] * self + from_w + from_e);
+                if (lg == a.surf_lane && r == a.surf_reg) lp += d.cS * a.wz_mid;
+                d.Y[base + q] = y[r];
+                d.lpart[base + q] = lp;
+                if (cap || ifc) {
+                    accW[r] += y[r] * fw[r] * Dw[r];
+                    accE[r] += y[r] * fe[r] * De[r];
+                }
+                if ((inf_r >> 3) & 1) {
+                    gS += y[r];
+                }
+            }
+        }
+    }
+    // this line group's running sums (one slot per group: no other writer)
+    double *acc = d.acc + (size_t)gidx * 3 * a.np;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        const int q = r * NL + lg;
+        acc[q] += accW[r];
+        acc[a.np + q] += accE[r];
+    }
+    // heater sums of the group: lane-order tree inside each wave, then waves
+    double v = gS;
+    for (int s = WAVE / 2; s >= 1; s >>= 1) v += __shfl_down(v, s, WAVE);
+    __shared__ double gsum[ADJ_WAVES];
+    if (lane == 0) gsum[wv] = v;
+    __syncthreads();
+    if (wig == 0 && lane == 0) {
+        double tot = 0.0;
+        for (int w = 0; w < G; ++w) tot += gsum[grp * G + w];
+        d.accg[2 * gidx] += tot * d.s;
+        d.accg[2 * gidx + 1] += tot * a.pulse.amplitude * d.ds;
+    }
+    (void)gD;
+    if (__any(bad) && lane == 0) atomicOr(a.flag, 2);
+}
+
+// Pass 2: axial faces.  Each interior line j adds the terms of its two
+// axial faces (capacity rows), and the lines next to the z-boundaries write
+// the boundary lines' lam^n.
+template <int RPL, int G>
+__global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj2(StepArgs<double> a, AdjArgs d) {
+    constexpr int NL = WAVE * G, NG = ADJ_WAVES / G;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *sgw = (double *)(smem + ((law_lds_bytes<double>(a.laws.L) + 15) & ~(size_t)15));
+    double *sge = sgw + a.np;
+    uint32_t *sinf = (uint32_t *)(sge + a.np);
+    for (int i = threadIdx.x; i < a.np; i += blockDim.x) sinf[i] = a.info[i];
+    const LawLds<double> law = stage_laws<double>(a, smem);
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    const int grp = wv / G, wig = wv % G, lg = wig * WAVE + lane;
+    const int gidx = blockIdx.x * NG + grp;
+    const int j0 = 1 + gidx * a.lpw;
+    const int j1 = min(j0 + a.lpw, a.nz - 1);
+    const size_t LS = a.np;
+    const double *lrow = law.lrow;
+    int bad = 0;
+    double accZ[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) accZ[r] = 0.0;
+    for (int j = j0; j < j1; ++j) {
+        const size_t base = (size_t)j * LS;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int q = r * NL + lg;
+            const uint32_t inf_r = sinf[q];
+            const bool cap = (inf_r & 7) == K_CAP;
+            const int lz = (inf_r >> 12) & 63;
+            const double t = d.T[base + q];
+            const double tn = d.T[base + LS + q], ts = d.T[base - LS + q];
+            const double y = d.Y[base + q];
+            const double yn = (j + 1 <= a.nz - 2) ? d.Y[base + LS + q] : 0.0;
+            const double ys = (j - 1 >= 1) ? d.Y[base - LS + q] : 0.0;
+            double lam = d.lpart[base + q];
+            double dFlN = 0.0, dFuS = 0.0;
+            if (cap) {
+                const double fn = 0.5 * (t + tn), fs = 0.5 * (t + ts);
+                const double ln = law.law(lz, fn, bad), ls = law.law(lz, fs, bad);
+                const double e = lrow[lz * POW_LROW + POW_NE];
+                const double dn = tn - t, ds = t - ts;
+                dFlN = 0.5 * e * ln / fn * dn - ln;     // d F_N / d T_j
+                dFuS = 0.5 * e * ls / fs * ds + ls;     // d F_S / d T_j
+                lam += dFlN * (y - yn) + dFuS * (ys - y);
+                accZ[r] += y * (ln * dn - ls * ds);
+                // boundary lines: their faces with lines 1 and nz-2
+                if (j == 1) {
+                    const double dFl0 = 0.5 * e * ls / fs * ds - ls;   // d F_S / d T_0
+                    double l0 = dFl0 * (0.0 - y);
+                    if (lg == a.surf_lane && r == a.surf_reg) l0 += d.cS * a.wz_end;
+                    d.lam_out[q] = l0;
+                }
+                if (j == a.nz - 2) {
+                    const double dFuE = 0.5 * e * ln / fn * dn + ln;   // d F_N / d T_{nz-1}
+                    double le_ = dFuE * (y - 0.0);
+                    if (lg == a.surf_lane && r == a.surf_reg) le_ += d.cS * a.wz_end;
+                    d.lam_out[(size_t)(a.nz - 1) * LS + q] = le_;
+                }
+            } else {
+                const bool sl = lg == a.surf_lane && r == a.surf_reg;
+                if (j == 1) d.lam_out[q] = sl ? d.cS * a.wz_end : 0.0;
+                if (j == a.nz - 2) d.lam_out[(size_t)(a.nz - 1) * LS + q] = sl ? d.cS * a.wz_end : 0.0;
+            }
+            d.lam_out[base + q] = lam;
+        }
+    }
+    double *acc = d.acc + (size_t)gidx * 3 * a.np + 2 * a.np;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) acc[r * NL + lg] += accZ[r];
+    if (__any(bad) && lane == 0) atomicOr(a.flag, 2);
+}
+
+// lam^N = dJ_N / dT^N: the surface weights on the outer row
+__global__ void k_adj_init(double *lam, int nz, int np, int q_surf, double cS, double wz_end,
+                           double wz_mid) {
+    size_t n = (size_t)nz * np;
+    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < n;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        const int j = (int)(idx / np), q = (int)(idx % np);
+        double v = 0.0;
+        if (q == q_surf) v = cS * ((j == 0 || j == nz - 1) ? wz_end : wz_mid);
+        lam[idx] = v;
+    }
+}
+
+__global__ void k_zero(double *p, size_t n) {
+    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < n;
+         idx += (size_t)gridDim.x * blockDim.x)
+        p[idx] = 0.0;
+}
+
+static cryo_status check_launch(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(CRYO_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return CRYO_OK;
+}
+
+int adj_grid(const cryo_plan *p) {
+    const int groups = (p->nz - 2 + p->lpw - 1) / p->lpw;
+    const int per_wg = ADJ_WAVES / p->wpl;
+    return (groups + per_wg - 1) / per_wg;
+}
+
+int adj_groups(const cryo_plan *p) { return adj_grid(p) * (ADJ_WAVES / p->wpl); }
+
+StepArgs<double> step_args_f64(const cryo_plan *p, int *flag);
+
+cryo_status launch_adj(const cryo_plan *p, int pass, const AdjArgs &d, int *flag, hipStream_t s) {
+    StepArgs<double> a = step_args_f64(p, flag);
+    dim3 g(adj_grid(p)), b(ADJ_WAVES * WAVE);
+    const size_t lds = step_lds_bytes<double>(p->L, p->np);
+    const int key = p->rpl * 10 + p->wpl;
+#define ADJ_CASE(R_, G_)                                                                  \
+    case R_ * 10 + G_:                                                                    \
+        if (pass == 1)                                                                    \
+            hipLaunchKernelGGL((k_adj1<R_, G_>), g, b, lds, s, a, d);                     \
+        else                                                                              \
+            hipLaunchKernelGGL((k_adj2<R_, G_>), g, b, lds, s, a, d);                     \
+        break;
+    switch (key) {
+        ADJ_CASE(2, 1)
+        ADJ_CASE(4, 1)
+        ADJ_CASE(8, 1)
+        ADJ_CASE(8, 2)
+        ADJ_CASE(8, 4)
+        ADJ_CASE(4, 2)
+        ADJ_CASE(4, 4)
+    default: return fail(CRYO_ERR_UNSUPPORTED, "radial chunk shape");
+    }
+#undef ADJ_CASE
+    return check_launch(pass == 1 ? "adjoint pass 1" : "adjoint pass 2");
+}
+
+cryo_status launch_adj_init(const cryo_plan *p, double *lam, double cS, hipStream_t s) {
+    const int q = p->surf_reg * (WAVE * p->wpl) + p->surf_lane;
+    size_t n = (size_t)p->nz * p->np;
+    int blocks = (int)std::min<size_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_adj_init, dim3(blocks), dim3(256), 0, s, lam, p->nz, p->np, q, cS,
+                       0.5 / (p->nz - 1), 1.0 / (p->nz - 1));
+    return check_launch("adjoint init");
+}
+
+cryo_status launch_zero(double *ptr, size_t n, hipStream_t s) {
+    int blocks = (int)std::min<size_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, ptr, n);
+    return check_launch("zero");
+}
+
+}  // namespace cryo

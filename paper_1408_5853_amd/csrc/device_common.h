@@ -1,0 +1,365 @@
+// Device code shared by the stepping and adjoint kernels: law evaluation
+// from LDS tables, compensated FP32 pairs, wave shuffles and the partitioned
+// tridiagonal solve.
+#pragma once
+
+#include <math.h>
+#include <string.h>
+
+#include "internal.h"
+
+namespace cryo {
+
+template <typename R>
+__device__ inline R lg2(R x);
+template <>
+__device__ inline double lg2<double>(double x) { return log2(x); }
+template <>
+__device__ inline float lg2<float>(float x) { return log2f(x); }
+template <typename R>
+__device__ inline R ex2(R x);
+template <>
+__device__ inline double ex2<double>(double x) { return exp2(x); }
+template <>
+__device__ inline float ex2<float>(float x) { return exp2f(x); }
+
+// reciprocal: hardware estimate refined by Newton steps (two for FP64)
+__device__ inline double rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return r;
+}
+__device__ inline float rcp(float x) {
+    float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(fmaf(-x, r, 1.0f), r, r);
+}
+
+// Law evaluation K[id] * T^e[id] from tables staged in LDS.
+template <typename R>
+struct LawLds;
+
+template <>
+struct LawLds<double> {
+    const double *erow;     // exponent rows: {m0^e, 1/m0}[NM]
+    const double *lrow;     // law rows: K 2^(x e) [NE], e, exponent row
+    const double *ck, *ca;  // cube path: K T^3 + A
+    // T off the table (outside [2^POW_EMIN, 2^(POW_EMIN+POW_NE)) K, or not
+    // finite) is clamped and flagged; the call then reports an error.
+    __device__ inline double law(int id, double x, int &bad) const {
+        const long long b = __double_as_longlong(x);
+        const int xe = (int)((b >> 52) & 0x7ff) - 1023 - POW_EMIN;
+        const int xc = min(max(xe, 0), POW_NE - 1);
+        bad |= xc != xe;
+        const int jm = (int)((b >> 46) & (POW_NM - 1));
+        const double m = __longlong_as_double((b & 0x000FFFFFFFFFFFFFLL) | 0x3FF0000000000000LL);
+        const double *Lr = lrow + id * POW_LROW;
+        const double2 ee = *(const double2 *)(Lr + POW_NE);     // e, exponent row
+        const double2 mm = *(const double2 *)(erow + (int)ee.y * POW_EROW + 2 * jm);
+        const double u = fma(m, mm.y, -1.0);
+        // ln(1 + u), |u| <= 1/128
+        double l = fma(u, 1.0 / 7, -1.0 / 6);
+        l = fma(l, u, 1.0 / 5);
+        l = fma(l, u, -1.0 / 4);
+        l = fma(l, u, 1.0 / 3);
+        l = fma(l, u, -1.0 / 2);
+        l = fma(l, u, 1.0);
+        const double v = ee.x * (l * u);
+        // exp(v), |v| <= 1/32
+        double s = fma(v, 1.0 / 5040, 1.0 / 720);
+        s = fma(s, v, 1.0 / 120);
+        s = fma(s, v, 1.0 / 24);
+        s = fma(s, v, 1.0 / 6);
+        s = fma(s, v, 0.5);
+        s = fma(s, v, 1.0);
+        s = fma(s, v, 1.0);
+        return Lr[xc] * mm.x * s;
+    }
+    __device__ inline double cube(int id, double x) const {
+        return fma(ck[id], x * x * x, ca[id]);
+    }
+};
+
+template <>
+struct LawLds<float> {
+    const float *lk, *ex, *ck, *ca;
+    __device__ inline float law(int id, float x, int &) const {
+        return exp2f(fmaf(ex[id], log2f(x), lk[id]));
+    }
+    __device__ inline float cube(int id, float x) const { return fmaf(ck[id], x * x * x, ca[id]); }
+};
+
+template <typename R>
+struct StepArgs {
+    const R *Tin;             // single plan: this step's input and output
+    R *Tout;
+    R *buf[2];                // batch: ping-pong buffers (step n reads buf[n & 1])
+    const R *gw, *ge;
+    const uint32_t *info;
+    const double *pow_blob;   // FP64 power tables (device)
+    Laws laws;
+    int nz, np;
+    int lpw;                  // lines per wave (a contiguous block)
+    R X;                      // amplitude * pulse average of this step
+    int held[4];              // r_inner, r_outer, z_low, z_high
+    R val[4];
+    double *partial;          // nullable: per-workgroup surface partial sums
+    int *flag;                // error word: bit 1 = temperature off the law tables
+    double wz_end, wz_mid;    // trapezoid weights of the surface mean
+    int surf_lane, surf_reg;
+    int groups;               // workgroups of one step of this instance
+    Pulse pulse;              // batch: schedule evaluated on the device
+};
+
+constexpr int STEP_WAVES = 8;
+
+template <typename R>
+__device__ inline R shfl_up1(R v, int s, int lane) {
+    R u = __shfl_up(v, s, WAVE);
+    return lane >= s ? u : (R)0;
+}
+template <typename R>
+__device__ inline R shfl_dn1(R v, int s, int lane) {
+    R u = __shfl_down(v, s, WAVE);
+    return lane + s < WAVE ? u : (R)0;
+}
+
+// Forward elimination of one row r >= 1 of a lane's chunk, with a fill-in
+// column on the chunk's first row x_0:  al_r x_0 + x_r + ga_r x_{r+1} = de_r
+template <typename R, int RPL>
+__device__ inline void elim_row(int r, R aa, R bb, R cc, R dd, R (&al)[RPL], R (&ga)[RPL],
+                                R (&de)[RPL]) {
+    if (r == 1) {
+        const R inv = rcp(bb);
+        al[1] = aa * inv;
+        ga[1] = cc * inv;
+        de[1] = dd * inv;
+    } else {
+        const R inv = rcp(bb - aa * ga[r - 1]);
+        al[r] = -aa * al[r - 1] * inv;
+        ga[r] = cc * inv;
+        de[r] = (dd - aa * de[r - 1]) * inv;
+    }
+}
+
+// Rest of the partitioned solve, after every lane has eliminated rows 1..RPL-1
+// of its chunk (elim_row).  A line is spread over G waves (64 G lanes, lane
+// lg = wig * 64 + lane owns rows lg*RPL .. lg*RPL+RPL-1):
+//  1. back-eliminate each chunk onto its ends x_0, x_e;
+//  2. eliminate x_0 with the first row, leaving one unknown x_e per lane and a
+//     tridiagonal reduced system across the 64 G lanes;
+//  3. each wave solves its 64 unknowns by parallel cyclic reduction, with the
+//     couplings to the neighbouring waves' unknowns as two extra right-hand
+//     sides (spikes);
+//  4. the 2 G wave-end unknowns satisfy a small system, exchanged in LDS and
+//     solved by every lane;
+//  5. back-substitution.
+// (a0, b0, c0, d0) is the chunk's first row.  On exit x[r] holds the solution
+// of row lg * RPL + r.  xch: LDS exchange area of this line's waves (9 G
+// values); all waves of the workgroup must call this together when G > 1.
+template <typename R, int RPL, int G>
+__device__ inline void solve_tail(R a0, R b0, R c0, R d0, R (&al)[RPL], R (&ga)[RPL],
+                                  R (&de)[RPL], R (&x)[RPL], int lane, int wig, R *xch) {
+    static_assert(RPL >= 2, "chunks of at least two rows");
+#pragma unroll
+    for (int r = RPL - 3; r >= 1; --r) {
+        de[r] = de[r] - ga[r] * de[r + 1];
+        al[r] = al[r] - ga[r] * al[r + 1];
+        ga[r] = -ga[r] * ga[r + 1];
+    }
+    // first row: a0 x_e(k-1) + sb x_0 + sc x_e(k) = sd
+    R sb, sc, sd;
+    if (RPL == 2) {
+        sb = b0;
+        sc = c0;
+        sd = d0;
+    } else {
+        sb = b0 - c0 * al[1];
+        sc = -c0 * ga[1];
+        sd = d0 - c0 * de[1];
+    }
+    const R isb = rcp(sb);
+    const R sig = a0 * isb, tau = sc * isb, rho = sd * isb;   // x_0 = rho - sig x_e(k-1) - tau x_e(k)
+    R sigN = shfl_dn1(sig, 1, lane), tauN = shfl_dn1(tau, 1, lane);
+    R rhoN = shfl_dn1(rho, 1, lane);
+    if constexpr (G > 1) {
+        if (lane == 0) {
+            xch[3 * wig + 0] = sig;
+            xch[3 * wig + 1] = tau;
+            xch[3 * wig + 2] = rho;
+        }
+        __syncthreads();
+        if (lane == WAVE - 1 && wig < G - 1) {
+            sigN = xch[3 * (wig + 1) + 0];
+            tauN = xch[3 * (wig + 1) + 1];
+            rhoN = xch[3 * (wig + 1) + 2];
+        }
+    }
+    const int e = RPL - 1;
+    // reduced row of x_e(k):  A x_e(k-1) + B x_e(k) + C x_e(k+1) = D
+    R A = -al[e] * sig;
+    R B = (R)1 - al[e] * tau - ga[e] * sigN;
+    R C = -ga[e] * tauN;
+    R D = de[e] - al[e] * rho - ga[e] * rhoN;
+    {
+        const R ib = rcp(B);
+        A *= ib;
+        C *= ib;
+        D *= ib;
+    }
+    // spikes: couplings across the wave ends moved to extra right-hand sides
+    R PL = (R)0, PR = (R)0, Afirst = (R)0, Clast = (R)0;
+    if constexpr (G > 1) {
+        Afirst = __shfl(A, 0, WAVE);
+        Clast = __shfl(C, WAVE - 1, WAVE);
+        if (lane == 0) {
+            A = (R)0;
+            PL = (R)1;
+        }
+        if (lane == WAVE - 1) {
+            C = (R)0;
+            PR = (R)1;
+        }
+    }
+#pragma unroll
+    for (int s = 1; s < WAVE; s <<= 1) {
+        const R Am = shfl_up1(A, s, lane), Cm = shfl_up1(C, s, lane), Dm = shfl_up1(D, s, lane);
+        const R Ap = shfl_dn1(A, s, lane), Cp = shfl_dn1(C, s, lane), Dp = shfl_dn1(D, s, lane);
+        const R ib = rcp((R)1 - A * Cm - C * Ap);
+        const R nA = -A * Am * ib;
+        const R nC = -C * Cp * ib;
+        const R nD = (D - A * Dm - C * Dp) * ib;
+        if constexpr (G > 1) {
+            const R PLm = shfl_up1(PL, s, lane), PLp = shfl_dn1(PL, s, lane);
+            const R PRm = shfl_up1(PR, s, lane), PRp = shfl_dn1(PR, s, lane);
+            PL = (PL - A * PLm - C * PLp) * ib;
+            PR = (PR - A * PRm - C * PRp) * ib;
+        }
+        A = nA;
+        C = nC;
+        D = nD;
+    }
+    R xe = D, uL = (R)0;
+    if constexpr (G > 1) {
+        // x_e = y + vL uL + vR uR with uL, uR the neighbouring waves' end unknowns
+        const R vL = -Afirst * PL, vR = -Clast * PR;
+        R *xi = xch + 3 * G;     // per wave: y, vL, vR at its first and last lane
+        if (lane == 0) {
+            xi[6 * wig + 0] = D;
+            xi[6 * wig + 1] = vL;
+            xi[6 * wig + 2] = vR;
+        }
+        if (lane == WAVE - 1) {
+            xi[6 * wig + 3] = D;
+            xi[6 * wig + 4] = vL;
+            xi[6 * wig + 5] = vR;
+        }
+        __syncthreads();
+        // f_w = y0 + vL0 l_{w-1} + vR0 f_{w+1};  l_w = y63 + vL63 l_{w-1} + vR63 f_{w+1}
+        // eliminate upwards: f_w = g_w + h_w f_{w+1}, l_w = p_w + q_w f_{w+1}
+        R gq[G], hq[G], pq[G], qq[G];
+        R pPrev = (R)0, qPrev = (R)0;
+#pragma unroll
+        for (int w = 0; w < G; ++w) {
+            const R y0 = xi[6 * w + 0], vL0 = xi[6 * w + 1], vR0 = xi[6 * w + 2];
+            const R y63 = xi[6 * w + 3], vL63 = xi[6 * w + 4], vR63 = xi[6 * w + 5];
+            const R den = rcp((R)1 - vL0 * qPrev);
+            gq[w] = (y0 + vL0 * pPrev) * den;
+            hq[w] = vR0 * den;
+            pq[w] = y63 + vL63 * (pPrev + qPrev * gq[w]);
+            qq[w] = vR63 + vL63 * qPrev * hq[w];
+            pPrev = pq[w];
+            qPrev = qq[w];
+        }
+        R fNext = (R)0, fw[G], lw[G];
+#pragma unroll
+        for (int w = G - 1; w >= 0; --w) {
+            fw[w] = gq[w] + hq[w] * fNext;
+            lw[w] = pq[w] + qq[w] * fNext;
+            fNext = fw[w];
+        }
+        R uR = (R)0;
+#pragma unroll
+        for (int w = 0; w < G; ++w) {
+            if (w == wig - 1) uL = lw[w];
+            if (w == wig + 1) uR = fw[w];
+        }
+        xe = D + vL * uL + vR * uR;
+    }
+    R xeP = shfl_up1(xe, 1, lane);
+    if (G > 1 && lane == 0) xeP = uL;
+    const R x0 = rho - sig * xeP - tau * xe;
+#pragma unroll
+    for (int r = 1; r < RPL - 1; ++r) x[r] = de[r] - al[r] * x0 - ga[r] * xe;
+    x[0] = x0;
+    x[e] = xe;
+}
+
+// FP32 fields carry a compensated pair per node (hi + lo, |lo| <= ulp(hi)/2):
+// a single float cannot hold per-step increments far below its ulp, so the
+// low part keeps them; arithmetic stays in FP32.
+template <typename R>
+struct Pair {
+    static constexpr bool on = false;
+};
+template <>
+struct Pair<float> {
+    static constexpr bool on = true;
+};
+
+// (a_hi + a_lo) - (b_hi + b_lo) for nearby values: the hi difference is exact
+template <typename R>
+__device__ inline R dif(R ah, R al, R bh, R bl) {
+    if constexpr (Pair<R>::on)
+        return (ah - bh) + (al - bl);
+    else
+        return ah - bh;
+}
+
+// LDS bytes of the staged tables: laws, then per-row gw, ge, info
+template <typename R>
+__host__ __device__ inline size_t law_lds_bytes(int L) {
+    const int nlaw = 3 * L + 2;
+    if constexpr (sizeof(R) == 8)
+        return sizeof(double) * pow_blob_doubles(L);
+    else
+        return sizeof(float) * 4 * nlaw;
+}
+template <typename R>
+__host__ __device__ inline size_t step_lds_bytes(int L, int np) {
+    size_t b = (law_lds_bytes<R>(L) + 15) & ~(size_t)15;
+    return b + (2 * sizeof(R) + sizeof(uint32_t)) * (size_t)np;
+}
+
+// Stage the law tables in LDS (dynamic shared memory); all threads call it.
+template <typename R>
+__device__ inline LawLds<R> stage_laws(const StepArgs<R> &a, unsigned char *smem) {
+    const int t = threadIdx.x, nt = blockDim.x, L = a.laws.L, nlaw = 3 * L + 2;
+    LawLds<R> v;
+    if constexpr (sizeof(R) == 8) {
+        double *d = (double *)smem;
+        const int nb = (int)pow_blob_doubles(L);
+        for (int i = t; i < nb; i += nt) d[i] = a.pow_blob[i];
+        v.erow = d;
+        v.lrow = d + (size_t)(2 * L + 1) * POW_EROW;
+        v.ck = v.lrow + (size_t)nlaw * POW_LROW;
+        v.ca = v.ck + nlaw;
+    } else {
+        float *f = (float *)smem;
+        for (int i = t; i < nlaw; i += nt) {
+            f[i] = (float)a.laws.lk[i];
+            f[nlaw + i] = (float)a.laws.e[i];
+            const bool capl = i >= 2 * L && i < 3 * L;
+            f[2 * nlaw + i] = capl ? (float)a.laws.K[i] : 0.0f;
+            f[3 * nlaw + i] = i == law_unit(L) ? 1.0f : 0.0f;
+        }
+        v.lk = f;
+        v.ex = f + nlaw;
+        v.ck = f + 2 * nlaw;
+        v.ca = f + 3 * nlaw;
+    }
+    __syncthreads();
+    return v;
+}
+
+}  // namespace cryo

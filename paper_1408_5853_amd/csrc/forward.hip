@@ -17,272 +17,143 @@
 // are reduced to one per lane, and parallel cyclic reduction across the wave
 // solves those; lanes then back-substitute their chunk.
 #include <math.h>
+#include <string.h>
 
-#include "internal.h"
+#include "device_common.h"
 
 namespace cryo {
 
-template <typename R>
-__device__ inline R lg2(R x);
-template <>
-__device__ inline double lg2<double>(double x) { return log2(x); }
-template <>
-__device__ inline float lg2<float>(float x) { return log2f(x); }
-template <typename R>
-__device__ inline R ex2(R x);
-template <>
-__device__ inline double ex2<double>(double x) { return exp2(x); }
-template <>
-__device__ inline float ex2<float>(float x) { return exp2f(x); }
-
-template <typename R>
-struct LawTable {
-    R p[2 * MAX_LAYERS], lk[2 * MAX_LAYERS];
-    R q[MAX_LAYERS], lrc[MAX_LAYERS];
-};
-
-template <typename R>
-struct StepArgs {
-    const R *Tin;
-    R *Tout;
-    const R *gw, *ge;
-    const uint32_t *info;
-    Laws laws;
-    int nz, np;
-    R X;                      // amplitude * pulse average of this step
-    int held[4];              // r_inner, r_outer, z_low, z_high
-    R val[4];
-    double *partial;          // nullable: per-workgroup surface partial sums
-    double wz_end, wz_mid;    // trapezoid weights of the surface mean
-    int surf_lane, surf_reg;
-};
-
-constexpr int STEP_WAVES = 4;
-
-template <typename R>
-__device__ inline R shfl_up1(R v, int s, int lane) {
-    R u = __shfl_up(v, s, WAVE);
-    return lane >= s ? u : (R)0;
-}
-template <typename R>
-__device__ inline R shfl_dn1(R v, int s, int lane) {
-    R u = __shfl_down(v, s, WAVE);
-    return lane + s < WAVE ? u : (R)0;
-}
-
-// Solve the wave's tridiagonal system; on entry lane k holds rows
-// k*RPL..k*RPL+RPL-1 in (a, b, c, d); on exit d holds the solution.
-template <typename R, int RPL>
-__device__ inline void wave_solve(R (&a)[RPL], R (&b)[RPL], R (&c)[RPL], R (&d)[RPL],
-                                  int lane) {
-    static_assert(RPL >= 2, "chunks of at least two rows");
-    // forward elimination of rows 1..RPL-1 with a fill-in column on row 0:
-    //   al_r x_0 + x_r + ga_r x_{r+1} = de_r
-    R al[RPL], ga[RPL], de[RPL];
-    {
-        R inv = (R)1 / b[1];
-        al[1] = a[1] * inv;
-        ga[1] = c[1] * inv;
-        de[1] = d[1] * inv;
-    }
-#pragma unroll
-    for (int r = 2; r < RPL; ++r) {
-        R inv = (R)1 / (b[r] - a[r] * ga[r - 1]);
-        al[r] = -a[r] * al[r - 1] * inv;
-        ga[r] = c[r] * inv;
-        de[r] = (d[r] - a[r] * de[r - 1]) * inv;
-    }
-    // backward elimination of rows RPL-3..1 onto the chunk ends x_0, x_e
-#pragma unroll
-    for (int r = RPL - 3; r >= 1; --r) {
-        de[r] = de[r] - ga[r] * de[r + 1];
-        al[r] = al[r] - ga[r] * al[r + 1];
-        ga[r] = -ga[r] * ga[r + 1];
-    }
-    // first row: a0 x_e(k-1) + sb x_0 + sc x_e(k) = sd
-    R sb, sc, sd;
-    if (RPL == 2) {
-        sb = b[0];
-        sc = c[0];
-        sd = d[0];
-    } else {
-        sb = b[0] - c[0] * al[1];
-        sc = -c[0] * ga[1];
-        sd = d[0] - c[0] * de[1];
-    }
-    R isb = (R)1 / sb;
-    R sig = a[0] * isb, tau = sc * isb, rho = sd * isb;    // x_0 = rho - sig x_e(k-1) - tau x_e(k)
-    const int e = RPL - 1;
-    R sigN = shfl_dn1(sig, 1, lane), tauN = shfl_dn1(tau, 1, lane), rhoN = shfl_dn1(rho, 1, lane);
-    // one unknown per lane: x_e(k)
-    R A = -al[e] * sig;
-    R B = (R)1 - al[e] * tau - ga[e] * sigN;
-    R C = -ga[e] * tauN;
-    R D = de[e] - al[e] * rho - ga[e] * rhoN;
-    {
-        R ib = (R)1 / B;
-        A *= ib;
-        C *= ib;
-        D *= ib;
-    }
-#pragma unroll
-    for (int s = 1; s < WAVE; s <<= 1) {
-        R Am = shfl_up1(A, s, lane), Cm = shfl_up1(C, s, lane), Dm = shfl_up1(D, s, lane);
-        R Ap = shfl_dn1(A, s, lane), Cp = shfl_dn1(C, s, lane), Dp = shfl_dn1(D, s, lane);
-        R nb = (R)1 - A * Cm - C * Ap;
-        R ib = (R)1 / nb;
-        R nA = -A * Am * ib;
-        R nC = -C * Cp * ib;
-        R nD = (D - A * Dm - C * Dp) * ib;
-        A = nA;
-        C = nC;
-        D = nD;
-    }
-    R xe = D;
-    R xeP = shfl_up1(xe, 1, lane);
-    R x0 = rho - sig * xeP - tau * xe;
-#pragma unroll
-    for (int r = 1; r < RPL - 1; ++r) d[r] = de[r] - al[r] * x0 - ga[r] * xe;
-    d[0] = x0;
-    d[e] = xe;
-}
-
-// FP32 fields carry a compensated pair per node (hi + lo, |lo| <= ulp(hi)/2):
-// a single float cannot hold per-step increments far below its ulp, so the
-// low part keeps them; arithmetic stays in FP32.
-template <typename R>
-struct Pair {
-    static constexpr bool on = false;
-};
-template <>
-struct Pair<float> {
-    static constexpr bool on = true;
-};
-
-// (a_hi + a_lo) - (b_hi + b_lo) for nearby values: the hi difference is exact
-template <typename R>
-__device__ inline R dif(R ah, R al, R bh, R bl) {
-    if constexpr (Pair<R>::on)
-        return (ah - bh) + (al - bl);
-    else
-        return ah - bh;
-}
-
-template <typename R, int RPL>
-__global__ __launch_bounds__(STEP_WAVES *WAVE) void k_step(StepArgs<R> a) {
+// One step of eq. (8).  A line is spread over G waves (NL = 64 G lanes, each
+// lane a chunk of RPL rows); a workgroup of STEP_WAVES waves runs
+// STEP_WAVES / G lines side by side.  Each line group marches up a block of
+// lpw consecutive interior lines, keeping the flux through the face between
+// the current and the next line: the north-face flux of line j is the
+// south-face flux of line j+1 (eq. (11)), so a capacity row evaluates two
+// conductivities per line (east r-face, north z-face) instead of three.
+template <typename R, int RPL, int G>
+__device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *__restrict__ Tin,
+                                 R *__restrict__ Tout, const R X, double *partial) {
     constexpr bool PAIR = Pair<R>::on;
-    __shared__ LawTable<R> lw;
+    constexpr int NL = WAVE * G;                      // lanes per line
+    constexpr int NG = STEP_WAVES / G;                // lines per workgroup
+    extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double wsum[STEP_WAVES];
+    __shared__ R xchg[NG][9 * G];
+    // per-row tables of the line (shared by every line) after the law tables
+    R *sgw = (R *)(smem + ((law_lds_bytes<R>(a.laws.L) + 15) & ~(size_t)15));
+    R *sge = sgw + a.np;
+    uint32_t *sinf = (uint32_t *)(sge + a.np);
+    for (int i = threadIdx.x; i < a.np; i += blockDim.x) {
+        sgw[i] = a.gw[i];
+        sge[i] = a.ge[i];
+        sinf[i] = a.info[i];
+    }
+    const LawLds<R> law = stage_laws<R>(a, smem);       // ends with a barrier
     const int t = threadIdx.x;
-    if (t < a.laws.n) {
-        lw.p[t] = (R)a.laws.p[t];
-        lw.lk[t] = (R)a.laws.lk[t];
-    }
-    if (t < a.laws.L) {
-        lw.q[t] = (R)a.laws.q[t];
-        lw.lrc[t] = (R)a.laws.lrc[t];
-    }
-    __syncthreads();
     const int lane = t & (WAVE - 1), wv = t / WAVE;
-    const int j = 1 + blockIdx.x * STEP_WAVES + wv;
+    const int grp = wv / G, wig = wv % G, lg = wig * WAVE + lane;
+    const int L = a.laws.L;
+    const int j0 = 1 + (blk * NG + grp) * a.lpw;
+    const int j1 = min(j0 + a.lpw, a.nz - 1);             // exclusive
     const size_t LS = (size_t)a.np * (PAIR ? 2 : 1);      // line stride
+    R *xch = xchg[grp];
+    // neighbour rows across the chunk ends (the row itself at the line ends)
+    const int qW = lg > 0 ? (RPL - 1) * NL + lg - 1 : 0;
+    const int qE = lg < NL - 1 ? lg + 1 : (RPL - 1) * NL + lg;
     double sv = 0.0;
-    if (j <= a.nz - 2) {
+    int bad = 0;
+    R FS[RPL];
+    {
+        // south-face flux of the block's first line (capacity rows); groups
+        // without lines work on line 1 and store nothing
+        const size_t bc = (size_t)min(j0, a.nz - 2) * LS;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int q = r * NL + lg;
+            const R T = Tin[bc + q], Tl = PAIR ? Tin[bc + a.np + q] : (R)0;
+            const R Tp = Tin[bc - LS + q], Tpl = PAIR ? Tin[bc - LS + a.np + q] : (R)0;
+            const uint32_t inf_r = sinf[q];
+            const bool cap = (inf_r & 7) == K_CAP;
+            const int l2 = (inf_r >> 12) & 63;
+            const R lamS = law.law(cap ? l2 : law_zero(L), (R)0.5 * (T + Tp), bad);
+            FS[r] = lamS * dif<R>(T, Tl, Tp, Tpl);
+        }
+    }
+    for (int it = 0; it < a.lpw; ++it) {
+        const int jr = j0 + it;
+        const bool active = jr < j1;
+        const int j = min(jr, a.nz - 2);
         const size_t base = (size_t)j * LS;
-        R Tc[RPL], Tn[RPL], Ts[RPL], gw[RPL], ge[RPL];
-        R Lc[RPL], Ln[RPL], Ls[RPL];                       // low parts (pairs)
-        uint32_t inf[RPL];
+        R Tc[RPL], Lc[RPL];
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
-            const int q = r * WAVE + lane;
-            Tc[r] = a.Tin[base + q];
-            Tn[r] = a.Tin[base + LS + q];
-            Ts[r] = a.Tin[base - LS + q];
-            if constexpr (PAIR) {
-                Lc[r] = a.Tin[base + a.np + q];
-                Ln[r] = a.Tin[base + LS + a.np + q];
-                Ls[r] = a.Tin[base - LS + a.np + q];
-            } else {
-                Lc[r] = Ln[r] = Ls[r] = (R)0;
-            }
-            inf[r] = a.info[q];
-            gw[r] = a.gw[q];
-            ge[r] = a.ge[q];
+            const int q = r * NL + lg;
+            Tc[r] = Tin[base + q];
+            Lc[r] = PAIR ? Tin[base + a.np + q] : (R)0;
         }
-        // r-neighbours across the chunk ends
-        const R TwF = __shfl_up(Tc[RPL - 1], 1, WAVE);
-        const R TeL = __shfl_down(Tc[0], 1, WAVE);
-        R LwF = (R)0, LeL = (R)0;
-        if constexpr (PAIR) {
-            LwF = __shfl_up(Lc[RPL - 1], 1, WAVE);
-            LeL = __shfl_down(Lc[0], 1, WAVE);
-        }
-        // east r-face conductivities, one per face (eq. (10), face-mean T)
-        R lamE[RPL];
+        const R TwF = Tin[base + qW], TeL = Tin[base + qE];
+        const R LwF = PAIR ? Tin[base + a.np + qW] : (R)0;
+        const R LeL = PAIR ? Tin[base + a.np + qE] : (R)0;
+        // west face of the chunk's first row: east face of the previous row
+        R lamW = law.law((sinf[qW] >> 6) & 63, (R)0.5 * (TwF + Tc[0]), bad);
+        R a0 = 0, b0 = 1, c0 = 0, d0 = 0;
+        R al[RPL], ga[RPL], de[RPL];
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
-            const R Te = (r < RPL - 1) ? Tc[r + 1] : TeL;
-            const uint32_t le = (inf[r] >> 4) & 31;
-            lamE[r] = ex2<R>(lw.p[le] * lg2<R>((R)0.5 * (Tc[r] + Te)) + lw.lk[le]);
-        }
-        const R lamWF = __shfl_up(lamE[RPL - 1], 1, WAVE);
-        R A[RPL], B[RPL], C[RPL], D[RPL];
-#pragma unroll
-        for (int r = 0; r < RPL; ++r) {
-            const uint32_t kind = inf[r] & 7;
+            const int q = r * NL + lg;
+            const uint32_t inf_r = sinf[q];
+            const uint32_t kind = inf_r & 7;
             const bool cap = kind == K_CAP;
             const R T = Tc[r], Tl = Lc[r];
+            const R Tnr = Tin[base + LS + q];
+            const R Lnr = PAIR ? Tin[base + LS + a.np + q] : (R)0;
             const R Tw = (r > 0) ? Tc[r - 1] : TwF;
             const R Te = (r < RPL - 1) ? Tc[r + 1] : TeL;
             const R Lw = (r > 0) ? Lc[r - 1] : LwF;
             const R Le = (r < RPL - 1) ? Lc[r + 1] : LeL;
-            const R lW = (r > 0) ? lamE[r - 1] : lamWF;
-            // slots 2/3: axial faces of a capacity row (eq. (11)), or the two
-            // layer laws at the node for an interface row (eq. (18))
-            const uint32_t l2 = (inf[r] >> 9) & 31, l3 = (inf[r] >> 14) & 31;
-            const uint32_t lc = (inf[r] >> 19) & 31;
-            const R th2 = cap ? (R)0.5 * (T + Tn[r]) : T;
-            const R th3 = cap ? (R)0.5 * (T + Ts[r]) : T;
-            const R lam2 = ex2<R>(lw.p[l2] * lg2<R>(th2) + lw.lk[l2]);
-            const R lam3 = ex2<R>(lw.p[l3] * lg2<R>(th3) + lw.lk[l3]);
-            const R rc = cap ? ex2<R>(lw.q[lc] * lg2<R>(T) + lw.lrc[lc]) : (R)0;
-            const R fw = gw[r] * (cap ? lW : lam2);
-            const R fe = ge[r] * (cap ? lamE[r] : lam3);
-            const R dW = dif<R>(Tw, Lw, T, Tl), dE = dif<R>(Te, Le, T, Tl);
-            R dd = fw * dW + fe * dE;
-            if (cap) {
-                dd += lam2 * dif<R>(Tn[r], Ln[r], T, Tl) - lam3 * dif<R>(T, Tl, Ts[r], Ls[r]);
-                if ((inf[r] >> 3) & 1) dd += a.X;
+            const int le = (inf_r >> 6) & 63, l2 = (inf_r >> 12) & 63;
+            const int l3 = (inf_r >> 18) & 63, lc = (inf_r >> 24) & 63;
+            const R lamE = law.law(le, (R)0.5 * (T + Te), bad);
+            // slot 2: north axial face (capacity) or inner-layer law at the node
+            const R lam2 = law.law(l2, cap ? (R)0.5 * (T + Tnr) : T, bad);
+            // slot 3: outer-layer law at an interface node; unit or zero otherwise
+            R lam3 = l3 == law_unit(L) ? (R)1 : (R)0;
+            if (__any(kind == K_IFACE)) {
+                const R v = law.law(l3, T, bad);
+                lam3 = kind == K_IFACE ? v : lam3;
             }
-            R aa = -fw, bb = fw + fe + rc, cc = -fe;
-            if (kind == K_LO) {
-                aa = 0;
-                bb = 1;
-                cc = a.held[0] ? (R)0 : (R)-1;
-                dd = a.held[0] ? dif<R>(a.val[0], (R)0, T, Tl) : dE;
-            } else if (kind == K_HI) {
-                cc = 0;
-                bb = 1;
-                aa = a.held[1] ? (R)0 : (R)-1;
-                dd = a.held[1] ? dif<R>(a.val[1], (R)0, T, Tl) : dW;
-            } else if (kind == K_PAD) {
-                aa = 0;
-                bb = 1;
-                cc = 0;
-                dd = 0;
+            const R rc = a.laws.cube ? law.cube(lc, T) : law.law(lc, T, bad);
+            const R fw = sgw[q] * (cap ? lamW : lam2);
+            const R fe = sge[q] * (cap ? lamE : lam3);
+            const R FN = lam2 * dif<R>(Tnr, Lnr, T, Tl);
+            R dd = fw * dif<R>(Tw, Lw, T, Tl) + fe * dif<R>(Te, Le, T, Tl);
+            dd += cap ? FN - FS[r] : (R)0;
+            dd += ((inf_r >> 3) & 1) ? X : (R)0;
+            if ((inf_r >> 4) & 1) dd = dif<R>(a.val[(inf_r >> 5) & 1], (R)0, T, Tl);
+            FS[r] = FN;
+            lamW = lamE;
+            const R aa = -fw, bb = fw + fe + rc, cc = -fe;
+            if (r == 0) {
+                a0 = aa;
+                b0 = bb;
+                c0 = cc;
+                d0 = dd;
+            } else {
+                elim_row<R, RPL>(r, aa, bb, cc, dd, al, ga, de);
             }
-            A[r] = aa;
-            B[r] = bb;
-            C[r] = cc;
-            D[r] = dd;
+            // keep the scheduler from hoisting every row's law evaluations
+            // at once (register pressure); rows still overlap pairwise
+            if (r & 1) __builtin_amdgcn_sched_barrier(0);
         }
-        wave_solve<R, RPL>(A, B, C, D, lane);
+        R X[RPL];
+        solve_tail<R, RPL, G>(a0, b0, c0, d0, al, ga, de, X, lane, wig, xch);
+        if (!active) continue;
         // new state: T + dT (pairs: error-free sum, then renormalise)
         R Hn[RPL], Lnw[RPL];
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
             if constexpr (PAIR) {
-                const R x = D[r], h = Tc[r];
+                const R x = X[r], h = Tc[r];
                 const R s = h + x;
                 const R bp = s - h;
                 const R err = (h - (s - bp)) + (x - bp);
@@ -291,11 +162,11 @@ __global__ __launch_bounds__(STEP_WAVES *WAVE) void k_step(StepArgs<R> a) {
                 Hn[r] = h2;
                 Lnw[r] = lo - (h2 - s);
             } else {
-                Hn[r] = Tc[r] + D[r];
+                Hn[r] = Tc[r] + X[r];
                 Lnw[r] = (R)0;
             }
-            a.Tout[base + r * WAVE + lane] = Hn[r];
-            if constexpr (PAIR) a.Tout[base + a.np + r * WAVE + lane] = Lnw[r];
+            Tout[base + r * NL + lg] = Hn[r];
+            if constexpr (PAIR) Tout[base + a.np + r * NL + lg] = Lnw[r];
         }
         // z-boundary lines: copied (insulated) or held, after the solve
 #pragma unroll
@@ -303,32 +174,69 @@ __global__ __launch_bounds__(STEP_WAVES *WAVE) void k_step(StepArgs<R> a) {
             const bool mine = side == 0 ? j == 1 : j == a.nz - 2;
             if (!mine) continue;
             const bool held = a.held[2 + side];
-            R *o = a.Tout + (side == 0 ? (size_t)0 : (size_t)(a.nz - 1) * LS);
+            R *o = Tout + (side == 0 ? (size_t)0 : (size_t)(a.nz - 1) * LS);
 #pragma unroll
             for (int r = 0; r < RPL; ++r) {
-                o[r * WAVE + lane] = held ? a.val[2 + side] : Hn[r];
-                if constexpr (PAIR) o[a.np + r * WAVE + lane] = held ? (R)0 : Lnw[r];
+                o[r * NL + lg] = held ? a.val[2 + side] : Hn[r];
+                if constexpr (PAIR) o[a.np + r * NL + lg] = held ? (R)0 : Lnw[r];
             }
         }
-        if (a.partial && lane == a.surf_lane) {
+        if (partial && lg == a.surf_lane) {
             double v = (double)Hn[0] + (double)Lnw[0];
 #pragma unroll
             for (int r = 1; r < RPL; ++r)
                 if (r == a.surf_reg) v = (double)Hn[r] + (double)Lnw[r];
-            sv = a.wz_mid * v;
+            sv += a.wz_mid * v;
             if (j == 1) sv += a.wz_end * (a.held[2] ? (double)a.val[2] : v);
             if (j == a.nz - 2) sv += a.wz_end * (a.held[3] ? (double)a.val[3] : v);
         }
     }
-    if (a.partial) {
-        if (lane == a.surf_lane) wsum[wv] = sv;
+    if (__any(bad)) {
+        if (lane == 0) atomicOr(a.flag, 2);
+    }
+    if (partial) {
+        if (lane == (a.surf_lane & (WAVE - 1))) wsum[wv] = sv;
         __syncthreads();
         if (t == 0) {
             double s = 0.0;
             for (int w = 0; w < STEP_WAVES; ++w) s += wsum[w];
-            a.partial[blockIdx.x] = s;
+            partial[blk] = s;
         }
     }
+}
+
+template <typename R, int RPL, int G>
+__global__ __launch_bounds__(STEP_WAVES *WAVE) void k_step(StepArgs<R> a) {
+    step_body<R, RPL, G>(a, blockIdx.x, a.Tin, a.Tout, a.X, a.partial);
+}
+
+// Pulse average over step k (eq. (4)), step units; the host's schedule.
+__device__ inline double source_fraction_dev(const Pulse &p, int64_t k) {
+    if (!(p.W > 0)) return 0.0;
+    const double lo = (double)k, hi = lo + 1.0;
+    double s = 0.0;
+    int64_t n = (int64_t)floor((lo - p.b0 - p.W) / p.P);
+    if (n < 0) n = 0;
+    for (int guard = 0; guard < 64; ++guard, ++n) {
+        const double b = p.b0 + (double)n * p.P;
+        if (b >= hi) break;
+        const double o = fmin(hi, b + p.W) - fmax(lo, b);
+        if (o > 0) s += o;
+    }
+    return s;
+}
+
+// One step of many instances: workgroup -> (instance, workgroup of that
+// instance); global step k = *k0 + n; buffers by the parity of n.
+template <typename R, int RPL, int G>
+__global__ __launch_bounds__(STEP_WAVES *WAVE) void k_step_batch(const StepArgs<R> *descs,
+                                                                 const int2 *wg_map, int64_t n,
+                                                                 const int64_t *k0) {
+    const int2 m = wg_map[blockIdx.x];
+    const StepArgs<R> &a = descs[m.x];
+    const double X = a.pulse.amplitude * source_fraction_dev(a.pulse, *k0 + n);
+    double *part = a.partial ? a.partial + (size_t)(n % SURF_CHUNK) * a.groups : nullptr;
+    step_body<R, RPL, G>(a, m.y, a.buf[n & 1], a.buf[(n + 1) & 1], (R)X, part);
 }
 
 // ABI field -> internal lines.  FP32 fields are two planes [2][nz][nr]
@@ -344,7 +252,8 @@ __global__ void k_to_internal(const R *T, R *Ti, int nz, int nr, int np, int rpl
         int j = (int)(idx / ((size_t)NPL * np));
         int rem = (int)(idx % ((size_t)NPL * np));
         int plane = rem / np, q = rem % np;
-        int i = (q % WAVE) * rpl + q / WAVE;
+        const int nl = np / rpl;                      // lanes per line
+        int i = (q % nl) * rpl + q / nl;
         R v = plane == 0 ? pad : (R)0;
         if (i < nr) v = T[((size_t)plane * nz + j) * nr + i];
         Ti[idx] = v;
@@ -361,7 +270,8 @@ __global__ void k_from_internal(const R *Ti, R *T, int nz, int nr, int np, int r
         int plane = (int)(idx / ((size_t)nz * nr));
         size_t rem = idx % ((size_t)nz * nr);
         int j = (int)(rem / nr), i = (int)(rem % nr);
-        R v = Ti[((size_t)j * NPL + plane) * np + (i % rpl) * WAVE + i / rpl];
+        const int nl = np / rpl;
+        R v = Ti[((size_t)j * NPL + plane) * np + (i % rpl) * nl + i / rpl];
         T[idx] = v;
         bad |= !isfinite(v);
     }
@@ -395,7 +305,11 @@ static cryo_status launch_check(const char *what) {
     return CRYO_OK;
 }
 
-int step_grid(const cryo_plan *p) { return (p->nz - 2 + STEP_WAVES - 1) / STEP_WAVES; }
+int step_grid(const cryo_plan *p) {
+    const int groups = (p->nz - 2 + p->lpw - 1) / p->lpw;
+    const int per_wg = STEP_WAVES / p->wpl;
+    return (groups + per_wg - 1) / per_wg;
+}
 
 template <typename R>
 static cryo_status to_internal_t(const cryo_plan *p, const void *T, void *Ti, int *flag,
@@ -437,16 +351,19 @@ cryo_status launch_fill(const cryo_plan *p, void *T, hipStream_t s) {
 
 template <typename R>
 static StepArgs<R> step_args(const cryo_plan *p, const void *Tin, void *Tout, double X,
-                             double *partial) {
+                             double *partial, int *flag) {
     StepArgs<R> a;
+    a.flag = flag;
     a.Tin = (const R *)Tin;
     a.Tout = (R *)Tout;
     a.gw = (const R *)p->d_gw;
     a.ge = (const R *)p->d_ge;
     a.info = p->d_info;
+    a.pow_blob = p->d_pow;
     a.laws = p->laws;
     a.nz = p->nz;
     a.np = p->np;
+    a.lpw = p->lpw;
     a.X = (R)X;
     for (int s = 0; s < 4; ++s) {
         a.held[s] = p->prob.bc.kind[s] == CRYO_HELD;
@@ -457,29 +374,36 @@ static StepArgs<R> step_args(const cryo_plan *p, const void *Tin, void *Tout, do
     a.wz_end = 0.5 / (p->nz - 1);
     a.surf_lane = p->surf_lane;
     a.surf_reg = p->surf_reg;
+    a.groups = step_grid(p);
+    a.pulse = p->pulse;
+    a.buf[0] = a.buf[1] = nullptr;
     return a;
 }
 
 template <typename R>
 static cryo_status step_t(const cryo_plan *p, const void *Tin, void *Tout, double X,
-                          double *partial, hipStream_t s) {
-    StepArgs<R> a = step_args<R>(p, Tin, Tout, X, partial);
+                          double *partial, int *flag, hipStream_t s) {
+    StepArgs<R> a = step_args<R>(p, Tin, Tout, X, partial, flag);
     dim3 g(step_grid(p)), b(STEP_WAVES * WAVE);
-    switch (p->rpl) {
-    case 2: hipLaunchKernelGGL((k_step<R, 2>), g, b, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_step<R, 4>), g, b, 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_step<R, 8>), g, b, 0, s, a); break;
-    case 16: hipLaunchKernelGGL((k_step<R, 16>), g, b, 0, s, a); break;
-    case 32: hipLaunchKernelGGL((k_step<R, 32>), g, b, 0, s, a); break;
-    default: return fail(CRYO_ERR_UNSUPPORTED, "radial chunk length");
+    const size_t lds = step_lds_bytes<R>(p->L, p->np);
+    const int key = p->rpl * 10 + p->wpl;
+    switch (key) {
+    case 21: hipLaunchKernelGGL((k_step<R, 2, 1>), g, b, lds, s, a); break;
+    case 41: hipLaunchKernelGGL((k_step<R, 4, 1>), g, b, lds, s, a); break;
+    case 81: hipLaunchKernelGGL((k_step<R, 8, 1>), g, b, lds, s, a); break;
+    case 82: hipLaunchKernelGGL((k_step<R, 8, 2>), g, b, lds, s, a); break;
+    case 84: hipLaunchKernelGGL((k_step<R, 8, 4>), g, b, lds, s, a); break;
+    case 42: hipLaunchKernelGGL((k_step<R, 4, 2>), g, b, lds, s, a); break;
+    case 44: hipLaunchKernelGGL((k_step<R, 4, 4>), g, b, lds, s, a); break;
+    default: return fail(CRYO_ERR_UNSUPPORTED, "radial chunk shape");
     }
     return launch_check("step");
 }
 
 cryo_status launch_step(const cryo_plan *p, const void *Tin, void *Tout, double X,
-                        double *partial, hipStream_t s) {
-    return p->dtype == CRYO_F64 ? step_t<double>(p, Tin, Tout, X, partial, s)
-                                : step_t<float>(p, Tin, Tout, X, partial, s);
+                        double *partial, int *flag, hipStream_t s) {
+    return p->dtype == CRYO_F64 ? step_t<double>(p, Tin, Tout, X, partial, flag, s)
+                                : step_t<float>(p, Tin, Tout, X, partial, flag, s);
 }
 
 cryo_status launch_surf_reduce(const cryo_plan *p, const double *partial, int nsteps,
@@ -489,4 +413,75 @@ cryo_status launch_surf_reduce(const cryo_plan *p, const double *partial, int ns
     return launch_check("surf_reduce");
 }
 
+}  // namespace cryo
+
+namespace cryo {
+
+// ---- batch support -------------------------------------------------------
+size_t step_desc_bytes(cryo_dtype dt) {
+    return dt == CRYO_F64 ? sizeof(StepArgs<double>) : sizeof(StepArgs<float>);
+}
+
+size_t step_lds(const cryo_plan *p) {
+    return p->dtype == CRYO_F64 ? step_lds_bytes<double>(p->L, p->np)
+                                : step_lds_bytes<float>(p->L, p->np);
+}
+
+void step_desc_fill(const cryo_plan *p, void *out, void *buf0, void *buf1, int *flag) {
+    if (p->dtype == CRYO_F64) {
+        StepArgs<double> a = step_args<double>(p, nullptr, nullptr, 0.0, nullptr, flag);
+        a.buf[0] = (double *)buf0;
+        a.buf[1] = (double *)buf1;
+        memcpy(out, &a, sizeof(a));
+    } else {
+        StepArgs<float> a = step_args<float>(p, nullptr, nullptr, 0.0, nullptr, flag);
+        a.buf[0] = (float *)buf0;
+        a.buf[1] = (float *)buf1;
+        memcpy(out, &a, sizeof(a));
+    }
+}
+
+template <typename R>
+static cryo_status step_batch_t(int rpl, int wpl, const void *desc, const int2 *map, int nwg,
+                                size_t lds, int64_t n, const int64_t *k0, hipStream_t s) {
+    const StepArgs<R> *d = (const StepArgs<R> *)desc;
+    dim3 g(nwg), b(STEP_WAVES * WAVE);
+    switch (rpl * 10 + wpl) {
+    case 21: hipLaunchKernelGGL((k_step_batch<R, 2, 1>), g, b, lds, s, d, map, n, k0); break;
+    case 41: hipLaunchKernelGGL((k_step_batch<R, 4, 1>), g, b, lds, s, d, map, n, k0); break;
+    case 81: hipLaunchKernelGGL((k_step_batch<R, 8, 1>), g, b, lds, s, d, map, n, k0); break;
+    case 82: hipLaunchKernelGGL((k_step_batch<R, 8, 2>), g, b, lds, s, d, map, n, k0); break;
+    case 84: hipLaunchKernelGGL((k_step_batch<R, 8, 4>), g, b, lds, s, d, map, n, k0); break;
+    case 42: hipLaunchKernelGGL((k_step_batch<R, 4, 2>), g, b, lds, s, d, map, n, k0); break;
+    case 44: hipLaunchKernelGGL((k_step_batch<R, 4, 4>), g, b, lds, s, d, map, n, k0); break;
+    default: return fail(CRYO_ERR_UNSUPPORTED, "radial chunk shape");
+    }
+    return launch_check("step_batch");
+}
+
+cryo_status launch_step_batch(cryo_dtype dt, int rpl, int wpl, const void *desc, const int2 *map,
+                              int nwg, size_t lds, int64_t n, const int64_t *k0, hipStream_t s) {
+    return dt == CRYO_F64 ? step_batch_t<double>(rpl, wpl, desc, map, nwg, lds, n, k0, s)
+                          : step_batch_t<float>(rpl, wpl, desc, map, nwg, lds, n, k0, s);
+}
+
+__global__ void k_set_i64(int64_t *p, int64_t v) { *p = v; }
+__global__ void k_add_i64(int64_t *p, int64_t v) { *p += v; }
+
+cryo_status launch_set_i64(int64_t *ptr, int64_t v, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, ptr, v);
+    return launch_check("set_i64");
+}
+
+cryo_status launch_add_i64(int64_t *ptr, int64_t v, hipStream_t s) {
+    hipLaunchKernelGGL(k_add_i64, dim3(1), dim3(1), 0, s, ptr, v);
+    return launch_check("add_i64");
+}
+
+}  // namespace cryo
+
+namespace cryo {
+StepArgs<double> step_args_f64(const cryo_plan *p, int *flag) {
+    return step_args<double>(p, nullptr, nullptr, 0.0, nullptr, flag);
+}
 }  // namespace cryo

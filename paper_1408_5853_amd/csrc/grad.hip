@@ -1,0 +1,258 @@
+// Gradient driver: J = sum_{n=1..N} (S_n - target_n)^2 of the surface mean S
+// and dJ/d[amplitude, width, thickness_m, k_scale_m] by the discrete
+// adjoint, with checkpoints every K steps and recompute of each segment.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace cryo {
+
+struct AdjArgs {
+    const double *T;
+    const double *X;
+    const double *lam_in;
+    double *Y;
+    double *lpart;
+    double *lam_out;
+    double *acc;
+    double *accg;
+    double s, ds;
+    double cS;
+};
+cryo_status launch_adj(const cryo_plan *p, int pass, const AdjArgs &d, int *flag, hipStream_t s);
+cryo_status launch_adj_init(const cryo_plan *p, double *lam, double cS, hipStream_t s);
+cryo_status launch_zero(double *ptr, size_t n, hipStream_t s);
+int adj_groups(const cryo_plan *p);
+
+static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// d/d(width) of the pulse average of step k (step units in, 1/s out): a pulse
+// end inside the step counts fully, one on a step boundary half on each side
+static double source_fraction_dwidth(const Pulse &p, double dt, int64_t k) {
+    if (!(p.W > 0)) return 0.0;
+    double lo = (double)k, hi = lo + 1.0, d = 0.0;
+    int64_t n = (int64_t)floor((lo - p.b0 - p.W) / p.P);
+    if (n < 0) n = 0;
+    for (;; ++n) {
+        double b = p.b0 + (double)n * p.P;
+        if (b >= hi) break;
+        double e = b + p.W;
+        if (e > lo && e < hi) d += 1.0;
+        else if (e == lo || e == hi) d += 0.5;
+    }
+    return d / dt;
+}
+
+struct GradLayout {
+    size_t flag, fwd_buf[2], part, ck, seg, lam[2], Y, lpart, acc, accg, surf, total;
+    int64_t nck, K;
+};
+
+static GradLayout grad_layout(const cryo_plan *p, int64_t N, int64_t ckpt) {
+    GradLayout g;
+    const size_t F = al256(8 * (size_t)p->nz * p->np);
+    int64_t K = ckpt > 0 ? ckpt : (int64_t)ceil(sqrt((double)std::max<int64_t>(N, 1)));
+    K = std::max<int64_t>(1, std::min<int64_t>(K, std::max<int64_t>(N, 1)));
+    g.K = K;
+    g.nck = (N + K - 1) / K;
+    size_t o = 0;
+    g.flag = o; o += 256;
+    g.fwd_buf[0] = o; o += F;
+    g.fwd_buf[1] = o; o += F;
+    g.part = o; o += al256(sizeof(double) * (size_t)SURF_CHUNK * step_grid(p));
+    g.ck = o; o += F * (size_t)std::max<int64_t>(g.nck, 1);
+    g.seg = o; o += F * (size_t)(K + 1);
+    g.lam[0] = o; o += F;
+    g.lam[1] = o; o += F;
+    g.Y = o; o += F;
+    g.lpart = o; o += F;
+    g.acc = o; o += al256(sizeof(double) * 3 * (size_t)p->np * adj_groups(p));
+    g.accg = o; o += al256(sizeof(double) * 2 * (size_t)adj_groups(p));
+    g.surf = o; o += al256(sizeof(double) * (size_t)std::max<int64_t>(N, 1));
+    g.total = o;
+    return g;
+}
+
+}  // namespace cryo
+
+using namespace cryo;
+
+extern "C" {
+
+cryo_status cryo_gradient_workspace_bytes(const cryo_plan *p, int64_t nsteps, int64_t ckpt,
+                                          size_t *bytes) {
+    if (!p || !bytes || nsteps < 1 || ckpt < 0) return fail(CRYO_ERR_ARG, "bad argument");
+    *bytes = grad_layout(p, nsteps, ckpt).total;
+    return CRYO_OK;
+}
+
+cryo_status cryo_gradient(const cryo_plan *pc, const void *T0, int64_t N, const double *target,
+                          int64_t ckpt, void *ws, size_t ws_bytes, double *J, double *grad,
+                          double *surf_out, void *stream) {
+    cryo_plan *p = const_cast<cryo_plan *>(pc);
+    if (!p || !T0 || N < 1 || !target || !J || !grad || ckpt < 0)
+        return fail(CRYO_ERR_ARG, "bad argument");
+    if (p->dtype != CRYO_F64) return fail(CRYO_ERR_UNSUPPORTED, "the adjoint needs an FP64 plan");
+    const GradLayout g = grad_layout(p, N, ckpt);
+    if (!ws || ws_bytes < g.total)
+        return fail(CRYO_ERR_WORKSPACE, "gradient workspace needs " + std::to_string(g.total) +
+                                            " bytes");
+    if (((uintptr_t)ws & 255) != 0) return fail(CRYO_ERR_WORKSPACE, "workspace must be 256-aligned");
+    cryo_status st = ensure_device(p);
+    if (st != CRYO_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ws;
+    int *flag = (int *)(w + g.flag);
+    const size_t F = al256(8 * (size_t)p->nz * p->np);
+    auto ckp = [&](int64_t i) { return (double *)(w + g.ck + F * i); };
+    auto segp = [&](int64_t i) { return (double *)(w + g.seg + F * i); };
+    double *surf = (double *)(w + g.surf);
+    double *part = (double *)(w + g.part);
+    const int G = step_grid(p);
+
+    // forward with checkpoints and the surface trace
+    st = launch_to_internal(p, T0, w + g.fwd_buf[0], flag, s);
+    if (st != CRYO_OK) return st;
+    int64_t done = 0;
+    for (int64_t k = 0; k < N; ++k) {
+        void *cur = w + g.fwd_buf[k & 1], *nxt = w + g.fwd_buf[(k + 1) & 1];
+        if (k % g.K == 0 &&
+            hipMemcpyAsync(ckp(k / g.K), cur, F, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return fail(CRYO_ERR_DEVICE, "checkpoint copy");
+        const double X = p->pulse.amplitude * source_fraction(p->pulse, k);
+        st = launch_step(p, cur, nxt, X, part + (size_t)(k % SURF_CHUNK) * G, flag, s);
+        if (st != CRYO_OK) return st;
+        if ((k + 1) % SURF_CHUNK == 0 || k + 1 == N) {
+            st = launch_surf_reduce(p, part, (int)(k + 1 - done), surf + done, s);
+            if (st != CRYO_OK) return st;
+            done = k + 1;
+        }
+    }
+    std::vector<double> S(N);
+    if (hipMemcpyAsync(S.data(), surf, sizeof(double) * N, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(CRYO_ERR_DEVICE, "surface trace copy");
+    double Jv = 0.0;
+    std::vector<double> cS(N + 1, 0.0);
+    for (int64_t n = 1; n <= N; ++n) {
+        const double dv = S[n - 1] - target[n - 1];
+        Jv += dv * dv;
+        cS[n] = 2.0 * dv;
+    }
+    if (surf_out) memcpy(surf_out, S.data(), sizeof(double) * N);
+
+    // backward
+    const int ngrp = adj_groups(p);
+    double *acc = (double *)(w + g.acc), *accg = (double *)(w + g.accg);
+    st = launch_zero(acc, 3 * (size_t)p->np * ngrp, s);
+    if (st == CRYO_OK) st = launch_zero(accg, 2 * (size_t)ngrp, s);
+    double *lam[2] = {(double *)(w + g.lam[0]), (double *)(w + g.lam[1])};
+    if (st == CRYO_OK) st = launch_adj_init(p, lam[0], cS[N], s);
+    if (st != CRYO_OK) return st;
+    int cur = 0;
+    for (int64_t sg = g.nck - 1; sg >= 0; --sg) {
+        const int64_t a = sg * g.K, b = std::min<int64_t>(N, a + g.K);
+        if (hipMemcpyAsync(segp(0), ckp(sg), F, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return fail(CRYO_ERR_DEVICE, "checkpoint restore");
+        for (int64_t k = a; k < b; ++k) {
+            const double X = p->pulse.amplitude * source_fraction(p->pulse, k);
+            st = launch_step(p, segp(k - a), segp(k - a + 1), X, nullptr, flag, s);
+            if (st != CRYO_OK) return st;
+        }
+        for (int64_t k = b - 1; k >= a; --k) {
+            AdjArgs d;
+            d.T = segp(k - a);
+            d.X = segp(k - a + 1);
+            d.lam_in = lam[cur];
+            d.Y = (double *)(w + g.Y);
+            d.lpart = (double *)(w + g.lpart);
+            d.lam_out = lam[cur ^ 1];
+            d.acc = acc;
+            d.accg = accg;
+            d.s = source_fraction(p->pulse, k);
+            d.ds = source_fraction_dwidth(p->pulse, p->prob.dt, k);
+            d.cS = k >= 1 ? cS[k] : 0.0;
+            st = launch_adj(p, 1, d, flag, s);
+            if (st == CRYO_OK) st = launch_adj(p, 2, d, flag, s);
+            if (st != CRYO_OK) return st;
+            cur ^= 1;
+        }
+    }
+    // row sums over line groups (fixed order), then the parameter gradient
+    std::vector<double> hacc(3 * (size_t)p->np * ngrp), hg(2 * (size_t)ngrp);
+    int hflag = 0;
+    if (hipMemcpyAsync(hacc.data(), acc, sizeof(double) * hacc.size(), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(hg.data(), accg, sizeof(double) * hg.size(), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(CRYO_ERR_DEVICE, "gradient sums copy");
+    if (hflag) return fail(CRYO_ERR_NONFINITE, "non-finite or out-of-range temperature produced");
+    const int nr = p->nr, L = p->L, np = p->np, rpl = p->rpl, NL = np / rpl;
+    std::vector<double> SW(nr, 0.0), SE(nr, 0.0), SZ(nr, 0.0);
+    for (int i = 0; i < nr; ++i) {
+        const int q = (i % rpl) * NL + i / rpl;
+        for (int gi = 0; gi < ngrp; ++gi) {
+            const double *A = hacc.data() + (size_t)gi * 3 * np;
+            SW[i] += A[q];
+            SE[i] += A[np + q];
+            SZ[i] += A[2 * np + q];
+        }
+    }
+    double gQ = 0.0, gW = 0.0;
+    for (int gi = 0; gi < ngrp; ++gi) {
+        gQ += hg[2 * gi];
+        gW += hg[2 * gi + 1];
+    }
+    // geometry derivatives: h_i = thick_m / n_m for intervals of layer m,
+    // r_i = r_inner + sum of h up to i
+    std::vector<double> dr((size_t)nr * L, 0.0), dh((size_t)(nr + 1) * L, 0.0);
+    for (int i = 1; i < nr; ++i) {
+        const int m = p->lay[i];
+        dh[(size_t)i * L + m] = 1.0 / p->layers[m].intervals;
+        for (int l = 0; l < L; ++l) dr[(size_t)i * L + l] = dr[(size_t)(i - 1) * L + l] + dh[(size_t)i * L + l];
+    }
+    std::vector<double> gd(L, 0.0), gs(L, 0.0);
+    const std::vector<double> &r = p->r, &h = p->h;
+    for (int i = 1; i < nr - 1; ++i) {
+        if (p->kind[i] == K_CAP) {
+            const int m = p->lay[i];
+            gs[m] -= (SW[i] + SE[i] - SZ[i]) / p->layers[m].mat.k_scale;
+            const double rw = 0.5 * (r[i] + r[i - 1]), re = 0.5 * (r[i] + r[i + 1]);
+            const double hb = 0.5 * (h[i] + h[i + 1]);
+            for (int l = 0; l < L; ++l) {
+                const double dri = dr[(size_t)i * L + l];
+                const double drw = 0.5 * (dri + dr[(size_t)(i - 1) * L + l]);
+                const double dre = 0.5 * (dri + dr[(size_t)(i + 1) * L + l]);
+                const double dhi = dh[(size_t)i * L + l], dhe = dh[(size_t)(i + 1) * L + l];
+                const double dhb = 0.5 * (dhi + dhe);
+                const double wW = drw / rw - dri / r[i] - dhb / hb - dhi / h[i];
+                const double wE = dre / re - dri / r[i] - dhb / hb - dhe / h[i + 1];
+                gd[l] -= SW[i] * wW + SE[i] * wE;
+            }
+        } else if (p->kind[i] == K_IFACE) {
+            const int a = p->lay[i], b = p->lay[i + 1];
+            gs[a] -= SW[i] / p->layers[a].mat.k_scale;
+            gs[b] -= SE[i] / p->layers[b].mat.k_scale;
+            for (int l = 0; l < L; ++l)
+                gd[l] -= SW[i] * dh[(size_t)(i + 1) * L + l] / h[i + 1] +
+                         SE[i] * dh[(size_t)i * L + l] / h[i];
+        }
+    }
+    *J = Jv;
+    grad[0] = gQ;
+    grad[1] = gW;
+    for (int l = 0; l < L; ++l) {
+        grad[2 + l] = gd[l];
+        grad[2 + L + l] = gs[l];
+    }
+    return CRYO_OK;
+}
+
+}  // extern "C"

@@ -99,10 +99,15 @@ static double dt_bound(const cryo_problem *pr, double Tm) {
     return 0.5 * eta * eta * best;
 }
 
-static int pick_rpl(int nr) {
+// Chunk shape of a line: rows per lane and waves per line.  Up to 8 rows per
+// lane (register budget of the FP64 solve), then more waves per line.
+static void pick_shape(int nr, int *rpl, int *wpl) {
     int r = 2;
-    while (WAVE * r < nr) r *= 2;
-    return r;
+    while (WAVE * r < nr && r < 8) r *= 2;
+    int w = 1;
+    while (WAVE * w * r < nr) w *= 2;
+    *rpl = r;
+    *wpl = w;
 }
 
 // Device copies of the per-row tables, made once on the first call that
@@ -129,15 +134,71 @@ cryo_status ensure_device(cryo_plan *p) {
     }
     if (e == hipSuccess)
         e = hipMemcpy(info, p->info.data(), sizeof(uint32_t) * np, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc((void **)&p->d_pow, sizeof(double) * p->pow_blob.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_pow, p->pow_blob.data(), sizeof(double) * p->pow_blob.size(),
+                      hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         if (p->d_gw) (void)hipFree(p->d_gw);
         if (p->d_ge) (void)hipFree(p->d_ge);
         if (info) (void)hipFree(info);
+        if (p->d_pow) (void)hipFree(p->d_pow);
         p->d_gw = p->d_ge = nullptr;
+        p->d_pow = nullptr;
         return fail(CRYO_ERR_DEVICE, std::string("device table upload: ") + hipGetErrorString(e));
     }
     p->d_info = info;
     return CRYO_OK;
+}
+
+// Lane-major per-row tables: row i = lg * rpl + reg of a line sits at
+// reg * (64 wpl) + lg, lg the lane within the line.
+static void build_row_tables(cryo_plan *p) {
+    const cryo_problem *prob = &p->prob;
+    const int nr = p->nr, L = p->L, np = p->np, rpl = p->rpl;
+    const int ZERO = law_zero(L), UNIT = law_unit(L);
+    int i;
+    p->gw.assign(np, 0.0);
+    p->ge.assign(np, 0.0);
+    p->info.assign(np, info_pack(K_PAD, 0, 0, 0, ZERO, ZERO, ZERO, UNIT));
+    const int *bk = prob->bc.kind;
+    for (i = 0; i < nr; ++i) {
+        int idx = (i % rpl) * (WAVE * p->wpl) + i / rpl;
+        uint32_t kind = p->kind[i];
+        uint32_t m = p->lay[i];
+        uint32_t lawE = (i < nr - 1) ? p->lay[i + 1] : ZERO;     // radial law of interval i+1
+        uint32_t law2 = ZERO, law3 = ZERO, lawC = ZERO, heat = 0, held = 0, side = 0;
+        double gw = 0.0, ge = 0.0;
+        if (kind == K_CAP) {
+            // eq. (13): A = -r_{i-1/2} lam_{i-1/2} / (r_i hbar_i h_i), C likewise
+            double hb = 0.5 * (p->h[i] + p->h[i + 1]);
+            gw = 0.5 * (p->r[i] + p->r[i - 1]) / (p->r[i] * hb * p->h[i]);
+            ge = 0.5 * (p->r[i] + p->r[i + 1]) / (p->r[i] * hb * p->h[i + 1]);
+            law2 = law3 = L + m;                                 // axial faces
+            lawC = 2 * L + m;
+            heat = (int)m == prob->pulse.layer ? 1u : 0u;
+        } else if (kind == K_IFACE) {
+            // eq. (18): lam*_m h_{i+1} (T_i - T_{i-1}) = lam*_{m+1} h_i (T_{i+1} - T_i)
+            gw = p->h[i + 1];
+            ge = p->h[i];
+            law2 = p->lay[i];
+            law3 = p->lay[i + 1];
+        } else if (kind == K_LO) {
+            // eq. (15)/(16): T_0 = T_1, or the held wall value
+            if (bk[0] == CRYO_HELD) { lawC = UNIT; held = 1; }
+            else { ge = 1.0; law3 = UNIT; }
+        } else {  // K_HI: eq. (15)/(17): T_{N} = T_{N-1}, or the held wall value
+            if (bk[1] == CRYO_HELD) { lawC = UNIT; held = 1; side = 1; }
+            else { gw = 1.0; law2 = UNIT; side = 1; }
+        }
+        p->gw[idx] = gw;
+        p->ge[idx] = ge;
+        p->info[idx] = info_pack(kind, heat, held, side, lawE, law2, law3, lawC);
+    }
+    p->surf_lane = (nr - 1) / rpl;
+    p->surf_reg = (nr - 1) % rpl;
+    p->surf_lane = (nr - 1) / rpl;
+    p->surf_reg = (nr - 1) % rpl;
 }
 
 }  // namespace cryo
@@ -184,8 +245,9 @@ cryo_status cryo_plan_create(const cryo_problem *prob, cryo_dtype dtype, cryo_pl
     p->nr = prob->geom.nr;
     p->nz = prob->geom.nz;
     p->L = prob->geom.n_layers;
-    p->rpl = pick_rpl(p->nr);
-    p->np = WAVE * p->rpl;
+    pick_shape(p->nr, &p->rpl, &p->wpl);
+    p->np = WAVE * p->wpl * p->rpl;
+    p->lpw = 2;
     p->eta = prob->geom.height / (p->nz - 1);
     const int nr = p->nr, L = p->L, np = p->np, rpl = p->rpl;
 
@@ -209,50 +271,51 @@ cryo_status cryo_plan_create(const cryo_problem *prob, cryo_dtype dtype, cryo_pl
     for (i = 1; i < nr - 1; ++i)
         if (p->lay[i] != p->lay[i + 1]) p->kind[i] = K_IFACE;
 
-    // laws: radial 0..L-1, axial (divided by eta^2) L..2L-1, capacity
+    // laws (see Laws): radial, axial / eta^2, capacity, zero, unit
     Laws &lw = p->laws;
     memset(&lw, 0, sizeof(lw));
     lw.L = L;
-    lw.n = 2 * L;
+    lw.cube = 1;
     for (int m = 0; m < L; ++m) {
         const cryo_material &mt = p->layers[m].mat;
-        double lk = log2(mt.k_scale * mt.k0) - mt.p * log2(mt.tref);
-        lw.p[m] = mt.p;
-        lw.lk[m] = lk;
-        lw.p[L + m] = mt.p;
-        lw.lk[L + m] = lk - log2(p->eta * p->eta);
-        lw.q[m] = mt.q;
-        lw.lrc[m] = log2(mt.rho * mt.c0 / prob->dt) - mt.q * log2(mt.tref);
+        double kr = mt.k_scale * mt.k0 * pow(mt.tref, -mt.p);
+        lw.K[m] = kr;
+        lw.K[L + m] = kr / (p->eta * p->eta);
+        lw.K[2 * L + m] = mt.rho * mt.c0 * pow(mt.tref, -mt.q) / prob->dt;
+        lw.e[m] = lw.e[L + m] = mt.p;
+        lw.e[2 * L + m] = mt.q;
+        if (mt.q != 3.0) lw.cube = 0;
+    }
+    const int nlaw = 3 * L + 2, ZERO = law_zero(L), UNIT = law_unit(L);
+    lw.K[ZERO] = 0.0;
+    lw.K[UNIT] = 1.0;
+    for (int id = 0; id < nlaw; ++id) lw.lk[id] = lw.K[id] > 0 ? log2(lw.K[id]) : -2000.0;
+
+    // FP64 power tables (see POW_*)
+    p->pow_blob.assign(pow_blob_doubles(L), 0.0);
+    double *B = p->pow_blob.data();
+    for (int row = 0; row <= 2 * L; ++row) {
+        double e = row < L ? lw.e[row] : (row < 2 * L ? lw.e[2 * L + row - L] : 0.0);
+        double *R = B + (size_t)row * POW_EROW;
+        for (int j = 0; j < POW_NM; ++j) {
+            double m0 = 1.0 + (j + 0.5) / POW_NM;
+            R[2 * j] = pow(m0, e);
+            R[2 * j + 1] = 1.0 / m0;
+        }
+    }
+    double *LR = B + (size_t)(2 * L + 1) * POW_EROW;
+    double *CK = LR + (size_t)nlaw * POW_LROW, *CA = CK + nlaw;
+    for (int id = 0; id < nlaw; ++id) {
+        double e = lw.e[id];
+        double *R = LR + (size_t)id * POW_LROW;
+        for (int x = 0; x < POW_NE; ++x) R[x] = lw.K[id] * exp2(e * (x + POW_EMIN));
+        R[POW_NE] = e;
+        R[POW_NE + 1] = exp_row(id, L);
+        CK[id] = (id >= 2 * L && id < 3 * L) ? lw.K[id] : 0.0;   // cube path: K T^3 + A
+        CA[id] = id == UNIT ? 1.0 : 0.0;
     }
 
-    // lane-major per-row tables: row i = lane * rpl + reg sits at reg * 64 + lane
-    p->gw.assign(np, 0.0);
-    p->ge.assign(np, 0.0);
-    p->info.assign(np, info_pack(K_PAD, 0, 0, 0, 0, 0));
-    for (i = 0; i < nr; ++i) {
-        int idx = (i % rpl) * WAVE + i / rpl;
-        uint32_t kind = p->kind[i];
-        uint32_t lawE = (i < nr - 1) ? p->lay[i + 1] : 0;
-        uint32_t m = p->lay[i];
-        uint32_t law2 = 0, law3 = 0, heat = 0;
-        if (kind == K_CAP) {
-            // eq. (13): A = -r_{i-1/2} lam_{i-1/2} / (r_i hbar_i h_i), C likewise
-            double hb = 0.5 * (p->h[i] + p->h[i + 1]);
-            p->gw[idx] = 0.5 * (p->r[i] + p->r[i - 1]) / (p->r[i] * hb * p->h[i]);
-            p->ge[idx] = 0.5 * (p->r[i] + p->r[i + 1]) / (p->r[i] * hb * p->h[i + 1]);
-            law2 = law3 = L + m;
-            heat = (int)m == prob->pulse.layer ? 1u : 0u;
-        } else if (kind == K_IFACE) {
-            // eq. (18): lam*_m h_{i+1} (T_i - T_{i-1}) = lam*_{m+1} h_i (T_{i+1} - T_i)
-            p->gw[idx] = p->h[i + 1];
-            p->ge[idx] = p->h[i];
-            law2 = p->lay[i];
-            law3 = p->lay[i + 1];
-        }
-        p->info[idx] = info_pack(kind, heat, lawE, law2, law3, m);
-    }
-    p->surf_lane = (nr - 1) / rpl;
-    p->surf_reg = (nr - 1) % rpl;
+    build_row_tables(p);
     p->pulse.b0 = snap(prob->pulse.t_on / prob->dt);
     p->pulse.W = snap(prob->pulse.width / prob->dt);
     p->pulse.P = snap(prob->pulse.period / prob->dt);
@@ -267,7 +330,39 @@ void cryo_plan_destroy(cryo_plan *p) {
     if (p->d_gw) (void)hipFree(p->d_gw);
     if (p->d_ge) (void)hipFree(p->d_ge);
     if (p->d_info) (void)hipFree(p->d_info);
+    if (p->d_pow) (void)hipFree(p->d_pow);
     delete p;
+}
+
+cryo_status cryo_plan_shape(const cryo_plan *p, int32_t *rows_per_lane,
+                            int32_t *waves_per_line, int32_t *lines_per_wave) {
+    if (!p) return fail(CRYO_ERR_ARG, "null plan");
+    if (rows_per_lane) *rows_per_lane = p->rpl;
+    if (waves_per_line) *waves_per_line = p->wpl;
+    if (lines_per_wave) *lines_per_wave = p->lpw;
+    return CRYO_OK;
+}
+
+cryo_status cryo_plan_set_shape(cryo_plan *p, int32_t rows_per_lane, int32_t waves_per_line,
+                                int32_t lines_per_wave) {
+    if (!p) return fail(CRYO_ERR_ARG, "null plan");
+    if (p->d_info) return fail(CRYO_ERR_ARG, "shape must be set before the plan's first run");
+    const int key = rows_per_lane * 10 + waves_per_line;
+    const bool built = key == 21 || key == 41 || key == 81 || key == 82 || key == 84 ||
+                       key == 42 || key == 44;
+    if (!built) return fail(CRYO_ERR_UNSUPPORTED, "no kernel for this chunk shape");
+    if ((int64_t)WAVE * waves_per_line * rows_per_lane < p->nr)
+        return fail(CRYO_ERR_ARG, "chunk shape too short for the radial line");
+    if (lines_per_wave < 1 || lines_per_wave > p->nz - 2)
+        return fail(CRYO_ERR_ARG, "lines per wave must be 1..nz-2");
+    p->lpw = lines_per_wave;
+    if (rows_per_lane != p->rpl || waves_per_line != p->wpl) {
+        p->rpl = rows_per_lane;
+        p->wpl = waves_per_line;
+        p->np = WAVE * p->wpl * p->rpl;
+        build_row_tables(p);
+    }
+    return CRYO_OK;
 }
 
 cryo_status cryo_grid_radii(const cryo_plan *p, double *r) {
@@ -323,7 +418,7 @@ cryo_status cryo_forward(const cryo_plan *p, void *T, int64_t k0, int64_t nsteps
     for (int64_t n = 0; n < nsteps; ++n) {
         double X = p->pulse.amplitude * source_fraction(p->pulse, k0 + n);
         double *pp = surf ? part + (size_t)(n % SURF_CHUNK) * G : nullptr;
-        st = launch_step(p, buf[n & 1], buf[(n + 1) & 1], X, pp, s);
+        st = launch_step(p, buf[n & 1], buf[(n + 1) & 1], X, pp, flag, s);
         if (st != CRYO_OK) return st;
         if (surf && ((n + 1) % SURF_CHUNK == 0 || n + 1 == nsteps)) {
             int cnt = (int)(n + 1 - done_surf);
@@ -342,7 +437,8 @@ cryo_status cryo_poll(const cryo_plan *p, const void *ws, void *stream) {
     if (hipMemcpyAsync(&flag, ws, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return fail(CRYO_ERR_DEVICE, "poll copy failed");
-    if (flag) return fail(CRYO_ERR_NONFINITE, "non-finite temperature produced");
+    if (flag) return fail(CRYO_ERR_NONFINITE, "non-finite temperature, or one outside the "
+                                              "supported range [1/16 K, 2^20 K), produced");
     return CRYO_OK;
 }
 

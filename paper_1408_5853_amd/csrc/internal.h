@@ -19,24 +19,56 @@ constexpr int SURF_CHUNK = 1024;    // steps per surface reduction round
 // Row classes of one radial line (eq. (13), eq. (18), eq. (15), padding).
 enum RowKind : uint32_t { K_PAD = 0, K_LO = 1, K_HI = 2, K_CAP = 3, K_IFACE = 4 };
 
-// Per-row packed info word:
-//   bits 0-2  kind, bit 3 heater capacity node,
-//   bits 4-8  law of the east r-face (radial law table),
-//   bits 9-13 law of slot 2, bits 14-18 law of slot 3 (combined table:
-//             0..L-1 radial laws, L..2L-1 axial laws already divided by eta^2),
-//   bits 19-23 capacity law (layer of the node).
-__host__ __device__ inline uint32_t info_pack(uint32_t kind, uint32_t heat, uint32_t lawE,
-                                              uint32_t law2, uint32_t law3, uint32_t lawC) {
-    return kind | (heat << 3) | (lawE << 4) | (law2 << 9) | (law3 << 14) | (lawC << 19);
+// Material laws.  A law id selects a multiplier K and an exponent row:
+//   ids 0..L-1    radial conductivity of layer m:  K = k_scale k0 tref^-p, e = p
+//   ids L..2L-1   axial conductivity / eta^2:      K = (that) / eta^2,     e = p
+//   ids 2L..3L-1  rho c / dt of layer m:           K = rho c0 tref^-q / dt, e = q
+//   id  3L        zero law (value 0),  id 3L+1  unit law (value 1)
+// value = K * T^e.  Exponent rows: 0..L-1 hold p_m, L..2L-1 hold q_m, 2L is 0.
+constexpr int MAX_LAWS = 3 * MAX_LAYERS + 2;
+__host__ __device__ inline int law_zero(int L) { return 3 * L; }
+__host__ __device__ inline int law_unit(int L) { return 3 * L + 1; }
+__host__ __device__ inline int exp_row(int law, int L) {
+    return law < 2 * L ? law % L : (law < 3 * L ? law - L : 2 * L);
 }
 
-// lambda = exp2(p * log2(T) + lk); rho c / dt = exp2(q * log2(T) + lrc)
+// Per-row packed info word:
+//   bits 0-2 kind, bit 3 heater capacity node, bit 4 held boundary row,
+//   bit 5 its side (0 inner, 1 outer), bits 6-11 law of the east r-face,
+//   bits 12-17 law of slot 2, bits 18-23 law of slot 3, bits 24-29 capacity law.
+// Slot 2 is the north axial face of a capacity row (eq. (11)), slot 3 is not
+// used by capacity rows (their south face is the previous line's north
+// face); an interface row (eq. (18)) evaluates its inner and outer layer laws
+// at the node in slots 2 and 3; boundary and padding rows use the zero and
+// unit laws so that one formula serves every row.
+__host__ __device__ inline uint32_t info_pack(uint32_t kind, uint32_t heat, uint32_t held,
+                                              uint32_t side, uint32_t lawE, uint32_t law2,
+                                              uint32_t law3, uint32_t lawC) {
+    return kind | (heat << 3) | (held << 4) | (side << 5) | (lawE << 6) | (law2 << 12) |
+           (law3 << 18) | (lawC << 24);
+}
+
 struct Laws {
-    double p[2 * MAX_LAYERS], lk[2 * MAX_LAYERS];
-    double q[MAX_LAYERS], lrc[MAX_LAYERS];
-    int n;          // number of entries in p/lk (2L)
     int L;
+    int cube;                       // every capacity exponent q is 3
+    double K[MAX_LAWS];             // multiplier per law id
+    double lk[MAX_LAWS];            // log2 K (-2000 for the zero law)
+    double e[MAX_LAWS];             // exponent per law id
 };
+
+// FP64 powers T^e from tables: T = 2^x m, m in [1,2); m0 = 1 + (j + 1/2)/64
+// for the top six mantissa bits j; u = m / m0 - 1 (|u| <= 1/128);
+// K T^e = [K 2^(x e)] m0^e (1 + u)^e, with (1 + u)^e = exp(e ln(1 + u)) by
+// fixed series: ln(1 + u) to degree 7, exp to degree 7 (|e ln(1+u)| <= 0.032
+// for |e| <= 4); truncation below 1e-17 relative.
+constexpr int POW_NM = 64, POW_NE = 24, POW_EMIN = -4;
+constexpr int POW_EROW = 2 * POW_NM;       // exponent row: {m0^e, 1/m0} pairs
+constexpr int POW_LROW = POW_NE + 2;       // law row: K 2^(x e) [NE], e, exponent row
+// blob: 2L+1 exponent rows, (3L+2) law rows, then cube multipliers and
+// addends [3L+2] each
+__host__ __device__ inline size_t pow_blob_doubles(int L) {
+    return (size_t)(2 * L + 1) * POW_EROW + (size_t)(3 * L + 2) * (POW_LROW + 2);
+}
 
 struct Pulse {      // in step units, snapped
     double b0, W, P;
@@ -52,7 +84,9 @@ struct cryo_plan {
     cryo_dtype dtype;
     int nr, nz, L;
     int rpl;                 // radial rows per lane (chunk length)
-    int np;                  // padded line length = 64 * rpl
+    int wpl;                 // waves per line
+    int np;                  // padded line length = 64 * wpl * rpl
+    int lpw;                 // interior lines marched by one wave per step
     double eta;
     std::vector<double> r, h;         // node radii, interval widths (h[0] unused)
     std::vector<int> lay;             // layer of interval i
@@ -61,11 +95,13 @@ struct cryo_plan {
     std::vector<double> gw, ge;
     std::vector<uint32_t> info;
     cryo::Laws laws;
+    std::vector<double> pow_blob;     // FP64 power tables (see POW_*)
     cryo::Pulse pulse;
     int surf_lane, surf_reg;          // owner of row nr-1
     // device tables (read-only, made at create time)
     void *d_gw = nullptr, *d_ge = nullptr;
     uint32_t *d_info = nullptr;
+    double *d_pow = nullptr;
     int device = 0;
 };
 
@@ -81,7 +117,7 @@ cryo_status launch_from_internal(const cryo_plan *p, const void *Ti, void *T, in
                                  hipStream_t s);
 cryo_status launch_fill(const cryo_plan *p, void *T, hipStream_t s);
 cryo_status launch_step(const cryo_plan *p, const void *Tin, void *Tout, double X,
-                        double *partial, hipStream_t s);
+                        double *partial, int *flag, hipStream_t s);
 cryo_status launch_surf_reduce(const cryo_plan *p, const double *partial, int nsteps,
                                double *out, hipStream_t s);
 int step_grid(const cryo_plan *p);

@@ -1,0 +1,111 @@
+"""The GPU discrete adjoint against the oracle adjoint (itself pinned by
+finite differences of the oracle forward), finite differences of the GPU
+forward, checkpoint invariance, the autograd boundary, and the full-size
+adjoint workload (512 x 2048, 50,000 steps) against the oracle on its
+exactly z-invariant reduction."""
+import numpy as np
+import pytest
+
+import cellgen
+import oracle
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+def _norm_err(g, ref, theta):
+    P = np.abs(theta)
+    scale = np.max(np.abs(ref * P))
+    return float(np.max(np.abs(g - ref) * P / scale))
+
+
+def _target(cell, n):
+    _, S = oracle.forward(cell, nsteps=n, surf=True)
+    rng = np.random.default_rng(0)
+    return S + rng.normal(scale=0.05, size=n) + 0.02
+
+
+@pytest.mark.parametrize("seed,nr,nz,zact", [(0, 14, 6, True), (1, 40, 9, True),
+                                              (2, 100, 5, False), (3, 300, 7, True)])
+def test_gpu_gradient_matches_oracle_adjoint(seed, nr, nz, zact):
+    import paper_1408_5853_amd as P
+    c = cellgen.tiny(seed, nr=nr, nz=nz, n_layers=3, nsteps=30, z_active=zact, dt=2e-6,
+                     amplitude=4e9, heater=2)
+    n = c["nsteps"]
+    tgt = _target(c, n)
+    say("case adjoint nr=%d nz=%d" % (nr, nz))
+    Jo, go, So = oracle.gradient(c, tgt)
+    Jg, gg, Sg = P.gradient(c, tgt, ckpt=7)
+    assert Jg == pytest.approx(Jo, rel=1e-9)
+    assert np.max(np.abs(Sg - So) / So) < 1e-10
+    e = _norm_err(gg, go, P.params_of(c))
+    say("  normalised gradient error %.3e" % e)
+    assert e < 1e-8, (gg, go)
+
+
+def test_gpu_gradient_every_chunk_shape_and_checkpoint_stride():
+    import paper_1408_5853_amd as P
+    c = cellgen.tiny(5, nr=200, nz=6, n_layers=4, nsteps=25, z_active=True, dt=2e-6,
+                     amplitude=4e9, heater=3)
+    tgt = _target(c, 25)
+    ref = None
+    for shape in [(4, 1, 1), (4, 2, 1), (8, 1, 2), (4, 4, 3)]:
+        for ck in (1, 6, 0):
+            plan = P.Plan(c)
+            plan.set_shape(*shape)
+            J, g, _ = plan.gradient(tgt, ckpt=ck)
+            if ref is None:
+                ref = (J, g)
+            assert J == pytest.approx(ref[0], rel=1e-12)
+            assert _norm_err(g, ref[1], P.params_of(c)) < 1e-11
+
+
+def test_gpu_gradient_central_differences():
+    import paper_1408_5853_amd as P
+    c = cellgen.tiny(6, nr=64, nz=6, n_layers=3, nsteps=40, z_active=True, dt=2e-6,
+                     amplitude=4e9, heater=2)
+    tgt = _target(c, 40)
+    J, g, _ = P.gradient(c, tgt)
+    th = P.params_of(c)
+    fd = np.zeros_like(g)
+    for q in range(len(th)):
+        h = 1e-4 * abs(th[q])
+        f = []
+        for k in (1, -1, 2, -2):
+            t2 = th.copy()
+            t2[q] += k * h
+            Jk, _, _ = P.gradient(P.with_params(c, t2), tgt)
+            f.append(Jk)
+        fd[q] = (8 * (f[0] - f[1]) - (f[2] - f[3])) / (12 * h)
+    assert _norm_err(g, fd, th) < 1e-6
+
+
+def test_autograd_function_returns_adjoint_gradient():
+    import torch
+
+    import paper_1408_5853_amd as P
+    c = cellgen.tiny(7, nr=50, nz=5, n_layers=3, nsteps=20, z_active=True, dt=2e-6,
+                     amplitude=4e9, heater=2)
+    tgt = _target(c, 20)
+    theta = torch.tensor(P.params_of(c), dtype=torch.float64, requires_grad=True)
+    J = P.CryoSolve.apply(theta, c, tgt, 20, 0)
+    J.backward()
+    Jr, gr, _ = P.gradient(c, tgt)
+    assert float(J) == pytest.approx(Jr, rel=1e-14)
+    assert np.allclose(theta.grad.numpy(), gr, rtol=1e-14, atol=0)
+
+
+def test_adjoint_workload_full_size_against_reduced_oracle():
+    # 512 x 2048 nodes, 6 layers, 50,000 steps; the cell is exactly
+    # z-invariant, so J and its gradient equal those of the 4-line reduction
+    import paper_1408_5853_amd as P
+    c = cellgen.config4(0)
+    n = c["nsteps"]
+    tgt = cellgen.tracking_target(c, n)
+    say("case adjoint workload 512x2048, %d steps" % n)
+    Jg, gg, _ = P.gradient(c, tgt)
+    Jo, go, _ = oracle.gradient(cellgen.with_nz(c, 4), tgt, ckpt=250)
+    e = _norm_err(gg, go, P.params_of(c))
+    say("  J gpu %.12e oracle %.12e, normalised gradient error %.3e" % (Jg, Jo, e))
+    assert Jg == pytest.approx(Jo, rel=1e-9)
+    assert e < 1e-6

@@ -135,3 +135,31 @@ def test_f32_within_1e4_kelvin(make, n):
     e, es = float(np.max(np.abs(Tg - To))), float(np.max(np.abs(Sg - So)))
     say("  max abs err field %.3e K surface %.3e K" % (e, es))
     assert e < F32_TOL_K and es < F32_TOL_K
+
+
+@pytest.mark.parametrize("shape", [(2, 1), (4, 1), (8, 1), (4, 2), (8, 2), (4, 4), (8, 4)])
+def test_every_chunk_shape_matches_oracle(shape):
+    import torch
+
+    import paper_1408_5853_amd as P
+    rpl, wpl = shape
+    nr = min(64 * rpl * wpl, 300)
+    c = cellgen.tiny(nr, nr=nr, nz=7, n_layers=4, z_active=True, dt=2e-7, amplitude=5e9)
+    rng = np.random.default_rng(3)
+    T0 = 28.0 + rng.uniform(0, 5, size=(c["nz"], c["nr"]))
+    To = oracle.forward(c, T0, nsteps=30)
+    for lpw in (1, 2, 5):
+        say("case shape %s lines/wave %d nr %d" % (shape, lpw, nr))
+        plan = P.Plan(c)
+        plan.set_shape(rpl, wpl, lpw)
+        T = plan.field_from(T0)
+        ws = plan.workspace(30)
+        plan.forward(T, 0, 30, ws=ws)
+        plan.poll(ws)
+        torch.cuda.synchronize()
+        Tg = plan.field_values(T)
+        assert rel_err(Tg, To) < F64_TOL
+        if lpw == 1:
+            ref = Tg
+        else:
+            assert np.array_equal(Tg, ref)      # the march order changes nothing
