@@ -1,13 +1,20 @@
 """Benchmark: Gcell-steps/s of the explicit-implicit stepper on one MI355X.
 
-Workload: the single-device cell, 1024 x 4096 (r, z) nodes, 8 layers, FP64,
-dt = 0.2 us, 2 ms / 20 ms pulse at 5e8 W/m^3.  A "step" is one time step of
-the whole grid (source schedule, coefficient evaluation, explicit z half,
-implicit radial line solves, boundary completion).  Inputs are seeded
-synthetic problems with the workload's shapes and value ranges; the field is
-resident in HBM before timing starts.
+Headline workload: the single-device cell, 1024 x 4096 (r, z) nodes, 8
+layers, FP64, dt = 0.2 us, 2 ms / 20 ms pulse at 5e8 W/m^3, 100,000 steps
+(one full period).  A "step" is one time step of the whole grid: pulse
+schedule, lagged coefficient evaluation, explicit z half, implicit radial
+line solves, boundary completion.  Inputs are seeded synthetic cells with
+the workload's shapes and value ranges; the field is resident in HBM before
+timing starts.
 
-Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+Extra measurements in the same JSON line (not part of `value`): the FP32
+(compensated pair) rate on the same cell, the batched design sweep (256
+uneven cells) against the same cells stepped one at a time, and the cost of
+a gradient (forward + checkpointed adjoint) relative to a forward on the
+adjoint workload (512 x 2048, 50,000 steps).
+
+Prints one JSON line.  --gpus above 1 is refused: the stepper runs on one GPU.
 """
 from __future__ import annotations
 
@@ -21,7 +28,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_CELL_STEP = {"f64": 16, "f32": 8}   # read T, write T^
+FP64_VECTOR_TFLOPS = 78.6
+BYTES_PER_CELL_STEP = 16          # read T, write T^ (FP64; an FP32 pair is also 8 B/node)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed(stream, fn):
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e-3
 
 
 def cpu_baseline(cell, seconds):
@@ -42,23 +66,85 @@ def cpu_baseline(cell, seconds):
             break
         n *= 4
     cells = sample["nr"] * sample["nz"] * n
-    return {"value": cells / dt / 1e9, "unit": "Gcell-steps/s", "cores": cores,
+    return {"value": round(cells / dt / 1e9, 5), "unit": "Gcell-steps/s", "cores": cores,
             "kind": "oracle",
-            "sample": "%d x %d nodes (full radial grid, 16 interior lines), %d steps, "
-                      "%.1f s on %d threads" % (sample["nr"], sample["nz"], n, dt, cores)}
+            "sample": "%d x %d nodes (the workload's full radial grid, 16 interior lines), "
+                      "%d steps, %.1f s on %d threads" % (sample["nr"], sample["nz"], n, dt, cores)}
+
+
+def rate(plan_cls, cell, dtype, steps, warmup, stream):
+    plan = plan_cls(cell, dtype)
+    T = plan.init()
+    ws = plan.workspace(max(steps, warmup))
+    if warmup:
+        plan.forward(T, 0, warmup, ws=ws)
+    secs = timed(stream, lambda: plan.forward(T, warmup, steps, ws=ws))
+    plan.poll(ws)
+    return secs, plan
+
+
+def batch_extra(P, steps, stream):
+    import cellgen
+    cells = cellgen.config3(0)
+    total = sum(c["nr"] * c["nz"] for c in cells)
+    b = P.Batch(cells, "f32")
+    T = b.init()
+    ws = b.workspace()
+    b.forward(T, 0, 64, ws)                                   # capture + warm
+    secs_b = timed(stream, lambda: b.forward(T, 64, steps, ws))
+    b.poll(ws)
+    # the same cells one at a time (each with its own launches)
+    plans = [P.Plan(c, "f32") for c in cells]
+    fields = [p.init() for p in plans]
+    wss = [p.workspace(steps) for p in plans]
+    for p, f, w in zip(plans, fields, wss):
+        p.forward(f, 0, 4, ws=w)
+
+    def one_by_one():
+        for p, f, w in zip(plans, fields, wss):
+            p.forward(f, 4, steps, ws=w)
+
+    secs_1 = timed(stream, one_by_one)
+    return {"workload": "design sweep: 256 cells, nr 128-512, nz 256-2048, 4-8 layers, FP32 pairs",
+            "steps": steps, "cells": total,
+            "batched_gcell_steps_s": round(total * steps / secs_b / 1e9, 2),
+            "one_at_a_time_gcell_steps_s": round(total * steps / secs_1 / 1e9, 2),
+            "speedup": round(secs_1 / secs_b, 2)}
+
+
+def gradient_extra(P, steps, stream):
+    import cellgen
+    import numpy as np
+    c = cellgen.config4(0)
+    tgt = cellgen.tracking_target(c, steps)
+    plan = P.Plan(c, "f64")
+    sh = P._gradient_shape(c)
+    plan.set_shape(*sh)
+    T = plan.init()
+    ws = plan.workspace(steps)
+    plan.forward(T, 0, 10, ws=ws)
+    T = plan.init()
+    t_fwd = timed(stream, lambda: plan.forward(T, 0, steps, ws=ws))
+    t0 = time.perf_counter()
+    J, g, _ = plan.gradient(tgt, nsteps=steps)
+    t_grad = time.perf_counter() - t0
+    return {"workload": "adjoint: 512x2048, 6 layers, FP64, checkpoint stride ceil(sqrt(N))",
+            "steps": steps, "forward_s": round(t_fwd, 3), "gradient_s": round(t_grad, 3),
+            "gradient_over_forward": round(t_grad / t_fwd, 2), "J": J,
+            "grad_finite": bool(np.all(np.isfinite(g)))}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20_000)
-    ap.add_argument("--warmup", type=int, default=500)
-    ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--steps", type=int, default=100_000)
+    ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on exactly one GPU; --gpus %d is not supported"
+        print("bench.py: the stepper runs on exactly one GPU; --gpus %d is not supported"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
 
@@ -67,28 +153,16 @@ def main():
     import cellgen
     import paper_1408_5853_amd as P
 
-    cell = cellgen.config2(0)
-    plan = P.Plan(cell, args.dtype)
-    T = plan.init()
-    ws = plan.workspace(max(args.steps, args.warmup))
     stream = torch.cuda.current_stream()
-    if args.warmup:
-        plan.forward(T, 0, args.warmup, ws=ws)
-    plan.poll(ws)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    plan.forward(T, args.warmup, args.steps, ws=ws)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
-    plan.poll(ws)
+    cell = cellgen.config2(0)
     cells = cell["nr"] * cell["nz"]
-    value = cells * args.steps / (ms * 1e-3) / 1e9
-    per_step_ms = ms / args.steps
-    bytes_per_launch = BYTES_PER_CELL_STEP[args.dtype] * cells
-    achieved = bytes_per_launch / (per_step_ms * 1e-3) / 1e9
+    log("bench: config 1024x4096 FP64, %d steps after %d warmup" % (args.steps, args.warmup))
+    secs, plan = rate(P.Plan, cell, "f64", args.steps, args.warmup, stream)
+    value = cells * args.steps / secs / 1e9
+    ms_step = 1e3 * secs / args.steps
+    # one k_step launch per step: the timed region / steps is its average
+    # duration plus the launch gap
+    achieved = BYTES_PER_CELL_STEP * cells / (secs / args.steps) / 1e9
     out = {
         "metric": "Gcell-steps/s & % HBM roofline (fwd, batched, adjoint) vs CPU oracle, 1 GPU",
         "value": round(value, 3),
@@ -96,22 +170,32 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(per_step_ms, 6),
+        "ms_per_step": round(ms_step, 6),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.dtype,
+        "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "single-device cell 1024x4096 (r,z) nodes, 8 layers, "
-                               "dt=2e-7 s, 2 ms/20 ms pulse at 5e8 W/m^3",
-                   "nr": cell["nr"], "nz": cell["nz"], "parallelism": "single-gpu"},
+        "config": {"workload": "single-device cell 1024x4096 (r,z) nodes, 8 layers, dt=2e-7 s, "
+                               "2 ms/20 ms pulse at 5e8 W/m^3",
+                   "nr": cell["nr"], "nz": cell["nz"], "kernel_shape": list(plan.shape())},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None,
-                     "kernel": "k_step (one launch per step)",
-                     "bytes_per_launch": bytes_per_launch},
+                     "traffic": None, "kernel": "k_step",
+                     "bytes_per_launch": BYTES_PER_CELL_STEP * cells,
+                     "note": "algorithmic 16 B/cell-step; the 64 MiB ping-pong state is "
+                             "L2/MALL resident and the kernel is FP64-VALU bound"},
     }
+    if not args.no_extra:
+        log("bench: FP32 pair rate")
+        s32, _ = rate(P.Plan, cell, "f32", 20_000, 500, stream)
+        out["extra"] = {"f32_pair_gcell_steps_s": round(cells * 20_000 / s32 / 1e9, 3)}
+        log("bench: batched sweep")
+        out["extra"]["batch"] = batch_extra(P, 2000, stream)
+        log("bench: gradient")
+        out["extra"]["gradient"] = gradient_extra(P, 50_000, stream)
     if not args.no_cpu:
+        log("bench: CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(cell, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

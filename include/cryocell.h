@@ -185,6 +185,18 @@ cryo_status cryo_forward(const cryo_plan *plan, void *T, int64_t k0,
  * CRYO_OK.  Synchronises `stream`. */
 cryo_status cryo_poll(const cryo_plan *plan, const void *ws, void *stream);
 
+/* ---- Autotuning ---------------------------------------------------------
+ * Time every built kernel shape (rows per lane x waves per line covering nr)
+ * and lines per wave 1, 2, 4, 8 on `prob` for `steps` steps and return the
+ * fastest as shape[3] (for cryo_plan_set_shape or cryo_batch_create), with
+ * its time per step (or -1 when taken from the cache).  The tuner allocates
+ * and frees its own trial field and workspaces.  `cache_path` (nullable)
+ * names a text file of earlier results keyed by dtype, nr, nz and layer
+ * count; new results are appended.  Synchronous on `stream`. */
+cryo_status cryo_autotune(const cryo_problem *prob, cryo_dtype dtype, int32_t steps,
+                          const char *cache_path, void *stream, int32_t *shape,
+                          double *us_per_step);
+
 /* ---- Gradient by the discrete adjoint -----------------------------------
  * J = sum_{n=1..N} (S_n - target_n)^2 with S_n the surface mean after step
  * n, and its gradient with respect to

@@ -15,6 +15,7 @@ from . import _abi
 from ._abi import CryoError, check, lib
 
 __all__ = ["Plan", "Batch", "CryoError", "CryoSolve", "gradient", "with_params", "params_of",
+           "autotune", "tune_batch",
            "validate", "stability_dt_max", "version"]
 
 
@@ -265,6 +266,35 @@ class Batch:
     def poll(self, ws, stream=None):
         bad = C.c_int32(-1)
         check(lib().cryo_batch_poll(self._h, _ptr(ws), _stream(stream), C.byref(bad)))
+
+
+def autotune(cell, dtype="f64", steps=20, cache=None, stream=None):
+    """Fastest (rows per lane, waves per line, lines per wave) for `cell`,
+    timed on the GPU; returns (shape, us per step or -1 if cached)."""
+    ps = _abi.ProblemStruct(cell)
+    sh = (C.c_int32 * 3)()
+    us = C.c_double()
+    check(lib().cryo_autotune(ps.ref(), _abi.F64 if dtype == "f64" else _abi.F32, int(steps),
+                              cache.encode() if cache else None, _stream(stream), sh,
+                              C.byref(us)))
+    return tuple(sh), us.value
+
+
+def tune_batch(cells, dtype="f32", steps=20, cache=None):
+    """Per-instance shapes for a Batch: instances are bucketed by radial
+    size and each bucket is tuned on its largest member."""
+    buckets = {}
+    for i, c in enumerate(cells):
+        key = int(c["nr"])
+        buckets.setdefault(key, []).append(i)
+    shapes = [None] * len(cells)
+    for key, idx in buckets.items():
+        rep = max(idx, key=lambda i: cells[i]["nz"])
+        sh, _ = autotune(cells[rep], dtype, steps, cache)
+        for i in idx:
+            lpw = min(sh[2], max(1, cells[i]["nz"] - 2))
+            shapes[i] = (sh[0], sh[1], lpw)
+    return shapes
 
 
 def params_of(cell):

@@ -24,7 +24,7 @@ SYMBOLS = [
     "cryo_plan_shape", "cryo_plan_set_shape",
     "cryo_batch_create", "cryo_batch_destroy", "cryo_batch_offsets", "cryo_batch_shape",
     "cryo_batch_workspace_bytes", "cryo_batch_init", "cryo_batch_forward", "cryo_batch_poll",
-    "cryo_gradient_workspace_bytes", "cryo_gradient",
+    "cryo_gradient_workspace_bytes", "cryo_gradient", "cryo_autotune",
 ]
 
 
@@ -73,6 +73,10 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError("libcryocell.so is not built; run paper_1408_5853_amd/build.py "
                               "(or __graft_entry__.build())")
+        # torch ships its own HIP runtime (same soname as the system one);
+        # load it first so that the process holds exactly one runtime and
+        # the tensors torch allocates live on the device this library sees
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         vp, dp, i64 = C.c_void_p, C.POINTER(C.c_double), C.c_int64
         pp = C.POINTER(Problem)
@@ -101,6 +105,7 @@ def lib():
         L.cryo_batch_init.argtypes = [vp, vp, vp]
         L.cryo_batch_forward.argtypes = [vp, vp, i64, i64, vp, C.c_size_t, vp]
         L.cryo_batch_poll.argtypes = [vp, vp, vp, i32p]
+        L.cryo_autotune.argtypes = [pp, C.c_int, C.c_int32, C.c_char_p, vp, i32p, dp]
         L.cryo_gradient_workspace_bytes.argtypes = [vp, i64, i64, C.POINTER(C.c_size_t)]
         L.cryo_gradient.argtypes = [vp, vp, i64, dp, i64, vp, C.c_size_t, dp, dp, dp, vp]
         for name in SYMBOLS:

@@ -247,7 +247,7 @@ cryo_status cryo_plan_create(const cryo_problem *prob, cryo_dtype dtype, cryo_pl
     p->L = prob->geom.n_layers;
     pick_shape(p->nr, &p->rpl, &p->wpl);
     p->np = WAVE * p->wpl * p->rpl;
-    p->lpw = 2;
+    p->lpw = 4;
     p->eta = prob->geom.height / (p->nz - 1);
     const int nr = p->nr, L = p->L, np = p->np, rpl = p->rpl;
 
