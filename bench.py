@@ -142,6 +142,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after the timed region, copy this many MiB device to device once "
+                         "(a kernel of known traffic that calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: the stepper runs on exactly one GPU; --gpus %d is not supported"
@@ -186,6 +189,14 @@ def main():
                      "note": "algorithmic 16 B/cell-step; the 64 MiB ping-pong state is "
                              "L2/MALL resident and the kernel is FP64-VALU bound"},
     }
+    if args.copy_mib:
+        n = args.copy_mib * (1 << 20) // 8
+        src = torch.rand(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": 8 * n, "written": 8 * n}
     if not args.no_extra:
         log("bench: FP32 pair rate")
         s32, _ = rate(P.Plan, cell, "f32", 20_000, 500, stream)

@@ -126,7 +126,9 @@ const char *cryo_last_error(void);
 const char *cryo_version(void);
 
 /* Host-only check of a descriptor: geometry, layer counts, laws, pulse and
- * boundary kinds.  Does not test stability.  No device calls. */
+ * boundary kinds; T_init and held wall values must lie in the temperature
+ * range of the FP64 law tables, [1/16 K, 2^20 K).  Does not test stability.
+ * No device calls. */
 cryo_status cryo_validate(const cryo_problem *prob);
 
 /* Largest dt allowed by the explicit z half, eq. (21):

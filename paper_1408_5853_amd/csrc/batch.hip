@@ -58,7 +58,6 @@ void step_desc_fill(const cryo_plan *p, void *out, void *buf0, void *buf1, int *
 cryo_status launch_step_batch(cryo_dtype dt, int rpl, int wpl, const void *desc,
                               const int2 *map, int nwg, size_t lds, int64_t n,
                               const int64_t *k0, hipStream_t s);
-size_t step_lds(const cryo_plan *p);
 cryo_status launch_set_i64(int64_t *ptr, int64_t v, hipStream_t s);
 cryo_status launch_add_i64(int64_t *ptr, int64_t v, hipStream_t s);
 

@@ -41,23 +41,27 @@ struct LawLds;
 
 template <>
 struct LawLds<double> {
-    const double *erow;     // exponent rows: {m0^e, 1/m0}[NM]
-    const double *lrow;     // law rows: K 2^(x e) [NE], e, exponent row
+    const double *erow;     // exponent rows: {m0^e, 2/m0}[NM]
+    const double *lrow;     // law rows: K 2^(x e) [NE], e, exponent row offset
     const double *ck, *ca;  // cube path: K T^3 + A
-    // T off the table (outside [2^POW_EMIN, 2^(POW_EMIN+POW_NE)) K, or not
-    // finite) is clamped and flagged; the call then reports an error.
-    __device__ inline double law(int id, double x, int &bad) const {
-        const long long b = __double_as_longlong(x);
-        const int xe = (int)((b >> 52) & 0x7ff) - 1023 - POW_EMIN;
-        const int xc = min(max(xe, 0), POW_NE - 1);
-        bad |= xc != xe;
-        const int jm = (int)((b >> 46) & (POW_NM - 1));
-        const double m = __longlong_as_double((b & 0x000FFFFFFFFFFFFFLL) | 0x3FF0000000000000LL);
+    // T on the table range [2^POW_EMIN, 2^(POW_EMIN+POW_NE)) K
+    static __device__ inline bool in_range(double x) {
+        return x >= POW_TLO && x < POW_THI;
+    }
+    // K[id] T^e[id]; T off the table range (or not finite) is clamped to its
+    // edge binade, so callers check the range themselves (in_range)
+    __device__ inline double lawc(int id, double x) const {
+        const double mh = __builtin_amdgcn_frexp_mant(x);          // x = mh 2^xe, mh in [1/2, 1)
+        const int xe = __builtin_amdgcn_frexp_exp(x);
+        const int xc = min(max(xe - 1 - POW_EMIN, 0), POW_NE - 1);
+        const int hi = (int)(__double_as_longlong(x) >> 32);
+        const int jm = (hi >> (20 - POW_MBITS)) & (POW_NM - 1);
         const double *Lr = lrow + id * POW_LROW;
-        const double2 ee = *(const double2 *)(Lr + POW_NE);     // e, exponent row
-        const double2 mm = *(const double2 *)(erow + (int)ee.y * POW_EROW + 2 * jm);
-        const double u = fma(m, mm.y, -1.0);
-        // ln(1 + u), |u| <= 1/128
+        const double2 ee = *(const double2 *)(Lr + POW_NE);     // e, exponent row offset
+        const int eoff = (int)__double_as_longlong(ee.y);
+        const double2 mm = *(const double2 *)(erow + eoff + 2 * jm);
+        const double u = fma(mh, mm.y, -1.0);                   // m / m0 - 1
+        // ln(1 + u), |u| <= 2^-(POW_MBITS+1)
         double l = fma(u, 1.0 / 7, -1.0 / 6);
         l = fma(l, u, 1.0 / 5);
         l = fma(l, u, -1.0 / 4);
@@ -65,7 +69,7 @@ struct LawLds<double> {
         l = fma(l, u, -1.0 / 2);
         l = fma(l, u, 1.0);
         const double v = ee.x * (l * u);
-        // exp(v), |v| <= 1/32
+        // exp(v)
         double s = fma(v, 1.0 / 5040, 1.0 / 720);
         s = fma(s, v, 1.0 / 120);
         s = fma(s, v, 1.0 / 24);
@@ -75,6 +79,11 @@ struct LawLds<double> {
         s = fma(s, v, 1.0);
         return Lr[xc] * mm.x * s;
     }
+    // as lawc, and flags an argument off the table range
+    __device__ inline double law(int id, double x, int &bad) const {
+        bad |= !in_range(x);
+        return lawc(id, x);
+    }
     __device__ inline double cube(int id, double x) const {
         return fma(ck[id], x * x * x, ca[id]);
     }
@@ -83,9 +92,11 @@ struct LawLds<double> {
 template <>
 struct LawLds<float> {
     const float *lk, *ex, *ck, *ca;
-    __device__ inline float law(int id, float x, int &) const {
+    static __device__ inline bool in_range(float) { return true; }
+    __device__ inline float lawc(int id, float x) const {
         return exp2f(fmaf(ex[id], log2f(x), lk[id]));
     }
+    __device__ inline float law(int id, float x, int &) const { return lawc(id, x); }
     __device__ inline float cube(int id, float x) const { return fmaf(ck[id], x * x * x, ca[id]); }
 };
 
@@ -94,7 +105,7 @@ struct StepArgs {
     const R *Tin;             // single plan: this step's input and output
     R *Tout;
     R *buf[2];                // batch: ping-pong buffers (step n reads buf[n & 1])
-    const R *gw, *ge;
+    const R *gw, *ge;         // per-row tables: west/east geometry factors
     const uint32_t *info;
     const double *pow_blob;   // FP64 power tables (device)
     Laws laws;
@@ -325,10 +336,21 @@ __host__ __device__ inline size_t law_lds_bytes(int L) {
     else
         return sizeof(float) * 4 * nlaw;
 }
+// The stepping kernel also keeps a two-slot ring of line buffers per wave
+// (the lines after the current one, loaded straight into LDS): a slot is
+// RPL rows x planes x 64 lanes.
 template <typename R>
-__host__ __device__ inline size_t step_lds_bytes(int L, int np) {
+__host__ __device__ inline size_t ring_lds_offset(int L, int np) {
     size_t b = (law_lds_bytes<R>(L) + 15) & ~(size_t)15;
-    return b + (2 * sizeof(R) + sizeof(uint32_t)) * (size_t)np;
+    return (b + (2 * sizeof(R) + sizeof(uint32_t)) * (size_t)np + 15) & ~(size_t)15;
+}
+template <typename R>
+__host__ __device__ inline size_t ring_slot_elems(int rpl) {
+    return (size_t)rpl * (Pair<R>::on ? 2 : 1) * WAVE;
+}
+template <typename R>
+__host__ __device__ inline size_t step_lds_bytes(int L, int np, int rpl = 0) {
+    return ring_lds_offset<R>(L, np) + 2 * (size_t)STEP_WAVES * ring_slot_elems<R>(rpl) * sizeof(R);
 }
 
 // Stage the law tables in LDS (dynamic shared memory); all threads call it.

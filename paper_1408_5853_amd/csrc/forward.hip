@@ -34,6 +34,7 @@ template <typename R, int RPL, int G>
 __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *__restrict__ Tin,
                                  R *__restrict__ Tout, const R X, double *partial) {
     constexpr bool PAIR = Pair<R>::on;
+    constexpr int NPL = PAIR ? 2 : 1;                 // planes per line (pairs: hi, lo)
     constexpr int NL = WAVE * G;                      // lanes per line
     constexpr int NG = STEP_WAVES / G;                // lines per workgroup
     extern __shared__ __align__(16) unsigned char smem[];
@@ -50,50 +51,94 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
     }
     const LawLds<R> law = stage_laws<R>(a, smem);       // ends with a barrier
     const int t = threadIdx.x;
-    const int lane = t & (WAVE - 1), wv = t / WAVE;
+    // the wave index is uniform: line indices and bases live in scalar registers
+    const int lane = t & (WAVE - 1), wv = __builtin_amdgcn_readfirstlane(t / WAVE);
     const int grp = wv / G, wig = wv % G, lg = wig * WAVE + lane;
     const int L = a.laws.L;
     const int j0 = 1 + (blk * NG + grp) * a.lpw;
     const int j1 = min(j0 + a.lpw, a.nz - 1);             // exclusive
-    const size_t LS = (size_t)a.np * (PAIR ? 2 : 1);      // line stride
+    const size_t LS = (size_t)a.np * NPL;                 // line stride
+    const size_t LO = PAIR ? (size_t)a.np : 0;            // offset of the low plane
     R *xch = xchg[grp];
     // neighbour rows across the chunk ends (the row itself at the line ends)
     const int qW = lg > 0 ? (RPL - 1) * NL + lg - 1 : 0;
     const int qE = lg < NL - 1 ? lg + 1 : (RPL - 1) * NL + lg;
     double sv = 0.0;
     int bad = 0;
-    R FS[RPL];
+    // Line ring: two LDS slots per wave hold the wave's part of the next line
+    // and of the line after it, loaded straight from memory into LDS (no
+    // registers in flight) one iteration ahead.  Slot layout: element
+    // (row r, plane p, lane) at (r NPL + p) WAVE + lane.  Groups past the last
+    // line march on clamped line indices (real lines, results discarded).
+    constexpr int SLOT = RPL * NPL * WAVE;
+    constexpr int EPL = 16 / (int)sizeof(R);              // elements per lane per load
+    constexpr int LPS = WAVE / EPL;                       // lanes per row-plane
+    R *ring = (R *)(smem + ring_lds_offset<R>(L, a.np)) + (size_t)wv * 2 * SLOT;
+    auto prefetch = [&](int slot, size_t lbase) {
+        R *dst = ring + slot * SLOT;
+        const int sub = lane / LPS, e0 = EPL * (lane % LPS);
+#pragma unroll
+        for (int i = 0; i < RPL * NPL / EPL; ++i) {
+            const int rp = i * EPL + sub;                 // row-plane of this lane
+            const R *src = Tin + lbase + (size_t)(rp % NPL) * LO + (size_t)(rp / NPL) * NL +
+                           wig * WAVE + e0;
+            __builtin_amdgcn_global_load_lds((const void *)src,
+                                             (__attribute__((address_space(3))) void *)(dst + i * EPL * WAVE),
+                                             16, 0, 0);
+        }
+    };
+    R FS[RPL], Tc[RPL], Lc[RPL];
+    R TwF, TeL, LwF = 0, LeL = 0;
     {
-        // south-face flux of the block's first line (capacity rows); groups
-        // without lines work on line 1 and store nothing
-        const size_t bc = (size_t)min(j0, a.nz - 2) * LS;
+        const int jb = min(j0, a.nz - 2);
+        const size_t bc = (size_t)jb * LS;
+        prefetch(1, bc + LS);
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
             const int q = r * NL + lg;
-            const R T = Tin[bc + q], Tl = PAIR ? Tin[bc + a.np + q] : (R)0;
-            const R Tp = Tin[bc - LS + q], Tpl = PAIR ? Tin[bc - LS + a.np + q] : (R)0;
+            Tc[r] = Tin[bc + q];
+            Lc[r] = PAIR ? Tin[bc + LO + q] : (R)0;
+        }
+        TwF = Tin[bc + qW];
+        TeL = Tin[bc + qE];
+        if constexpr (PAIR) {
+            LwF = Tin[bc + LO + qW];
+            LeL = Tin[bc + LO + qE];
+        }
+        // south-face flux of the block's first line (capacity rows)
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int q = r * NL + lg;
+            const R Tp = Tin[bc - LS + q], Tpl = PAIR ? Tin[bc - LS + LO + q] : (R)0;
             const uint32_t inf_r = sinf[q];
             const bool cap = (inf_r & 7) == K_CAP;
             const int l2 = (inf_r >> 12) & 63;
-            const R lamS = law.law(cap ? l2 : law_zero(L), (R)0.5 * (T + Tp), bad);
-            FS[r] = lamS * dif<R>(T, Tl, Tp, Tpl);
+            const R lamS = law.law(cap ? l2 : law_zero(L), (R)0.5 * (Tc[r] + Tp), bad);
+            FS[r] = lamS * dif<R>(Tc[r], Lc[r], Tp, Tpl);
         }
+        // the next line's slot must have landed before the first row reads it
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     }
     for (int it = 0; it < a.lpw; ++it) {
         const int jr = j0 + it;
         const bool active = jr < j1;
         const int j = min(jr, a.nz - 2);
         const size_t base = (size_t)j * LS;
-        R Tc[RPL], Lc[RPL];
-#pragma unroll
-        for (int r = 0; r < RPL; ++r) {
-            const int q = r * NL + lg;
-            Tc[r] = Tin[base + q];
-            Lc[r] = PAIR ? Tin[base + a.np + q] : (R)0;
+        const R *sn = ring + ((it + 1) & 1) * SLOT;      // line j+1
+        // the other slot (line j, already read into registers) takes line j+2;
+        // its reads must have completed before the load overwrites it
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        prefetch(it & 1, (size_t)min(j + 2, a.nz - 1) * LS);
+        R TwP, TeP, LwP = 0, LeP = 0;                      // next line's chunk-end neighbours
+        {
+            const size_t bn = (size_t)min(j + 1, a.nz - 2) * LS;
+            TwP = Tin[bn + qW];
+            TeP = Tin[bn + qE];
+            if constexpr (PAIR) {
+                LwP = Tin[bn + LO + qW];
+                LeP = Tin[bn + LO + qE];
+            }
         }
-        const R TwF = Tin[base + qW], TeL = Tin[base + qE];
-        const R LwF = PAIR ? Tin[base + a.np + qW] : (R)0;
-        const R LeL = PAIR ? Tin[base + a.np + qE] : (R)0;
         // west face of the chunk's first row: east face of the previous row
         R lamW = law.law((sinf[qW] >> 6) & 63, (R)0.5 * (TwF + Tc[0]), bad);
         R a0 = 0, b0 = 1, c0 = 0, d0 = 0;
@@ -105,30 +150,32 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
             const uint32_t kind = inf_r & 7;
             const bool cap = kind == K_CAP;
             const R T = Tc[r], Tl = Lc[r];
-            const R Tnr = Tin[base + LS + q];
-            const R Lnr = PAIR ? Tin[base + LS + a.np + q] : (R)0;
+            const R Tnr = sn[r * NPL * WAVE + lane];
+            const R Lnr = PAIR ? sn[(r * NPL + 1) * WAVE + lane] : (R)0;
             const R Tw = (r > 0) ? Tc[r - 1] : TwF;
             const R Te = (r < RPL - 1) ? Tc[r + 1] : TeL;
             const R Lw = (r > 0) ? Lc[r - 1] : LwF;
             const R Le = (r < RPL - 1) ? Lc[r + 1] : LeL;
             const int le = (inf_r >> 6) & 63, l2 = (inf_r >> 12) & 63;
             const int l3 = (inf_r >> 18) & 63, lc = (inf_r >> 24) & 63;
-            const R lamE = law.law(le, (R)0.5 * (T + Te), bad);
+            // every face mean lies between two nodes: one range check per node
+            if constexpr (!PAIR) bad |= !LawLds<R>::in_range(T);
+            const R lamE = law.lawc(le, (R)0.5 * (T + Te));
             // slot 2: north axial face (capacity) or inner-layer law at the node
-            const R lam2 = law.law(l2, cap ? (R)0.5 * (T + Tnr) : T, bad);
+            const R lam2 = law.lawc(l2, cap ? (R)0.5 * (T + Tnr) : T);
             // slot 3: outer-layer law at an interface node; unit or zero otherwise
             R lam3 = l3 == law_unit(L) ? (R)1 : (R)0;
             if (__any(kind == K_IFACE)) {
-                const R v = law.law(l3, T, bad);
+                const R v = law.lawc(l3, T);
                 lam3 = kind == K_IFACE ? v : lam3;
             }
-            const R rc = a.laws.cube ? law.cube(lc, T) : law.law(lc, T, bad);
+            const R rc = a.laws.cube ? law.cube(lc, T) : law.lawc(lc, T);
             const R fw = sgw[q] * (cap ? lamW : lam2);
             const R fe = sge[q] * (cap ? lamE : lam3);
             const R FN = lam2 * dif<R>(Tnr, Lnr, T, Tl);
             R dd = fw * dif<R>(Tw, Lw, T, Tl) + fe * dif<R>(Te, Le, T, Tl);
             dd += cap ? FN - FS[r] : (R)0;
-            dd += ((inf_r >> 3) & 1) ? X : (R)0;
+            dd += (R)((inf_r >> 3) & 1) * X;                // heater capacity rows
             if ((inf_r >> 4) & 1) dd = dif<R>(a.val[(inf_r >> 5) & 1], (R)0, T, Tl);
             FS[r] = FN;
             lamW = lamE;
@@ -147,49 +194,62 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
         }
         R X[RPL];
         solve_tail<R, RPL, G>(a0, b0, c0, d0, al, ga, de, X, lane, wig, xch);
-        if (!active) continue;
-        // new state: T + dT (pairs: error-free sum, then renormalise)
-        R Hn[RPL], Lnw[RPL];
-#pragma unroll
-        for (int r = 0; r < RPL; ++r) {
-            if constexpr (PAIR) {
-                const R x = X[r], h = Tc[r];
-                const R s = h + x;
-                const R bp = s - h;
-                const R err = (h - (s - bp)) + (x - bp);
-                const R lo = Lc[r] + err;
-                const R h2 = s + lo;
-                Hn[r] = h2;
-                Lnw[r] = lo - (h2 - s);
-            } else {
-                Hn[r] = Tc[r] + X[r];
-                Lnw[r] = (R)0;
-            }
-            Tout[base + r * NL + lg] = Hn[r];
-            if constexpr (PAIR) Tout[base + a.np + r * NL + lg] = Lnw[r];
-        }
-        // z-boundary lines: copied (insulated) or held, after the solve
-#pragma unroll
-        for (int side = 0; side < 2; ++side) {
-            const bool mine = side == 0 ? j == 1 : j == a.nz - 2;
-            if (!mine) continue;
-            const bool held = a.held[2 + side];
-            R *o = Tout + (side == 0 ? (size_t)0 : (size_t)(a.nz - 1) * LS);
+        // the line after next (slot) and the next neighbours have landed
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        if (active) {
+            // new state: T + dT (pairs: error-free sum, then renormalise)
+            R Hn[RPL], Lnw[RPL];
 #pragma unroll
             for (int r = 0; r < RPL; ++r) {
-                o[r * NL + lg] = held ? a.val[2 + side] : Hn[r];
-                if constexpr (PAIR) o[a.np + r * NL + lg] = held ? (R)0 : Lnw[r];
+                if constexpr (PAIR) {
+                    const R x = X[r], h = Tc[r];
+                    const R s = h + x;
+                    const R bp = s - h;
+                    const R err = (h - (s - bp)) + (x - bp);
+                    const R lo = Lc[r] + err;
+                    const R h2 = s + lo;
+                    Hn[r] = h2;
+                    Lnw[r] = lo - (h2 - s);
+                } else {
+                    Hn[r] = Tc[r] + X[r];
+                    Lnw[r] = (R)0;
+                }
+                Tout[base + r * NL + lg] = Hn[r];
+                if constexpr (PAIR) Tout[base + LO + r * NL + lg] = Lnw[r];
+            }
+            // z-boundary lines: copied (insulated) or held, after the solve
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const bool mine = side == 0 ? j == 1 : j == a.nz - 2;
+                if (!mine) continue;
+                const bool held = a.held[2 + side];
+                R *o = Tout + (side == 0 ? (size_t)0 : (size_t)(a.nz - 1) * LS);
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) {
+                    o[r * NL + lg] = held ? a.val[2 + side] : Hn[r];
+                    if constexpr (PAIR) o[LO + r * NL + lg] = held ? (R)0 : Lnw[r];
+                }
+            }
+            if (partial && lg == a.surf_lane) {
+                double v = (double)Hn[0] + (double)Lnw[0];
+#pragma unroll
+                for (int r = 1; r < RPL; ++r)
+                    if (r == a.surf_reg) v = (double)Hn[r] + (double)Lnw[r];
+                sv += a.wz_mid * v;
+                if (j == 1) sv += a.wz_end * (a.held[2] ? (double)a.val[2] : v);
+                if (j == a.nz - 2) sv += a.wz_end * (a.held[3] ? (double)a.val[3] : v);
             }
         }
-        if (partial && lg == a.surf_lane) {
-            double v = (double)Hn[0] + (double)Lnw[0];
+        // next line: registers from its slot
 #pragma unroll
-            for (int r = 1; r < RPL; ++r)
-                if (r == a.surf_reg) v = (double)Hn[r] + (double)Lnw[r];
-            sv += a.wz_mid * v;
-            if (j == 1) sv += a.wz_end * (a.held[2] ? (double)a.val[2] : v);
-            if (j == a.nz - 2) sv += a.wz_end * (a.held[3] ? (double)a.val[3] : v);
+        for (int r = 0; r < RPL; ++r) {
+            Tc[r] = sn[r * NPL * WAVE + lane];
+            Lc[r] = PAIR ? sn[(r * NPL + 1) * WAVE + lane] : (R)0;
         }
+        TwF = TwP;
+        TeL = TeP;
+        LwF = LwP;
+        LeL = LeP;
     }
     if (__any(bad)) {
         if (lane == 0) atomicOr(a.flag, 2);
@@ -356,8 +416,8 @@ static StepArgs<R> step_args(const cryo_plan *p, const void *Tin, void *Tout, do
     a.flag = flag;
     a.Tin = (const R *)Tin;
     a.Tout = (R *)Tout;
-    a.gw = (const R *)p->d_gw;
-    a.ge = (const R *)p->d_ge;
+    a.gw = (const R *)p->d_rows;
+    a.ge = a.gw + p->np;
     a.info = p->d_info;
     a.pow_blob = p->d_pow;
     a.laws = p->laws;
@@ -385,7 +445,7 @@ static cryo_status step_t(const cryo_plan *p, const void *Tin, void *Tout, doubl
                           double *partial, int *flag, hipStream_t s) {
     StepArgs<R> a = step_args<R>(p, Tin, Tout, X, partial, flag);
     dim3 g(step_grid(p)), b(STEP_WAVES * WAVE);
-    const size_t lds = step_lds_bytes<R>(p->L, p->np);
+    const size_t lds = step_lds_bytes<R>(p->L, p->np, p->rpl);
     const int key = p->rpl * 10 + p->wpl;
     switch (key) {
     case 21: hipLaunchKernelGGL((k_step<R, 2, 1>), g, b, lds, s, a); break;
@@ -423,8 +483,8 @@ size_t step_desc_bytes(cryo_dtype dt) {
 }
 
 size_t step_lds(const cryo_plan *p) {
-    return p->dtype == CRYO_F64 ? step_lds_bytes<double>(p->L, p->np)
-                                : step_lds_bytes<float>(p->L, p->np);
+    return p->dtype == CRYO_F64 ? step_lds_bytes<double>(p->L, p->np, p->rpl)
+                                : step_lds_bytes<float>(p->L, p->np, p->rpl);
 }
 
 void step_desc_fill(const cryo_plan *p, void *out, void *buf0, void *buf1, int *flag) {

@@ -75,13 +75,15 @@ static cryo_status check_problem(const cryo_problem *pr) {
     for (int s = 0; s < 4; ++s) {
         if (pr->bc.kind[s] != CRYO_INSULATED && pr->bc.kind[s] != CRYO_HELD)
             return fail(CRYO_ERR_ARG, "boundary kind must be 0 or 1");
-        if (pr->bc.kind[s] == CRYO_HELD && !(pr->bc.value[s] > 0))
-            return fail(CRYO_ERR_ARG, "held boundary temperature must be > 0");
+        if (pr->bc.kind[s] == CRYO_HELD &&
+            !(pr->bc.value[s] >= POW_TLO && pr->bc.value[s] < POW_THI))
+            return fail(CRYO_ERR_ARG, "held boundary temperature must lie in [1/16 K, 2^20 K)");
     }
     if (g.r_inner == 0 && pr->bc.kind[0] != CRYO_INSULATED)
         return fail(CRYO_ERR_ARG, "r_inner = 0 (the axis) must be insulated");
     if (!(pr->dt > 0) || !std::isfinite(pr->dt)) return fail(CRYO_ERR_ARG, "dt must be > 0");
-    if (!(pr->T_init > 0)) return fail(CRYO_ERR_ARG, "T_init must be > 0");
+    if (!(pr->T_init >= POW_TLO && pr->T_init < POW_THI))
+        return fail(CRYO_ERR_ARG, "T_init must lie in [1/16 K, 2^20 K)");
     return CRYO_OK;
 }
 
@@ -117,19 +119,18 @@ cryo_status ensure_device(cryo_plan *p) {
     (void)hipGetDevice(&p->device);
     const int np = p->np;
     size_t es = p->dtype == CRYO_F64 ? sizeof(double) : sizeof(float);
-    hipError_t e = hipMalloc(&p->d_gw, es * np);
-    if (e == hipSuccess) e = hipMalloc(&p->d_ge, es * np);
+    // one array of two planes: gw, ge
+    std::vector<double> rows(p->gw);
+    rows.insert(rows.end(), p->ge.begin(), p->ge.end());
+    hipError_t e = hipMalloc(&p->d_rows, es * 2 * np);
     uint32_t *info = nullptr;
     if (e == hipSuccess) e = hipMalloc((void **)&info, sizeof(uint32_t) * np);
     if (e == hipSuccess) {
         if (p->dtype == CRYO_F64) {
-            e = hipMemcpy(p->d_gw, p->gw.data(), es * np, hipMemcpyHostToDevice);
-            if (e == hipSuccess)
-                e = hipMemcpy(p->d_ge, p->ge.data(), es * np, hipMemcpyHostToDevice);
+            e = hipMemcpy(p->d_rows, rows.data(), es * 2 * np, hipMemcpyHostToDevice);
         } else {
-            std::vector<float> a(p->gw.begin(), p->gw.end()), b(p->ge.begin(), p->ge.end());
-            e = hipMemcpy(p->d_gw, a.data(), es * np, hipMemcpyHostToDevice);
-            if (e == hipSuccess) e = hipMemcpy(p->d_ge, b.data(), es * np, hipMemcpyHostToDevice);
+            std::vector<float> a(rows.begin(), rows.end());
+            e = hipMemcpy(p->d_rows, a.data(), es * 2 * np, hipMemcpyHostToDevice);
         }
     }
     if (e == hipSuccess)
@@ -139,11 +140,10 @@ cryo_status ensure_device(cryo_plan *p) {
         e = hipMemcpy(p->d_pow, p->pow_blob.data(), sizeof(double) * p->pow_blob.size(),
                       hipMemcpyHostToDevice);
     if (e != hipSuccess) {
-        if (p->d_gw) (void)hipFree(p->d_gw);
-        if (p->d_ge) (void)hipFree(p->d_ge);
+        if (p->d_rows) (void)hipFree(p->d_rows);
         if (info) (void)hipFree(info);
         if (p->d_pow) (void)hipFree(p->d_pow);
-        p->d_gw = p->d_ge = nullptr;
+        p->d_rows = nullptr;
         p->d_pow = nullptr;
         return fail(CRYO_ERR_DEVICE, std::string("device table upload: ") + hipGetErrorString(e));
     }
@@ -197,8 +197,6 @@ static void build_row_tables(cryo_plan *p) {
     }
     p->surf_lane = (nr - 1) / rpl;
     p->surf_reg = (nr - 1) % rpl;
-    p->surf_lane = (nr - 1) / rpl;
-    p->surf_reg = (nr - 1) % rpl;
 }
 
 }  // namespace cryo
@@ -249,7 +247,7 @@ cryo_status cryo_plan_create(const cryo_problem *prob, cryo_dtype dtype, cryo_pl
     p->np = WAVE * p->wpl * p->rpl;
     p->lpw = 4;
     p->eta = prob->geom.height / (p->nz - 1);
-    const int nr = p->nr, L = p->L, np = p->np, rpl = p->rpl;
+    const int nr = p->nr, L = p->L;
 
     // grid, eq. (9): r_{i+1} = r_i + h_{i+1}; equal intervals within a layer
     p->r.assign(nr, 0.0);
@@ -300,7 +298,7 @@ cryo_status cryo_plan_create(const cryo_problem *prob, cryo_dtype dtype, cryo_pl
         for (int j = 0; j < POW_NM; ++j) {
             double m0 = 1.0 + (j + 0.5) / POW_NM;
             R[2 * j] = pow(m0, e);
-            R[2 * j + 1] = 1.0 / m0;
+            R[2 * j + 1] = 2.0 / m0;          // applied to the frexp mantissa in [1/2, 1)
         }
     }
     double *LR = B + (size_t)(2 * L + 1) * POW_EROW;
@@ -310,11 +308,17 @@ cryo_status cryo_plan_create(const cryo_problem *prob, cryo_dtype dtype, cryo_pl
         double *R = LR + (size_t)id * POW_LROW;
         for (int x = 0; x < POW_NE; ++x) R[x] = lw.K[id] * exp2(e * (x + POW_EMIN));
         R[POW_NE] = e;
-        R[POW_NE + 1] = exp_row(id, L);
+        // the exponent row's offset in doubles, stored as integer bits
+        const int64_t off = (int64_t)exp_row(id, L) * POW_EROW;
+        memcpy(&R[POW_NE + 1], &off, sizeof off);
         CK[id] = (id >= 2 * L && id < 3 * L) ? lw.K[id] : 0.0;   // cube path: K T^3 + A
         CA[id] = id == UNIT ? 1.0 : 0.0;
     }
 
+    if (step_lds(p) > MAX_STEP_LDS) {
+        delete p;
+        return fail(CRYO_ERR_UNSUPPORTED, "tables and line ring exceed a workgroup's LDS");
+    }
     build_row_tables(p);
     p->pulse.b0 = snap(prob->pulse.t_on / prob->dt);
     p->pulse.W = snap(prob->pulse.width / prob->dt);
@@ -327,8 +331,7 @@ cryo_status cryo_plan_create(const cryo_problem *prob, cryo_dtype dtype, cryo_pl
 
 void cryo_plan_destroy(cryo_plan *p) {
     if (!p) return;
-    if (p->d_gw) (void)hipFree(p->d_gw);
-    if (p->d_ge) (void)hipFree(p->d_ge);
+    if (p->d_rows) (void)hipFree(p->d_rows);
     if (p->d_info) (void)hipFree(p->d_info);
     if (p->d_pow) (void)hipFree(p->d_pow);
     delete p;
@@ -357,9 +360,16 @@ cryo_status cryo_plan_set_shape(cryo_plan *p, int32_t rows_per_lane, int32_t wav
         return fail(CRYO_ERR_ARG, "lines per wave must be 1..nz-2");
     p->lpw = lines_per_wave;
     if (rows_per_lane != p->rpl || waves_per_line != p->wpl) {
+        const int rpl0 = p->rpl, wpl0 = p->wpl;
         p->rpl = rows_per_lane;
         p->wpl = waves_per_line;
         p->np = WAVE * p->wpl * p->rpl;
+        if (step_lds(p) > MAX_STEP_LDS) {
+            p->rpl = rpl0;
+            p->wpl = wpl0;
+            p->np = WAVE * p->wpl * p->rpl;
+            return fail(CRYO_ERR_UNSUPPORTED, "chunk shape needs more LDS than a workgroup has");
+        }
         build_row_tables(p);
     }
     return CRYO_OK;

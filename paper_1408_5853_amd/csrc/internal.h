@@ -56,14 +56,15 @@ struct Laws {
     double e[MAX_LAWS];             // exponent per law id
 };
 
-// FP64 powers T^e from tables: T = 2^x m, m in [1,2); m0 = 1 + (j + 1/2)/64
-// for the top six mantissa bits j; u = m / m0 - 1 (|u| <= 1/128);
+// FP64 powers T^e from tables: T = 2^x m, m in [1,2); m0 = 1 + (j + 1/2)/NM
+// for the top POW_MBITS mantissa bits j; u = m / m0 - 1 (|u| <= 1/(2 NM));
 // K T^e = [K 2^(x e)] m0^e (1 + u)^e, with (1 + u)^e = exp(e ln(1 + u)) by
-// fixed series: ln(1 + u) to degree 7, exp to degree 7 (|e ln(1+u)| <= 0.032
-// for |e| <= 4); truncation below 1e-17 relative.
-constexpr int POW_NM = 64, POW_NE = 24, POW_EMIN = -4;
-constexpr int POW_EROW = 2 * POW_NM;       // exponent row: {m0^e, 1/m0} pairs
-constexpr int POW_LROW = POW_NE + 2;       // law row: K 2^(x e) [NE], e, exponent row
+// Taylor series: ln(1 + u) to degree 7, exp to degree 7; for |e| <= 4 the
+// truncation stays below 1e-16 relative.
+constexpr int POW_MBITS = 6, POW_NM = 1 << POW_MBITS, POW_NE = 24, POW_EMIN = -4;
+constexpr double POW_TLO = 0.0625, POW_THI = 1048576.0;   // 2^EMIN, 2^(EMIN+NE)
+constexpr int POW_EROW = 2 * POW_NM;       // exponent row: {m0^e, 2/m0} pairs
+constexpr int POW_LROW = POW_NE + 2;       // law row: K 2^(x e) [NE], e, exponent row offset
 // blob: 2L+1 exponent rows, (3L+2) law rows, then cube multipliers and
 // addends [3L+2] each
 __host__ __device__ inline size_t pow_blob_doubles(int L) {
@@ -99,7 +100,7 @@ struct cryo_plan {
     cryo::Pulse pulse;
     int surf_lane, surf_reg;          // owner of row nr-1
     // device tables (read-only, made at create time)
-    void *d_gw = nullptr, *d_ge = nullptr;
+    void *d_rows = nullptr;           // [2][np]: gw, ge
     uint32_t *d_info = nullptr;
     double *d_pow = nullptr;
     int device = 0;
@@ -121,5 +122,7 @@ cryo_status launch_step(const cryo_plan *p, const void *Tin, void *Tout, double 
 cryo_status launch_surf_reduce(const cryo_plan *p, const double *partial, int nsteps,
                                double *out, hipStream_t s);
 int step_grid(const cryo_plan *p);
+size_t step_lds(const cryo_plan *p);            // dynamic LDS of the stepping kernel
+constexpr size_t MAX_STEP_LDS = 160 * 1024 - 4096;   // leaves room for static LDS
 cryo_status ensure_device(cryo_plan *p);
 }  // namespace cryo
