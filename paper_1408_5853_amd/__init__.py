@@ -173,6 +173,16 @@ class Plan:
         k_scale_m] by the discrete adjoint (FP64 plans).  Returns (J, grad,
         surface trace) as float, numpy, numpy.  Synchronous."""
         torch = _torch()
+        if self.shape()[0] > 8:
+            # the adjoint kernels take up to 8 rows per lane: switch to the
+            # gradient shape while the plan has not run yet (else the library
+            # reports the shape as unsupported)
+            sh = _gradient_shape(self.cell)
+            if sh is not None:
+                try:
+                    self.set_shape(*sh)
+                except CryoError:
+                    pass
         n = int(self.cell["nsteps"] if nsteps is None else nsteps)
         tgt = np.ascontiguousarray(np.asarray(target, dtype=np.float64)[:n])
         if tgt.size < n:

@@ -151,6 +151,8 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj1(StepArgs<double> a, Ad
                 c0 = aa;          // sup of the first transposed row
             } else {
                 elim_row<double, RPL>(r - 1, ccm2, bbm1, aa, mum1, al, ga, de);
+                // eliminate here rather than at the solve (register pressure)
+                asm volatile("" : "+v"(al[r - 1]), "+v"(ga[r - 1]), "+v"(de[r - 1]));
             }
             ccm2 = ccm1;
             ccm1 = cc;

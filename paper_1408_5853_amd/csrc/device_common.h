@@ -42,7 +42,8 @@ struct LawLds;
 template <>
 struct LawLds<double> {
     const double *erow;     // exponent rows: {m0^e, 2/m0}[NM]
-    const double *lrow;     // law rows: K 2^(x e) [NE], e, exponent row offset
+    const double *lrow;     // law rows: K 2^(x e) [NE], e, binomials
+    int L;                  // layers (law ids -> exponent rows)
     const double *ck, *ca;  // cube path: K T^3 + A
     // T on the table range [2^POW_EMIN, 2^(POW_EMIN+POW_NE)) K
     static __device__ inline bool in_range(double x) {
@@ -57,26 +58,21 @@ struct LawLds<double> {
         const int hi = (int)(__double_as_longlong(x) >> 32);
         const int jm = (hi >> (20 - POW_MBITS)) & (POW_NM - 1);
         const double *Lr = lrow + id * POW_LROW;
-        const double2 ee = *(const double2 *)(Lr + POW_NE);     // e, exponent row offset
-        const int eoff = (int)__double_as_longlong(ee.y);
-        const double2 mm = *(const double2 *)(erow + eoff + 2 * jm);
+        const double2 ee = *(const double2 *)(Lr + POW_NE);     // e
+        const double2 c23 = *(const double2 *)(Lr + POW_NE + 2);
+        const double2 c45 = *(const double2 *)(Lr + POW_NE + 4);
+        const double2 c67 = *(const double2 *)(Lr + POW_NE + 6);
+        // exponent row from the law id (no dependent table read)
+        const double2 mm = *(const double2 *)(erow + exp_row(id, L) * POW_EROW + 2 * jm);
         const double u = fma(mh, mm.y, -1.0);                   // m / m0 - 1
-        // ln(1 + u), |u| <= 2^-(POW_MBITS+1)
-        double l = fma(u, 1.0 / 7, -1.0 / 6);
-        l = fma(l, u, 1.0 / 5);
-        l = fma(l, u, -1.0 / 4);
-        l = fma(l, u, 1.0 / 3);
-        l = fma(l, u, -1.0 / 2);
-        l = fma(l, u, 1.0);
-        const double v = ee.x * (l * u);
-        // exp(v)
-        double s = fma(v, 1.0 / 5040, 1.0 / 720);
-        s = fma(s, v, 1.0 / 120);
-        s = fma(s, v, 1.0 / 24);
-        s = fma(s, v, 1.0 / 6);
-        s = fma(s, v, 0.5);
-        s = fma(s, v, 1.0);
-        s = fma(s, v, 1.0);
+        // (1 + u)^e, |u| <= 2^-(POW_MBITS+1)
+        double s = fma(c67.y, u, c67.x);
+        s = fma(s, u, c45.y);
+        s = fma(s, u, c45.x);
+        s = fma(s, u, c23.y);
+        s = fma(s, u, c23.x);
+        s = fma(s, u, ee.x);
+        s = fma(s, u, 1.0);
         return Lr[xc] * mm.x * s;
     }
     // as lawc, and flags an argument off the table range
@@ -122,7 +118,7 @@ struct StepArgs {
     Pulse pulse;              // batch: schedule evaluated on the device
 };
 
-constexpr int STEP_WAVES = 8;
+constexpr int STEP_WAVES = STEP_WAVES_HOST;
 
 template <typename R>
 __device__ inline R shfl_up1(R v, int s, int lane) {
@@ -348,9 +344,20 @@ template <typename R>
 __host__ __device__ inline size_t ring_slot_elems(int rpl) {
     return (size_t)rpl * (Pair<R>::on ? 2 : 1) * WAVE;
 }
+// the ring is used while a slot stays within 4 KiB (LDS budget)
+template <typename R>
+__host__ __device__ constexpr bool ring_used(int rpl) {
+    return rpl * (Pair<R>::on ? 2 : 1) * WAVE * sizeof(R) <= 4096;
+}
+// without the ring, FP64 keeps the carried axial fluxes in its place
 template <typename R>
 __host__ __device__ inline size_t step_lds_bytes(int L, int np, int rpl = 0) {
-    return ring_lds_offset<R>(L, np) + 2 * (size_t)STEP_WAVES * ring_slot_elems<R>(rpl) * sizeof(R);
+    size_t extra = 0;
+    if (ring_used<R>(rpl))
+        extra = 2 * (size_t)STEP_WAVES * ring_slot_elems<R>(rpl);
+    else if (sizeof(R) == 8)
+        extra = (size_t)STEP_WAVES * rpl * WAVE;
+    return ring_lds_offset<R>(L, np) + extra * sizeof(R);
 }
 
 // Stage the law tables in LDS (dynamic shared memory); all threads call it.
@@ -363,6 +370,7 @@ __device__ inline LawLds<R> stage_laws(const StepArgs<R> &a, unsigned char *smem
         const int nb = (int)pow_blob_doubles(L);
         for (int i = t; i < nb; i += nt) d[i] = a.pow_blob[i];
         v.erow = d;
+        v.L = L;
         v.lrow = d + (size_t)(2 * L + 1) * POW_EROW;
         v.ck = v.lrow + (size_t)nlaw * POW_LROW;
         v.ca = v.ck + nlaw;

@@ -70,11 +70,15 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
     // registers in flight) one iteration ahead.  Slot layout: element
     // (row r, plane p, lane) at (r NPL + p) WAVE + lane.  Groups past the last
     // line march on clamped line indices (real lines, results discarded).
+    // Shapes whose slots would not fit (ring_used) read the lines from memory
+    // directly instead.
     constexpr int SLOT = RPL * NPL * WAVE;
+    constexpr bool RING = ring_used<R>(RPL);
     constexpr int EPL = 16 / (int)sizeof(R);              // elements per lane per load
     constexpr int LPS = WAVE / EPL;                       // lanes per row-plane
     R *ring = (R *)(smem + ring_lds_offset<R>(L, a.np)) + (size_t)wv * 2 * SLOT;
     auto prefetch = [&](int slot, size_t lbase) {
+        if constexpr (!RING) return;
         R *dst = ring + slot * SLOT;
         const int sub = lane / LPS, e0 = EPL * (lane % LPS);
 #pragma unroll
@@ -87,7 +91,20 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
                                              16, 0, 0);
         }
     };
-    R FS[RPL], Tc[RPL], Lc[RPL];
+    // carried south-face fluxes: registers, or (FP64 without the ring) LDS in
+    // the ring's place
+    constexpr bool FS_LDS = !RING && sizeof(R) == 8;
+    R FSr[FS_LDS ? 1 : RPL];
+    R *fsl = (R *)(smem + ring_lds_offset<R>(L, a.np)) + (size_t)wv * RPL * WAVE + lane;
+    auto fs_get = [&](int r) -> R {
+        if constexpr (FS_LDS) return fsl[r * WAVE];
+        else return FSr[r];
+    };
+    auto fs_set = [&](int r, R v) {
+        if constexpr (FS_LDS) fsl[r * WAVE] = v;
+        else FSr[r] = v;
+    };
+    R Tc[RPL], Lc[RPL];
     R TwF, TeL, LwF = 0, LeL = 0;
     {
         const int jb = min(j0, a.nz - 2);
@@ -114,10 +131,11 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
             const bool cap = (inf_r & 7) == K_CAP;
             const int l2 = (inf_r >> 12) & 63;
             const R lamS = law.law(cap ? l2 : law_zero(L), (R)0.5 * (Tc[r] + Tp), bad);
-            FS[r] = lamS * dif<R>(Tc[r], Lc[r], Tp, Tpl);
+            fs_set(r, lamS * dif<R>(Tc[r], Lc[r], Tp, Tpl));
+            if (r & 1) __builtin_amdgcn_sched_barrier(0);      // register pressure
         }
         // the next line's slot must have landed before the first row reads it
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        if constexpr (RING) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     }
     for (int it = 0; it < a.lpw; ++it) {
         const int jr = j0 + it;
@@ -127,8 +145,10 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
         const R *sn = ring + ((it + 1) & 1) * SLOT;      // line j+1
         // the other slot (line j, already read into registers) takes line j+2;
         // its reads must have completed before the load overwrites it
-        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-        prefetch(it & 1, (size_t)min(j + 2, a.nz - 1) * LS);
+        if constexpr (RING) {
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+            prefetch(it & 1, (size_t)min(j + 2, a.nz - 1) * LS);
+        }
         R TwP, TeP, LwP = 0, LeP = 0;                      // next line's chunk-end neighbours
         {
             const size_t bn = (size_t)min(j + 1, a.nz - 2) * LS;
@@ -150,8 +170,14 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
             const uint32_t kind = inf_r & 7;
             const bool cap = kind == K_CAP;
             const R T = Tc[r], Tl = Lc[r];
-            const R Tnr = sn[r * NPL * WAVE + lane];
-            const R Lnr = PAIR ? sn[(r * NPL + 1) * WAVE + lane] : (R)0;
+            R Tnr, Lnr = 0;
+            if constexpr (RING) {
+                Tnr = sn[r * NPL * WAVE + lane];
+                if constexpr (PAIR) Lnr = sn[(r * NPL + 1) * WAVE + lane];
+            } else {
+                Tnr = Tin[base + LS + q];
+                if constexpr (PAIR) Lnr = Tin[base + LS + LO + q];
+            }
             const R Tw = (r > 0) ? Tc[r - 1] : TwF;
             const R Te = (r < RPL - 1) ? Tc[r + 1] : TeL;
             const R Lw = (r > 0) ? Lc[r - 1] : LwF;
@@ -174,10 +200,10 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
             const R fe = sge[q] * (cap ? lamE : lam3);
             const R FN = lam2 * dif<R>(Tnr, Lnr, T, Tl);
             R dd = fw * dif<R>(Tw, Lw, T, Tl) + fe * dif<R>(Te, Le, T, Tl);
-            dd += cap ? FN - FS[r] : (R)0;
+            dd += cap ? FN - fs_get(r) : (R)0;
             dd += (R)((inf_r >> 3) & 1) * X;                // heater capacity rows
             if ((inf_r >> 4) & 1) dd = dif<R>(a.val[(inf_r >> 5) & 1], (R)0, T, Tl);
-            FS[r] = FN;
+            fs_set(r, FN);
             lamW = lamE;
             const R aa = -fw, bb = fw + fe + rc, cc = -fe;
             if (r == 0) {
@@ -187,15 +213,18 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
                 d0 = dd;
             } else {
                 elim_row<R, RPL>(r, aa, bb, cc, dd, al, ga, de);
+                // eliminate here, not where the results are first used (the
+                // solve): sinking it would keep every row's coefficients live
+                asm volatile("" : "+v"(al[r]), "+v"(ga[r]), "+v"(de[r]));
             }
             // keep the scheduler from hoisting every row's law evaluations
             // at once (register pressure); rows still overlap pairwise
-            if (r & 1) __builtin_amdgcn_sched_barrier(0);
+            if (RPL >= 16 || (r & 1)) __builtin_amdgcn_sched_barrier(0);
         }
         R X[RPL];
         solve_tail<R, RPL, G>(a0, b0, c0, d0, al, ga, de, X, lane, wig, xch);
         // the line after next (slot) and the next neighbours have landed
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        if constexpr (RING) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         if (active) {
             // new state: T + dT (pairs: error-free sum, then renormalise)
             R Hn[RPL], Lnw[RPL];
@@ -223,7 +252,10 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
                 const bool mine = side == 0 ? j == 1 : j == a.nz - 2;
                 if (!mine) continue;
                 const bool held = a.held[2 + side];
-                R *o = Tout + (side == 0 ? (size_t)0 : (size_t)(a.nz - 1) * LS);
+                // formed here (cold path), not hoisted out of the line loop
+                size_t ob = side == 0 ? (size_t)0 : (size_t)(a.nz - 1) * LS;
+                asm volatile("" : "+v"(ob));
+                R *o = Tout + ob;
 #pragma unroll
                 for (int r = 0; r < RPL; ++r) {
                     o[r * NL + lg] = held ? a.val[2 + side] : Hn[r];
@@ -231,20 +263,28 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
                 }
             }
             if (partial && lg == a.surf_lane) {
+                int sreg = a.surf_reg;
+                asm volatile("" : "+v"(sreg));               // cold path: no hoisting
                 double v = (double)Hn[0] + (double)Lnw[0];
 #pragma unroll
                 for (int r = 1; r < RPL; ++r)
-                    if (r == a.surf_reg) v = (double)Hn[r] + (double)Lnw[r];
+                    if (r == sreg) v = (double)Hn[r] + (double)Lnw[r];
                 sv += a.wz_mid * v;
                 if (j == 1) sv += a.wz_end * (a.held[2] ? (double)a.val[2] : v);
                 if (j == a.nz - 2) sv += a.wz_end * (a.held[3] ? (double)a.val[3] : v);
             }
         }
-        // next line: registers from its slot
+        // next line: registers from its slot, or from memory
+        const size_t bn = (size_t)min(j + 1, a.nz - 2) * LS;
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
-            Tc[r] = sn[r * NPL * WAVE + lane];
-            Lc[r] = PAIR ? sn[(r * NPL + 1) * WAVE + lane] : (R)0;
+            if constexpr (RING) {
+                Tc[r] = sn[r * NPL * WAVE + lane];
+                Lc[r] = PAIR ? sn[(r * NPL + 1) * WAVE + lane] : (R)0;
+            } else {
+                Tc[r] = Tin[bn + r * NL + lg];
+                Lc[r] = PAIR ? Tin[bn + LO + r * NL + lg] : (R)0;
+            }
         }
         TwF = TwP;
         TeL = TeP;
@@ -455,6 +495,7 @@ static cryo_status step_t(const cryo_plan *p, const void *Tin, void *Tout, doubl
     case 84: hipLaunchKernelGGL((k_step<R, 8, 4>), g, b, lds, s, a); break;
     case 42: hipLaunchKernelGGL((k_step<R, 4, 2>), g, b, lds, s, a); break;
     case 44: hipLaunchKernelGGL((k_step<R, 4, 4>), g, b, lds, s, a); break;
+    case 161: hipLaunchKernelGGL((k_step<R, 16, 1>), g, b, lds, s, a); break;
     default: return fail(CRYO_ERR_UNSUPPORTED, "radial chunk shape");
     }
     return launch_check("step");
@@ -514,6 +555,7 @@ static cryo_status step_batch_t(int rpl, int wpl, const void *desc, const int2 *
     case 84: hipLaunchKernelGGL((k_step_batch<R, 8, 4>), g, b, lds, s, d, map, n, k0); break;
     case 42: hipLaunchKernelGGL((k_step_batch<R, 4, 2>), g, b, lds, s, d, map, n, k0); break;
     case 44: hipLaunchKernelGGL((k_step_batch<R, 4, 4>), g, b, lds, s, d, map, n, k0); break;
+    case 161: hipLaunchKernelGGL((k_step_batch<R, 16, 1>), g, b, lds, s, d, map, n, k0); break;
     default: return fail(CRYO_ERR_UNSUPPORTED, "radial chunk shape");
     }
     return launch_check("step_batch");

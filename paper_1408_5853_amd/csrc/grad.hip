@@ -98,6 +98,9 @@ cryo_status cryo_gradient(const cryo_plan *pc, const void *T0, int64_t N, const 
     if (!p || !T0 || N < 1 || !target || !J || !grad || ckpt < 0)
         return fail(CRYO_ERR_ARG, "bad argument");
     if (p->dtype != CRYO_F64) return fail(CRYO_ERR_UNSUPPORTED, "the adjoint needs an FP64 plan");
+    if (p->rpl > 8)
+        return fail(CRYO_ERR_UNSUPPORTED, "the adjoint kernels take up to 8 rows per lane; set "
+                                          "a shape such as (4, waves, 1) before the plan's first run");
     const GradLayout g = grad_layout(p, N, ckpt);
     if (!ws || ws_bytes < g.total)
         return fail(CRYO_ERR_WORKSPACE, "gradient workspace needs " + std::to_string(g.total) +

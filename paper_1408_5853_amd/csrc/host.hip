@@ -101,15 +101,26 @@ static double dt_bound(const cryo_problem *pr, double Tm) {
     return 0.5 * eta * eta * best;
 }
 
-// Chunk shape of a line: rows per lane and waves per line.  Up to 8 rows per
-// lane (register budget of the FP64 solve), then more waves per line.
+// Chunk shape of a line: rows per lane and waves per line.  One wave per line
+// up to 1024 rows (16 rows per lane), then 8 rows per lane over more waves.
 static void pick_shape(int nr, int *rpl, int *wpl) {
     int r = 2;
-    while (WAVE * r < nr && r < 8) r *= 2;
+    while (WAVE * r < nr && r < 16) r *= 2;
     int w = 1;
-    while (WAVE * w * r < nr) w *= 2;
+    if (WAVE * r < nr) {
+        r = 8;
+        while (WAVE * w * r < nr) w *= 2;
+    }
     *rpl = r;
     *wpl = w;
+}
+
+// Lines per wave: about one workgroup per compute unit of an MI355X (256),
+// so that every unit works and each line group amortises its start-up line.
+static int pick_lpw(int nz, int wpl) {
+    const int per_wg = STEP_WAVES_HOST / wpl;
+    const double l = (double)(nz - 2) / ((double)per_wg * 256.0);
+    return std::min(8, std::max(1, (int)std::lround(l)));
 }
 
 // Device copies of the per-row tables, made once on the first call that
@@ -207,7 +218,7 @@ extern "C" {
 
 const char *cryo_last_error(void) { return g_err.c_str(); }
 
-const char *cryo_version(void) { return "cryocell 0.1 (gfx950)"; }
+const char *cryo_version(void) { return "cryocell 0.2 (gfx950)"; }
 
 cryo_status cryo_validate(const cryo_problem *prob) { return check_problem(prob); }
 
@@ -245,7 +256,7 @@ cryo_status cryo_plan_create(const cryo_problem *prob, cryo_dtype dtype, cryo_pl
     p->L = prob->geom.n_layers;
     pick_shape(p->nr, &p->rpl, &p->wpl);
     p->np = WAVE * p->wpl * p->rpl;
-    p->lpw = 4;
+    p->lpw = pick_lpw(p->nz, p->wpl);
     p->eta = prob->geom.height / (p->nz - 1);
     const int nr = p->nr, L = p->L;
 
@@ -308,9 +319,12 @@ cryo_status cryo_plan_create(const cryo_problem *prob, cryo_dtype dtype, cryo_pl
         double *R = LR + (size_t)id * POW_LROW;
         for (int x = 0; x < POW_NE; ++x) R[x] = lw.K[id] * exp2(e * (x + POW_EMIN));
         R[POW_NE] = e;
-        // the exponent row's offset in doubles, stored as integer bits
-        const int64_t off = (int64_t)exp_row(id, L) * POW_EROW;
-        memcpy(&R[POW_NE + 1], &off, sizeof off);
+        // binomial coefficients of (1 + u)^e, k = 2..POW_DEG
+        double c = e;
+        for (int k = 2; k <= POW_DEG; ++k) {
+            c = c * (e - (k - 1)) / k;
+            R[POW_NE + k] = c;
+        }
         CK[id] = (id >= 2 * L && id < 3 * L) ? lw.K[id] : 0.0;   // cube path: K T^3 + A
         CA[id] = id == UNIT ? 1.0 : 0.0;
     }
@@ -352,7 +366,7 @@ cryo_status cryo_plan_set_shape(cryo_plan *p, int32_t rows_per_lane, int32_t wav
     if (p->d_info) return fail(CRYO_ERR_ARG, "shape must be set before the plan's first run");
     const int key = rows_per_lane * 10 + waves_per_line;
     const bool built = key == 21 || key == 41 || key == 81 || key == 82 || key == 84 ||
-                       key == 42 || key == 44;
+                       key == 42 || key == 44 || key == 161;
     if (!built) return fail(CRYO_ERR_UNSUPPORTED, "no kernel for this chunk shape");
     if ((int64_t)WAVE * waves_per_line * rows_per_lane < p->nr)
         return fail(CRYO_ERR_ARG, "chunk shape too short for the radial line");

@@ -15,6 +15,7 @@ constexpr int WAVE = 64;
 constexpr int MAX_LAYERS = 16;
 constexpr int MAX_NR = 2048;
 constexpr int SURF_CHUNK = 1024;    // steps per surface reduction round
+constexpr int STEP_WAVES_HOST = 8;  // waves per stepping workgroup
 
 // Row classes of one radial line (eq. (13), eq. (18), eq. (15), padding).
 enum RowKind : uint32_t { K_PAD = 0, K_LO = 1, K_HI = 2, K_CAP = 3, K_IFACE = 4 };
@@ -29,7 +30,7 @@ constexpr int MAX_LAWS = 3 * MAX_LAYERS + 2;
 __host__ __device__ inline int law_zero(int L) { return 3 * L; }
 __host__ __device__ inline int law_unit(int L) { return 3 * L + 1; }
 __host__ __device__ inline int exp_row(int law, int L) {
-    return law < 2 * L ? law % L : (law < 3 * L ? law - L : 2 * L);
+    return law < L ? law : min(law - L, 2 * L);
 }
 
 // Per-row packed info word:
@@ -58,13 +59,17 @@ struct Laws {
 
 // FP64 powers T^e from tables: T = 2^x m, m in [1,2); m0 = 1 + (j + 1/2)/NM
 // for the top POW_MBITS mantissa bits j; u = m / m0 - 1 (|u| <= 1/(2 NM));
-// K T^e = [K 2^(x e)] m0^e (1 + u)^e, with (1 + u)^e = exp(e ln(1 + u)) by
-// Taylor series: ln(1 + u) to degree 7, exp to degree 7; for |e| <= 4 the
+// K T^e = [K 2^(x e)] m0^e (1 + u)^e, with (1 + u)^e summed as its binomial
+// series to degree 7 (coefficients per law in the law row); for |e| <= 4 the
 // truncation stays below 1e-16 relative.
 constexpr int POW_MBITS = 6, POW_NM = 1 << POW_MBITS, POW_NE = 24, POW_EMIN = -4;
+constexpr int POW_DEG = 7;
 constexpr double POW_TLO = 0.0625, POW_THI = 1048576.0;   // 2^EMIN, 2^(EMIN+NE)
 constexpr int POW_EROW = 2 * POW_NM;       // exponent row: {m0^e, 2/m0} pairs
-constexpr int POW_LROW = POW_NE + 2;       // law row: K 2^(x e) [NE], e, exponent row offset
+// law row: K 2^(x e) [NE], e, (unused), binomial(e, k) k = 2..7, then two
+// pad doubles: a 272-byte stride puts the rows of different laws in different
+// LDS banks (lanes of one wave read several laws at once)
+constexpr int POW_LROW = POW_NE + 2 + (POW_DEG - 1) + 2;
 // blob: 2L+1 exponent rows, (3L+2) law rows, then cube multipliers and
 // addends [3L+2] each
 __host__ __device__ inline size_t pow_blob_doubles(int L) {

@@ -137,7 +137,10 @@ def test_f32_within_1e4_kelvin(make, n):
     assert e < F32_TOL_K and es < F32_TOL_K
 
 
-@pytest.mark.parametrize("shape", [(2, 1), (4, 1), (8, 1), (4, 2), (8, 2), (4, 4), (8, 4)])
+SHAPES = [(2, 1), (4, 1), (8, 1), (4, 2), (8, 2), (4, 4), (8, 4), (16, 1)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
 def test_every_chunk_shape_matches_oracle(shape):
     import torch
 
@@ -163,3 +166,30 @@ def test_every_chunk_shape_matches_oracle(shape):
             ref = Tg
         else:
             assert np.array_equal(Tg, ref)      # the march order changes nothing
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_every_chunk_shape_f32_pairs_match_oracle(shape):
+    """FP32 pairs through every kernel shape (with and without the LDS line
+    ring), at ragged nr, against the FP64 oracle."""
+    import torch
+
+    import paper_1408_5853_amd as P
+    rpl, wpl = shape
+    nr = 64 * rpl * wpl - 37 if 64 * rpl * wpl > 200 else 64 * rpl * wpl - 5
+    c = cellgen.tiny(nr + 1, nr=nr, nz=9, n_layers=4, z_active=True, dt=2e-7, amplitude=5e9)
+    rng = np.random.default_rng(5)
+    T0 = 28.0 + rng.uniform(0, 5, size=(c["nz"], c["nr"]))
+    To = oracle.forward(c, T0, nsteps=40)
+    for lpw in (1, 3):
+        say("case f32 shape %s lines/wave %d nr %d" % (shape, lpw, nr))
+        plan = P.Plan(c, "f32")
+        plan.set_shape(rpl, wpl, lpw)
+        T = plan.field_from(T0)
+        ws = plan.workspace(40)
+        plan.forward(T, 0, 40, ws=ws)
+        plan.poll(ws)
+        torch.cuda.synchronize()
+        e = float(np.max(np.abs(plan.field_values(T) - To)))
+        say("  max abs err %.3e K" % e)
+        assert e < F32_TOL_K
