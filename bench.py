@@ -10,9 +10,11 @@ timing starts.
 
 Extra measurements in the same JSON line (not part of `value`): the FP32
 (compensated pair) rate on the same cell, the batched design sweep (256
-uneven cells) against the same cells stepped one at a time, and the cost of
-a gradient (forward + checkpointed adjoint) relative to a forward on the
-adjoint workload (512 x 2048, 50,000 steps).
+uneven cells) against the same cells stepped one at a time, the cost of a
+gradient (forward + checkpointed adjoint) relative to a forward on the
+adjoint workload (512 x 2048, 50,000 steps), and gradients per second of the
+batched-adjoint design loop (64 designs of 512 x 1024, a bounded sample of
+500 steps and 2 Adam iterations).
 
 Prints one JSON line.  --gpus above 1 is refused: the stepper runs on one GPU.
 """
@@ -30,6 +32,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_TFLOPS = 78.6
 BYTES_PER_CELL_STEP = 16          # read T, write T^ (FP64; an FP32 pair is also 8 B/node)
+
+# HBM bytes per step launch measured with rocprofv3 (FETCH_SIZE x 2.000 +
+# WRITE_SIZE x 1.000, factors from a 256 MiB copy; profiles/k_step_f64_1024x4096.md),
+# keyed by library version and kernel shape: any other build reports null.
+MEASURED_TRAFFIC = {("cryocell 0.2 (gfx950)", (16, 1, 2)): 93.28e6}
 
 
 def log(*a):
@@ -85,7 +92,7 @@ def rate(plan_cls, cell, dtype, steps, warmup, stream):
 
 def batch_extra(P, steps, stream):
     import cellgen
-    cells = cellgen.config3(0)
+    cells = cellgen.sweep_cells(0)
     total = sum(c["nr"] * c["nz"] for c in cells)
     b = P.Batch(cells, "f32")
     T = b.init()
@@ -115,7 +122,7 @@ def batch_extra(P, steps, stream):
 def gradient_extra(P, steps, stream):
     import cellgen
     import numpy as np
-    c = cellgen.config4(0)
+    c = cellgen.adjoint_cell(0)
     tgt = cellgen.tracking_target(c, steps)
     plan = P.Plan(c, "f64")
     sh = P._gradient_shape(c)
@@ -132,6 +139,28 @@ def gradient_extra(P, steps, stream):
             "steps": steps, "forward_s": round(t_fwd, 3), "gradient_s": round(t_grad, 3),
             "gradient_over_forward": round(t_grad / t_fwd, 2), "J": J,
             "grad_finite": bool(np.all(np.isfinite(g)))}
+
+
+def design_extra(P, steps, iters, stream):
+    """The batched-adjoint design loop on a bounded sample: all 64 designs of
+    512 x 1024 nodes, `steps` steps each, `iters` Adam iterations (iters + 1
+    gradient_many calls of 64 gradients)."""
+    import cellgen
+    from paper_1408_5853_amd.design import design_adam
+    cells = cellgen.design_cells(0, nsteps=steps)
+    tg = [cellgen.tracking_target(c, steps) for c in cells]
+    P.gradient_many(cells[:2], tg[:2], streams=2)                # warm
+    t0 = time.perf_counter()
+    _, hist = design_adam(cells, tg, iters=iters, lr=0.05, streams=4)
+    secs = time.perf_counter() - t0
+    ngrad = len(cells) * (iters + 1)
+    cell_steps = sum(c["nr"] * c["nz"] for c in cells) * steps * (iters + 1)
+    return {"workload": "design loop: 64 designs of 512x1024, FP64 adjoint, Adam lr 0.05 in "
+                        "log(amplitude, width, thicknesses)",
+            "steps": steps, "adam_iterations": iters, "gradients": ngrad,
+            "seconds": round(secs, 3), "gradients_per_s": round(ngrad / secs, 2),
+            "forward_equivalent_gcell_steps_s": round(cell_steps / secs / 1e9, 2),
+            "mean_J_first": float(hist[0].mean()), "mean_J_last": float(hist[-1].mean())}
 
 
 def main():
@@ -157,9 +186,9 @@ def main():
     import paper_1408_5853_amd as P
 
     stream = torch.cuda.current_stream()
-    cell = cellgen.config2(0)
+    cell = cellgen.device_cell(0)
     cells = cell["nr"] * cell["nz"]
-    log("bench: config 1024x4096 FP64, %d steps after %d warmup" % (args.steps, args.warmup))
+    log("bench: device cell 1024x4096 FP64, %d steps after %d warmup" % (args.steps, args.warmup))
     secs, plan = rate(P.Plan, cell, "f64", args.steps, args.warmup, stream)
     value = cells * args.steps / secs / 1e9
     ms_step = 1e3 * secs / args.steps
@@ -184,10 +213,13 @@ def main():
                    "nr": cell["nr"], "nz": cell["nz"], "kernel_shape": list(plan.shape())},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "kernel": "k_step",
+                     "traffic": MEASURED_TRAFFIC.get((P.version(), tuple(plan.shape()))),
+                     "kernel": "k_step",
                      "bytes_per_launch": BYTES_PER_CELL_STEP * cells,
-                     "note": "algorithmic 16 B/cell-step; the 64 MiB ping-pong state is "
-                             "L2/MALL resident and the kernel is FP64-VALU bound"},
+                     "note": "algorithmic 16 B/cell-step; traffic = rocprofv3 FETCH_SIZE and "
+                             "WRITE_SIZE scaled by a 256 MiB copy; the 64 MiB ping-pong "
+                             "state stays in L2/MALL and the kernel is bound by FP64 VALU "
+                             "issue and LDS latency (47 % VALU busy), not by HBM"},
     }
     if args.copy_mib:
         n = args.copy_mib * (1 << 20) // 8
@@ -205,6 +237,8 @@ def main():
         out["extra"]["batch"] = batch_extra(P, 2000, stream)
         log("bench: gradient")
         out["extra"]["gradient"] = gradient_extra(P, 50_000, stream)
+        log("bench: design loop")
+        out["extra"]["design_loop"] = design_extra(P, 500, 2, stream)
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(cell, args.cpu_seconds)

@@ -113,7 +113,7 @@ def _weights_2mm(rng, n_layers, heater):
     return [2e-3 * x / s for x in w]
 
 
-def config1(seed=0, z_active=False, nsteps=10_000):
+def small_cell(seed=0, z_active=False, nsteps=10_000):
     """64 x 128 nodes, 4 layers (substrate, insulator, heater film, outer
     shell) summing to 2 mm, dt = 1 us, 1 ms pulse every 10 ms."""
     rng = np.random.default_rng([1, seed])
@@ -123,7 +123,7 @@ def config1(seed=0, z_active=False, nsteps=10_000):
                  z_active=z_active, heater=2)
 
 
-def config2(seed=0, z_active=False, nsteps=100_000, nr=1024, nz=4096):
+def device_cell(seed=0, z_active=False, nsteps=100_000, nr=1024, nz=4096):
     """1024 x 4096 nodes, 8 layers summing to 2 mm, dt = 0.2 us, 2 ms pulse
     every 20 ms, amplitude 5e8 W/m^3, 100,000 steps (one period)."""
     rng = np.random.default_rng([2, seed])
@@ -137,7 +137,7 @@ def config2(seed=0, z_active=False, nsteps=100_000, nr=1024, nz=4096):
 
 
 def paper_shape(seed=0, nsteps=100_000):
-    """631 x 1201 nodes with config-1 laws, dt = 0.25 us, 100,000 steps: the
+    """631 x 1201 nodes with the small cell's laws, dt = 0.25 us, 100,000 steps: the
     grid and run length of the paper's timing table (Table 4, last column)."""
     rng = np.random.default_rng([6, seed])
     thick = _weights_2mm(rng, 4, 2)
@@ -146,7 +146,7 @@ def paper_shape(seed=0, nsteps=100_000):
                  heater=2)
 
 
-def config3(seed=0, n_instances=256, nsteps=20_000):
+def sweep_cells(seed=0, n_instances=256, nsteps=20_000):
     """Batched design sweep: uneven grids from 128x256 to 512x2048, 4-8
     layers of 20 um - 1 mm, per-instance amplitude, width, period;
     dt_i = period_i / 20,000."""
@@ -165,7 +165,7 @@ def config3(seed=0, n_instances=256, nsteps=20_000):
     return out
 
 
-def config4(seed=0, z_active=False, nsteps=50_000, nr=512, nz=2048):
+def adjoint_cell(seed=0, z_active=False, nsteps=50_000, nr=512, nz=2048):
     """Adjoint workload: 512 x 2048 nodes, 6 layers of 20 um - 1 mm, 5e8
     W/m^3, 1 ms pulse every 10 ms, dt = 0.2 us, 50,000 steps."""
     rng = np.random.default_rng([4, seed])
@@ -176,10 +176,10 @@ def config4(seed=0, z_active=False, nsteps=50_000, nr=512, nz=2048):
     return cell
 
 
-def config5(seed=0, n_designs=64, nsteps=100_000, nr=512, nz=1024):
+def design_cells(seed=0, n_designs=64, nsteps=100_000, nr=512, nz=1024):
     """Batched adjoint: 64 designs of 512 x 1024, period 10 ms, dt = 0.5 us,
     100,000 steps; per-design amplitude, width, layer count and
-    thicknesses from the config-3 ranges."""
+    thicknesses from the design-sweep ranges."""
     rng = np.random.default_rng([5, seed])
     out = []
     for _ in range(n_designs):

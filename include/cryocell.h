@@ -219,6 +219,20 @@ cryo_status cryo_gradient(const cryo_plan *plan, const void *T0, int64_t nsteps,
                           const double *target, int64_t ckpt, void *ws, size_t ws_bytes,
                           double *J, double *grad, double *surf, void *stream);
 
+/* Gradients of n designs (the batched design loop): the same as n calls of
+ * cryo_gradient, design i with plans[i], T0[i], targets[i] (nsteps values),
+ * ws[i] of ws_bytes[i] bytes (cryo_gradient_workspace_bytes of plans[i]),
+ * results J[i], grad[i] (2 + 2 L_i values) and surf_out[i] (nullable array,
+ * nullable entries).  The designs run on n_streams library-created streams
+ * of default priority: every forward is enqueued, then each design's trace is
+ * read, then every backward sweep is enqueued, then the sums are reduced; the
+ * results equal those of the single calls bit for bit.  Synchronous; errors
+ * name the failing design. */
+cryo_status cryo_gradient_many(int32_t n, cryo_plan *const *plans, const void *const *T0,
+                               int64_t nsteps, const double *const *targets, int64_t ckpt,
+                               void *const *ws, const size_t *ws_bytes, int32_t n_streams,
+                               double *J, double *const *grad, double *const *surf_out);
+
 /* ---- Batched design sweeps ---------------------------------------------
  * Many independent cells (uneven grids, own dt, layers and pulse) stepped
  * together: instances are grouped by kernel shape; each step is one launch
@@ -231,7 +245,8 @@ cryo_status cryo_gradient(const cryo_plan *plan, const void *T0, int64_t nsteps,
 
 /* Create a batch of n instances.  `shapes` (nullable) gives per instance
  * (rows_per_lane, waves_per_line, lines_per_wave), e.g. from cryo_autotune;
- * otherwise each plan's default.  Errors name the failing instance. */
+ * otherwise each plan's default chunk shape with 4 lines per wave.  Errors
+ * name the failing instance. */
 cryo_status cryo_batch_create(int32_t n, const cryo_problem *probs, cryo_dtype dtype,
                               const int32_t *shapes, cryo_batch **out);
 void cryo_batch_destroy(cryo_batch *batch);

@@ -345,6 +345,42 @@ def gradient(cell, target, T0=None, nsteps=None, ckpt=0):
     return plan.gradient(target, T0=T0, nsteps=nsteps, ckpt=ckpt)
 
 
+def gradient_many(cells, targets, nsteps=None, ckpt=0, streams=4, T0s=None):
+    """Gradients of many designs in one call (FP64, the library's concurrent
+    design loop over `streams` HIP streams).  Returns (J [n], [grad_i],
+    [surface trace_i]); equal bit for bit to gradient() per design."""
+    torch = _torch()
+    n = len(cells)
+    N = int(cells[0]["nsteps"] if nsteps is None else nsteps)
+    plans, fields, wss, tg = [], [], [], []
+    for i, c in enumerate(cells):
+        plan = Plan(c, "f64")
+        sh = _gradient_shape(c)
+        if sh is not None:
+            plan.set_shape(*sh)
+        plans.append(plan)
+        fields.append(plan.init() if T0s is None or T0s[i] is None else plan.field_from(T0s[i]))
+        b = C.c_size_t()
+        check(lib().cryo_gradient_workspace_bytes(plan._h, N, int(ckpt), C.byref(b)))
+        wss.append(torch.empty(b.value, dtype=torch.uint8, device="cuda"))
+        t = np.ascontiguousarray(np.asarray(targets[i], dtype=np.float64)[:N])
+        if t.size < N:
+            raise ValueError("target %d needs nsteps values" % i)
+        tg.append(t)
+    vp, dp = C.c_void_p, C.POINTER(C.c_double)
+    grads = [np.zeros(2 + 2 * len(c["layers"])) for c in cells]
+    surfs = [np.zeros(N) for _ in cells]
+    J = np.zeros(n)
+    torch.cuda.synchronize()
+    check(lib().cryo_gradient_many(
+        n, (vp * n)(*[p._h for p in plans]), (vp * n)(*[_ptr(f) for f in fields]), N,
+        (dp * n)(*[t.ctypes.data_as(dp) for t in tg]), int(ckpt),
+        (vp * n)(*[_ptr(w) for w in wss]), (C.c_size_t * n)(*[w.numel() for w in wss]),
+        int(streams), J.ctypes.data_as(dp), (dp * n)(*[g.ctypes.data_as(dp) for g in grads]),
+        (dp * n)(*[x.ctypes.data_as(dp) for x in surfs])))
+    return J, grads, surfs
+
+
 def _make_solve():
     import torch
 

@@ -26,7 +26,7 @@ SYMBOLS = [
     "cryo_plan_shape", "cryo_plan_set_shape",
     "cryo_batch_create", "cryo_batch_destroy", "cryo_batch_offsets", "cryo_batch_shape",
     "cryo_batch_workspace_bytes", "cryo_batch_init", "cryo_batch_forward", "cryo_batch_poll",
-    "cryo_gradient_workspace_bytes", "cryo_gradient", "cryo_autotune",
+    "cryo_gradient_workspace_bytes", "cryo_gradient", "cryo_gradient_many", "cryo_autotune",
 ]
 
 
@@ -110,6 +110,10 @@ def lib():
         L.cryo_autotune.argtypes = [pp, C.c_int, C.c_int32, C.c_char_p, vp, i32p, dp]
         L.cryo_gradient_workspace_bytes.argtypes = [vp, i64, i64, C.POINTER(C.c_size_t)]
         L.cryo_gradient.argtypes = [vp, vp, i64, dp, i64, vp, C.c_size_t, dp, dp, dp, vp]
+        L.cryo_gradient_many.argtypes = [C.c_int32, C.POINTER(vp), C.POINTER(vp), i64,
+                                         C.POINTER(dp), i64, C.POINTER(vp),
+                                         C.POINTER(C.c_size_t), C.c_int32, dp, C.POINTER(dp),
+                                         C.POINTER(dp)]
         for name in SYMBOLS:
             if name not in ("cryo_last_error", "cryo_version", "cryo_plan_destroy",
                             "cryo_batch_destroy"):

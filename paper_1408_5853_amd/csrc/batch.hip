@@ -133,6 +133,10 @@ cryo_status cryo_batch_create(int32_t n, const cryo_problem *probs, cryo_dtype d
         cryo_status st = cryo_plan_create(&probs[i], dtype, &p);
         if (st == CRYO_OK && shapes)
             st = cryo_plan_set_shape(p, shapes[3 * i], shapes[3 * i + 1], shapes[3 * i + 2]);
+        else if (st == CRYO_OK)
+            // the instances fill the device together: longer line blocks
+            // amortise each block's start-up line
+            st = cryo_plan_set_shape(p, p->rpl, p->wpl, std::min(BATCH_LPW, p->nz - 2));
         if (st != CRYO_OK) {
             std::string m = "instance " + std::to_string(i) + ": " + cryo_last_error();
             if (p) cryo_plan_destroy(p);

@@ -80,23 +80,26 @@ static GradLayout grad_layout(const cryo_plan *p, int64_t N, int64_t ckpt) {
 
 }  // namespace cryo
 
-using namespace cryo;
+namespace cryo {
 
-extern "C" {
+// One gradient in phases, so that many can be in flight on several streams:
+// enqueue the forward with checkpoints, read the surface trace (J and the
+// adjoint seeds), enqueue the backward sweep, reduce the sums on the host.
+struct GradRun {
+    cryo_plan *p;
+    const void *T0;
+    int64_t N;
+    const double *target;
+    char *w;
+    GradLayout g;
+    hipStream_t s;
+    std::vector<double> S, cS;
+    double J;
+};
 
-cryo_status cryo_gradient_workspace_bytes(const cryo_plan *p, int64_t nsteps, int64_t ckpt,
-                                          size_t *bytes) {
-    if (!p || !bytes || nsteps < 1 || ckpt < 0) return fail(CRYO_ERR_ARG, "bad argument");
-    *bytes = grad_layout(p, nsteps, ckpt).total;
-    return CRYO_OK;
-}
-
-cryo_status cryo_gradient(const cryo_plan *pc, const void *T0, int64_t N, const double *target,
-                          int64_t ckpt, void *ws, size_t ws_bytes, double *J, double *grad,
-                          double *surf_out, void *stream) {
-    cryo_plan *p = const_cast<cryo_plan *>(pc);
-    if (!p || !T0 || N < 1 || !target || !J || !grad || ckpt < 0)
-        return fail(CRYO_ERR_ARG, "bad argument");
+static cryo_status grad_check(const cryo_plan *p, int64_t N, const double *target, int64_t ckpt,
+                              const void *T0, void *ws, size_t ws_bytes) {
+    if (!p || !T0 || N < 1 || !target || ckpt < 0) return fail(CRYO_ERR_ARG, "bad argument");
     if (p->dtype != CRYO_F64) return fail(CRYO_ERR_UNSUPPORTED, "the adjoint needs an FP64 plan");
     if (p->rpl > 8)
         return fail(CRYO_ERR_UNSUPPORTED, "the adjoint kernels take up to 8 rows per lane; set "
@@ -106,60 +109,81 @@ cryo_status cryo_gradient(const cryo_plan *pc, const void *T0, int64_t N, const 
         return fail(CRYO_ERR_WORKSPACE, "gradient workspace needs " + std::to_string(g.total) +
                                             " bytes");
     if (((uintptr_t)ws & 255) != 0) return fail(CRYO_ERR_WORKSPACE, "workspace must be 256-aligned");
+    return CRYO_OK;
+}
+
+static size_t field_f64(const cryo_plan *p) { return al256(8 * (size_t)p->nz * p->np); }
+
+// forward with checkpoints and the surface trace (enqueued on r.s)
+static cryo_status grad_forward(GradRun &r) {
+    cryo_plan *p = r.p;
     cryo_status st = ensure_device(p);
     if (st != CRYO_OK) return st;
-    hipStream_t s = (hipStream_t)stream;
-    char *w = (char *)ws;
+    const GradLayout &g = r.g;
+    char *w = r.w;
+    hipStream_t s = r.s;
     int *flag = (int *)(w + g.flag);
-    const size_t F = al256(8 * (size_t)p->nz * p->np);
-    auto ckp = [&](int64_t i) { return (double *)(w + g.ck + F * i); };
-    auto segp = [&](int64_t i) { return (double *)(w + g.seg + F * i); };
+    const size_t F = field_f64(p);
     double *surf = (double *)(w + g.surf);
     double *part = (double *)(w + g.part);
     const int G = step_grid(p);
-
-    // forward with checkpoints and the surface trace
-    st = launch_to_internal(p, T0, w + g.fwd_buf[0], flag, s);
+    st = launch_to_internal(p, r.T0, w + g.fwd_buf[0], flag, s);
     if (st != CRYO_OK) return st;
     int64_t done = 0;
-    for (int64_t k = 0; k < N; ++k) {
+    for (int64_t k = 0; k < r.N; ++k) {
         void *cur = w + g.fwd_buf[k & 1], *nxt = w + g.fwd_buf[(k + 1) & 1];
-        if (k % g.K == 0 &&
-            hipMemcpyAsync(ckp(k / g.K), cur, F, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        if (k % g.K == 0 && hipMemcpyAsync(w + g.ck + F * (k / g.K), cur, F,
+                                           hipMemcpyDeviceToDevice, s) != hipSuccess)
             return fail(CRYO_ERR_DEVICE, "checkpoint copy");
         const double X = p->pulse.amplitude * source_fraction(p->pulse, k);
         st = launch_step(p, cur, nxt, X, part + (size_t)(k % SURF_CHUNK) * G, flag, s);
         if (st != CRYO_OK) return st;
-        if ((k + 1) % SURF_CHUNK == 0 || k + 1 == N) {
+        if ((k + 1) % SURF_CHUNK == 0 || k + 1 == r.N) {
             st = launch_surf_reduce(p, part, (int)(k + 1 - done), surf + done, s);
             if (st != CRYO_OK) return st;
             done = k + 1;
         }
     }
-    std::vector<double> S(N);
-    if (hipMemcpyAsync(S.data(), surf, sizeof(double) * N, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-        return fail(CRYO_ERR_DEVICE, "surface trace copy");
-    double Jv = 0.0;
-    std::vector<double> cS(N + 1, 0.0);
-    for (int64_t n = 1; n <= N; ++n) {
-        const double dv = S[n - 1] - target[n - 1];
-        Jv += dv * dv;
-        cS[n] = 2.0 * dv;
-    }
-    if (surf_out) memcpy(surf_out, S.data(), sizeof(double) * N);
+    return CRYO_OK;
+}
 
-    // backward
+// wait for the forward, read the trace: J and the seeds dJ/dS_n
+static cryo_status grad_objective(GradRun &r) {
+    r.S.assign(r.N, 0.0);
+    if (hipMemcpyAsync(r.S.data(), r.w + r.g.surf, sizeof(double) * r.N, hipMemcpyDeviceToHost,
+                       r.s) != hipSuccess ||
+        hipStreamSynchronize(r.s) != hipSuccess)
+        return fail(CRYO_ERR_DEVICE, "surface trace copy");
+    r.J = 0.0;
+    r.cS.assign(r.N + 1, 0.0);
+    for (int64_t n = 1; n <= r.N; ++n) {
+        const double dv = r.S[n - 1] - r.target[n - 1];
+        r.J += dv * dv;
+        r.cS[n] = 2.0 * dv;
+    }
+    return CRYO_OK;
+}
+
+// segments backwards: restore the checkpoint, recompute, adjoint steps
+static cryo_status grad_backward(GradRun &r) {
+    cryo_plan *p = r.p;
+    const GradLayout &g = r.g;
+    char *w = r.w;
+    hipStream_t s = r.s;
+    int *flag = (int *)(w + g.flag);
+    const size_t F = field_f64(p);
+    auto ckp = [&](int64_t i) { return (double *)(w + g.ck + F * i); };
+    auto segp = [&](int64_t i) { return (double *)(w + g.seg + F * i); };
     const int ngrp = adj_groups(p);
     double *acc = (double *)(w + g.acc), *accg = (double *)(w + g.accg);
-    st = launch_zero(acc, 3 * (size_t)p->np * ngrp, s);
+    cryo_status st = launch_zero(acc, 3 * (size_t)p->np * ngrp, s);
     if (st == CRYO_OK) st = launch_zero(accg, 2 * (size_t)ngrp, s);
     double *lam[2] = {(double *)(w + g.lam[0]), (double *)(w + g.lam[1])};
-    if (st == CRYO_OK) st = launch_adj_init(p, lam[0], cS[N], s);
+    if (st == CRYO_OK) st = launch_adj_init(p, lam[0], r.cS[r.N], s);
     if (st != CRYO_OK) return st;
     int cur = 0;
     for (int64_t sg = g.nck - 1; sg >= 0; --sg) {
-        const int64_t a = sg * g.K, b = std::min<int64_t>(N, a + g.K);
+        const int64_t a = sg * g.K, b = std::min<int64_t>(r.N, a + g.K);
         if (hipMemcpyAsync(segp(0), ckp(sg), F, hipMemcpyDeviceToDevice, s) != hipSuccess)
             return fail(CRYO_ERR_DEVICE, "checkpoint restore");
         for (int64_t k = a; k < b; ++k) {
@@ -179,21 +203,32 @@ cryo_status cryo_gradient(const cryo_plan *pc, const void *T0, int64_t N, const 
             d.accg = accg;
             d.s = source_fraction(p->pulse, k);
             d.ds = source_fraction_dwidth(p->pulse, p->prob.dt, k);
-            d.cS = k >= 1 ? cS[k] : 0.0;
+            d.cS = k >= 1 ? r.cS[k] : 0.0;
             st = launch_adj(p, 1, d, flag, s);
             if (st == CRYO_OK) st = launch_adj(p, 2, d, flag, s);
             if (st != CRYO_OK) return st;
             cur ^= 1;
         }
     }
-    // row sums over line groups (fixed order), then the parameter gradient
+    return CRYO_OK;
+}
+
+// wait for the backward; row sums over line groups (fixed order), then the
+// parameter gradient
+static cryo_status grad_finish(GradRun &run, double *grad) {
+    cryo_plan *p = run.p;
+    const GradLayout &g = run.g;
+    char *w = run.w;
+    hipStream_t s = run.s;
+    const int ngrp = adj_groups(p);
+    const double *acc = (const double *)(w + g.acc), *accg = (const double *)(w + g.accg);
     std::vector<double> hacc(3 * (size_t)p->np * ngrp), hg(2 * (size_t)ngrp);
     int hflag = 0;
     if (hipMemcpyAsync(hacc.data(), acc, sizeof(double) * hacc.size(), hipMemcpyDeviceToHost, s) !=
             hipSuccess ||
         hipMemcpyAsync(hg.data(), accg, sizeof(double) * hg.size(), hipMemcpyDeviceToHost, s) !=
             hipSuccess ||
-        hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&hflag, w + g.flag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return fail(CRYO_ERR_DEVICE, "gradient sums copy");
     if (hflag) return fail(CRYO_ERR_NONFINITE, "non-finite or out-of-range temperature produced");
@@ -248,7 +283,6 @@ cryo_status cryo_gradient(const cryo_plan *pc, const void *T0, int64_t N, const 
                          SE[i] * dh[(size_t)i * L + l] / h[i];
         }
     }
-    *J = Jv;
     grad[0] = gQ;
     grad[1] = gW;
     for (int l = 0; l < L; ++l) {
@@ -256,6 +290,93 @@ cryo_status cryo_gradient(const cryo_plan *pc, const void *T0, int64_t N, const 
         grad[2 + L + l] = gs[l];
     }
     return CRYO_OK;
+}
+
+}  // namespace cryo
+
+using namespace cryo;
+
+extern "C" {
+
+cryo_status cryo_gradient_workspace_bytes(const cryo_plan *p, int64_t nsteps, int64_t ckpt,
+                                          size_t *bytes) {
+    if (!p || !bytes || nsteps < 1 || ckpt < 0) return fail(CRYO_ERR_ARG, "bad argument");
+    *bytes = grad_layout(p, nsteps, ckpt).total;
+    return CRYO_OK;
+}
+
+cryo_status cryo_gradient(const cryo_plan *pc, const void *T0, int64_t N, const double *target,
+                          int64_t ckpt, void *ws, size_t ws_bytes, double *J, double *grad,
+                          double *surf_out, void *stream) {
+    if (!J || !grad) return fail(CRYO_ERR_ARG, "bad argument");
+    cryo_status st = grad_check(pc, N, target, ckpt, T0, ws, ws_bytes);
+    if (st != CRYO_OK) return st;
+    GradRun r;
+    r.p = const_cast<cryo_plan *>(pc);
+    r.T0 = T0;
+    r.N = N;
+    r.target = target;
+    r.w = (char *)ws;
+    r.g = grad_layout(pc, N, ckpt);
+    r.s = (hipStream_t)stream;
+    st = grad_forward(r);
+    if (st == CRYO_OK) st = grad_objective(r);
+    if (st == CRYO_OK) st = grad_backward(r);
+    if (st == CRYO_OK) st = grad_finish(r, grad);
+    if (st != CRYO_OK) return st;
+    *J = r.J;
+    if (surf_out) memcpy(surf_out, r.S.data(), sizeof(double) * N);
+    return CRYO_OK;
+}
+
+cryo_status cryo_gradient_many(int32_t n, cryo_plan *const *plans, const void *const *T0,
+                               int64_t N, const double *const *targets, int64_t ckpt,
+                               void *const *ws, const size_t *ws_bytes, int32_t n_streams,
+                               double *J, double *const *grad, double *const *surf_out) {
+    if (n < 1 || !plans || !T0 || !targets || !ws || !ws_bytes || !J || !grad || n_streams < 1)
+        return fail(CRYO_ERR_ARG, "bad argument");
+    for (int i = 0; i < n; ++i) {
+        cryo_status st = grad_check(plans[i], N, targets[i], ckpt, T0[i], ws[i], ws_bytes[i]);
+        if (st != CRYO_OK) return fail(st, "design " + std::to_string(i) + ": " + cryo_last_error());
+        if (!grad[i]) return fail(CRYO_ERR_ARG, "design " + std::to_string(i) + ": null grad");
+    }
+    const int ns = std::min<int>(n_streams, n);
+    std::vector<hipStream_t> streams(ns, nullptr);
+    cryo_status st = CRYO_OK;
+    for (int k = 0; k < ns && st == CRYO_OK; ++k)
+        if (hipStreamCreateWithFlags(&streams[k], hipStreamNonBlocking) != hipSuccess)
+            st = fail(CRYO_ERR_DEVICE, "stream creation");
+    std::vector<GradRun> runs(n);
+    for (int i = 0; i < n && st == CRYO_OK; ++i) {
+        GradRun &r = runs[i];
+        r.p = plans[i];
+        r.T0 = T0[i];
+        r.N = N;
+        r.target = targets[i];
+        r.w = (char *)ws[i];
+        r.g = grad_layout(plans[i], N, ckpt);
+        r.s = streams[i % ns];
+    }
+    // all forwards in flight, then each trace as it completes, then all
+    // backward sweeps, then the reductions
+    for (int i = 0; i < n && st == CRYO_OK; ++i) st = grad_forward(runs[i]);
+    for (int i = 0; i < n && st == CRYO_OK; ++i) st = grad_objective(runs[i]);
+    for (int i = 0; i < n && st == CRYO_OK; ++i) st = grad_backward(runs[i]);
+    for (int i = 0; i < n && st == CRYO_OK; ++i) {
+        st = grad_finish(runs[i], grad[i]);
+        if (st == CRYO_OK) {
+            J[i] = runs[i].J;
+            if (surf_out && surf_out[i]) memcpy(surf_out[i], runs[i].S.data(), sizeof(double) * N);
+        } else {
+            st = fail(st, "design " + std::to_string(i) + ": " + cryo_last_error());
+        }
+    }
+    for (hipStream_t x : streams)
+        if (x) {
+            (void)hipStreamSynchronize(x);
+            (void)hipStreamDestroy(x);
+        }
+    return st;
 }
 
 }  // extern "C"

@@ -16,6 +16,7 @@ constexpr int MAX_LAYERS = 16;
 constexpr int MAX_NR = 2048;
 constexpr int SURF_CHUNK = 1024;    // steps per surface reduction round
 constexpr int STEP_WAVES_HOST = 8;  // waves per stepping workgroup
+constexpr int BATCH_LPW = 4;        // default lines per wave of batch instances
 
 // Row classes of one radial line (eq. (13), eq. (18), eq. (15), padding).
 enum RowKind : uint32_t { K_PAD = 0, K_LO = 1, K_HI = 2, K_CAP = 3, K_IFACE = 4 };

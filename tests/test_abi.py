@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_validation_rejects_bad_descriptors():
-    good = cellgen.config1(0)
+    good = cellgen.small_cell(0)
     P.validate(good)
     bad = []
     c = cellgen.scaled(good); c["layers"] = [dict(l) for l in c["layers"]]
@@ -50,7 +50,7 @@ def test_validation_rejects_bad_descriptors():
 
 
 def test_unstable_dt_is_refused():
-    c = cellgen.config1(0)
+    c = cellgen.small_cell(0)
     dmax = P.stability_dt_max(c, 28.0)
     assert c["dt"] <= dmax
     P.Plan(cellgen.scaled(c, dt=0.999 * dmax))
@@ -61,14 +61,14 @@ def test_unstable_dt_is_refused():
 
 def test_stability_bound_formula():
     # eq. (21): tau <= eta^2/2 * min rho c / lambda, here at T = tref
-    c = cellgen.config1(1)
+    c = cellgen.small_cell(1)
     eta = c["height"] / (c["nz"] - 1)
     want = min(l["rho"] * l["c0"] / (l["k_scale"] * l["k0"]) for l in c["layers"])
     assert P.stability_dt_max(c, 30.0) == pytest.approx(0.5 * eta * eta * want, rel=1e-14)
 
 
 def test_nr_above_limit_unsupported():
-    c = cellgen.config1(0)
+    c = cellgen.small_cell(0)
     c = cellgen.scaled(c, nr=4097)
     c["layers"] = [dict(l) for l in c["layers"]]
     c["layers"][0]["intervals"] += 4097 - 64
@@ -77,8 +77,8 @@ def test_nr_above_limit_unsupported():
     assert e.value.status == 6
 
 
-@pytest.mark.parametrize("make", [lambda: cellgen.config1(0), lambda: cellgen.config2(0),
-                                  lambda: cellgen.config3(0, 3)[2],
+@pytest.mark.parametrize("make", [lambda: cellgen.small_cell(0), lambda: cellgen.device_cell(0),
+                                  lambda: cellgen.sweep_cells(0, 3)[2],
                                   lambda: cellgen.tiny(1)])
 def test_library_grid_and_schedule_match_oracle(make):
     c = make()
@@ -91,6 +91,6 @@ def test_library_grid_and_schedule_match_oracle(make):
 
 
 def test_workspace_grows_with_grid():
-    a = P.Plan(cellgen.config1(0)).workspace_bytes(100)
-    b = P.Plan(cellgen.config2(0, nz=64)).workspace_bytes(100)
+    a = P.Plan(cellgen.small_cell(0)).workspace_bytes(100)
+    b = P.Plan(cellgen.device_cell(0, nz=64)).workspace_bytes(100)
     assert 0 < a < b

@@ -6,18 +6,18 @@ import cellgen
 
 
 def test_seeded_and_reproducible():
-    assert cellgen.config1(3) == cellgen.config1(3)
-    assert cellgen.config1(3) != cellgen.config1(4)
+    assert cellgen.small_cell(3) == cellgen.small_cell(3)
+    assert cellgen.small_cell(3) != cellgen.small_cell(4)
 
 
 def test_intervals_fill_the_radial_grid():
-    for c in [cellgen.config1(0), cellgen.config2(0), cellgen.config4(0)] + cellgen.config3(0, 16):
+    for c in [cellgen.small_cell(0), cellgen.device_cell(0), cellgen.adjoint_cell(0)] + cellgen.sweep_cells(0, 16):
         ints = [l["intervals"] for l in c["layers"]]
         assert sum(ints) == c["nr"] - 1 and min(ints) >= 10
 
 
 def test_stability_cap_respected_at_coldest_temperature():
-    for c in [cellgen.config1(s) for s in range(5)] + cellgen.config3(0, 32):
+    for c in [cellgen.small_cell(s) for s in range(5)] + cellgen.sweep_cells(0, 32):
         eta = c["height"] / (4096 - 1 if c["nr"] == 1024 else c["nz"] - 1)
         for l in c["layers"]:
             x = cellgen.T0 / l["tref"]
@@ -25,13 +25,13 @@ def test_stability_cap_respected_at_coldest_temperature():
             assert c["dt"] <= eta * eta / (2 * kappa) * (1 + 1e-12)
 
 
-def test_config2_reduced_axis_keeps_materials():
-    a, b = cellgen.config2(0), cellgen.config2(0, nz=4)
+def test_device_cell_reduced_axis_keeps_materials():
+    a, b = cellgen.device_cell(0), cellgen.device_cell(0, nz=4)
     assert a["layers"] == b["layers"] and b["nz"] == 4
 
 
 def test_tracking_target_shape_and_levels():
-    c = cellgen.config4(0)
+    c = cellgen.adjoint_cell(0)
     t = cellgen.tracking_target(c, 60_000)
     assert t.shape == (60_000,) and set(np.unique(t)) == {28.0, 42.0}
     assert t[:4999].min() == 42.0 and t[5000:49_999].max() == 28.0

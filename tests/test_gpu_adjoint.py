@@ -99,7 +99,7 @@ def test_adjoint_workload_full_size_against_reduced_oracle():
     # 512 x 2048 nodes, 6 layers, 50,000 steps; the cell is exactly
     # z-invariant, so J and its gradient equal those of the 4-line reduction
     import paper_1408_5853_amd as P
-    c = cellgen.config4(0)
+    c = cellgen.adjoint_cell(0)
     n = c["nsteps"]
     tgt = cellgen.tracking_target(c, n)
     say("case adjoint workload 512x2048, %d steps" % n)

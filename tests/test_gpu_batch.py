@@ -29,7 +29,7 @@ def _run_batch(cells, n, dtype, k0=0):
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("n", [5, 64, 77])
 def test_batch_bitwise_equals_single_runs(dtype, n):
-    cells = [cellgen.with_nz(c, 40) for c in cellgen.config3(0, 6)]
+    cells = [cellgen.with_nz(c, 40) for c in cellgen.sweep_cells(0, 6)]
     say("case batch of %d, %s, %d steps" % (len(cells), dtype, n))
     got, b = _run_batch(cells, n, dtype, k0=11)
     for i, c in enumerate(cells):
@@ -38,7 +38,7 @@ def test_batch_bitwise_equals_single_runs(dtype, n):
 
 
 def _extremes(k=2):
-    cells = cellgen.config3(0, 256)
+    cells = cellgen.sweep_cells(0, 256)
     order = sorted(range(len(cells)), key=lambda i: cells[i]["nr"] * cells[i]["nz"])
     return [cells[i] for i in order[:k] + order[-k:]]
 

@@ -1,0 +1,93 @@
+"""The concurrent design loop (many gradients in one call) against single
+gradient calls (bit for bit), against the oracle adjoint on small designs and,
+at full size (64 designs' shape: 512 x 1024 nodes), against the oracle on
+the exactly z-invariant reduction; and the first Adam step of the design loop
+descends."""
+import numpy as np
+import pytest
+
+import cellgen
+import oracle
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+def _norm_err(g, ref, theta):
+    P = np.abs(theta)
+    scale = np.max(np.abs(ref * P))
+    return float(np.max(np.abs(g - ref) * P / scale))
+
+
+def _small_designs(n, nsteps):
+    out = []
+    for i in range(n):
+        c = cellgen.tiny(20 + i, nr=40 + 57 * i, nz=5 + (i % 3), n_layers=3 + (i % 3),
+                         nsteps=nsteps, z_active=bool(i % 2), dt=2e-6, amplitude=3e9 + 5e8 * i,
+                         heater=2)
+        out.append(c)
+    return out
+
+
+def _targets(cells, n):
+    return [cellgen.tracking_target(c, n) for c in cells]
+
+
+def test_gradient_many_equals_single_calls_bitwise():
+    import paper_1408_5853_amd as P
+    cells = _small_designs(5, 24)
+    tg = _targets(cells, 24)
+    say("case gradient_many 5 designs, 3 streams")
+    J, grads, surfs = P.gradient_many(cells, tg, ckpt=5, streams=3)
+    for i, c in enumerate(cells):
+        Ji, gi, Si = P.gradient(c, tg[i], ckpt=5)
+        assert J[i] == Ji
+        assert np.array_equal(grads[i], gi)
+        assert np.array_equal(surfs[i], Si)
+
+
+@pytest.mark.parametrize("streams", [1, 4])
+def test_gradient_many_matches_oracle_adjoint(streams):
+    import paper_1408_5853_amd as P
+    cells = _small_designs(3, 20)
+    tg = _targets(cells, 20)
+    say("case gradient_many vs oracle, streams %d" % streams)
+    J, grads, _ = P.gradient_many(cells, tg, streams=streams)
+    for i, c in enumerate(cells):
+        Jo, go, _ = oracle.gradient(c, tg[i])
+        assert J[i] == pytest.approx(Jo, rel=1e-9)
+        e = _norm_err(grads[i], go, P.params_of(c))
+        say("  design %d normalised gradient error %.3e" % (i, e))
+        assert e < 1e-8
+
+
+def test_design_cells_full_size_against_reduced_oracle():
+    # two of the 64 designs at full size (512 x 1024 nodes), 400 steps; the
+    # designs are exactly z-invariant, so J and its gradient equal those of
+    # the 4-line reduction
+    import paper_1408_5853_amd as P
+    cells = cellgen.design_cells(0, n_designs=2, nsteps=400)
+    n = 400
+    tg = _targets(cells, n)
+    say("case design cells 2 x 512x1024, %d steps" % n)
+    J, grads, _ = P.gradient_many(cells, tg, streams=2)
+    for i, c in enumerate(cells):
+        Jo, go, _ = oracle.gradient(cellgen.with_nz(c, 4), tg[i])
+        e = _norm_err(grads[i], go, P.params_of(c))
+        say("  design %d J gpu %.12e oracle %.12e, gradient error %.3e" % (i, J[i], Jo, e))
+        assert J[i] == pytest.approx(Jo, rel=1e-9)
+        assert e < 1e-6
+
+
+def test_design_adam_first_step_descends():
+    from paper_1408_5853_amd.design import design_adam, design_params
+    cells = _small_designs(3, 30)
+    tg = [t + 3.0 for t in _targets(cells, 30)]          # reachable by more heat
+    say("case design loop, 1 Adam step, lr 0.01")
+    new, hist = design_adam(cells, tg, iters=1, lr=0.01, streams=2)
+    assert hist.shape == (2, 3)
+    for i in range(3):
+        say("  design %d J %.6e -> %.6e" % (i, hist[0, i], hist[1, i]))
+        assert hist[1, i] < hist[0, i]
+        ratio = design_params(new[i]) / design_params(cells[i])
+        assert np.all(np.abs(np.log(ratio)) <= 0.0101)   # Adam steps at most lr

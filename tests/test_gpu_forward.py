@@ -28,18 +28,18 @@ def _check64(cell, nsteps, T0=None, k0=0):
     return Tg, To
 
 
-def test_config1_full_run_f64():
-    _check64(cellgen.config1(0), 10_000)
+def test_small_cell_full_run_f64():
+    _check64(cellgen.small_cell(0), 10_000)
 
 
-def test_config1_z_active_twin_full_run_f64():
-    Tg, To = _check64(cellgen.config1(0, z_active=True), 10_000)
+def test_small_cell_z_active_twin_full_run_f64():
+    Tg, To = _check64(cellgen.small_cell(0, z_active=True), 10_000)
     assert np.ptp(To[:, -1]) > 1e-3      # the axial half is exercised
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3, 4])
-def test_config1_seeds_f64(seed):
-    _check64(cellgen.config1(seed, z_active=seed % 2 == 0), 3000)
+def test_small_cell_seeds_f64(seed):
+    _check64(cellgen.small_cell(seed, z_active=seed % 2 == 0), 3000)
 
 
 @pytest.mark.parametrize("nr,nz", [(5, 3), (64, 4), (100, 7), (129, 5), (300, 9), (631, 6),
@@ -67,20 +67,20 @@ def test_boundary_combinations_f64(bc):
     _check64(c, 60, T0=T0)
 
 
-def test_config2_reduced_axis_f64():
-    # the as-written config 2 is exactly z-invariant, so its oracle runs at
+def test_device_cell_reduced_axis_f64():
+    # the as-written device cell is exactly z-invariant, so its oracle runs at
     # nz = 4 with the same radial grid, dt and steps
-    c = cellgen.config2(0, nz=4)
+    c = cellgen.device_cell(0, nz=4)
     _check64(c, 3000)
 
 
-def test_config2_full_size_z_invariant_and_matches_reduced():
-    c = cellgen.config2(0)
+def test_device_cell_full_size_z_invariant_and_matches_reduced():
+    c = cellgen.device_cell(0)
     n = 200
-    say("case config2 full size, %d steps" % n)
+    say("case device_cell full size, %d steps" % n)
     Tg, Sg = run_gpu(c, n)
     assert np.all(Tg == Tg[1][None, :]), "lines differ: a race or halo error"
-    To, So = oracle.forward(cellgen.config2(0, nz=4), nsteps=n, surf=True)
+    To, So = oracle.forward(cellgen.device_cell(0, nz=4), nsteps=n, surf=True)
     assert rel_err(Tg[1], To[1]) < F64_TOL
     assert rel_err(Sg, So) < F64_TOL
 
@@ -91,7 +91,7 @@ def test_paper_shape_prefix_f64():
 
 
 def test_restart_is_bitwise_equal():
-    c = cellgen.config1(0, z_active=True)
+    c = cellgen.small_cell(0, z_active=True)
     T1, S1 = run_gpu(c, 700)
     Ta, Sa = run_gpu(c, 300)
     Tb, Sb = run_gpu(c, 400, T0=Ta, k0=300)
@@ -100,14 +100,14 @@ def test_restart_is_bitwise_equal():
 
 
 def test_run_to_run_bitwise_determinism():
-    c = cellgen.config1(3, z_active=True)
+    c = cellgen.small_cell(3, z_active=True)
     a = run_gpu(c, 500)
     b = run_gpu(c, 500)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
 def test_zero_steps_is_identity():
-    c = cellgen.config1(0)
+    c = cellgen.small_cell(0)
     rng = np.random.default_rng(0)
     T0 = 28 + rng.uniform(0, 1, size=(c["nz"], c["nr"]))
     T, _ = run_gpu(c, 0, T0=T0, surf=False)
@@ -116,7 +116,7 @@ def test_zero_steps_is_identity():
 
 def test_nonfinite_input_is_reported():
     import paper_1408_5853_amd as P
-    c = cellgen.config1(0)
+    c = cellgen.small_cell(0)
     T0 = np.full((c["nz"], c["nr"]), 28.0)
     T0[5, 7] = np.nan
     with pytest.raises(P.CryoError) as e:
@@ -124,9 +124,9 @@ def test_nonfinite_input_is_reported():
     assert e.value.status == 4
 
 
-@pytest.mark.parametrize("make,n", [(lambda: cellgen.config1(0), 10_000),
-                                    (lambda: cellgen.config1(0, z_active=True), 10_000),
-                                    (lambda: cellgen.config2(0, nz=4), 20_000)])
+@pytest.mark.parametrize("make,n", [(lambda: cellgen.small_cell(0), 10_000),
+                                    (lambda: cellgen.small_cell(0, z_active=True), 10_000),
+                                    (lambda: cellgen.device_cell(0, nz=4), 20_000)])
 def test_f32_within_1e4_kelvin(make, n):
     c = make()
     say("case f32 nr=%d nz=%d steps=%d" % (c["nr"], c["nz"], n))

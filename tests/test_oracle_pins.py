@@ -71,7 +71,7 @@ def test_schedule_exact_fractions(dt, t_on, w, P):
 def test_schedule_workload_edges_snap():
     # 1 ms pulse every 10 ms at dt = 1 us: exactly 1000 on-steps per period,
     # despite 1e-3/1e-6 not being exact in binary
-    c = cellgen.config1(0)
+    c = cellgen.small_cell(0)
     s = np.array([oracle.source_fraction(c, k) for k in range(20_500)])
     want = np.zeros_like(s)
     for n0 in (0, 10_000, 20_000):
@@ -376,14 +376,14 @@ def test_heat_balance_exact_single_layer_insulated():
 def test_zero_source_keeps_uniform_field():
     # with no source a uniform field is a fixed point of eq. (8); only the
     # rounding of the row sums moves it
-    c = cellgen.config1(1)
+    c = cellgen.small_cell(1)
     c["amplitude"] = 0.0
     T = oracle.forward(c, nsteps=3000)
     assert np.max(np.abs(T - 28.0)) < 1e-11
 
 
 def test_as_written_config_is_exactly_z_invariant():
-    c = cellgen.config1(2)
+    c = cellgen.small_cell(2)
     T = oracle.forward(c, nsteps=1500)
     assert np.all(T == T[1][None, :])
     assert T.max() > 28.0
@@ -393,7 +393,7 @@ def test_as_written_config_is_exactly_z_invariant():
 
 
 def test_maximum_principle_and_heating():
-    c = cellgen.config1(3, z_active=True)
+    c = cellgen.small_cell(3, z_active=True)
     T, S = oracle.forward(c, nsteps=3000, surf=True)
     assert T.min() > 28.0 - 1e-9
     assert np.all(np.diff(S[:900]) >= -1e-12)     # heating phase: surface rises
