@@ -22,9 +22,11 @@ def _norm_err(g, ref, theta):
 def _small_designs(n, nsteps):
     out = []
     for i in range(n):
-        c = cellgen.tiny(20 + i, nr=40 + 57 * i, nz=5 + (i % 3), n_layers=3 + (i % 3),
+        L = 3 + (i % 3)
+        # heater in the outer layer: the surface sees the pulse within the run
+        c = cellgen.tiny(20 + i, nr=40 + 57 * i, nz=5 + (i % 3), n_layers=L,
                          nsteps=nsteps, z_active=bool(i % 2), dt=2e-6, amplitude=3e9 + 5e8 * i,
-                         heater=2)
+                         heater=L - 1)
         out.append(c)
     return out
 
@@ -64,9 +66,12 @@ def test_gradient_many_matches_oracle_adjoint(streams):
 def test_design_cells_full_size_against_reduced_oracle():
     # two of the 64 designs at full size (512 x 1024 nodes), 400 steps; the
     # designs are exactly z-invariant, so J and its gradient equal those of
-    # the 4-line reduction
+    # the 4-line reduction.  Designs 0 and 9: their surfaces respond within
+    # 400 steps (in several others the pulse has not reached the surface yet
+    # and the gradient is zero up to rounding)
     import paper_1408_5853_amd as P
-    cells = cellgen.design_cells(0, n_designs=2, nsteps=400)
+    allc = cellgen.design_cells(0, n_designs=10, nsteps=400)
+    cells = [allc[0], allc[9]]
     n = 400
     tg = _targets(cells, n)
     say("case design cells 2 x 512x1024, %d steps" % n)
