@@ -78,7 +78,6 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj1(StepArgs<double> a, Ad
     const size_t LS = a.np;
     const int qW = lg > 0 ? (RPL - 1) * NL + lg - 1 : 0;
     const int qE = lg < NL - 1 ? lg + 1 : (RPL - 1) * NL + lg;
-    const double *lrow = law.lrow;
     int bad = 0;
     double accW[RPL], accE[RPL], gS = 0.0, gD = 0.0;
 #pragma unroll
@@ -103,7 +102,7 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj1(StepArgs<double> a, Ad
             const int le = (sinf[qW] >> 6) & 63;
             const double tf = 0.5 * (TwF + T[0]);
             lamW = law.law(le, tf, bad);
-            dlamW = lrow[le * POW_LROW + POW_NE] * lamW / tf;
+            dlamW = law.expo(le) * lamW / tf;
         }
         double a0 = 0, b0 = 1, c0 = 0, d0 = 0, ccm2 = 0, bbm1 = 1, ccm1 = 0, mum1 = 0;
         double al[RPL], ga[RPL], de[RPL];
@@ -119,7 +118,7 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj1(StepArgs<double> a, Ad
             const int l3 = (inf_r >> 18) & 63, lc = (inf_r >> 24) & 63;
             const double tf = 0.5 * (t + Te);
             const double lamE = law.law(le, tf, bad);
-            const double dlamE = lrow[le * POW_LROW + POW_NE] * lamE / tf;
+            const double dlamE = law.expo(le) * lamE / tf;
             // interface: the two layer laws at the node; boundary rows: unit/zero
             double l2v = l2 == law_unit(a.laws.L) ? 1.0 : 0.0, l3v = l3 == law_unit(a.laws.L) ? 1.0 : 0.0;
             double dl2 = 0.0, dl3 = 0.0;
@@ -128,8 +127,8 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj1(StepArgs<double> a, Ad
                 if (ifc) {
                     l2v = va;
                     l3v = vb;
-                    dl2 = lrow[l2 * POW_LROW + POW_NE] * va / t;
-                    dl3 = lrow[l3 * POW_LROW + POW_NE] * vb / t;
+                    dl2 = law.expo(l2) * va / t;
+                    dl3 = law.expo(l3) * vb / t;
                 }
             }
             const double rc = a.laws.cube ? law.cube(lc, t) : law.law(lc, t, bad);
@@ -204,7 +203,7 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj1(StepArgs<double> a, Ad
                     drc = 3.0 * law.ck[lc] * t * t;
                 } else {
                     rc = law.law(lc, t, bad);
-                    drc = lrow[lc * POW_LROW + POW_NE] * rc / t;
+                    drc = law.expo(lc) * rc / t;
                 }
                 double self = 0.0;
                 if (cap || ifc) self = fwT[r] * Dw[r] + feT[r] * De[r] + drc * (X[r] - t) - rc;
@@ -277,7 +276,6 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj2(StepArgs<double> a, Ad
     const int j0 = 1 + gidx * a.lpw;
     const int j1 = min(j0 + a.lpw, a.nz - 1);
     const size_t LS = a.np;
-    const double *lrow = law.lrow;
     int bad = 0;
     double accZ[RPL];
 #pragma unroll
@@ -300,7 +298,7 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj2(StepArgs<double> a, Ad
             if (cap) {
                 const double fn = 0.5 * (t + tn), fs = 0.5 * (t + ts);
                 const double ln = law.law(lz, fn, bad), ls = law.law(lz, fs, bad);
-                const double e = lrow[lz * POW_LROW + POW_NE];
+                const double e = law.expo(lz);
                 const double dn = tn - t, ds = t - ts;
                 dFlN = 0.5 * e * ln / fn * dn - ln;     // d F_N / d T_j
                 dFuS = 0.5 * e * ls / fs * ds + ls;     // d F_S / d T_j

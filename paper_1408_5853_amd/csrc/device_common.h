@@ -41,29 +41,27 @@ struct LawLds;
 
 template <>
 struct LawLds<double> {
-    const double *erow;     // exponent rows: {m0^e, 2/m0}[NM]
-    const double *lrow;     // law rows: K 2^(x e) [NE], e, binomials
-    int L;                  // layers (law ids -> exponent rows)
+    const double *blk;      // law blocks (POW_BLK doubles per law id)
     const double *ck, *ca;  // cube path: K T^3 + A
     // T on the table range [2^POW_EMIN, 2^(POW_EMIN+POW_NE)) K
     static __device__ inline bool in_range(double x) {
         return x >= POW_TLO && x < POW_THI;
     }
+    __device__ inline double expo(int id) const { return blk[id * POW_BLK + POW_BE]; }
     // K[id] T^e[id]; T off the table range (or not finite) is clamped to its
     // edge binade, so callers check the range themselves (in_range)
     __device__ inline double lawc(int id, double x) const {
         const double mh = __builtin_amdgcn_frexp_mant(x);          // x = mh 2^xe, mh in [1/2, 1)
         const int xe = __builtin_amdgcn_frexp_exp(x);
-        const int xc = min(max(xe - 1 - POW_EMIN, 0), POW_NE - 1);
+        const int xc = min(max(xe, POW_EMIN + 1), POW_EMIN + POW_NE) - (POW_EMIN + 1);
         const int hi = (int)(__double_as_longlong(x) >> 32);
         const int jm = (hi >> (20 - POW_MBITS)) & (POW_NM - 1);
-        const double *Lr = lrow + id * POW_LROW;
-        const double2 ee = *(const double2 *)(Lr + POW_NE);     // e
-        const double2 c23 = *(const double2 *)(Lr + POW_NE + 2);
-        const double2 c45 = *(const double2 *)(Lr + POW_NE + 4);
-        const double2 c67 = *(const double2 *)(Lr + POW_NE + 6);
-        // exponent row from the law id (no dependent table read)
-        const double2 mm = *(const double2 *)(erow + exp_row(id, L) * POW_EROW + 2 * jm);
+        const double *B = blk + id * POW_BLK;
+        const double2 ee = *(const double2 *)(B + POW_BE);      // e
+        const double2 c23 = *(const double2 *)(B + POW_BE + 2);
+        const double2 c45 = *(const double2 *)(B + POW_BE + 4);
+        const double2 c67 = *(const double2 *)(B + POW_BE + 6);
+        const double2 mm = *(const double2 *)(B + 2 * jm);
         const double u = fma(mh, mm.y, -1.0);                   // m / m0 - 1
         // (1 + u)^e, |u| <= 2^-(POW_MBITS+1)
         double s = fma(c67.y, u, c67.x);
@@ -73,7 +71,7 @@ struct LawLds<double> {
         s = fma(s, u, c23.x);
         s = fma(s, u, ee.x);
         s = fma(s, u, 1.0);
-        return Lr[xc] * mm.x * s;
+        return B[POW_BX + xc] * mm.x * s;
     }
     // as lawc, and flags an argument off the table range
     __device__ inline double law(int id, double x, int &bad) const {
@@ -344,18 +342,24 @@ template <typename R>
 __host__ __device__ inline size_t ring_slot_elems(int rpl) {
     return (size_t)rpl * (Pair<R>::on ? 2 : 1) * WAVE;
 }
-// the ring is used while a slot stays within 4 KiB (LDS budget)
+// The ring serves FP32 pairs while a slot stays within 4 KiB; FP64 spends
+// that LDS on its law tables instead (its prefetch gained nothing measurable).
 template <typename R>
 __host__ __device__ constexpr bool ring_used(int rpl) {
-    return rpl * (Pair<R>::on ? 2 : 1) * WAVE * sizeof(R) <= 4096;
+    return sizeof(R) == 4 && rpl * 2 * WAVE * sizeof(R) <= 4096;
 }
-// without the ring, FP64 keeps the carried axial fluxes in its place
+// FP64 with 16 rows per lane keeps the carried axial fluxes in LDS (registers)
+template <typename R>
+__host__ __device__ constexpr bool fs_in_lds(int rpl) {
+    return sizeof(R) == 8 && rpl >= 16;
+}
+// the ring, or the FP64 carried fluxes, after the tables
 template <typename R>
 __host__ __device__ inline size_t step_lds_bytes(int L, int np, int rpl = 0) {
     size_t extra = 0;
     if (ring_used<R>(rpl))
         extra = 2 * (size_t)STEP_WAVES * ring_slot_elems<R>(rpl);
-    else if (sizeof(R) == 8)
+    else if (fs_in_lds<R>(rpl))
         extra = (size_t)STEP_WAVES * rpl * WAVE;
     return ring_lds_offset<R>(L, np) + extra * sizeof(R);
 }
@@ -369,10 +373,8 @@ __device__ inline LawLds<R> stage_laws(const StepArgs<R> &a, unsigned char *smem
         double *d = (double *)smem;
         const int nb = (int)pow_blob_doubles(L);
         for (int i = t; i < nb; i += nt) d[i] = a.pow_blob[i];
-        v.erow = d;
-        v.L = L;
-        v.lrow = d + (size_t)(2 * L + 1) * POW_EROW;
-        v.ck = v.lrow + (size_t)nlaw * POW_LROW;
+        v.blk = d;
+        v.ck = d + (size_t)nlaw * POW_BLK;
         v.ca = v.ck + nlaw;
     } else {
         float *f = (float *)smem;

@@ -65,13 +65,12 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
     const int qE = lg < NL - 1 ? lg + 1 : (RPL - 1) * NL + lg;
     double sv = 0.0;
     int bad = 0;
-    // Line ring: two LDS slots per wave hold the wave's part of the next line
-    // and of the line after it, loaded straight from memory into LDS (no
-    // registers in flight) one iteration ahead.  Slot layout: element
-    // (row r, plane p, lane) at (r NPL + p) WAVE + lane.  Groups past the last
+    // Line ring (FP32 pairs, ring_used): two LDS slots per wave hold the wave's
+    // part of the next line and of the line after it, loaded straight from
+    // memory into LDS (no registers in flight) one iteration ahead.  Slot
+    // layout: element (row r, plane p, lane) at (r NPL + p) WAVE + lane.  Other
+    // cases read the next line from memory directly.  Groups past the last
     // line march on clamped line indices (real lines, results discarded).
-    // Shapes whose slots would not fit (ring_used) read the lines from memory
-    // directly instead.
     constexpr int SLOT = RPL * NPL * WAVE;
     constexpr bool RING = ring_used<R>(RPL);
     constexpr int EPL = 16 / (int)sizeof(R);              // elements per lane per load
@@ -91,9 +90,8 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
                                              16, 0, 0);
         }
     };
-    // carried south-face fluxes: registers, or (FP64 without the ring) LDS in
-    // the ring's place
-    constexpr bool FS_LDS = !RING && sizeof(R) == 8;
+    // carried south-face fluxes: registers, or (FP64, 16 rows per lane) LDS
+    constexpr bool FS_LDS = fs_in_lds<R>(RPL);
     R FSr[FS_LDS ? 1 : RPL];
     R *fsl = (R *)(smem + ring_lds_offset<R>(L, a.np)) + (size_t)wv * RPL * WAVE + lane;
     auto fs_get = [&](int r) -> R {
@@ -305,9 +303,17 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
     }
 }
 
+// Workgroups are dealt to the 8 XCDs in turn (workgroup b on XCD b mod 8);
+// each XCD gets a contiguous range of line groups, so that the lines shared by
+// neighbouring groups meet in the same L2.  A bijection of 0..nb-1.
+__device__ inline int xcd_block(int b, int nb) {
+    const int x = b & 7, i = b >> 3, per = nb >> 3, rem = nb & 7;
+    return x * per + min(x, rem) + i;
+}
+
 template <typename R, int RPL, int G>
 __global__ __launch_bounds__(STEP_WAVES *WAVE) void k_step(StepArgs<R> a) {
-    step_body<R, RPL, G>(a, blockIdx.x, a.Tin, a.Tout, a.X, a.partial);
+    step_body<R, RPL, G>(a, xcd_block(blockIdx.x, gridDim.x), a.Tin, a.Tout, a.X, a.partial);
 }
 
 // Pulse average over step k (eq. (4)), step units; the host's schedule.

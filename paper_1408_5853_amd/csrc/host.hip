@@ -218,7 +218,7 @@ extern "C" {
 
 const char *cryo_last_error(void) { return g_err.c_str(); }
 
-const char *cryo_version(void) { return "cryocell 0.2 (gfx950)"; }
+const char *cryo_version(void) { return "cryocell 0.3 (gfx950)"; }
 
 cryo_status cryo_validate(const cryo_problem *prob) { return check_problem(prob); }
 
@@ -300,30 +300,25 @@ cryo_status cryo_plan_create(const cryo_problem *prob, cryo_dtype dtype, cryo_pl
     lw.K[UNIT] = 1.0;
     for (int id = 0; id < nlaw; ++id) lw.lk[id] = lw.K[id] > 0 ? log2(lw.K[id]) : -2000.0;
 
-    // FP64 power tables (see POW_*)
+    // FP64 power tables (see POW_*): one block per law id
     p->pow_blob.assign(pow_blob_doubles(L), 0.0);
     double *B = p->pow_blob.data();
-    for (int row = 0; row <= 2 * L; ++row) {
-        double e = row < L ? lw.e[row] : (row < 2 * L ? lw.e[2 * L + row - L] : 0.0);
-        double *R = B + (size_t)row * POW_EROW;
+    double *CK = B + (size_t)nlaw * POW_BLK, *CA = CK + nlaw;
+    for (int id = 0; id < nlaw; ++id) {
+        const double e = lw.e[id];
+        double *R = B + (size_t)id * POW_BLK;
         for (int j = 0; j < POW_NM; ++j) {
-            double m0 = 1.0 + (j + 0.5) / POW_NM;
+            const double m0 = 1.0 + (j + 0.5) / POW_NM;
             R[2 * j] = pow(m0, e);
             R[2 * j + 1] = 2.0 / m0;          // applied to the frexp mantissa in [1/2, 1)
         }
-    }
-    double *LR = B + (size_t)(2 * L + 1) * POW_EROW;
-    double *CK = LR + (size_t)nlaw * POW_LROW, *CA = CK + nlaw;
-    for (int id = 0; id < nlaw; ++id) {
-        double e = lw.e[id];
-        double *R = LR + (size_t)id * POW_LROW;
-        for (int x = 0; x < POW_NE; ++x) R[x] = lw.K[id] * exp2(e * (x + POW_EMIN));
-        R[POW_NE] = e;
+        for (int x = 0; x < POW_NE; ++x) R[POW_BX + x] = lw.K[id] * exp2(e * (x + POW_EMIN));
+        R[POW_BE] = e;
         // binomial coefficients of (1 + u)^e, k = 2..POW_DEG
         double c = e;
         for (int k = 2; k <= POW_DEG; ++k) {
             c = c * (e - (k - 1)) / k;
-            R[POW_NE + k] = c;
+            R[POW_BE + k] = c;
         }
         CK[id] = (id >= 2 * L && id < 3 * L) ? lw.K[id] : 0.0;   // cube path: K T^3 + A
         CA[id] = id == UNIT ? 1.0 : 0.0;

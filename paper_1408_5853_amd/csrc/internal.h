@@ -30,9 +30,6 @@ enum RowKind : uint32_t { K_PAD = 0, K_LO = 1, K_HI = 2, K_CAP = 3, K_IFACE = 4 
 constexpr int MAX_LAWS = 3 * MAX_LAYERS + 2;
 __host__ __device__ inline int law_zero(int L) { return 3 * L; }
 __host__ __device__ inline int law_unit(int L) { return 3 * L + 1; }
-__host__ __device__ inline int exp_row(int law, int L) {
-    return law < L ? law : min(law - L, 2 * L);
-}
 
 // Per-row packed info word:
 //   bits 0-2 kind, bit 3 heater capacity node, bit 4 held boundary row,
@@ -61,20 +58,23 @@ struct Laws {
 // FP64 powers T^e from tables: T = 2^x m, m in [1,2); m0 = 1 + (j + 1/2)/NM
 // for the top POW_MBITS mantissa bits j; u = m / m0 - 1 (|u| <= 1/(2 NM));
 // K T^e = [K 2^(x e)] m0^e (1 + u)^e, with (1 + u)^e summed as its binomial
-// series to degree 7 (coefficients per law in the law row); for |e| <= 4 the
-// truncation stays below 1e-16 relative.
+// series to degree 7; for |e| <= 4 the truncation stays below 1e-16 relative.
+// One block of doubles per law id:
+//   [0, 2 NM)            {m0^e, 2/m0} for j = 0..NM-1
+//   [2 NM, 2 NM + NE)    K 2^(x e) for binades x = EMIN..EMIN+NE-1
+//   2 NM + NE            e; the next slot is unused
+//   2 NM + NE + 2 ..     binomial(e, k), k = 2..7
+//   then 2 pad doubles: a 1296-byte block shifts successive laws by 4 LDS
+//   banks, so lanes reading different laws do not collide
 constexpr int POW_MBITS = 6, POW_NM = 1 << POW_MBITS, POW_NE = 24, POW_EMIN = -4;
 constexpr int POW_DEG = 7;
 constexpr double POW_TLO = 0.0625, POW_THI = 1048576.0;   // 2^EMIN, 2^(EMIN+NE)
-constexpr int POW_EROW = 2 * POW_NM;       // exponent row: {m0^e, 2/m0} pairs
-// law row: K 2^(x e) [NE], e, (unused), binomial(e, k) k = 2..7, then two
-// pad doubles: a 272-byte stride puts the rows of different laws in different
-// LDS banks (lanes of one wave read several laws at once)
-constexpr int POW_LROW = POW_NE + 2 + (POW_DEG - 1) + 2;
-// blob: 2L+1 exponent rows, (3L+2) law rows, then cube multipliers and
-// addends [3L+2] each
+constexpr int POW_BX = 2 * POW_NM;                 // binade multipliers
+constexpr int POW_BE = POW_BX + POW_NE;            // exponent, then binomials from +2
+constexpr int POW_BLK = POW_BE + 2 + (POW_DEG - 1) + 2;
+// blob: (3L+2) law blocks, then cube multipliers and addends [3L+2] each
 __host__ __device__ inline size_t pow_blob_doubles(int L) {
-    return (size_t)(2 * L + 1) * POW_EROW + (size_t)(3 * L + 2) * (POW_LROW + 2);
+    return (size_t)(3 * L + 2) * (POW_BLK + 2);
 }
 
 struct Pulse {      // in step units, snapped
