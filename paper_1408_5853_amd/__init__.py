@@ -328,12 +328,21 @@ def with_params(cell, theta):
 
 
 def _gradient_shape(cell):
-    # four radial rows per lane keep the adjoint kernel within registers
-    nr = int(cell["nr"])
-    w = 1
-    while 64 * 4 * w < nr:
-        w *= 2
-    return (4, w, 1) if w <= 4 else None
+    # one wave per line with 8 rows per lane up to nr = 512, else 4 rows per
+    # lane over more waves (the adjoint kernels fit their registers there);
+    # lines per wave as the plan picks them (about one workgroup per compute
+    # unit), so that the adjoint's axial pass carries faces along each block
+    nr, nz = int(cell["nr"]), int(cell["nz"])
+    if nr <= 512:
+        rpl, w = (2, 1) if nr <= 128 else ((4, 1) if nr <= 256 else (8, 1))
+    else:
+        rpl, w = 4, 1
+        while 64 * 4 * w < nr:
+            w *= 2
+        if w > 4:
+            return None
+    lpw = min(8, max(1, int(round((nz - 2) / ((8 // w) * 256.0)))))
+    return (rpl, w, lpw)
 
 
 def gradient(cell, target, T0=None, nsteps=None, ckpt=0):

@@ -38,6 +38,14 @@ struct AdjArgs {
 
 constexpr int ADJ_WAVES = 8;
 
+// pass 1 keeps per-row sums in LDS after the law and row tables
+__host__ __device__ inline size_t adj_acc_offset(int L, int np) {
+    return ring_lds_offset<double>(L, np);
+}
+__host__ __device__ inline size_t adj_lds_bytes(int L, int np, int rpl) {
+    return adj_acc_offset(L, np) + 2 * (size_t)ADJ_WAVES * rpl * WAVE * sizeof(double);
+}
+
 // exchange of one value per lane with the neighbouring lanes of the line
 // (shuffles inside a wave, LDS across the waves of the line)
 template <int G>
@@ -70,7 +78,7 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj1(StepArgs<double> a, Ad
         sinf[i] = a.info[i];
     }
     const LawLds<double> law = stage_laws<double>(a, smem);
-    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    const int lane = threadIdx.x & (WAVE - 1), wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int grp = wv / G, wig = wv % G, lg = wig * WAVE + lane;
     const int gidx = blockIdx.x * NG + grp;                  // line group
     const int j0 = 1 + gidx * a.lpw;
@@ -78,32 +86,37 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj1(StepArgs<double> a, Ad
     const size_t LS = a.np;
     const int qW = lg > 0 ? (RPL - 1) * NL + lg - 1 : 0;
     const int qE = lg < NL - 1 ? lg + 1 : (RPL - 1) * NL + lg;
-    int bad = 0;
-    double accW[RPL], accE[RPL], gS = 0.0, gD = 0.0;
+    // per-row sums over the group's lines, in LDS (registers): [wave][row][lane]
+    double *accW = (double *)(smem + adj_acc_offset(a.laws.L, a.np)) + (size_t)wv * RPL * WAVE + lane;
+    double *accE = accW + (size_t)ADJ_WAVES * RPL * WAVE;
+    double gS = 0.0;
 #pragma unroll
-    for (int r = 0; r < RPL; ++r) accW[r] = accE[r] = 0.0;
+    for (int r = 0; r < RPL; ++r) accW[r * WAVE] = accE[r * WAVE] = 0.0;
     for (int it = 0; it < a.lpw; ++it) {
         const int jr = j0 + it;
         const bool active = jr < j1;
         const int j = min(jr, a.nz - 2);
         const size_t base = (size_t)j * LS;
-        double T[RPL], X[RPL], fw[RPL], fe[RPL], fwT[RPL], feT[RPL];
+        double T[RPL], MU[RPL], fw[RPL], fe[RPL];
+        // the line's loads up front (latency overlaps the row work)
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
             const int q = r * NL + lg;
             T[r] = d.T[base + q];
-            X[r] = d.X[base + q];
+            MU[r] = d.lam_in[base + q];
+        }
+        // boundary-copy lines feed their sensitivity back to the copied line
+        if (j == 1 && !a.held[2]) {
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) MU[r] += d.lam_in[r * NL + lg];
+        }
+        if (j == a.nz - 2 && !a.held[3]) {
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) MU[r] += d.lam_in[(size_t)(a.nz - 1) * LS + r * NL + lg];
         }
         const double TwF = d.T[base + qW], TeL = d.T[base + qE];
-        const double XwF = d.X[base + qW], XeL = d.X[base + qE];
         // west face of the chunk's first row
-        double lamW, dlamW;
-        {
-            const int le = (sinf[qW] >> 6) & 63;
-            const double tf = 0.5 * (TwF + T[0]);
-            lamW = law.law(le, tf, bad);
-            dlamW = law.expo(le) * lamW / tf;
-        }
+        double lamW = law.lawc((sinf[qW] >> 6) & 63, 0.5 * (TwF + T[0]));
         double a0 = 0, b0 = 1, c0 = 0, d0 = 0, ccm2 = 0, bbm1 = 1, ccm1 = 0, mum1 = 0;
         double al[RPL], ga[RPL], de[RPL];
         double aa0 = 0, ccL = 0;
@@ -116,31 +129,21 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj1(StepArgs<double> a, Ad
             const double t = T[r], Te = (r < RPL - 1) ? T[r + 1] : TeL;
             const int le = (inf_r >> 6) & 63, l2 = (inf_r >> 12) & 63;
             const int l3 = (inf_r >> 18) & 63, lc = (inf_r >> 24) & 63;
-            const double tf = 0.5 * (t + Te);
-            const double lamE = law.law(le, tf, bad);
-            const double dlamE = law.expo(le) * lamE / tf;
+            const double lamE = law.lawc(le, 0.5 * (t + Te));
             // interface: the two layer laws at the node; boundary rows: unit/zero
             double l2v = l2 == law_unit(a.laws.L) ? 1.0 : 0.0, l3v = l3 == law_unit(a.laws.L) ? 1.0 : 0.0;
-            double dl2 = 0.0, dl3 = 0.0;
             if (__any(ifc)) {
-                const double va = law.law(l2, t, bad), vb = law.law(l3, t, bad);
+                const double va = law.lawc(l2, t), vb = law.lawc(l3, t);
                 if (ifc) {
                     l2v = va;
                     l3v = vb;
-                    dl2 = law.expo(l2) * va / t;
-                    dl3 = law.expo(l3) * vb / t;
                 }
             }
-            const double rc = a.laws.cube ? law.cube(lc, t) : law.law(lc, t, bad);
+            const double rc = a.laws.cube ? law.cube(lc, t) : law.lawc(lc, t);
             fw[r] = sgw[q] * (cap ? lamW : l2v);
             fe[r] = sge[q] * (cap ? lamE : l3v);
-            fwT[r] = sgw[q] * (cap ? 0.5 * dlamW : dl2);
-            feT[r] = sge[q] * (cap ? 0.5 * dlamE : dl3);
             const double aa = -fw[r], bb = fw[r] + fe[r] + rc, cc = -fe[r];
-            // boundary-copy lines feed their sensitivity back to the copied line
-            double mu = d.lam_in[base + q];
-            if (j == 1 && !a.held[2]) mu += d.lam_in[q];
-            if (j == a.nz - 2 && !a.held[3]) mu += d.lam_in[(size_t)(a.nz - 1) * LS + q];
+            const double mu = MU[r];
             // transposed row r-1 = (cc_{r-2}, bb_{r-1}, aa_r | mu_{r-1})
             if (r == 0) {
                 aa0 = aa;
@@ -159,7 +162,6 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj1(StepArgs<double> a, Ad
             mum1 = mu;
             if (r == RPL - 1) ccL = cc;
             lamW = lamE;
-            dlamW = dlamE;
             if (r & 1) __builtin_amdgcn_sched_barrier(0);
         }
         // chunk ends: sub of the first row = cc of the previous row, sup of the
@@ -173,13 +175,42 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj1(StepArgs<double> a, Ad
         elim_row<double, RPL>(RPL - 1, ccm2, bbm1, aaNext, mum1, al, ga, de);
         double y[RPL];
         solve_tail<double, RPL, G>(a0, b0, c0, d0, al, ga, de, y, lane, wig, xchg[grp]);
+        // T^{n+1} of the line, loaded after the solve (registers)
+        double X[RPL];
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) X[r] = d.X[base + r * NL + lg];
+        const double XwF = d.X[base + qW], XeL = d.X[base + qE];
         // radial part of lam^n:  dJ - [y_i dr_i/dT_i + y_{i-1} dr_{i-1}/dT_i + y_{i+1} dr_{i+1}/dT_i]
-        double Dw[RPL], De[RPL];
+        // face conductivity derivatives: d(gw lam_W)/dT_i = (1/2) e lam' ... on
+        // capacity rows (face-mean argument), e lam / T at interface nodes
+        double Dw[RPL], De[RPL], fwT[RPL], feT[RPL];
+        double ieW = 0.0;          // 1/2 e_W / tf_W of row 0 (west face of the chunk)
+        {
+            const uint32_t iw = sinf[qW];
+            ieW = 0.5 * law.expo((iw >> 6) & 63) * rcp(0.5 * (TwF + T[0]));
+        }
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
+            const int q = r * NL + lg;
             const double xw = (r > 0) ? X[r - 1] : XwF, xe = (r < RPL - 1) ? X[r + 1] : XeL;
             Dw[r] = X[r] - xw;
             De[r] = X[r] - xe;
+            const uint32_t inf_r = sinf[q];
+            const uint32_t kind = inf_r & 7;
+            const double t = T[r], Te = (r < RPL - 1) ? T[r + 1] : TeL;
+            const double ieE = 0.5 * law.expo((inf_r >> 6) & 63) * rcp(0.5 * (t + Te));
+            if (kind == K_CAP) {
+                fwT[r] = fw[r] * ieW;
+                feT[r] = fe[r] * ieE;
+            } else if (kind == K_IFACE) {
+                const double it = rcp(t);
+                fwT[r] = fw[r] * law.expo((inf_r >> 12) & 63) * it;
+                feT[r] = fe[r] * law.expo((inf_r >> 18) & 63) * it;
+            } else {
+                fwT[r] = 0.0;
+                feT[r] = 0.0;
+            }
+            ieW = ieE;
         }
         // coupling terms leaving each row towards its r-neighbours (capacity rows:
         // the face conductivity depends on both nodes)
@@ -202,8 +233,8 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj1(StepArgs<double> a, Ad
                     rc = law.cube(lc, t);
                     drc = 3.0 * law.ck[lc] * t * t;
                 } else {
-                    rc = law.law(lc, t, bad);
-                    drc = law.expo(lc) * rc / t;
+                    rc = law.lawc(lc, t);
+                    drc = law.expo(lc) * rc * rcp(t);
                 }
                 double self = 0.0;
                 if (cap || ifc) self = fwT[r] * Dw[r] + feT[r] * De[r] + drc * (X[r] - t) - rc;
@@ -225,8 +256,8 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj1(StepArgs<double> a, Ad
                 d.Y[base + q] = y[r];
                 d.lpart[base + q] = lp;
                 if (cap || ifc) {
-                    accW[r] += y[r] * fw[r] * Dw[r];
-                    accE[r] += y[r] * fe[r] * De[r];
+                    accW[r * WAVE] += y[r] * fw[r] * Dw[r];
+                    accE[r * WAVE] += y[r] * fe[r] * De[r];
                 }
                 if ((inf_r >> 3) & 1) {
                     gS += y[r];
@@ -239,8 +270,8 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj1(StepArgs<double> a, Ad
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
         const int q = r * NL + lg;
-        acc[q] += accW[r];
-        acc[a.np + q] += accE[r];
+        acc[q] += accW[r * WAVE];
+        acc[a.np + q] += accE[r * WAVE];
     }
     // heater sums of the group: lane-order tree inside each wave, then waves
     double v = gS;
@@ -254,8 +285,6 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj1(StepArgs<double> a, Ad
         d.accg[2 * gidx] += tot * d.s;
         d.accg[2 * gidx + 1] += tot * a.pulse.amplitude * d.ds;
     }
-    (void)gD;
-    if (__any(bad) && lane == 0) atomicOr(a.flag, 2);
 }
 
 // Pass 2: axial faces.  Each interior line j adds the terms of its two
@@ -270,49 +299,83 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj2(StepArgs<double> a, Ad
     uint32_t *sinf = (uint32_t *)(sge + a.np);
     for (int i = threadIdx.x; i < a.np; i += blockDim.x) sinf[i] = a.info[i];
     const LawLds<double> law = stage_laws<double>(a, smem);
-    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    const int lane = threadIdx.x & (WAVE - 1), wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int grp = wv / G, wig = wv % G, lg = wig * WAVE + lane;
     const int gidx = blockIdx.x * NG + grp;
     const int j0 = 1 + gidx * a.lpw;
     const int j1 = min(j0 + a.lpw, a.nz - 1);
     const size_t LS = a.np;
-    int bad = 0;
     double accZ[RPL];
+    // carried from the previous line of the group: the face (j-1, j) flux
+    // F = lam (T_j - T_{j-1}) and dF/dT_j; and the lines j, j-1 (T, Y)
+    double cF[RPL], cdF[RPL], Tc[RPL], Yc[RPL], Ys[RPL];
+    // groups past the last line read line nz-2 and do no line
+    const int jb = min(j0, a.nz - 2);
 #pragma unroll
-    for (int r = 0; r < RPL; ++r) accZ[r] = 0.0;
+    for (int r = 0; r < RPL; ++r) {
+        const int q = r * NL + lg;
+        accZ[r] = cF[r] = cdF[r] = 0.0;
+        Tc[r] = d.T[(size_t)jb * LS + q];
+        Yc[r] = d.Y[(size_t)jb * LS + q];
+        Ys[r] = jb - 1 >= 1 ? d.Y[(size_t)(jb - 1) * LS + q] : 0.0;
+    }
     for (int j = j0; j < j1; ++j) {
         const size_t base = (size_t)j * LS;
+        // the line above and this line's partial lam^n, up front
+        double Tn[RPL], Yn[RPL], LP[RPL], TsF[RPL];
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int q = r * NL + lg;
+            Tn[r] = d.T[base + LS + q];
+            Yn[r] = (j + 1 <= a.nz - 2) ? d.Y[base + LS + q] : 0.0;
+            LP[r] = d.lpart[base + q];
+            TsF[r] = j == j0 ? d.T[base - LS + q] : 0.0;
+        }
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
             const int q = r * NL + lg;
             const uint32_t inf_r = sinf[q];
             const bool cap = (inf_r & 7) == K_CAP;
             const int lz = (inf_r >> 12) & 63;
-            const double t = d.T[base + q];
-            const double tn = d.T[base + LS + q], ts = d.T[base - LS + q];
-            const double y = d.Y[base + q];
-            const double yn = (j + 1 <= a.nz - 2) ? d.Y[base + LS + q] : 0.0;
-            const double ys = (j - 1 >= 1) ? d.Y[base - LS + q] : 0.0;
-            double lam = d.lpart[base + q];
-            double dFlN = 0.0, dFuS = 0.0;
+            const double t = Tc[r], tn = Tn[r];
+            const double y = Yc[r], yn = Yn[r], ys = Ys[r];
+            double lam = LP[r];
             if (cap) {
-                const double fn = 0.5 * (t + tn), fs = 0.5 * (t + ts);
-                const double ln = law.law(lz, fn, bad), ls = law.law(lz, fs, bad);
                 const double e = law.expo(lz);
-                const double dn = tn - t, ds = t - ts;
-                dFlN = 0.5 * e * ln / fn * dn - ln;     // d F_N / d T_j
-                dFuS = 0.5 * e * ls / fs * ds + ls;     // d F_S / d T_j
+                // north face (j, j+1)
+                const double fn = 0.5 * (t + tn);
+                const double ln = law.lawc(lz, fn);
+                const double dn = tn - t;
+                const double gn = 0.5 * e * ln * rcp(fn);
+                const double dFlN = gn * dn - ln;                   // d F_N / d T_j
+                // south face (j-1, j): carried, or evaluated on the group's first line
+                double FS, dFuS, gs = 0.0, ls = 0.0, ds = 0.0;
+                if (j == j0) {
+                    const double ts = TsF[r];
+                    const double fs = 0.5 * (t + ts);
+                    ls = law.lawc(lz, fs);
+                    ds = t - ts;
+                    gs = 0.5 * e * ls * rcp(fs);
+                    FS = ls * ds;
+                    dFuS = gs * ds + ls;                            // d F_S / d T_j
+                } else {
+                    FS = cF[r];
+                    dFuS = cdF[r];
+                }
                 lam += dFlN * (y - yn) + dFuS * (ys - y);
-                accZ[r] += y * (ln * dn - ls * ds);
-                // boundary lines: their faces with lines 1 and nz-2
+                accZ[r] += y * (ln * dn - FS);
+                cF[r] = ln * dn;
+                cdF[r] = gn * dn + ln;                              // d F_N / d T_{j+1}
+                // boundary lines: their faces with lines 1 and nz-2 (line 1 is
+                // always the first line of its group)
                 if (j == 1) {
-                    const double dFl0 = 0.5 * e * ls / fs * ds - ls;   // d F_S / d T_0
+                    const double dFl0 = gs * ds - ls;               // d F_S / d T_0
                     double l0 = dFl0 * (0.0 - y);
                     if (lg == a.surf_lane && r == a.surf_reg) l0 += d.cS * a.wz_end;
                     d.lam_out[q] = l0;
                 }
                 if (j == a.nz - 2) {
-                    const double dFuE = 0.5 * e * ln / fn * dn + ln;   // d F_N / d T_{nz-1}
+                    const double dFuE = gn * dn + ln;               // d F_N / d T_{nz-1}
                     double le_ = dFuE * (y - 0.0);
                     if (lg == a.surf_lane && r == a.surf_reg) le_ += d.cS * a.wz_end;
                     d.lam_out[(size_t)(a.nz - 1) * LS + q] = le_;
@@ -324,11 +387,16 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj2(StepArgs<double> a, Ad
             }
             d.lam_out[base + q] = lam;
         }
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            Ys[r] = Yc[r];
+            Yc[r] = Yn[r];
+            Tc[r] = Tn[r];
+        }
     }
     double *acc = d.acc + (size_t)gidx * 3 * a.np + 2 * a.np;
 #pragma unroll
     for (int r = 0; r < RPL; ++r) acc[r * NL + lg] += accZ[r];
-    if (__any(bad) && lane == 0) atomicOr(a.flag, 2);
 }
 
 // lam^N = dJ_N / dT^N: the surface weights on the outer row
@@ -369,7 +437,7 @@ StepArgs<double> step_args_f64(const cryo_plan *p, int *flag);
 cryo_status launch_adj(const cryo_plan *p, int pass, const AdjArgs &d, int *flag, hipStream_t s) {
     StepArgs<double> a = step_args_f64(p, flag);
     dim3 g(adj_grid(p)), b(ADJ_WAVES * WAVE);
-    const size_t lds = step_lds_bytes<double>(p->L, p->np);
+    const size_t lds = adj_lds_bytes(p->L, p->np, p->rpl);
     const int key = p->rpl * 10 + p->wpl;
 #define ADJ_CASE(R_, G_)                                                                  \
     case R_ * 10 + G_:                                                                    \
