@@ -3,7 +3,9 @@
 TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the benchmark's
 CPU-baseline leg are the only callers.  The product path never imports this
 package.  The oracle follows the paper's scheme (eqs. (8)-(20)) literally; see
-the header of ``oracle.c`` for the readings it takes.
+the header of ``oracle.c`` for the readings it takes.  ``dense_np`` is a second,
+independent implementation (dense NumPy solves, complex-step capable) that
+pins this one.
 """
 from __future__ import annotations
 
