@@ -163,6 +163,22 @@ def design_extra(P, steps, iters, stream):
             "mean_J_first": float(hist[0].mean()), "mean_J_last": float(hist[-1].mean())}
 
 
+def paper_shape_extra(P, steps, stream):
+    """The paper's largest timed grid (631 x 1201 nodes, 100,000 steps in its
+    Table 4) on a bounded sample of steps, beside the paper's figure for its
+    OpenCL code (context only: other hardware, other laws and domain)."""
+    import cellgen
+    c = cellgen.paper_shape(0)
+    secs, plan = rate(P.Plan, c, "f64", steps, 200, stream)
+    cells = c["nr"] * c["nz"]
+    return {"workload": "paper-shape cell 631x1201, FP64", "steps": steps,
+            "kernel_shape": list(plan.shape()),
+            "gcell_steps_s": round(cells * steps / secs / 1e9, 2),
+            "projected_s_for_100000_steps": round(secs / steps * 1e5, 2),
+            "paper_table4_context": "631x1201, 100,000 steps: 12.9 min on its GPU "
+                                    "(0.098 Gcell-steps/s), 64.0 min on its CPU"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -237,6 +253,8 @@ def main():
         out["extra"]["batch"] = batch_extra(P, 2000, stream)
         log("bench: gradient")
         out["extra"]["gradient"] = gradient_extra(P, 50_000, stream)
+        log("bench: paper shape")
+        out["extra"]["paper_shape"] = paper_shape_extra(P, 10_000, stream)
         log("bench: design loop")
         out["extra"]["design_loop"] = design_extra(P, 500, 2, stream)
     if not args.no_cpu:

@@ -149,9 +149,9 @@ void cryo_plan_destroy(cryo_plan *plan);
  * lanes) per radial line, and interior lines marched by one line group per
  * step.  The plan picks one at create time; cryo_plan_set_shape overrides it
  * (the autotuner's hook) and must precede the plan's first device call.
- * Built shapes: (2,1) (4,1) (8,1) (4,2) (8,2) (4,4) (8,4) (16,1) (the
- * gradient runs every shape but (16,1)); 64 * waves *
- * rows must cover nr.  Results do not depend on lines_per_wave; different
+ * Built shapes: one wave per line with 2, 3, 4, 5, 6, 7, 8, 10, 12 or 16
+ * rows per lane, and (4,2) (8,2) (4,4) (8,4); 64 * waves * rows must cover
+ * nr.  The gradient runs (2,1) (4,1) (8,1) (4,2) (8,2) (4,4) (8,4).  Results do not depend on lines_per_wave; different
  * chunk shapes change only rounding. */
 cryo_status cryo_plan_shape(const cryo_plan *plan, int32_t *rows_per_lane,
                             int32_t *waves_per_line, int32_t *lines_per_wave);
@@ -210,8 +210,8 @@ cryo_status cryo_autotune(const cryo_problem *prob, cryo_dtype dtype, int32_t st
  * the thicknesses, and the pulse-edge steps (a pulse end on a step boundary
  * takes the mean of the two one-sided derivatives).  States are checkpointed
  * every ckpt steps (0: ceil(sqrt(N))) and each segment is recomputed.
- * FP64 plans with at most 8 rows per lane only (CRYO_ERR_UNSUPPORTED
- * otherwise).  T0 is a device field; target, J, grad and surf (nullable, N
+ * FP64 plans with one of the gradient's shapes only (CRYO_ERR_UNSUPPORTED
+ * otherwise, see cryo_plan_set_shape).  T0 is a device field; target, J, grad and surf (nullable, N
  * values) are host arrays.  Synchronous on `stream`. */
 cryo_status cryo_gradient_workspace_bytes(const cryo_plan *plan, int64_t nsteps, int64_t ckpt,
                                           size_t *bytes);

@@ -173,8 +173,8 @@ class Plan:
         k_scale_m] by the discrete adjoint (FP64 plans).  Returns (J, grad,
         surface trace) as float, numpy, numpy.  Synchronous."""
         torch = _torch()
-        if self.shape()[0] > 8:
-            # the adjoint kernels take up to 8 rows per lane: switch to the
+        if self.shape()[:2] not in _ADJOINT_SHAPES:
+            # the adjoint kernels take 2, 4 or 8 rows per lane: switch to the
             # gradient shape while the plan has not run yet (else the library
             # reports the shape as unsupported)
             sh = _gradient_shape(self.cell)
@@ -325,6 +325,9 @@ def with_params(cell, theta):
         c["layers"][m]["thickness"] = float(theta[2 + m])
         c["layers"][m]["k_scale"] = float(theta[2 + L + m])
     return c
+
+
+_ADJOINT_SHAPES = {(2, 1), (4, 1), (8, 1), (4, 2), (8, 2), (4, 4), (8, 4)}
 
 
 def _gradient_shape(cell):

@@ -346,12 +346,14 @@ __host__ __device__ inline size_t ring_slot_elems(int rpl) {
 // that LDS on its law tables instead (its prefetch gained nothing measurable).
 template <typename R>
 __host__ __device__ constexpr bool ring_used(int rpl) {
-    return sizeof(R) == 4 && rpl * 2 * WAVE * sizeof(R) <= 4096;
+    // a slot of rpl rows x 2 planes x 64 lanes, filled in 16-byte pieces
+    return sizeof(R) == 4 && rpl * 2 * WAVE * sizeof(R) <= 4096 && (rpl * 2) % 4 == 0;
 }
-// FP64 with 16 rows per lane keeps the carried axial fluxes in LDS (registers)
+// FP64 with 10 or more rows per lane keeps the carried axial fluxes in LDS
+// (registers)
 template <typename R>
 __host__ __device__ constexpr bool fs_in_lds(int rpl) {
-    return sizeof(R) == 8 && rpl >= 16;
+    return sizeof(R) == 8 && rpl >= 10;
 }
 // the ring, or the FP64 carried fluxes, after the tables
 template <typename R>

@@ -90,7 +90,7 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
                                              16, 0, 0);
         }
     };
-    // carried south-face fluxes: registers, or (FP64, 16 rows per lane) LDS
+    // carried south-face fluxes: registers, or (FP64, 10+ rows per lane) LDS
     constexpr bool FS_LDS = fs_in_lds<R>(RPL);
     R FSr[FS_LDS ? 1 : RPL];
     R *fsl = (R *)(smem + ring_lds_offset<R>(L, a.np)) + (size_t)wv * RPL * WAVE + lane;
@@ -217,7 +217,7 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
             }
             // keep the scheduler from hoisting every row's law evaluations
             // at once (register pressure); rows still overlap pairwise
-            if (RPL >= 16 || (r & 1)) __builtin_amdgcn_sched_barrier(0);
+            if (RPL >= 10 || (r & 1)) __builtin_amdgcn_sched_barrier(0);
         }
         R X[RPL];
         solve_tail<R, RPL, G>(a0, b0, c0, d0, al, ga, de, X, lane, wig, xch);
@@ -494,14 +494,10 @@ static cryo_status step_t(const cryo_plan *p, const void *Tin, void *Tout, doubl
     const size_t lds = step_lds_bytes<R>(p->L, p->np, p->rpl);
     const int key = p->rpl * 10 + p->wpl;
     switch (key) {
-    case 21: hipLaunchKernelGGL((k_step<R, 2, 1>), g, b, lds, s, a); break;
-    case 41: hipLaunchKernelGGL((k_step<R, 4, 1>), g, b, lds, s, a); break;
-    case 81: hipLaunchKernelGGL((k_step<R, 8, 1>), g, b, lds, s, a); break;
-    case 82: hipLaunchKernelGGL((k_step<R, 8, 2>), g, b, lds, s, a); break;
-    case 84: hipLaunchKernelGGL((k_step<R, 8, 4>), g, b, lds, s, a); break;
-    case 42: hipLaunchKernelGGL((k_step<R, 4, 2>), g, b, lds, s, a); break;
-    case 44: hipLaunchKernelGGL((k_step<R, 4, 4>), g, b, lds, s, a); break;
-    case 161: hipLaunchKernelGGL((k_step<R, 16, 1>), g, b, lds, s, a); break;
+#define STEP_CASE(RP, GW) \
+    case RP * 10 + GW: hipLaunchKernelGGL((k_step<R, RP, GW>), g, b, lds, s, a); break;
+        CRYO_FOR_SHAPES(STEP_CASE)
+#undef STEP_CASE
     default: return fail(CRYO_ERR_UNSUPPORTED, "radial chunk shape");
     }
     return launch_check("step");
@@ -554,14 +550,12 @@ static cryo_status step_batch_t(int rpl, int wpl, const void *desc, const int2 *
     const StepArgs<R> *d = (const StepArgs<R> *)desc;
     dim3 g(nwg), b(STEP_WAVES * WAVE);
     switch (rpl * 10 + wpl) {
-    case 21: hipLaunchKernelGGL((k_step_batch<R, 2, 1>), g, b, lds, s, d, map, n, k0); break;
-    case 41: hipLaunchKernelGGL((k_step_batch<R, 4, 1>), g, b, lds, s, d, map, n, k0); break;
-    case 81: hipLaunchKernelGGL((k_step_batch<R, 8, 1>), g, b, lds, s, d, map, n, k0); break;
-    case 82: hipLaunchKernelGGL((k_step_batch<R, 8, 2>), g, b, lds, s, d, map, n, k0); break;
-    case 84: hipLaunchKernelGGL((k_step_batch<R, 8, 4>), g, b, lds, s, d, map, n, k0); break;
-    case 42: hipLaunchKernelGGL((k_step_batch<R, 4, 2>), g, b, lds, s, d, map, n, k0); break;
-    case 44: hipLaunchKernelGGL((k_step_batch<R, 4, 4>), g, b, lds, s, d, map, n, k0); break;
-    case 161: hipLaunchKernelGGL((k_step_batch<R, 16, 1>), g, b, lds, s, d, map, n, k0); break;
+#define BATCH_CASE(RP, GW) \
+    case RP * 10 + GW: \
+        hipLaunchKernelGGL((k_step_batch<R, RP, GW>), g, b, lds, s, d, map, n, k0); \
+        break;
+        CRYO_FOR_SHAPES(BATCH_CASE)
+#undef BATCH_CASE
     default: return fail(CRYO_ERR_UNSUPPORTED, "radial chunk shape");
     }
     return launch_check("step_batch");

@@ -101,9 +101,10 @@ static cryo_status grad_check(const cryo_plan *p, int64_t N, const double *targe
                               const void *T0, void *ws, size_t ws_bytes) {
     if (!p || !T0 || N < 1 || !target || ckpt < 0) return fail(CRYO_ERR_ARG, "bad argument");
     if (p->dtype != CRYO_F64) return fail(CRYO_ERR_UNSUPPORTED, "the adjoint needs an FP64 plan");
-    if (p->rpl > 8)
-        return fail(CRYO_ERR_UNSUPPORTED, "the adjoint kernels take up to 8 rows per lane; set "
-                                          "a shape such as (4, waves, 1) before the plan's first run");
+    const int key = p->rpl * 10 + p->wpl;
+    if (!(key == 21 || key == 41 || key == 81 || key == 42 || key == 82 || key == 44 || key == 84))
+        return fail(CRYO_ERR_UNSUPPORTED, "the adjoint kernels take 2, 4 or 8 rows per lane; set "
+                                          "such a shape before the plan's first run");
     const GradLayout g = grad_layout(p, N, ckpt);
     if (!ws || ws_bytes < g.total)
         return fail(CRYO_ERR_WORKSPACE, "gradient workspace needs " + std::to_string(g.total) +

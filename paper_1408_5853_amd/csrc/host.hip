@@ -102,16 +102,18 @@ static double dt_bound(const cryo_problem *pr, double Tm) {
 }
 
 // Chunk shape of a line: rows per lane and waves per line.  One wave per line
-// up to 1024 rows (16 rows per lane), then 8 rows per lane over more waves.
+// with the fewest rows per lane that cover nr (up to 1024 rows), then 8 rows
+// per lane over more waves.
 static void pick_shape(int nr, int *rpl, int *wpl) {
-    int r = 2;
-    while (WAVE * r < nr && r < 16) r *= 2;
+    for (int r : ONE_WAVE_RPL)
+        if (WAVE * r >= nr) {
+            *rpl = r;
+            *wpl = 1;
+            return;
+        }
     int w = 1;
-    if (WAVE * r < nr) {
-        r = 8;
-        while (WAVE * w * r < nr) w *= 2;
-    }
-    *rpl = r;
+    while (WAVE * w * 8 < nr) w *= 2;
+    *rpl = 8;
     *wpl = w;
 }
 
@@ -359,10 +361,8 @@ cryo_status cryo_plan_set_shape(cryo_plan *p, int32_t rows_per_lane, int32_t wav
                                 int32_t lines_per_wave) {
     if (!p) return fail(CRYO_ERR_ARG, "null plan");
     if (p->d_info) return fail(CRYO_ERR_ARG, "shape must be set before the plan's first run");
-    const int key = rows_per_lane * 10 + waves_per_line;
-    const bool built = key == 21 || key == 41 || key == 81 || key == 82 || key == 84 ||
-                       key == 42 || key == 44 || key == 161;
-    if (!built) return fail(CRYO_ERR_UNSUPPORTED, "no kernel for this chunk shape");
+    if (!shape_built(rows_per_lane, waves_per_line))
+        return fail(CRYO_ERR_UNSUPPORTED, "no kernel for this chunk shape");
     if ((int64_t)WAVE * waves_per_line * rows_per_lane < p->nr)
         return fail(CRYO_ERR_ARG, "chunk shape too short for the radial line");
     if (lines_per_wave < 1 || lines_per_wave > p->nz - 2)

@@ -18,6 +18,20 @@ constexpr int SURF_CHUNK = 1024;    // steps per surface reduction round
 constexpr int STEP_WAVES_HOST = 8;  // waves per stepping workgroup
 constexpr int BATCH_LPW = 4;        // default lines per wave of batch instances
 
+// Built chunk shapes (rows per lane, waves per line) of the stepping kernel:
+// one wave per line with 2..16 rows per lane (so that padding stays small
+// for any nr up to 1024), then 4 or 8 rows per lane over 2 or 4 waves.
+#define CRYO_FOR_SHAPES(X) \
+    X(2, 1) X(3, 1) X(4, 1) X(5, 1) X(6, 1) X(7, 1) X(8, 1) X(10, 1) X(12, 1) X(16, 1) \
+    X(4, 2) X(8, 2) X(4, 4) X(8, 4)
+constexpr int ONE_WAVE_RPL[] = {2, 3, 4, 5, 6, 7, 8, 10, 12, 16};
+inline bool shape_built(int rpl, int wpl) {
+#define CRYO_SHAPE_EQ(RP, GW) if (rpl == RP && wpl == GW) return true;
+    CRYO_FOR_SHAPES(CRYO_SHAPE_EQ)
+#undef CRYO_SHAPE_EQ
+    return false;
+}
+
 // Row classes of one radial line (eq. (13), eq. (18), eq. (15), padding).
 enum RowKind : uint32_t { K_PAD = 0, K_LO = 1, K_HI = 2, K_CAP = 3, K_IFACE = 4 };
 

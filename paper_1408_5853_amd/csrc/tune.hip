@@ -68,7 +68,9 @@ cryo_status cryo_autotune(const cryo_problem *prob, cryo_dtype dtype, int32_t st
         return CRYO_OK;
     }
     hipStream_t s = (hipStream_t)stream;
-    const int shapes[][2] = {{2, 1}, {4, 1}, {8, 1}, {4, 2}, {8, 2}, {4, 4}, {8, 4}, {16, 1}};
+#define TUNE_SHAPE(RP, GW) {RP, GW},
+    const int shapes[][2] = {CRYO_FOR_SHAPES(TUNE_SHAPE)};
+#undef TUNE_SHAPE
     const int lpws[] = {1, 2, 4, 8};
     double best = 1e300;
     int32_t bs[3] = {0, 0, 0};

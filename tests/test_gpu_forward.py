@@ -137,7 +137,8 @@ def test_f32_within_1e4_kelvin(make, n):
     assert e < F32_TOL_K and es < F32_TOL_K
 
 
-SHAPES = [(2, 1), (4, 1), (8, 1), (4, 2), (8, 2), (4, 4), (8, 4), (16, 1)]
+SHAPES = [(2, 1), (3, 1), (4, 1), (5, 1), (6, 1), (7, 1), (8, 1), (10, 1), (12, 1), (16, 1),
+          (4, 2), (8, 2), (4, 4), (8, 4)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
