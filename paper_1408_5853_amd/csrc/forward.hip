@@ -120,11 +120,18 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
             LwF = Tin[bc + LO + qW];
             LeL = Tin[bc + LO + qE];
         }
-        // south-face flux of the block's first line (capacity rows)
+        // south-face flux of the block's first line (capacity rows); the line
+        // below is loaded up front
+        R Tpv[RPL], Tplv[RPL];
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            Tpv[r] = Tin[bc - LS + r * NL + lg];
+            Tplv[r] = PAIR ? Tin[bc - LS + LO + r * NL + lg] : (R)0;
+        }
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
             const int q = r * NL + lg;
-            const R Tp = Tin[bc - LS + q], Tpl = PAIR ? Tin[bc - LS + LO + q] : (R)0;
+            const R Tp = Tpv[r], Tpl = Tplv[r];
             const uint32_t inf_r = sinf[q];
             const bool cap = (inf_r & 7) == K_CAP;
             const int l2 = (inf_r >> 12) & 63;
@@ -161,10 +168,31 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
         R lamW = law.law((sinf[qW] >> 6) & 63, (R)0.5 * (TwF + Tc[0]), bad);
         R a0 = 0, b0 = 1, c0 = 0, d0 = 0;
         R al[RPL], ga[RPL], de[RPL];
+        // without the ring: the next line's values come from memory two rows
+        // ahead of their use (software pipelined across the rows' regions)
+        constexpr int PF = 2;
+        R TnP[RPL], LnP[RPL];
+        if constexpr (!RING) {
+#pragma unroll
+            for (int r = 0; r < PF && r < RPL; ++r) {
+                TnP[r] = Tin[base + LS + r * NL + lg];
+                LnP[r] = PAIR ? Tin[base + LS + LO + r * NL + lg] : (R)0;
+            }
+        }
+        // the rows' info words, one row ahead (they head each row's chain of
+        // table lookups)
+        uint32_t infn = sinf[lg];
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
             const int q = r * NL + lg;
-            const uint32_t inf_r = sinf[q];
+            const uint32_t inf_r = infn;
+            if (r + 1 < RPL) infn = sinf[q + NL];
+            if constexpr (!RING) {
+                if (r + PF < RPL) {
+                    TnP[r + PF] = Tin[base + LS + q + PF * NL];
+                    LnP[r + PF] = PAIR ? Tin[base + LS + LO + q + PF * NL] : (R)0;
+                }
+            }
             const uint32_t kind = inf_r & 7;
             const bool cap = kind == K_CAP;
             const R T = Tc[r], Tl = Lc[r];
@@ -173,8 +201,8 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
                 Tnr = sn[r * NPL * WAVE + lane];
                 if constexpr (PAIR) Lnr = sn[(r * NPL + 1) * WAVE + lane];
             } else {
-                Tnr = Tin[base + LS + q];
-                if constexpr (PAIR) Lnr = Tin[base + LS + LO + q];
+                Tnr = TnP[r];
+                if constexpr (PAIR) Lnr = LnP[r];
             }
             const R Tw = (r > 0) ? Tc[r - 1] : TwF;
             const R Te = (r < RPL - 1) ? Tc[r + 1] : TeL;
