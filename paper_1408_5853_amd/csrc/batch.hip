@@ -18,6 +18,7 @@ constexpr int GRAPH_STEPS = 32;      // steps per captured graph block (even)
 
 struct Bucket {
     int rpl, wpl;
+    bool cube;                       // every capacity exponent is 3
     std::vector<int> inst;           // instance indices
     std::vector<int2> map;           // workgroup -> (instance, workgroup of instance)
     size_t desc_off = 0, map_off = 0;  // byte offsets in the device block
@@ -55,7 +56,7 @@ static int64_t abi_elems(const cryo_plan *p) {
 // descriptor builders live with the kernels (forward.hip)
 size_t step_desc_bytes(cryo_dtype dt);
 void step_desc_fill(const cryo_plan *p, void *out, void *buf0, void *buf1, int *flag);
-cryo_status launch_step_batch(cryo_dtype dt, int rpl, int wpl, const void *desc,
+cryo_status launch_step_batch(cryo_dtype dt, int rpl, int wpl, bool cube, const void *desc,
                               const int2 *map, int nwg, size_t lds, int64_t n,
                               const int64_t *k0, hipStream_t s);
 cryo_status launch_set_i64(int64_t *ptr, int64_t v, hipStream_t s);
@@ -88,12 +89,13 @@ static cryo_status batch_build_buckets(cryo_batch *b) {
     std::map<int, int> idx;
     for (size_t i = 0; i < b->plans.size(); ++i) {
         const cryo_plan *p = b->plans[i];
-        int key = p->rpl * 10 + p->wpl;
+        int key = p->rpl * 10 + p->wpl + (p->laws.cube ? 1000 : 0);
         if (!idx.count(key)) {
             idx[key] = (int)b->buckets.size();
             Bucket bk;
             bk.rpl = p->rpl;
             bk.wpl = p->wpl;
+            bk.cube = p->laws.cube != 0;
             b->buckets.push_back(bk);
         }
         Bucket &bk = b->buckets[idx[key]];
@@ -234,7 +236,7 @@ cryo_status cryo_batch_forward(cryo_batch *b, void *T, int64_t k0, int64_t nstep
                 for (int i : bk.inst) lds = std::max(lds, step_lds(b->plans[i]));
                 (void)p0;
                 cryo_status r = launch_step_batch(
-                    b->dtype, bk.rpl, bk.wpl, (const char *)b->d_block + bk.desc_off,
+                    b->dtype, bk.rpl, bk.wpl, bk.cube, (const char *)b->d_block + bk.desc_off,
                     (const int2 *)((const char *)b->d_block + bk.map_off), (int)bk.map.size(),
                     lds, m, k0p, strm);
                 if (r != CRYO_OK) return r;

@@ -50,10 +50,15 @@ struct LawLds<double> {
     __device__ inline double expo(int id) const { return blk[id * POW_BLK + POW_BE]; }
     // K[id] T^e[id]; T off the table range (or not finite) is clamped to its
     // edge binade, so callers check the range themselves (in_range)
-    __device__ inline double lawc(int id, double x) const {
+    __device__ inline double lawc(int id, double x) const { return pw<1>(id, x); }
+    // K[id] (s/2)^e[id]: the law at the mean of two values given their sum s
+    // (halving only moves the binade: same tables, index one binade lower)
+    __device__ inline double lawm(int id, double s) const { return pw<2>(id, s); }
+    template <int SH>
+    __device__ inline double pw(int id, double x) const {
         const double mh = __builtin_amdgcn_frexp_mant(x);          // x = mh 2^xe, mh in [1/2, 1)
         const int xe = __builtin_amdgcn_frexp_exp(x);
-        const int xc = min(max(xe, POW_EMIN + 1), POW_EMIN + POW_NE) - (POW_EMIN + 1);
+        const int xc = min(max(xe, POW_EMIN + SH), POW_EMIN + POW_NE + SH - 1) - (POW_EMIN + SH);
         const int hi = (int)(__double_as_longlong(x) >> 32);
         const int jm = (hi >> (20 - POW_MBITS)) & (POW_NM - 1);
         const double *B = blk + id * POW_BLK;
@@ -83,14 +88,15 @@ struct LawLds<double> {
     }
 };
 
+// FP32: 2^(e log2 s + lk); the stepping kernel's tables hold lk = log2 K - e,
+// so that s is the sum of the two values whose mean the law is taken at
 template <>
 struct LawLds<float> {
     const float *lk, *ex, *ck, *ca;
     static __device__ inline bool in_range(float) { return true; }
-    __device__ inline float lawc(int id, float x) const {
-        return exp2f(fmaf(ex[id], log2f(x), lk[id]));
+    __device__ inline float lawm(int id, float s) const {
+        return exp2f(fmaf(ex[id], log2f(s), lk[id]));
     }
-    __device__ inline float law(int id, float x, int &) const { return lawc(id, x); }
     __device__ inline float cube(int id, float x) const { return fmaf(ck[id], x * x * x, ca[id]); }
 };
 
@@ -118,6 +124,18 @@ struct StepArgs {
 
 constexpr int STEP_WAVES = STEP_WAVES_HOST;
 
+// v of lane (idx4 / 4) mod 64: the permute takes address bits 7:2 as the
+// source lane, so idx4 = 4 lane + (256 - 4 s) reads lane - s around the wave
+// and the constant folds into the instruction's offset field
+__device__ inline float lane_read(float v, int idx4) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(idx4, __builtin_bit_cast(int, v)));
+}
+__device__ inline double lane_read(double v, int idx4) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_ds_bpermute(idx4, (int)b);
+    const int hi = __builtin_amdgcn_ds_bpermute(idx4, (int)(b >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
 template <typename R>
 __device__ inline R shfl_up1(R v, int s, int lane) {
     R u = __shfl_up(v, s, WAVE);
@@ -185,8 +203,18 @@ __device__ inline void solve_tail(R a0, R b0, R c0, R d0, R (&al)[RPL], R (&ga)[
     }
     const R isb = rcp(sb);
     const R sig = a0 * isb, tau = sc * isb, rho = sd * isb;   // x_0 = rho - sig x_e(k-1) - tau x_e(k)
-    R sigN = shfl_dn1(sig, 1, lane), tauN = shfl_dn1(tau, 1, lane);
-    R rhoN = shfl_dn1(rho, 1, lane);
+    // Lane reads wrap around the wave: a value from past either end only meets
+    // a coefficient that is exactly zero there (the line's first row has no
+    // west coupling, its last no east coupling, the spikes zero the wave
+    // ends, and cyclic reduction keeps couplings beyond the ends zero), and
+    // every lane's values are finite, so no select is needed.
+    // (l4 is opaque to the optimiser: the twelve addresses are formed here,
+    // not hoisted out of the caller's loop into registers held throughout)
+    int l4 = lane << 2;
+    asm volatile("" : "+v"(l4));
+    const int up1 = l4 + 4 * (WAVE - 1), dn1 = l4 + 4;
+    R sigN = lane_read(sig, dn1), tauN = lane_read(tau, dn1);
+    R rhoN = lane_read(rho, dn1);
     if constexpr (G > 1) {
         if (lane == 0) {
             xch[3 * wig + 0] = sig;
@@ -228,15 +256,16 @@ __device__ inline void solve_tail(R a0, R b0, R c0, R d0, R (&al)[RPL], R (&ga)[
     }
 #pragma unroll
     for (int s = 1; s < WAVE; s <<= 1) {
-        const R Am = shfl_up1(A, s, lane), Cm = shfl_up1(C, s, lane), Dm = shfl_up1(D, s, lane);
-        const R Ap = shfl_dn1(A, s, lane), Cp = shfl_dn1(C, s, lane), Dp = shfl_dn1(D, s, lane);
+        const int iu = l4 + 4 * (WAVE - s), id = l4 + 4 * s;
+        const R Am = lane_read(A, iu), Cm = lane_read(C, iu), Dm = lane_read(D, iu);
+        const R Ap = lane_read(A, id), Cp = lane_read(C, id), Dp = lane_read(D, id);
         const R ib = rcp((R)1 - A * Cm - C * Ap);
         const R nA = -A * Am * ib;
         const R nC = -C * Cp * ib;
         const R nD = (D - A * Dm - C * Dp) * ib;
         if constexpr (G > 1) {
-            const R PLm = shfl_up1(PL, s, lane), PLp = shfl_dn1(PL, s, lane);
-            const R PRm = shfl_up1(PR, s, lane), PRp = shfl_dn1(PR, s, lane);
+            const R PLm = lane_read(PL, iu), PLp = lane_read(PL, id);
+            const R PRm = lane_read(PR, iu), PRp = lane_read(PR, id);
             PL = (PL - A * PLm - C * PLp) * ib;
             PR = (PR - A * PRm - C * PRp) * ib;
         }
@@ -291,7 +320,7 @@ __device__ inline void solve_tail(R a0, R b0, R c0, R d0, R (&al)[RPL], R (&ga)[
         }
         xe = D + vL * uL + vR * uR;
     }
-    R xeP = shfl_up1(xe, 1, lane);
+    R xeP = lane_read(xe, up1);
     if (G > 1 && lane == 0) xeP = uL;
     const R x0 = rho - sig * xeP - tau * xe;
 #pragma unroll

@@ -30,7 +30,8 @@ namespace cryo {
 // the current and the next line: the north-face flux of line j is the
 // south-face flux of line j+1 (eq. (11)), so a capacity row evaluates two
 // conductivities per line (east r-face, north z-face) instead of three.
-template <typename R, int RPL, int G>
+// CUBE: every capacity law has exponent 3 (c(T) by multiplication).
+template <typename R, int RPL, int G, bool CUBE>
 __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *__restrict__ Tin,
                                  R *__restrict__ Tout, const R X, double *partial) {
     constexpr bool PAIR = Pair<R>::on;
@@ -135,7 +136,8 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
             const uint32_t inf_r = sinf[q];
             const bool cap = (inf_r & 7) == K_CAP;
             const int l2 = (inf_r >> 12) & 63;
-            const R lamS = law.law(cap ? l2 : law_zero(L), (R)0.5 * (Tc[r] + Tp), bad);
+            if constexpr (!PAIR) bad |= !LawLds<R>::in_range(Tp);
+            const R lamS = law.lawm(cap ? l2 : law_zero(L), Tc[r] + Tp);
             fs_set(r, lamS * dif<R>(Tc[r], Lc[r], Tp, Tpl));
             if (r & 1) __builtin_amdgcn_sched_barrier(0);      // register pressure
         }
@@ -165,7 +167,7 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
             }
         }
         // west face of the chunk's first row: east face of the previous row
-        R lamW = law.law((sinf[qW] >> 6) & 63, (R)0.5 * (TwF + Tc[0]), bad);
+        R lamW = law.lawm((sinf[qW] >> 6) & 63, TwF + Tc[0]);
         R a0 = 0, b0 = 1, c0 = 0, d0 = 0;
         R al[RPL], ga[RPL], de[RPL];
         // without the ring: the next line's values come from memory two rows
@@ -209,26 +211,32 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
             const R Lw = (r > 0) ? Lc[r - 1] : LwF;
             const R Le = (r < RPL - 1) ? Lc[r + 1] : LeL;
             const int le = (inf_r >> 6) & 63, l2 = (inf_r >> 12) & 63;
-            const int l3 = (inf_r >> 18) & 63, lc = (inf_r >> 24) & 63;
+            const int lc = (inf_r >> 24) & 63;
             // every face mean lies between two nodes: one range check per node
             if constexpr (!PAIR) bad |= !LawLds<R>::in_range(T);
-            const R lamE = law.lawc(le, (R)0.5 * (T + Te));
-            // slot 2: north axial face (capacity) or inner-layer law at the node
-            const R lam2 = law.lawc(l2, cap ? (R)0.5 * (T + Tnr) : T);
-            // slot 3: outer-layer law at an interface node; unit or zero otherwise
-            R lam3 = l3 == law_unit(L) ? (R)1 : (R)0;
-            if (__any(kind == K_IFACE)) {
-                const R v = law.lawc(l3, T);
-                lam3 = kind == K_IFACE ? v : lam3;
-            }
-            const R rc = a.laws.cube ? law.cube(lc, T) : law.lawc(lc, T);
+            // laws are evaluated from the sum of the two values they average
+            const R lamE = law.lawm(le, T + Te);
+            // (16 rows per lane: the two evaluations one after the other, or
+            // the scheduler hoists both sets of table reads at once)
+            if (RPL >= 16) __builtin_amdgcn_sched_barrier(0);
+            // slot 2: the north axial face of a capacity row (the row's radial
+            // law: capacity rows are scaled by eta^2), the ratio of the inner
+            // to the outer layer's law at an interface node (its row divided
+            // by the outer law), or unit / zero (boundary, padding)
+            const R lam2 = law.lawm(l2, T + (cap ? Tnr : T));
+            R rc;
+            if constexpr (CUBE) rc = law.cube(lc, T);
+            else rc = law.lawm(lc, T + T);
             const R fw = sgw[q] * (cap ? lamW : lam2);
-            const R fe = sge[q] * (cap ? lamE : lam3);
+            const R fe = sge[q] * (cap ? lamE : (R)1);
             const R FN = lam2 * dif<R>(Tnr, Lnr, T, Tl);
             R dd = fw * dif<R>(Tw, Lw, T, Tl) + fe * dif<R>(Te, Le, T, Tl);
             dd += cap ? FN - fs_get(r) : (R)0;
             dd += (R)((inf_r >> 3) & 1) * X;                // heater capacity rows
-            if ((inf_r >> 4) & 1) dd = dif<R>(a.val[(inf_r >> 5) & 1], (R)0, T, Tl);
+            // held walls: rows 0 and nr - 1 are unit rows with dT = value - T
+            if (r == 0 && a.held[0]) dd = lg == 0 ? dif<R>(a.val[0], (R)0, T, Tl) : dd;
+            if (r == a.surf_reg && a.held[1])
+                dd = lg == a.surf_lane ? dif<R>(a.val[1], (R)0, T, Tl) : dd;
             fs_set(r, FN);
             lamW = lamE;
             const R aa = -fw, bb = fw + fe + rc, cc = -fe;
@@ -339,9 +347,10 @@ __device__ inline int xcd_block(int b, int nb) {
     return x * per + min(x, rem) + i;
 }
 
-template <typename R, int RPL, int G>
+template <typename R, int RPL, int G, bool CUBE>
 __global__ __launch_bounds__(STEP_WAVES *WAVE) void k_step(StepArgs<R> a) {
-    step_body<R, RPL, G>(a, xcd_block(blockIdx.x, gridDim.x), a.Tin, a.Tout, a.X, a.partial);
+    step_body<R, RPL, G, CUBE>(a, xcd_block(blockIdx.x, gridDim.x), a.Tin, a.Tout, a.X,
+                               a.partial);
 }
 
 // Pulse average over step k (eq. (4)), step units; the host's schedule.
@@ -362,7 +371,7 @@ __device__ inline double source_fraction_dev(const Pulse &p, int64_t k) {
 
 // One step of many instances: workgroup -> (instance, workgroup of that
 // instance); global step k = *k0 + n; buffers by the parity of n.
-template <typename R, int RPL, int G>
+template <typename R, int RPL, int G, bool CUBE>
 __global__ __launch_bounds__(STEP_WAVES *WAVE) void k_step_batch(const StepArgs<R> *descs,
                                                                  const int2 *wg_map, int64_t n,
                                                                  const int64_t *k0) {
@@ -370,7 +379,7 @@ __global__ __launch_bounds__(STEP_WAVES *WAVE) void k_step_batch(const StepArgs<
     const StepArgs<R> &a = descs[m.x];
     const double X = a.pulse.amplitude * source_fraction_dev(a.pulse, *k0 + n);
     double *part = a.partial ? a.partial + (size_t)(n % SURF_CHUNK) * a.groups : nullptr;
-    step_body<R, RPL, G>(a, m.y, a.buf[n & 1], a.buf[(n + 1) & 1], (R)X, part);
+    step_body<R, RPL, G, CUBE>(a, m.y, a.buf[n & 1], a.buf[(n + 1) & 1], (R)X, part);
 }
 
 // ABI field -> internal lines.  FP32 fields are two planes [2][nz][nr]
@@ -483,22 +492,27 @@ cryo_status launch_fill(const cryo_plan *p, void *T, hipStream_t s) {
     return launch_check("fill");
 }
 
+// Arguments of the stepping kernel (its row tables and laws: capacity rows
+// scaled by eta^2, so the source is too), or with `rows_as_written` the
+// tables of the rows as the equations write them (adjoint kernels).
 template <typename R>
 static StepArgs<R> step_args(const cryo_plan *p, const void *Tin, void *Tout, double X,
-                             double *partial, int *flag) {
+                             double *partial, int *flag, bool rows_as_written = false) {
     StepArgs<R> a;
+    const bool f = !rows_as_written;
+    const double xs = f ? p->eta * p->eta : 1.0;
     a.flag = flag;
     a.Tin = (const R *)Tin;
     a.Tout = (R *)Tout;
-    a.gw = (const R *)p->d_rows;
+    a.gw = (const R *)p->d_rows + (f ? 2 * (size_t)p->np : 0);
     a.ge = a.gw + p->np;
-    a.info = p->d_info;
-    a.pow_blob = p->d_pow;
-    a.laws = p->laws;
+    a.info = p->d_info + (f ? p->np : 0);
+    a.pow_blob = p->d_pow + (f ? p->pow_blob.size() : 0);
+    a.laws = f ? p->flaws : p->laws;
     a.nz = p->nz;
     a.np = p->np;
     a.lpw = p->lpw;
-    a.X = (R)X;
+    a.X = (R)(X * xs);
     for (int s = 0; s < 4; ++s) {
         a.held[s] = p->prob.bc.kind[s] == CRYO_HELD;
         a.val[s] = (R)p->prob.bc.value[s];
@@ -510,6 +524,7 @@ static StepArgs<R> step_args(const cryo_plan *p, const void *Tin, void *Tout, do
     a.surf_reg = p->surf_reg;
     a.groups = step_grid(p);
     a.pulse = p->pulse;
+    a.pulse.amplitude *= xs;
     a.buf[0] = a.buf[1] = nullptr;
     return a;
 }
@@ -523,7 +538,10 @@ static cryo_status step_t(const cryo_plan *p, const void *Tin, void *Tout, doubl
     const int key = p->rpl * 10 + p->wpl;
     switch (key) {
 #define STEP_CASE(RP, GW) \
-    case RP * 10 + GW: hipLaunchKernelGGL((k_step<R, RP, GW>), g, b, lds, s, a); break;
+    case RP * 10 + GW: \
+        if (a.laws.cube) hipLaunchKernelGGL((k_step<R, RP, GW, true>), g, b, lds, s, a); \
+        else hipLaunchKernelGGL((k_step<R, RP, GW, false>), g, b, lds, s, a); \
+        break;
         CRYO_FOR_SHAPES(STEP_CASE)
 #undef STEP_CASE
     default: return fail(CRYO_ERR_UNSUPPORTED, "radial chunk shape");
@@ -573,14 +591,18 @@ void step_desc_fill(const cryo_plan *p, void *out, void *buf0, void *buf1, int *
 }
 
 template <typename R>
-static cryo_status step_batch_t(int rpl, int wpl, const void *desc, const int2 *map, int nwg,
-                                size_t lds, int64_t n, const int64_t *k0, hipStream_t s) {
+static cryo_status step_batch_t(int rpl, int wpl, bool cube, const void *desc, const int2 *map,
+                                int nwg, size_t lds, int64_t n, const int64_t *k0,
+                                hipStream_t s) {
     const StepArgs<R> *d = (const StepArgs<R> *)desc;
     dim3 g(nwg), b(STEP_WAVES * WAVE);
     switch (rpl * 10 + wpl) {
 #define BATCH_CASE(RP, GW) \
     case RP * 10 + GW: \
-        hipLaunchKernelGGL((k_step_batch<R, RP, GW>), g, b, lds, s, d, map, n, k0); \
+        if (cube) \
+            hipLaunchKernelGGL((k_step_batch<R, RP, GW, true>), g, b, lds, s, d, map, n, k0); \
+        else \
+            hipLaunchKernelGGL((k_step_batch<R, RP, GW, false>), g, b, lds, s, d, map, n, k0); \
         break;
         CRYO_FOR_SHAPES(BATCH_CASE)
 #undef BATCH_CASE
@@ -589,10 +611,11 @@ static cryo_status step_batch_t(int rpl, int wpl, const void *desc, const int2 *
     return launch_check("step_batch");
 }
 
-cryo_status launch_step_batch(cryo_dtype dt, int rpl, int wpl, const void *desc, const int2 *map,
-                              int nwg, size_t lds, int64_t n, const int64_t *k0, hipStream_t s) {
-    return dt == CRYO_F64 ? step_batch_t<double>(rpl, wpl, desc, map, nwg, lds, n, k0, s)
-                          : step_batch_t<float>(rpl, wpl, desc, map, nwg, lds, n, k0, s);
+cryo_status launch_step_batch(cryo_dtype dt, int rpl, int wpl, bool cube, const void *desc,
+                              const int2 *map, int nwg, size_t lds, int64_t n, const int64_t *k0,
+                              hipStream_t s) {
+    return dt == CRYO_F64 ? step_batch_t<double>(rpl, wpl, cube, desc, map, nwg, lds, n, k0, s)
+                          : step_batch_t<float>(rpl, wpl, cube, desc, map, nwg, lds, n, k0, s);
 }
 
 __global__ void k_set_i64(int64_t *p, int64_t v) { *p = v; }
@@ -612,6 +635,6 @@ cryo_status launch_add_i64(int64_t *ptr, int64_t v, hipStream_t s) {
 
 namespace cryo {
 StepArgs<double> step_args_f64(const cryo_plan *p, int *flag) {
-    return step_args<double>(p, nullptr, nullptr, 0.0, nullptr, flag);
+    return step_args<double>(p, nullptr, nullptr, 0.0, nullptr, flag, true);
 }
 }  // namespace cryo

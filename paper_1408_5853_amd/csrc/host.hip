@@ -42,6 +42,34 @@ double source_fraction(const Pulse &p, int64_t k) {
     return s;
 }
 
+// FP64 power tables (see POW_*): one block per law id, then the cube path's
+// multipliers and addends (K T^3 + A)
+static void fill_pow_blob(const Laws &lw, std::vector<double> &blob) {
+    const int L = lw.L, nlaw = 3 * L + 2, UNIT = law_unit(L);
+    blob.assign(pow_blob_doubles(L), 0.0);
+    double *B = blob.data();
+    double *CK = B + (size_t)nlaw * POW_BLK, *CA = CK + nlaw;
+    for (int id = 0; id < nlaw; ++id) {
+        const double e = lw.e[id];
+        double *R = B + (size_t)id * POW_BLK;
+        for (int j = 0; j < POW_NM; ++j) {
+            const double m0 = 1.0 + (j + 0.5) / POW_NM;
+            R[2 * j] = pow(m0, e);
+            R[2 * j + 1] = 2.0 / m0;          // applied to the frexp mantissa in [1/2, 1)
+        }
+        for (int x = 0; x < POW_NE; ++x) R[POW_BX + x] = lw.K[id] * exp2(e * (x + POW_EMIN));
+        R[POW_BE] = e;
+        // binomial coefficients of (1 + u)^e, k = 2..POW_DEG
+        double c = e;
+        for (int k = 2; k <= POW_DEG; ++k) {
+            c = c * (e - (k - 1)) / k;
+            R[POW_BE + k] = c;
+        }
+        CK[id] = (id >= 2 * L && id < 3 * L) ? lw.K[id] : 0.0;
+        CA[id] = id == UNIT ? 1.0 : 0.0;
+    }
+}
+
 static cryo_status check_problem(const cryo_problem *pr) {
     if (!pr) return fail(CRYO_ERR_ARG, "null problem");
     const cryo_geometry &g = pr->geom;
@@ -132,25 +160,31 @@ cryo_status ensure_device(cryo_plan *p) {
     (void)hipGetDevice(&p->device);
     const int np = p->np;
     size_t es = p->dtype == CRYO_F64 ? sizeof(double) : sizeof(float);
-    // one array of two planes: gw, ge
+    // one array of four planes: gw, ge, fgw, fge
     std::vector<double> rows(p->gw);
     rows.insert(rows.end(), p->ge.begin(), p->ge.end());
-    hipError_t e = hipMalloc(&p->d_rows, es * 2 * np);
+    rows.insert(rows.end(), p->fgw.begin(), p->fgw.end());
+    rows.insert(rows.end(), p->fge.begin(), p->fge.end());
+    std::vector<uint32_t> infos(p->info);
+    infos.insert(infos.end(), p->finfo.begin(), p->finfo.end());
+    std::vector<double> blobs(p->pow_blob);
+    blobs.insert(blobs.end(), p->fpow_blob.begin(), p->fpow_blob.end());
+    hipError_t e = hipMalloc(&p->d_rows, es * 4 * np);
     uint32_t *info = nullptr;
-    if (e == hipSuccess) e = hipMalloc((void **)&info, sizeof(uint32_t) * np);
+    if (e == hipSuccess) e = hipMalloc((void **)&info, sizeof(uint32_t) * 2 * np);
     if (e == hipSuccess) {
         if (p->dtype == CRYO_F64) {
-            e = hipMemcpy(p->d_rows, rows.data(), es * 2 * np, hipMemcpyHostToDevice);
+            e = hipMemcpy(p->d_rows, rows.data(), es * 4 * np, hipMemcpyHostToDevice);
         } else {
             std::vector<float> a(rows.begin(), rows.end());
-            e = hipMemcpy(p->d_rows, a.data(), es * 2 * np, hipMemcpyHostToDevice);
+            e = hipMemcpy(p->d_rows, a.data(), es * 4 * np, hipMemcpyHostToDevice);
         }
     }
     if (e == hipSuccess)
-        e = hipMemcpy(info, p->info.data(), sizeof(uint32_t) * np, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMalloc((void **)&p->d_pow, sizeof(double) * p->pow_blob.size());
+        e = hipMemcpy(info, infos.data(), sizeof(uint32_t) * 2 * np, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc((void **)&p->d_pow, sizeof(double) * blobs.size());
     if (e == hipSuccess)
-        e = hipMemcpy(p->d_pow, p->pow_blob.data(), sizeof(double) * p->pow_blob.size(),
+        e = hipMemcpy(p->d_pow, blobs.data(), sizeof(double) * blobs.size(),
                       hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         if (p->d_rows) (void)hipFree(p->d_rows);
@@ -171,9 +205,13 @@ static void build_row_tables(cryo_plan *p) {
     const int nr = p->nr, L = p->L, np = p->np, rpl = p->rpl;
     const int ZERO = law_zero(L), UNIT = law_unit(L);
     int i;
+    const double e2 = p->eta * p->eta;
     p->gw.assign(np, 0.0);
     p->ge.assign(np, 0.0);
     p->info.assign(np, info_pack(K_PAD, 0, 0, 0, ZERO, ZERO, ZERO, UNIT));
+    p->fgw.assign(np, 0.0);
+    p->fge.assign(np, 0.0);
+    p->finfo = p->info;
     const int *bk = prob->bc.kind;
     for (i = 0; i < nr; ++i) {
         int idx = (i % rpl) * (WAVE * p->wpl) + i / rpl;
@@ -207,6 +245,26 @@ static void build_row_tables(cryo_plan *p) {
         p->gw[idx] = gw;
         p->ge[idx] = ge;
         p->info[idx] = info_pack(kind, heat, held, side, lawE, law2, law3, lawC);
+        // the stepping kernel's form: capacity rows times eta^2 (slot 2 then
+        // takes the radial law), interface rows divided by the outer law
+        // (slot 2 the ratio law, slot 3 one); boundary rows fold their unit or
+        // zero slot laws into gw, ge
+        double fgw = gw, fge = ge;
+        uint32_t f2 = law2;
+        if (kind == K_CAP) {
+            fgw *= e2;
+            fge *= e2;
+            f2 = m;
+        } else if (kind == K_IFACE) {
+            f2 = L + p->lay[i];
+        } else {
+            fgw = law2 == (uint32_t)UNIT ? gw : 0.0;
+            fge = law3 == (uint32_t)UNIT ? ge : 0.0;
+            f2 = UNIT;
+        }
+        p->fgw[idx] = fgw;
+        p->fge[idx] = fge;
+        p->finfo[idx] = info_pack(kind, heat, held, side, lawE, f2, ZERO, lawC);
     }
     p->surf_lane = (nr - 1) / rpl;
     p->surf_reg = (nr - 1) % rpl;
@@ -302,29 +360,30 @@ cryo_status cryo_plan_create(const cryo_problem *prob, cryo_dtype dtype, cryo_pl
     lw.K[UNIT] = 1.0;
     for (int id = 0; id < nlaw; ++id) lw.lk[id] = lw.K[id] > 0 ? log2(lw.K[id]) : -2000.0;
 
-    // FP64 power tables (see POW_*): one block per law id
-    p->pow_blob.assign(pow_blob_doubles(L), 0.0);
-    double *B = p->pow_blob.data();
-    double *CK = B + (size_t)nlaw * POW_BLK, *CA = CK + nlaw;
-    for (int id = 0; id < nlaw; ++id) {
-        const double e = lw.e[id];
-        double *R = B + (size_t)id * POW_BLK;
-        for (int j = 0; j < POW_NM; ++j) {
-            const double m0 = 1.0 + (j + 0.5) / POW_NM;
-            R[2 * j] = pow(m0, e);
-            R[2 * j + 1] = 2.0 / m0;          // applied to the frexp mantissa in [1/2, 1)
+    fill_pow_blob(lw, p->pow_blob);
+
+    // the stepping kernel's laws (see Laws): capacity rows scaled by eta^2,
+    // interface rows by 1 / (outer law); FP32 takes log2 K - e, its laws being
+    // evaluated from the sum of the two values they average
+    Laws &fl = p->flaws;
+    memset(&fl, 0, sizeof(fl));
+    fl.L = L;
+    fl.cube = lw.cube;
+    const double e2 = p->eta * p->eta;
+    for (int m = 0; m < L; ++m) {
+        fl.K[m] = lw.K[m];
+        fl.e[m] = lw.e[m];
+        fl.K[2 * L + m] = lw.K[2 * L + m] * e2;
+        fl.e[2 * L + m] = lw.e[2 * L + m];
+        if (m + 1 < L) {
+            fl.K[L + m] = lw.K[m] / lw.K[m + 1];
+            fl.e[L + m] = lw.e[m] - lw.e[m + 1];
         }
-        for (int x = 0; x < POW_NE; ++x) R[POW_BX + x] = lw.K[id] * exp2(e * (x + POW_EMIN));
-        R[POW_BE] = e;
-        // binomial coefficients of (1 + u)^e, k = 2..POW_DEG
-        double c = e;
-        for (int k = 2; k <= POW_DEG; ++k) {
-            c = c * (e - (k - 1)) / k;
-            R[POW_BE + k] = c;
-        }
-        CK[id] = (id >= 2 * L && id < 3 * L) ? lw.K[id] : 0.0;   // cube path: K T^3 + A
-        CA[id] = id == UNIT ? 1.0 : 0.0;
     }
+    fl.K[UNIT] = 1.0;
+    for (int id = 0; id < nlaw; ++id)
+        fl.lk[id] = fl.K[id] > 0 ? log2(fl.K[id]) - fl.e[id] : -2000.0;
+    fill_pow_blob(fl, p->fpow_blob);
 
     if (step_lds(p) > MAX_STEP_LDS) {
         delete p;

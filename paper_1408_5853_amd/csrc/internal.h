@@ -41,6 +41,13 @@ enum RowKind : uint32_t { K_PAD = 0, K_LO = 1, K_HI = 2, K_CAP = 3, K_IFACE = 4 
 //   ids 2L..3L-1  rho c / dt of layer m:           K = rho c0 tref^-q / dt, e = q
 //   id  3L        zero law (value 0),  id 3L+1  unit law (value 1)
 // value = K * T^e.  Exponent rows: 0..L-1 hold p_m, L..2L-1 hold q_m, 2L is 0.
+// The stepping kernel has a second law set (`flaws`) in which every capacity
+// row is multiplied by eta^2 (so its axial faces use the radial law) and
+// every interface row is divided by the outer layer's law:
+//   ids 0..L-1    radial conductivity of layer m (as above)
+//   ids L..2L-2   lambda_m / lambda_{m+1}: K = K_m / K_{m+1}, e = p_m - p_{m+1}
+//   ids 2L..3L-1  eta^2 rho c / dt of layer m
+//   zero and unit laws as above.
 constexpr int MAX_LAWS = 3 * MAX_LAYERS + 2;
 __host__ __device__ inline int law_zero(int L) { return 3 * L; }
 __host__ __device__ inline int law_unit(int L) { return 3 * L + 1; }
@@ -53,7 +60,10 @@ __host__ __device__ inline int law_unit(int L) { return 3 * L + 1; }
 // used by capacity rows (their south face is the previous line's north
 // face); an interface row (eq. (18)) evaluates its inner and outer layer laws
 // at the node in slots 2 and 3; boundary and padding rows use the zero and
-// unit laws so that one formula serves every row.
+// unit laws so that one formula serves every row.  The stepping kernel's
+// words (`finfo`, law ids of `flaws`): slot 2 of a capacity row is the
+// radial law of its layer, slot 2 of an interface row the ratio law, slot 3
+// is unused, and held walls are found by position (rows 0 and nr - 1).
 __host__ __device__ inline uint32_t info_pack(uint32_t kind, uint32_t heat, uint32_t held,
                                               uint32_t side, uint32_t lawE, uint32_t law2,
                                               uint32_t law3, uint32_t lawC) {
@@ -112,17 +122,23 @@ struct cryo_plan {
     std::vector<double> r, h;         // node radii, interval widths (h[0] unused)
     std::vector<int> lay;             // layer of interval i
     std::vector<int> kind;            // row class per node
-    // host copies of the lane-major tables
+    // host copies of the lane-major tables: rows of eqs. (13), (15), (18) as
+    // written (adjoint), and the stepping kernel's form of the same rows
+    // (capacity rows times eta^2, interface rows divided by the outer law)
     std::vector<double> gw, ge;
     std::vector<uint32_t> info;
     cryo::Laws laws;
     std::vector<double> pow_blob;     // FP64 power tables (see POW_*)
+    std::vector<double> fgw, fge;
+    std::vector<uint32_t> finfo;
+    cryo::Laws flaws;
+    std::vector<double> fpow_blob;
     cryo::Pulse pulse;
     int surf_lane, surf_reg;          // owner of row nr-1
     // device tables (read-only, made at create time)
-    void *d_rows = nullptr;           // [2][np]: gw, ge
-    uint32_t *d_info = nullptr;
-    double *d_pow = nullptr;
+    void *d_rows = nullptr;           // [4][np]: gw, ge, fgw, fge
+    uint32_t *d_info = nullptr;       // [2][np]: info, finfo
+    double *d_pow = nullptr;          // pow_blob, then fpow_blob
     int device = 0;
 };
 
