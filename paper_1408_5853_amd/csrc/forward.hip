@@ -206,6 +206,9 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
                 Tnr = TnP[r];
                 if constexpr (PAIR) Lnr = LnP[r];
             }
+            // read unconditionally at the row's start: a read under the
+            // capacity test becomes a branch that waits for it at once
+            const R FS = fs_get(r);
             const R Tw = (r > 0) ? Tc[r - 1] : TwF;
             const R Te = (r < RPL - 1) ? Tc[r + 1] : TeL;
             const R Lw = (r > 0) ? Lc[r - 1] : LwF;
@@ -216,9 +219,6 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
             if constexpr (!PAIR) bad |= !LawLds<R>::in_range(T);
             // laws are evaluated from the sum of the two values they average
             const R lamE = law.lawm(le, T + Te);
-            // (16 rows per lane: the two evaluations one after the other, or
-            // the scheduler hoists both sets of table reads at once)
-            if (RPL >= 16) __builtin_amdgcn_sched_barrier(0);
             // slot 2: the north axial face of a capacity row (the row's radial
             // law: capacity rows are scaled by eta^2), the ratio of the inner
             // to the outer layer's law at an interface node (its row divided
@@ -231,7 +231,7 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
             const R fe = sge[q] * (cap ? lamE : (R)1);
             const R FN = lam2 * dif<R>(Tnr, Lnr, T, Tl);
             R dd = fw * dif<R>(Tw, Lw, T, Tl) + fe * dif<R>(Te, Le, T, Tl);
-            dd += cap ? FN - fs_get(r) : (R)0;
+            dd += cap ? FN - FS : (R)0;
             dd += (R)((inf_r >> 3) & 1) * X;                // heater capacity rows
             // held walls: rows 0 and nr - 1 are unit rows with dT = value - T
             if (r == 0 && a.held[0]) dd = lg == 0 ? dif<R>(a.val[0], (R)0, T, Tl) : dd;
@@ -308,16 +308,17 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
                 if (j == a.nz - 2) sv += a.wz_end * (a.held[3] ? (double)a.val[3] : v);
             }
         }
-        // next line: registers from its slot, or from memory
-        const size_t bn = (size_t)min(j + 1, a.nz - 2) * LS;
+        // next line: registers from its ring slot, or the values the rows
+        // read as their north neighbours (line j + 1; past the last interior
+        // line only inactive iterations use them)
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
             if constexpr (RING) {
                 Tc[r] = sn[r * NPL * WAVE + lane];
                 Lc[r] = PAIR ? sn[(r * NPL + 1) * WAVE + lane] : (R)0;
             } else {
-                Tc[r] = Tin[bn + r * NL + lg];
-                Lc[r] = PAIR ? Tin[bn + LO + r * NL + lg] : (R)0;
+                Tc[r] = TnP[r];
+                Lc[r] = LnP[r];
             }
         }
         TwF = TwP;
