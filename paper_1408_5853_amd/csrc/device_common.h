@@ -24,9 +24,10 @@ template <>
 __device__ inline float ex2<float>(float x) { return exp2f(x); }
 
 // reciprocal: hardware estimate (relative error below 5e-8 on gfx950)
-// refined by one Newton step (below 3e-15).  Every solve here works in
-// delta form, so a pivot off by that much perturbs only the increment, by
-// a relative 3e-15.
+// refined by one Newton step (below 3e-15).  The step's solves work in delta
+// form, so a pivot off by that much perturbs only the increment, by a
+// relative 3e-15; the adjoint's uses (transposed solves, derivative factors)
+// carry it into the gradient at the same relative size.
 __device__ inline double rcp(double x) {
     const double r = __builtin_amdgcn_rcp(x);
     return fma(fma(-x, r, 1.0), r, r);
