@@ -231,7 +231,7 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj1(StepArgs<double> a, Ad
                 double rc, drc;
                 if (a.laws.cube) {
                     rc = law.cube(lc, t);
-                    drc = 3.0 * law.ck[lc] * t * t;
+                    drc = 3.0 * law.cka[2 * lc] * t * t;
                 } else {
                     rc = law.lawc(lc, t);
                     drc = law.expo(lc) * rc * rcp(t);

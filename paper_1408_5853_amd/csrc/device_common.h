@@ -44,7 +44,7 @@ struct LawLds;
 template <>
 struct LawLds<double> {
     const double *blk;      // law blocks (POW_BLK doubles per law id)
-    const double *ck, *ca;  // cube path: K T^3 + A
+    const double *cka;      // cube path: K T^3 + A, pairs {K, A} per law id
     // T on the table range [2^POW_EMIN, 2^(POW_EMIN+POW_NE)) K
     static __device__ inline bool in_range(double x) {
         return x >= POW_TLO && x < POW_THI;
@@ -84,7 +84,8 @@ struct LawLds<double> {
         return lawc(id, x);
     }
     __device__ inline double cube(int id, double x) const {
-        return fma(ck[id], x * x * x, ca[id]);
+        const double2 k = *(const double2 *)(cka + 2 * id);
+        return fma(k.x, x * x * x, k.y);
     }
 };
 
@@ -92,12 +93,15 @@ struct LawLds<double> {
 // so that s is the sum of the two values whose mean the law is taken at
 template <>
 struct LawLds<float> {
-    const float *lk, *ex, *ck, *ca;
+    const float *lk, *ex, *cka;
     static __device__ inline bool in_range(float) { return true; }
     __device__ inline float lawm(int id, float s) const {
         return exp2f(fmaf(ex[id], log2f(s), lk[id]));
     }
-    __device__ inline float cube(int id, float x) const { return fmaf(ck[id], x * x * x, ca[id]); }
+    __device__ inline float cube(int id, float x) const {
+        const float2 k = *(const float2 *)(cka + 2 * id);
+        return fmaf(k.x, x * x * x, k.y);
+    }
 };
 
 template <typename R>
@@ -405,21 +409,19 @@ __device__ inline LawLds<R> stage_laws(const StepArgs<R> &a, unsigned char *smem
         const int nb = (int)pow_blob_doubles(L);
         for (int i = t; i < nb; i += nt) d[i] = a.pow_blob[i];
         v.blk = d;
-        v.ck = d + (size_t)nlaw * POW_BLK;
-        v.ca = v.ck + nlaw;
+        v.cka = d + (size_t)nlaw * POW_BLK;
     } else {
         float *f = (float *)smem;
         for (int i = t; i < nlaw; i += nt) {
             f[i] = (float)a.laws.lk[i];
             f[nlaw + i] = (float)a.laws.e[i];
             const bool capl = i >= 2 * L && i < 3 * L;
-            f[2 * nlaw + i] = capl ? (float)a.laws.K[i] : 0.0f;
-            f[3 * nlaw + i] = i == law_unit(L) ? 1.0f : 0.0f;
+            f[2 * nlaw + 2 * i] = capl ? (float)a.laws.K[i] : 0.0f;
+            f[2 * nlaw + 2 * i + 1] = i == law_unit(L) ? 1.0f : 0.0f;
         }
         v.lk = f;
         v.ex = f + nlaw;
-        v.ck = f + 2 * nlaw;
-        v.ca = f + 3 * nlaw;
+        v.cka = f + 2 * nlaw;
     }
     __syncthreads();
     return v;

@@ -19,6 +19,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <type_traits>
+
 #include "device_common.h"
 
 namespace cryo {
@@ -35,6 +37,7 @@ template <typename R, int RPL, int G, bool CUBE>
 __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *__restrict__ Tin,
                                  R *__restrict__ Tout, const R X, double *partial) {
     constexpr bool PAIR = Pair<R>::on;
+    using R2 = std::conditional_t<sizeof(R) == 8, double2, float2>;
     constexpr int NPL = PAIR ? 2 : 1;                 // planes per line (pairs: hi, lo)
     constexpr int NL = WAVE * G;                      // lanes per line
     constexpr int NG = STEP_WAVES / G;                // lines per workgroup
@@ -144,6 +147,17 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
         // the next line's slot must have landed before the first row reads it
         if constexpr (RING) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     }
+    // the first rows of the line above the current one, loaded one line ahead
+    constexpr int PF = 2;
+    R TnQ[PF], LnQ[PF];
+    if constexpr (!RING) {
+        const size_t bq = (size_t)(min(j0, a.nz - 2) + 1) * LS;
+#pragma unroll
+        for (int r = 0; r < PF && r < RPL; ++r) {
+            TnQ[r] = Tin[bq + r * NL + lg];
+            LnQ[r] = PAIR ? Tin[bq + LO + r * NL + lg] : (R)0;
+        }
+    }
     for (int it = 0; it < a.lpw; ++it) {
         const int jr = j0 + it;
         const bool active = jr < j1;
@@ -171,14 +185,14 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
         R a0 = 0, b0 = 1, c0 = 0, d0 = 0;
         R al[RPL], ga[RPL], de[RPL];
         // without the ring: the next line's values come from memory two rows
-        // ahead of their use (software pipelined across the rows' regions)
-        constexpr int PF = 2;
+        // ahead of their use (software pipelined across the rows' regions);
+        // the first two were loaded before the previous line's solve
         R TnP[RPL], LnP[RPL];
         if constexpr (!RING) {
 #pragma unroll
             for (int r = 0; r < PF && r < RPL; ++r) {
-                TnP[r] = Tin[base + LS + r * NL + lg];
-                LnP[r] = PAIR ? Tin[base + LS + LO + r * NL + lg] : (R)0;
+                TnP[r] = TnQ[r];
+                LnP[r] = LnQ[r];
             }
         }
         // the rows' info words, one row ahead (they head each row's chain of
@@ -254,6 +268,16 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
             // keep the scheduler from hoisting every row's law evaluations
             // at once (register pressure); rows still overlap pairwise
             if (RPL >= 10 || (r & 1)) __builtin_amdgcn_sched_barrier(0);
+        }
+        if constexpr (!RING) {
+            // the next iteration's first rows above (its line is min(jr + 1,
+            // nz - 2), one past the last interior line only when inactive)
+            const size_t bq = (size_t)(min(jr + 1, a.nz - 2) + 1) * LS;
+#pragma unroll
+            for (int r = 0; r < PF && r < RPL; ++r) {
+                TnQ[r] = Tin[bq + r * NL + lg];
+                LnQ[r] = PAIR ? Tin[bq + LO + r * NL + lg] : (R)0;
+            }
         }
         R X[RPL];
         solve_tail<R, RPL, G>(a0, b0, c0, d0, al, ga, de, X, lane, wig, xch);

@@ -48,7 +48,7 @@ static void fill_pow_blob(const Laws &lw, std::vector<double> &blob) {
     const int L = lw.L, nlaw = 3 * L + 2, UNIT = law_unit(L);
     blob.assign(pow_blob_doubles(L), 0.0);
     double *B = blob.data();
-    double *CK = B + (size_t)nlaw * POW_BLK, *CA = CK + nlaw;
+    double *CKA = B + (size_t)nlaw * POW_BLK;                     // {K, A} per id
     for (int id = 0; id < nlaw; ++id) {
         const double e = lw.e[id];
         double *R = B + (size_t)id * POW_BLK;
@@ -65,8 +65,8 @@ static void fill_pow_blob(const Laws &lw, std::vector<double> &blob) {
             c = c * (e - (k - 1)) / k;
             R[POW_BE + k] = c;
         }
-        CK[id] = (id >= 2 * L && id < 3 * L) ? lw.K[id] : 0.0;
-        CA[id] = id == UNIT ? 1.0 : 0.0;
+        CKA[2 * id] = (id >= 2 * L && id < 3 * L) ? lw.K[id] : 0.0;
+        CKA[2 * id + 1] = id == UNIT ? 1.0 : 0.0;
     }
 }
 

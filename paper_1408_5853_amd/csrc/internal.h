@@ -96,7 +96,7 @@ constexpr double POW_TLO = 0.0625, POW_THI = 1048576.0;   // 2^EMIN, 2^(EMIN+NE)
 constexpr int POW_BX = 2 * POW_NM;                 // binade multipliers
 constexpr int POW_BE = POW_BX + POW_NE;            // exponent, then binomials from +2
 constexpr int POW_BLK = POW_BE + 2 + (POW_DEG - 1) + 2;
-// blob: (3L+2) law blocks, then cube multipliers and addends [3L+2] each
+// blob: (3L+2) law blocks, then {cube multiplier, addend} pairs per law id
 __host__ __device__ inline size_t pow_blob_doubles(int L) {
     return (size_t)(3 * L + 2) * (POW_BLK + 2);
 }
