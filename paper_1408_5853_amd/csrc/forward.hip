@@ -19,8 +19,6 @@
 #include <math.h>
 #include <string.h>
 
-#include <type_traits>
-
 #include "device_common.h"
 
 namespace cryo {
@@ -37,7 +35,6 @@ template <typename R, int RPL, int G, bool CUBE>
 __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *__restrict__ Tin,
                                  R *__restrict__ Tout, const R X, double *partial) {
     constexpr bool PAIR = Pair<R>::on;
-    using R2 = std::conditional_t<sizeof(R) == 8, double2, float2>;
     constexpr int NPL = PAIR ? 2 : 1;                 // planes per line (pairs: hi, lo)
     constexpr int NL = WAVE * G;                      // lanes per line
     constexpr int NG = STEP_WAVES / G;                // lines per workgroup
