@@ -36,7 +36,7 @@ BYTES_PER_CELL_STEP = 16          # read T, write T^ (FP64; an FP32 pair is also
 # HBM bytes per step launch measured with rocprofv3 (FETCH_SIZE x 2.000 +
 # WRITE_SIZE x 1.000, factors from a 256 MiB copy; profiles/k_step_f64_1024x4096.md),
 # keyed by library version and kernel shape: any other build reports null.
-MEASURED_TRAFFIC = {("cryocell 0.4 (gfx950)", (16, 1, 2)): 95.28e6}
+MEASURED_TRAFFIC = {("cryocell 0.5 (gfx950)", (16, 1, 2)): 84.65e6}
 
 
 def log(*a):
@@ -235,7 +235,7 @@ def main():
                      "note": "algorithmic 16 B/cell-step; traffic = rocprofv3 FETCH_SIZE and "
                              "WRITE_SIZE scaled by a 256 MiB copy; the 64 MiB ping-pong "
                              "state stays in L2/MALL and the kernel is bound by FP64 VALU "
-                             "issue and LDS latency (44 % VALU busy), not by HBM"},
+                             "issue and LDS latency (45 % VALU busy), not by HBM"},
     }
     if args.copy_mib:
         n = args.copy_mib * (1 << 20) // 8
