@@ -63,7 +63,7 @@ __device__ inline void nb_exchange(double v_last, double v_first, double &from_p
     }
 }
 
-template <int RPL, int G>
+template <int RPL, int G, bool CUBE>
 __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj1(StepArgs<double> a, AdjArgs d) {
     constexpr int NL = WAVE * G, NG = ADJ_WAVES / G;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -139,7 +139,9 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj1(StepArgs<double> a, Ad
                     l3v = vb;
                 }
             }
-            const double rc = a.laws.cube ? law.cube(lc, t) : law.lawc(lc, t);
+            double rc;
+            if constexpr (CUBE) rc = law.cube(lc, t);
+            else rc = law.lawc(lc, t);
             fw[r] = sgw[q] * (cap ? lamW : l2v);
             fe[r] = sge[q] * (cap ? lamE : l3v);
             const double aa = -fw[r], bb = fw[r] + fe[r] + rc, cc = -fe[r];
@@ -162,7 +164,7 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj1(StepArgs<double> a, Ad
             mum1 = mu;
             if (r == RPL - 1) ccL = cc;
             lamW = lamE;
-            if (r & 1) __builtin_amdgcn_sched_barrier(0);
+            __builtin_amdgcn_sched_barrier(0);
         }
         // chunk ends: sub of the first row = cc of the previous row, sup of the
         // last row = aa of the next row
@@ -182,87 +184,87 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj1(StepArgs<double> a, Ad
         const double XwF = d.X[base + qW], XeL = d.X[base + qE];
         // radial part of lam^n:  dJ - [y_i dr_i/dT_i + y_{i-1} dr_{i-1}/dT_i + y_{i+1} dr_{i+1}/dT_i]
         // face conductivity derivatives: d(gw lam_W)/dT_i = (1/2) e lam' ... on
-        // capacity rows (face-mean argument), e lam / T at interface nodes
-        double Dw[RPL], De[RPL], fwT[RPL], feT[RPL];
-        double ieW = 0.0;          // 1/2 e_W / tf_W of row 0 (west face of the chunk)
-        {
-            const uint32_t iw = sinf[qW];
-            ieW = 0.5 * law.expo((iw >> 6) & 63) * rcp(0.5 * (TwF + T[0]));
-        }
-#pragma unroll
-        for (int r = 0; r < RPL; ++r) {
+        // capacity rows (face-mean argument), e lam / T at interface nodes.
+        // Row r's factors: Dw, De (differences of T^{n+1}), fwT, feT; ie is
+        // 1/2 e / (face mean) of the east face, carried as the next row's west.
+        auto factors = [&](int r, double ieW, double &Dw, double &De, double &fwT, double &feT,
+                           double &ieE) {
             const int q = r * NL + lg;
             const double xw = (r > 0) ? X[r - 1] : XwF, xe = (r < RPL - 1) ? X[r + 1] : XeL;
-            Dw[r] = X[r] - xw;
-            De[r] = X[r] - xe;
+            Dw = X[r] - xw;
+            De = X[r] - xe;
             const uint32_t inf_r = sinf[q];
             const uint32_t kind = inf_r & 7;
             const double t = T[r], Te = (r < RPL - 1) ? T[r + 1] : TeL;
-            const double ieE = 0.5 * law.expo((inf_r >> 6) & 63) * rcp(0.5 * (t + Te));
-            if (kind == K_CAP) {
-                fwT[r] = fw[r] * ieW;
-                feT[r] = fe[r] * ieE;
-            } else if (kind == K_IFACE) {
-                const double it = rcp(t);
-                fwT[r] = fw[r] * law.expo((inf_r >> 12) & 63) * it;
-                feT[r] = fe[r] * law.expo((inf_r >> 18) & 63) * it;
-            } else {
-                fwT[r] = 0.0;
-                feT[r] = 0.0;
-            }
-            ieW = ieE;
+            ieE = 0.5 * law.expo((inf_r >> 6) & 63) * rcp(0.5 * (t + Te));
+            const double it = rcp(t);
+            const bool cap = kind == K_CAP, ifc = kind == K_IFACE;
+            fwT = cap ? fw[r] * ieW : ifc ? fw[r] * law.expo((inf_r >> 12) & 63) * it : 0.0;
+            feT = cap ? fe[r] * ieE : ifc ? fe[r] * law.expo((inf_r >> 18) & 63) * it : 0.0;
+        };
+        double ieW0;               // 1/2 e_W / tf_W of row 0 (west face of the chunk)
+        {
+            const uint32_t iw = sinf[qW];
+            ieW0 = 0.5 * law.expo((iw >> 6) & 63) * rcp(0.5 * (TwF + T[0]));
         }
-        // coupling terms leaving each row towards its r-neighbours (capacity rows:
-        // the face conductivity depends on both nodes)
-        const bool capF = (sinf[lg] & 7) == K_CAP, capL = (sinf[(RPL - 1) * NL + lg] & 7) == K_CAP;
-        const double qwF = capF ? y[0] * fwT[0] * Dw[0] : 0.0;                  // to row i0-1
-        const double qeL = capL ? y[RPL - 1] * feT[RPL - 1] * De[RPL - 1] : 0.0; // to row i0+RPL
+        // coupling terms leaving the chunk towards the neighbouring lanes'
+        // rows (capacity rows: the face conductivity depends on both nodes)
+        double qwF, qeL;
+        {
+            double Dw, De, fwT, feT, ie;
+            factors(0, ieW0, Dw, De, fwT, feT, ie);
+            qwF = (sinf[lg] & 7) == K_CAP ? y[0] * fwT * Dw : 0.0;            // to row i0-1
+            const uint32_t il = sinf[(RPL - 2) * NL + lg];
+            const double TL = T[RPL - 2];
+            const double ieL = RPL >= 2 ? 0.5 * law.expo((il >> 6) & 63) * rcp(0.5 * (TL + T[RPL - 1]))
+                                        : ieW0;
+            factors(RPL - 1, RPL >= 2 ? ieL : ieW0, Dw, De, fwT, feT, ie);
+            qeL = (sinf[(RPL - 1) * NL + lg] & 7) == K_CAP ? y[RPL - 1] * feT * De : 0.0;
+        }
         double qePrev, qwNext;
         nb_exchange<G>(qeL, qwF, qePrev, qwNext, lane, wig, xb[grp]);
         if (active) {
+            // one pass over the rows: row r's coupling into row r-1 completes
+            // row r-1, which is stored one row late
+            double ieW = ieW0, oe_prev = qePrev, lp_prev = 0.0;
 #pragma unroll
             for (int r = 0; r < RPL; ++r) {
                 const int q = r * NL + lg;
                 const uint32_t inf_r = sinf[q];
                 const uint32_t kind = inf_r & 7;
                 const bool cap = kind == K_CAP, ifc = kind == K_IFACE;
+                double Dw, De, fwT, feT, ieE;
+                factors(r, ieW, Dw, De, fwT, feT, ieE);
+                ieW = ieE;
                 const double t = T[r];
                 const int lc = (inf_r >> 24) & 63;
                 double rc, drc;
-                if (a.laws.cube) {
+                if constexpr (CUBE) {
                     rc = law.cube(lc, t);
                     drc = 3.0 * law.cka[2 * lc] * t * t;
                 } else {
                     rc = law.lawc(lc, t);
                     drc = law.expo(lc) * rc * rcp(t);
                 }
-                double self = 0.0;
-                if (cap || ifc) self = fwT[r] * Dw[r] + feT[r] * De[r] + drc * (X[r] - t) - rc;
-                double from_w, from_e;    // y_{i-1} dr_{i-1}/dT_i, y_{i+1} dr_{i+1}/dT_i
-                if (r > 0) {
-                    const bool cw = (sinf[q - NL] & 7) == K_CAP;
-                    from_w = cw ? y[r - 1] * feT[r - 1] * De[r - 1] : 0.0;
-                } else {
-                    from_w = qePrev;
-                }
-                if (r < RPL - 1) {
-                    const bool ce = (sinf[q + NL] & 7) == K_CAP;
-                    from_e = ce ? y[r + 1] * fwT[r + 1] * Dw[r + 1] : 0.0;
-                } else {
-                    from_e = qwNext;
-                }
-                double lp = -(y[r] * self + from_w + from_e);
+                const bool cf = cap || ifc;
+                const double self = cf ? fwT * Dw + feT * De + drc * (X[r] - t) - rc : 0.0;
+                const double ow = cap ? y[r] * fwT * Dw : 0.0;       // into row r-1
+                const double oe = cap ? y[r] * feT * De : 0.0;       // into row r+1
+                double lp = -(y[r] * self + oe_prev);
                 if (lg == a.surf_lane && r == a.surf_reg) lp += d.cS * a.wz_mid;
+                if (r > 0) d.lpart[base + q - NL] = lp_prev - ow;
                 d.Y[base + q] = y[r];
-                d.lpart[base + q] = lp;
-                if (cap || ifc) {
-                    accW[r * WAVE] += y[r] * fw[r] * Dw[r];
-                    accE[r * WAVE] += y[r] * fe[r] * De[r];
-                }
-                if ((inf_r >> 3) & 1) {
-                    gS += y[r];
-                }
+                oe_prev = oe;
+                lp_prev = lp;
+                // (unconditional: a read under a row test is a branch that
+                // waits for it at once)
+                const double aw = accW[r * WAVE], ae = accE[r * WAVE];
+                accW[r * WAVE] = cf ? fma(y[r] * fw[r], Dw, aw) : aw;
+                accE[r * WAVE] = cf ? fma(y[r] * fe[r], De, ae) : ae;
+                gS += ((inf_r >> 3) & 1) ? y[r] : 0.0;
+                __builtin_amdgcn_sched_barrier(0);
             }
+            d.lpart[base + (RPL - 1) * NL + lg] = lp_prev - qwNext;
         }
     }
     // this line group's running sums (one slot per group: no other writer)
@@ -311,81 +313,74 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj2(StepArgs<double> a, Ad
     double cF[RPL], cdF[RPL], Tc[RPL], Yc[RPL], Ys[RPL];
     // groups past the last line read line nz-2 and do no line
     const int jb = min(j0, a.nz - 2);
+    const size_t bb = (size_t)jb * LS;
+    // start-up: the south faces (jb-1, jb) of the group's first line, and for
+    // line 1 the lower boundary line's lam^n (that face's dF/dT_0)
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
         const int q = r * NL + lg;
-        accZ[r] = cF[r] = cdF[r] = 0.0;
-        Tc[r] = d.T[(size_t)jb * LS + q];
-        Yc[r] = d.Y[(size_t)jb * LS + q];
-        Ys[r] = jb - 1 >= 1 ? d.Y[(size_t)(jb - 1) * LS + q] : 0.0;
+        const uint32_t inf_r = sinf[q];
+        const bool cap = (inf_r & 7) == K_CAP;
+        const int lz = cap ? (inf_r >> 12) & 63 : law_zero(a.laws.L);
+        const double t = d.T[bb + q], ts = d.T[bb - LS + q];
+        const double y = d.Y[bb + q];
+        const double e = law.expo(lz);
+        const double fs = 0.5 * (t + ts);
+        const double ls = law.lawc(lz, fs), ds = t - ts;
+        const double gs = 0.5 * e * ls * rcp(fs);
+        accZ[r] = 0.0;
+        cF[r] = ls * ds;
+        cdF[r] = gs * ds + ls;                                 // d F_S / d T_j
+        Tc[r] = t;
+        Yc[r] = y;
+        Ys[r] = jb - 1 >= 1 ? d.Y[bb - LS + q] : 0.0;
+        if (j0 == 1 && j0 < j1) {
+            double l0 = (gs * ds - ls) * (0.0 - y);            // d F_S / d T_0
+            if (lg == a.surf_lane && r == a.surf_reg) l0 += d.cS * a.wz_end;
+            d.lam_out[q] = l0;
+        }
+        __builtin_amdgcn_sched_barrier(0);
     }
     for (int j = j0; j < j1; ++j) {
         const size_t base = (size_t)j * LS;
         // the line above and this line's partial lam^n, up front
-        double Tn[RPL], Yn[RPL], LP[RPL], TsF[RPL];
+        double Tn[RPL], Yn[RPL], LP[RPL];
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
             const int q = r * NL + lg;
             Tn[r] = d.T[base + LS + q];
             Yn[r] = (j + 1 <= a.nz - 2) ? d.Y[base + LS + q] : 0.0;
             LP[r] = d.lpart[base + q];
-            TsF[r] = j == j0 ? d.T[base - LS + q] : 0.0;
         }
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
             const int q = r * NL + lg;
             const uint32_t inf_r = sinf[q];
             const bool cap = (inf_r & 7) == K_CAP;
-            const int lz = (inf_r >> 12) & 63;
+            // non-capacity rows take the zero law: every face term vanishes
+            const int lz = cap ? (inf_r >> 12) & 63 : law_zero(a.laws.L);
             const double t = Tc[r], tn = Tn[r];
             const double y = Yc[r], yn = Yn[r], ys = Ys[r];
-            double lam = LP[r];
-            if (cap) {
-                const double e = law.expo(lz);
-                // north face (j, j+1)
-                const double fn = 0.5 * (t + tn);
-                const double ln = law.lawc(lz, fn);
-                const double dn = tn - t;
-                const double gn = 0.5 * e * ln * rcp(fn);
-                const double dFlN = gn * dn - ln;                   // d F_N / d T_j
-                // south face (j-1, j): carried, or evaluated on the group's first line
-                double FS, dFuS, gs = 0.0, ls = 0.0, ds = 0.0;
-                if (j == j0) {
-                    const double ts = TsF[r];
-                    const double fs = 0.5 * (t + ts);
-                    ls = law.lawc(lz, fs);
-                    ds = t - ts;
-                    gs = 0.5 * e * ls * rcp(fs);
-                    FS = ls * ds;
-                    dFuS = gs * ds + ls;                            // d F_S / d T_j
-                } else {
-                    FS = cF[r];
-                    dFuS = cdF[r];
-                }
-                lam += dFlN * (y - yn) + dFuS * (ys - y);
-                accZ[r] += y * (ln * dn - FS);
-                cF[r] = ln * dn;
-                cdF[r] = gn * dn + ln;                              // d F_N / d T_{j+1}
-                // boundary lines: their faces with lines 1 and nz-2 (line 1 is
-                // always the first line of its group)
-                if (j == 1) {
-                    const double dFl0 = gs * ds - ls;               // d F_S / d T_0
-                    double l0 = dFl0 * (0.0 - y);
-                    if (lg == a.surf_lane && r == a.surf_reg) l0 += d.cS * a.wz_end;
-                    d.lam_out[q] = l0;
-                }
-                if (j == a.nz - 2) {
-                    const double dFuE = gn * dn + ln;               // d F_N / d T_{nz-1}
-                    double le_ = dFuE * (y - 0.0);
-                    if (lg == a.surf_lane && r == a.surf_reg) le_ += d.cS * a.wz_end;
-                    d.lam_out[(size_t)(a.nz - 1) * LS + q] = le_;
-                }
-            } else {
-                const bool sl = lg == a.surf_lane && r == a.surf_reg;
-                if (j == 1) d.lam_out[q] = sl ? d.cS * a.wz_end : 0.0;
-                if (j == a.nz - 2) d.lam_out[(size_t)(a.nz - 1) * LS + q] = sl ? d.cS * a.wz_end : 0.0;
+            const double e = law.expo(lz);
+            // north face (j, j+1); the south face (j-1, j) is carried
+            const double fn = 0.5 * (t + tn);
+            const double ln = law.lawc(lz, fn);
+            const double dn = tn - t;
+            const double gn = 0.5 * e * ln * rcp(fn);
+            const double dFlN = gn * dn - ln;                       // d F_N / d T_j
+            const double lam = LP[r] + dFlN * (y - yn) + cdF[r] * (ys - y);
+            accZ[r] += y * (ln * dn - cF[r]);
+            cF[r] = ln * dn;
+            cdF[r] = gn * dn + ln;                                  // d F_N / d T_{j+1}
+            if (j == a.nz - 2) {
+                // the upper boundary line: its face with line nz-2
+                double le_ = cdF[r] * (y - 0.0);                    // d F_N / d T_{nz-1}
+                if (lg == a.surf_lane && r == a.surf_reg) le_ += d.cS * a.wz_end;
+                d.lam_out[(size_t)(a.nz - 1) * LS + q] = le_;
             }
             d.lam_out[base + q] = lam;
+            // one row at a time (register pressure)
+            __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
@@ -441,10 +436,12 @@ cryo_status launch_adj(const cryo_plan *p, int pass, const AdjArgs &d, int *flag
     const int key = p->rpl * 10 + p->wpl;
 #define ADJ_CASE(R_, G_)                                                                  \
     case R_ * 10 + G_:                                                                    \
-        if (pass == 1)                                                                    \
-            hipLaunchKernelGGL((k_adj1<R_, G_>), g, b, lds, s, a, d);                     \
-        else                                                                              \
+        if (pass == 2)                                                                    \
             hipLaunchKernelGGL((k_adj2<R_, G_>), g, b, lds, s, a, d);                     \
+        else if (a.laws.cube)                                                             \
+            hipLaunchKernelGGL((k_adj1<R_, G_, true>), g, b, lds, s, a, d);               \
+        else                                                                              \
+            hipLaunchKernelGGL((k_adj1<R_, G_, false>), g, b, lds, s, a, d);              \
         break;
     switch (key) {
         ADJ_CASE(2, 1)
