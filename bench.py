@@ -36,7 +36,9 @@ BYTES_PER_CELL_STEP = 16          # read T, write T^ (FP64; an FP32 pair is also
 # HBM bytes per step launch measured with rocprofv3 (FETCH_SIZE x 2.000 +
 # WRITE_SIZE x 1.000, factors from a 256 MiB copy; profiles/k_step_f64_1024x4096.md),
 # keyed by library version and kernel shape: any other build reports null.
-MEASURED_TRAFFIC = {("cryocell 0.5 (gfx950)", (16, 1, 2)): 84.65e6}
+# (0.6 changed only the adjoint kernels: its k_step is the code measured on 0.5.)
+MEASURED_TRAFFIC = {("cryocell 0.5 (gfx950)", (16, 1, 2)): 84.65e6,
+                    ("cryocell 0.6 (gfx950)", (16, 1, 2)): 84.65e6}
 
 
 def log(*a):
