@@ -16,25 +16,19 @@
 // Parameter sensitivities are accumulated per row (radial flux terms y fw Dw
 // and y fe De, axial term y (F_N - F_S)) and per heater (y s, y Q ds/dw);
 // the host turns the row sums into d/d thickness and d/d k_scale.
+//
+// The rows are those the stepping kernel solves: each line's rows multiplied
+// by row constants (capacity rows by eta^2, interface rows by 1 / lambda of
+// the outer layer at the node).  With r' = S r and S independent of T^{n+1},
+// y' = S^{-1} y and y' dr'/dT^n = y dr/dT^n wherever r = 0 (the step's
+// solution), so lam^n and the row sums (y' fw' = y fw, y' fe' = y fe) are
+// those of the rows as written; only the source's derivative carries S.
 #include <math.h>
 #include <string.h>
 
 #include "device_common.h"
 
 namespace cryo {
-
-struct AdjArgs {
-    const double *T;        // T^n (internal layout)
-    const double *X;        // T^{n+1}
-    const double *lam_in;   // lam^{n+1}
-    double *Y;              // pass 1 out: y
-    double *lpart;          // pass 1 out: radial part of lam^n
-    double *lam_out;        // pass 2 out: lam^n
-    double *acc;            // per line group: [groups][3][np] row sums
-    double *accg;           // per line group: [groups][2]  (y s, y Q ds/dw)
-    double s, ds;           // pulse average of step n and its width derivative
-    double cS;              // dJ_n / dS_n (0 for n = 0)
-};
 
 constexpr int ADJ_WAVES = 8;
 
@@ -130,20 +124,21 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj1(StepArgs<double> a, Ad
             const int le = (inf_r >> 6) & 63, l2 = (inf_r >> 12) & 63;
             const int l3 = (inf_r >> 18) & 63, lc = (inf_r >> 24) & 63;
             const double lamE = law.lawc(le, 0.5 * (t + Te));
-            // interface: the two layer laws at the node; boundary rows: unit/zero
-            double l2v = l2 == law_unit(a.laws.L) ? 1.0 : 0.0, l3v = l3 == law_unit(a.laws.L) ? 1.0 : 0.0;
+            // rows in the stepping kernel's scaled form: an interface row's
+            // west coefficient is the ratio law at the node and its east one
+            // h_i; boundary rows have their unit or zero laws folded into gw,
+            // ge (slot 2 is the unit law there, the zero law on padding)
+            double l2v = l2 == law_unit(a.laws.L) ? 1.0 : 0.0;
             if (__any(ifc)) {
-                const double va = law.lawc(l2, t), vb = law.lawc(l3, t);
-                if (ifc) {
-                    l2v = va;
-                    l3v = vb;
-                }
+                const double va = law.lawc(l2, t);
+                if (ifc) l2v = va;
             }
+            (void)l3;
             double rc;
             if constexpr (CUBE) rc = law.cube(lc, t);
             else rc = law.lawc(lc, t);
             fw[r] = sgw[q] * (cap ? lamW : l2v);
-            fe[r] = sge[q] * (cap ? lamE : l3v);
+            fe[r] = sge[q] * (cap ? lamE : 1.0);
             const double aa = -fw[r], bb = fw[r] + fe[r] + rc, cc = -fe[r];
             const double mu = MU[r];
             // transposed row r-1 = (cc_{r-2}, bb_{r-1}, aa_r | mu_{r-1})
@@ -284,7 +279,7 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj1(StepArgs<double> a, Ad
     if (wig == 0 && lane == 0) {
         double tot = 0.0;
         for (int w = 0; w < G; ++w) tot += gsum[grp * G + w];
-        d.accg[2 * gidx] += tot * d.s;
+        d.accg[2 * gidx] += tot * d.xs * d.s;
         d.accg[2 * gidx + 1] += tot * a.pulse.amplitude * d.ds;
     }
 }

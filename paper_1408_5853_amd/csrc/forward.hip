@@ -657,6 +657,6 @@ cryo_status launch_add_i64(int64_t *ptr, int64_t v, hipStream_t s) {
 
 namespace cryo {
 StepArgs<double> step_args_f64(const cryo_plan *p, int *flag) {
-    return step_args<double>(p, nullptr, nullptr, 0.0, nullptr, flag, true);
+    return step_args<double>(p, nullptr, nullptr, 0.0, nullptr, flag);
 }
 }  // namespace cryo

@@ -12,18 +12,6 @@
 
 namespace cryo {
 
-struct AdjArgs {
-    const double *T;
-    const double *X;
-    const double *lam_in;
-    double *Y;
-    double *lpart;
-    double *lam_out;
-    double *acc;
-    double *accg;
-    double s, ds;
-    double cS;
-};
 cryo_status launch_adj(const cryo_plan *p, int pass, const AdjArgs &d, int *flag, hipStream_t s);
 cryo_status launch_adj_init(const cryo_plan *p, double *lam, double cS, hipStream_t s);
 cryo_status launch_zero(double *ptr, size_t n, hipStream_t s);
@@ -205,6 +193,7 @@ static cryo_status grad_backward(GradRun &r) {
             d.s = source_fraction(p->pulse, k);
             d.ds = source_fraction_dwidth(p->pulse, p->prob.dt, k);
             d.cS = k >= 1 ? r.cS[k] : 0.0;
+            d.xs = p->eta * p->eta;
             st = launch_adj(p, 1, d, flag, s);
             if (st == CRYO_OK) st = launch_adj(p, 2, d, flag, s);
             if (st != CRYO_OK) return st;

@@ -101,6 +101,21 @@ __host__ __device__ inline size_t pow_blob_doubles(int L) {
     return (size_t)(3 * L + 2) * (POW_BLK + 2);
 }
 
+// Arguments of the adjoint kernels of one step (FP64, internal layout).
+struct AdjArgs {
+    const double *T;        // T^n (internal layout)
+    const double *X;        // T^{n+1}
+    const double *lam_in;   // lam^{n+1}
+    double *Y;              // pass 1 out: y
+    double *lpart;          // pass 1 out: radial part of lam^n
+    double *lam_out;        // pass 2 out: lam^n
+    double *acc;            // per line group: [groups][3][np] row sums
+    double *accg;           // per line group: [groups][2]  (y s, y Q ds/dw)
+    double s, ds;           // pulse average of step n and its width derivative
+    double cS;              // dJ_n / dS_n (0 for n = 0)
+    double xs;              // scale of the capacity rows (eta^2): the source's too
+};
+
 struct Pulse {      // in step units, snapped
     double b0, W, P;
     double amplitude;
