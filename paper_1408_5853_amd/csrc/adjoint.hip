@@ -262,25 +262,32 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj1(StepArgs<double> a, Ad
             d.lpart[base + (RPL - 1) * NL + lg] = lp_prev - qwNext;
         }
     }
-    // this line group's running sums (one slot per group: no other writer)
-    double *acc = d.acc + (size_t)gidx * 3 * a.np;
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-        const int q = r * NL + lg;
-        acc[q] += accW[r * WAVE];
-        acc[a.np + q] += accE[r * WAVE];
-    }
-    // heater sums of the group: lane-order tree inside each wave, then waves
+    // heater sums: lane-order tree inside each wave
     double v = gS;
     for (int s = WAVE / 2; s >= 1; s >>= 1) v += __shfl_down(v, s, WAVE);
     __shared__ double gsum[ADJ_WAVES];
     if (lane == 0) gsum[wv] = v;
     __syncthreads();
-    if (wig == 0 && lane == 0) {
+    // this workgroup's running sums (one slot per workgroup: no other writer),
+    // its line groups added in a fixed order
+    const double *accL = (const double *)(smem + adj_acc_offset(a.laws.L, a.np));
+    double *acc = d.acc + (size_t)blockIdx.x * 3 * a.np;
+    for (int q = threadIdx.x; q < a.np; q += blockDim.x) {
+        const int r = q / NL, lq = q % NL, w0 = lq / WAVE, ln = lq % WAVE;
+        double sw = 0.0, se = 0.0;
+        for (int g = 0; g < NG; ++g) {
+            const size_t o = (size_t)(g * G + w0) * RPL * WAVE + (size_t)r * WAVE + ln;
+            sw += accL[o];
+            se += accL[(size_t)ADJ_WAVES * RPL * WAVE + o];
+        }
+        acc[q] += sw;
+        acc[a.np + q] += se;
+    }
+    if (threadIdx.x == 0) {
         double tot = 0.0;
-        for (int w = 0; w < G; ++w) tot += gsum[grp * G + w];
-        d.accg[2 * gidx] += tot * d.xs * d.s;
-        d.accg[2 * gidx + 1] += tot * a.pulse.amplitude * d.ds;
+        for (int w = 0; w < ADJ_WAVES; ++w) tot += gsum[w];
+        d.accg[2 * blockIdx.x] += tot * d.xs * d.s;
+        d.accg[2 * blockIdx.x + 1] += tot * a.pulse.amplitude * d.ds;
     }
 }
 
@@ -384,9 +391,19 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj2(StepArgs<double> a, Ad
             Tc[r] = Tn[r];
         }
     }
-    double *acc = d.acc + (size_t)gidx * 3 * a.np + 2 * a.np;
+    // this workgroup's sums, its line groups added in a fixed order
+    double *accL = (double *)(smem + adj_acc_offset(a.laws.L, a.np));
 #pragma unroll
-    for (int r = 0; r < RPL; ++r) acc[r * NL + lg] += accZ[r];
+    for (int r = 0; r < RPL; ++r) accL[(size_t)wv * RPL * WAVE + r * WAVE + lane] = accZ[r];
+    __syncthreads();
+    double *acc = d.acc + (size_t)blockIdx.x * 3 * a.np + 2 * a.np;
+    for (int q = threadIdx.x; q < a.np; q += blockDim.x) {
+        const int r = q / NL, lq = q % NL, w0 = lq / WAVE, ln = lq % WAVE;
+        double sz = 0.0;
+        for (int g = 0; g < NG; ++g)
+            sz += accL[(size_t)(g * G + w0) * RPL * WAVE + (size_t)r * WAVE + ln];
+        acc[q] += sz;
+    }
 }
 
 // lam^N = dJ_N / dT^N: the surface weights on the outer row
@@ -420,7 +437,8 @@ int adj_grid(const cryo_plan *p) {
     return (groups + per_wg - 1) / per_wg;
 }
 
-int adj_groups(const cryo_plan *p) { return adj_grid(p) * (ADJ_WAVES / p->wpl); }
+// row-sum slots: one per workgroup of the adjoint passes
+int adj_slots(const cryo_plan *p) { return adj_grid(p); }
 
 StepArgs<double> step_args_f64(const cryo_plan *p, int *flag);
 

@@ -15,7 +15,7 @@ namespace cryo {
 cryo_status launch_adj(const cryo_plan *p, int pass, const AdjArgs &d, int *flag, hipStream_t s);
 cryo_status launch_adj_init(const cryo_plan *p, double *lam, double cS, hipStream_t s);
 cryo_status launch_zero(double *ptr, size_t n, hipStream_t s);
-int adj_groups(const cryo_plan *p);
+int adj_slots(const cryo_plan *p);
 
 static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
@@ -59,8 +59,8 @@ static GradLayout grad_layout(const cryo_plan *p, int64_t N, int64_t ckpt) {
     g.lam[1] = o; o += F;
     g.Y = o; o += F;
     g.lpart = o; o += F;
-    g.acc = o; o += al256(sizeof(double) * 3 * (size_t)p->np * adj_groups(p));
-    g.accg = o; o += al256(sizeof(double) * 2 * (size_t)adj_groups(p));
+    g.acc = o; o += al256(sizeof(double) * 3 * (size_t)p->np * adj_slots(p));
+    g.accg = o; o += al256(sizeof(double) * 2 * (size_t)adj_slots(p));
     g.surf = o; o += al256(sizeof(double) * (size_t)std::max<int64_t>(N, 1));
     g.total = o;
     return g;
@@ -163,7 +163,7 @@ static cryo_status grad_backward(GradRun &r) {
     const size_t F = field_f64(p);
     auto ckp = [&](int64_t i) { return (double *)(w + g.ck + F * i); };
     auto segp = [&](int64_t i) { return (double *)(w + g.seg + F * i); };
-    const int ngrp = adj_groups(p);
+    const int ngrp = adj_slots(p);
     double *acc = (double *)(w + g.acc), *accg = (double *)(w + g.accg);
     cryo_status st = launch_zero(acc, 3 * (size_t)p->np * ngrp, s);
     if (st == CRYO_OK) st = launch_zero(accg, 2 * (size_t)ngrp, s);
@@ -203,14 +203,14 @@ static cryo_status grad_backward(GradRun &r) {
     return CRYO_OK;
 }
 
-// wait for the backward; row sums over line groups (fixed order), then the
+// wait for the backward; row sums over workgroup slots (fixed order), then the
 // parameter gradient
 static cryo_status grad_finish(GradRun &run, double *grad) {
     cryo_plan *p = run.p;
     const GradLayout &g = run.g;
     char *w = run.w;
     hipStream_t s = run.s;
-    const int ngrp = adj_groups(p);
+    const int ngrp = adj_slots(p);
     const double *acc = (const double *)(w + g.acc), *accg = (const double *)(w + g.accg);
     std::vector<double> hacc(3 * (size_t)p->np * ngrp), hg(2 * (size_t)ngrp);
     int hflag = 0;

@@ -109,8 +109,8 @@ struct AdjArgs {
     double *Y;              // pass 1 out: y
     double *lpart;          // pass 1 out: radial part of lam^n
     double *lam_out;        // pass 2 out: lam^n
-    double *acc;            // per line group: [groups][3][np] row sums
-    double *accg;           // per line group: [groups][2]  (y s, y Q ds/dw)
+    double *acc;            // per workgroup: [workgroups][3][np] row sums
+    double *accg;           // per workgroup: [workgroups][2]  (y s, y Q ds/dw)
     double s, ds;           // pulse average of step n and its width derivative
     double cS;              // dJ_n / dS_n (0 for n = 0)
     double xs;              // scale of the capacity rows (eta^2): the source's too
