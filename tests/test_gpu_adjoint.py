@@ -109,3 +109,25 @@ def test_adjoint_workload_full_size_against_reduced_oracle():
     say("  J gpu %.12e oracle %.12e, normalised gradient error %.3e" % (Jg, Jo, e))
     assert Jg == pytest.approx(Jo, rel=1e-9)
     assert e < 1e-6
+
+
+@pytest.mark.parametrize("shape", [(4, 1, 1), (8, 1, 2), (4, 2, 1)])
+def test_gpu_gradient_general_power_laws(shape):
+    """Capacity exponents other than 3 (the general power path of both
+    adjoint passes) and conductivity exponents far apart across layers."""
+    import paper_1408_5853_amd as P
+    c = cellgen.tiny(9, nr=120, nz=7, n_layers=3, nsteps=25, z_active=True, dt=2e-6,
+                     amplitude=4e9, heater=2)
+    for m, (q, p) in enumerate([(2.0, -1.5), (3.5, 2.5), (1.5, 0.3)]):
+        c["layers"][m]["q"] = q
+        c["layers"][m]["p"] = p
+    tgt = _target(c, c["nsteps"])
+    say("case adjoint general laws shape %s" % (shape,))
+    Jo, go, _ = oracle.gradient(c, tgt)
+    plan = P.Plan(c)
+    plan.set_shape(*shape)
+    Jg, gg, _ = plan.gradient(tgt, ckpt=6)
+    assert Jg == pytest.approx(Jo, rel=1e-9)
+    e = _norm_err(gg, go, P.params_of(c))
+    say("  normalised gradient error %.3e" % e)
+    assert e < 1e-8, (gg, go)

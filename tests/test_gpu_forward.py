@@ -194,3 +194,48 @@ def test_every_chunk_shape_f32_pairs_match_oracle(shape):
         e = float(np.max(np.abs(plan.field_values(T) - To)))
         say("  max abs err %.3e K" % e)
         assert e < F32_TOL_K
+
+
+def _general_exponents(c, qs, ps=None):
+    """Capacity exponents other than 3 (the general power path instead of the
+    cube) and, optionally, conductivity exponents far apart across layers
+    (interface ratio laws of larger exponent)."""
+    for m, l in enumerate(c["layers"]):
+        l["q"] = qs[m % len(qs)]
+        if ps is not None:
+            l["p"] = ps[m % len(ps)]
+    return c
+
+
+@pytest.mark.parametrize("qs,ps", [((2.4,), None), ((1.0, 3.0, 0.5), None),
+                                   ((2.0, 3.5, 1.5), (-1.5, 2.5, 0.3))])
+@pytest.mark.parametrize("shape", [(3, 1), (16, 1), (4, 4)])
+def test_general_power_laws_match_oracle_f64(qs, ps, shape):
+    import torch
+
+    import paper_1408_5853_amd as P
+    rpl, wpl = shape
+    nr = min(64 * rpl * wpl - 3, 300)
+    c = _general_exponents(cellgen.tiny(17, nr=nr, nz=6, n_layers=3, z_active=True,
+                                        dt=2e-7, amplitude=5e9), qs, ps)
+    rng = np.random.default_rng(11)
+    T0 = 28.0 + rng.uniform(0, 5, size=(c["nz"], c["nr"]))
+    To = oracle.forward(c, T0, nsteps=40)
+    for dtype in ("f64", "f32"):
+        say("case general laws qs=%s ps=%s shape %s %s nr %d" % (qs, ps, shape, dtype, nr))
+        plan = P.Plan(c, dtype)
+        plan.set_shape(rpl, wpl, 2)
+        T = plan.field_from(T0)
+        ws = plan.workspace(40)
+        plan.forward(T, 0, 40, ws=ws)
+        plan.poll(ws)
+        torch.cuda.synchronize()
+        Tg = plan.field_values(T)
+        if dtype == "f64":
+            e = rel_err(Tg, To)
+            say("  max rel err %.3e" % e)
+            assert e < F64_TOL
+        else:
+            e = float(np.max(np.abs(Tg - To)))
+            say("  max abs err %.3e K" % e)
+            assert e < F32_TOL_K
