@@ -57,12 +57,13 @@ __device__ inline void nb_exchange(double v_last, double v_first, double &from_p
     }
 }
 
-template <int RPL, int G, bool CUBE>
-__global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj1(StepArgs<double> a, AdjArgs d) {
-    constexpr int NL = WAVE * G, NG = ADJ_WAVES / G;
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double xchg[NG][9 * G];
-    __shared__ double xb[NG][2 * G];
+// Row tables and laws in LDS (dynamic shared memory); all threads call it.
+struct AdjLds {
+    const double *sgw, *sge;
+    const uint32_t *sinf;
+    LawLds<double> law;
+};
+__device__ inline AdjLds adj_stage(const StepArgs<double> &a, unsigned char *smem) {
     double *sgw = (double *)(smem + ((law_lds_bytes<double>(a.laws.L) + 15) & ~(size_t)15));
     double *sge = sgw + a.np;
     uint32_t *sinf = (uint32_t *)(sge + a.np);
@@ -71,7 +72,24 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj1(StepArgs<double> a, Ad
         sge[i] = a.ge[i];
         sinf[i] = a.info[i];
     }
-    const LawLds<double> law = stage_laws<double>(a, smem);
+    AdjLds t;
+    t.sgw = sgw;
+    t.sge = sge;
+    t.sinf = sinf;
+    t.law = stage_laws<double>(a, smem);      // ends with a barrier
+    return t;
+}
+
+// Pass 1 of one step over this workgroup's line groups (tables staged).
+template <int RPL, int G, bool CUBE>
+__device__ inline void adj1_body(const StepArgs<double> &a, const AdjArgs &d,
+                                 unsigned char *smem, const AdjLds &tb) {
+    constexpr int NL = WAVE * G, NG = ADJ_WAVES / G;
+    __shared__ double xchg[NG][9 * G];
+    __shared__ double xb[NG][2 * G];
+    const double *sgw = tb.sgw, *sge = tb.sge;
+    const uint32_t *sinf = tb.sinf;
+    const LawLds<double> &law = tb.law;
     const int lane = threadIdx.x & (WAVE - 1), wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int grp = wv / G, wig = wv % G, lg = wig * WAVE + lane;
     const int gidx = blockIdx.x * NG + grp;                  // line group
@@ -291,18 +309,22 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj1(StepArgs<double> a, Ad
     }
 }
 
+template <int RPL, int G, bool CUBE>
+__global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj1(StepArgs<double> a, AdjArgs d) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const AdjLds tb = adj_stage(a, smem);
+    adj1_body<RPL, G, CUBE>(a, d, smem, tb);
+}
+
 // Pass 2: axial faces.  Each interior line j adds the terms of its two
 // axial faces (capacity rows), and the lines next to the z-boundaries write
 // the boundary lines' lam^n.
 template <int RPL, int G>
-__global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj2(StepArgs<double> a, AdjArgs d) {
+__device__ inline void adj2_body(const StepArgs<double> &a, const AdjArgs &d,
+                                 unsigned char *smem, const AdjLds &tb) {
     constexpr int NL = WAVE * G, NG = ADJ_WAVES / G;
-    extern __shared__ __align__(16) unsigned char smem[];
-    double *sgw = (double *)(smem + ((law_lds_bytes<double>(a.laws.L) + 15) & ~(size_t)15));
-    double *sge = sgw + a.np;
-    uint32_t *sinf = (uint32_t *)(sge + a.np);
-    for (int i = threadIdx.x; i < a.np; i += blockDim.x) sinf[i] = a.info[i];
-    const LawLds<double> law = stage_laws<double>(a, smem);
+    const uint32_t *sinf = tb.sinf;
+    const LawLds<double> &law = tb.law;
     const int lane = threadIdx.x & (WAVE - 1), wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int grp = wv / G, wig = wv % G, lg = wig * WAVE + lane;
     const int gidx = blockIdx.x * NG + grp;
@@ -406,6 +428,28 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj2(StepArgs<double> a, Ad
     }
 }
 
+template <int RPL, int G>
+__global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj2(StepArgs<double> a, AdjArgs d) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const AdjLds tb = adj_stage(a, smem);
+    adj2_body<RPL, G>(a, d, smem, tb);
+}
+
+// Pass 2 of step k and pass 1 of step k - 1 in one launch: each line group
+// finishes lam^k of its lines (written to memory, read back by the same
+// lanes), then runs the next step's line solves on it.  Every value that
+// crosses line groups (y^k of the neighbouring lines) is read in the first
+// phase and written only to the other buffer in the second.
+template <int RPL, int G, bool CUBE>
+__global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj21(StepArgs<double> a, AdjArgs d2,
+                                                           AdjArgs d1) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const AdjLds tb = adj_stage(a, smem);
+    adj2_body<RPL, G>(a, d2, smem, tb);
+    __syncthreads();           // the LDS row sums area passes to the next phase
+    adj1_body<RPL, G, CUBE>(a, d1, smem, tb);
+}
+
 // lam^N = dJ_N / dT^N: the surface weights on the outer row
 __global__ void k_adj_init(double *lam, int nz, int np, int q_surf, double cS, double wz_end,
                            double wz_mid) {
@@ -442,15 +486,23 @@ int adj_slots(const cryo_plan *p) { return adj_grid(p); }
 
 StepArgs<double> step_args_f64(const cryo_plan *p, int *flag);
 
-cryo_status launch_adj(const cryo_plan *p, int pass, const AdjArgs &d, int *flag, hipStream_t s) {
+// pass 1, pass 2, or (pass 21) pass 2 of step k with d and pass 1 of step k-1
+// with d1
+cryo_status launch_adj(const cryo_plan *p, int pass, const AdjArgs &d, int *flag, hipStream_t s,
+                       const AdjArgs *d1) {
     StepArgs<double> a = step_args_f64(p, flag);
     dim3 g(adj_grid(p)), b(ADJ_WAVES * WAVE);
     const size_t lds = adj_lds_bytes(p->L, p->np, p->rpl);
     const int key = p->rpl * 10 + p->wpl;
+    if (pass == 21 && !d1) return fail(CRYO_ERR_ARG, "fused adjoint passes need two steps");
 #define ADJ_CASE(R_, G_)                                                                  \
     case R_ * 10 + G_:                                                                    \
         if (pass == 2)                                                                    \
             hipLaunchKernelGGL((k_adj2<R_, G_>), g, b, lds, s, a, d);                     \
+        else if (pass == 21 && a.laws.cube)                                               \
+            hipLaunchKernelGGL((k_adj21<R_, G_, true>), g, b, lds, s, a, d, *d1);         \
+        else if (pass == 21)                                                              \
+            hipLaunchKernelGGL((k_adj21<R_, G_, false>), g, b, lds, s, a, d, *d1);        \
         else if (a.laws.cube)                                                             \
             hipLaunchKernelGGL((k_adj1<R_, G_, true>), g, b, lds, s, a, d);               \
         else                                                                              \
@@ -467,7 +519,8 @@ cryo_status launch_adj(const cryo_plan *p, int pass, const AdjArgs &d, int *flag
     default: return fail(CRYO_ERR_UNSUPPORTED, "radial chunk shape");
     }
 #undef ADJ_CASE
-    return check_launch(pass == 1 ? "adjoint pass 1" : "adjoint pass 2");
+    return check_launch(pass == 1 ? "adjoint pass 1" : pass == 2 ? "adjoint pass 2"
+                                                                  : "adjoint passes 2+1");
 }
 
 cryo_status launch_adj_init(const cryo_plan *p, double *lam, double cS, hipStream_t s) {

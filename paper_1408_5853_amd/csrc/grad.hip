@@ -12,7 +12,8 @@
 
 namespace cryo {
 
-cryo_status launch_adj(const cryo_plan *p, int pass, const AdjArgs &d, int *flag, hipStream_t s);
+cryo_status launch_adj(const cryo_plan *p, int pass, const AdjArgs &d, int *flag, hipStream_t s,
+                       const AdjArgs *d1 = nullptr);
 cryo_status launch_adj_init(const cryo_plan *p, double *lam, double cS, hipStream_t s);
 cryo_status launch_zero(double *ptr, size_t n, hipStream_t s);
 int adj_slots(const cryo_plan *p);
@@ -37,7 +38,7 @@ static double source_fraction_dwidth(const Pulse &p, double dt, int64_t k) {
 }
 
 struct GradLayout {
-    size_t flag, fwd_buf[2], part, ck, seg, lam[2], Y, lpart, acc, accg, surf, total;
+    size_t flag, fwd_buf[2], part, ck, seg, lam[2], Y[2], lpart[2], acc, accg, surf, total;
     int64_t nck, K;
 };
 
@@ -57,8 +58,12 @@ static GradLayout grad_layout(const cryo_plan *p, int64_t N, int64_t ckpt) {
     g.seg = o; o += F * (size_t)(K + 1);
     g.lam[0] = o; o += F;
     g.lam[1] = o; o += F;
-    g.Y = o; o += F;
-    g.lpart = o; o += F;
+    // y and the radial part of lam, by step parity (the fused passes read
+    // step k's while writing step k-1's)
+    g.Y[0] = o; o += F;
+    g.Y[1] = o; o += F;
+    g.lpart[0] = o; o += F;
+    g.lpart[1] = o; o += F;
     g.acc = o; o += al256(sizeof(double) * 3 * (size_t)p->np * adj_slots(p));
     g.accg = o; o += al256(sizeof(double) * 2 * (size_t)adj_slots(p));
     g.surf = o; o += al256(sizeof(double) * (size_t)std::max<int64_t>(N, 1));
@@ -180,25 +185,34 @@ static cryo_status grad_backward(GradRun &r) {
             st = launch_step(p, segp(k - a), segp(k - a + 1), X, nullptr, flag, s);
             if (st != CRYO_OK) return st;
         }
-        for (int64_t k = b - 1; k >= a; --k) {
+        // adjoint step k: pass 1 reads lam^{k+1} (lam[cur]) and writes y^k,
+        // pass 2 writes lam^k (lam[cur ^ 1]); pass 2 of step k and pass 1 of
+        // step k-1 run as one launch inside the segment
+        auto args = [&](int64_t k, int c) {
             AdjArgs d;
             d.T = segp(k - a);
             d.X = segp(k - a + 1);
-            d.lam_in = lam[cur];
-            d.Y = (double *)(w + g.Y);
-            d.lpart = (double *)(w + g.lpart);
-            d.lam_out = lam[cur ^ 1];
+            d.lam_in = lam[c];
+            d.Y = (double *)(w + g.Y[k & 1]);
+            d.lpart = (double *)(w + g.lpart[k & 1]);
+            d.lam_out = lam[c ^ 1];
             d.acc = acc;
             d.accg = accg;
             d.s = source_fraction(p->pulse, k);
             d.ds = source_fraction_dwidth(p->pulse, p->prob.dt, k);
             d.cS = k >= 1 ? r.cS[k] : 0.0;
             d.xs = p->eta * p->eta;
-            st = launch_adj(p, 1, d, flag, s);
-            if (st == CRYO_OK) st = launch_adj(p, 2, d, flag, s);
-            if (st != CRYO_OK) return st;
+            return d;
+        };
+        st = launch_adj(p, 1, args(b - 1, cur), flag, s);
+        for (int64_t k = b - 1; k > a && st == CRYO_OK; --k) {
+            const AdjArgs d2 = args(k, cur), d1 = args(k - 1, cur ^ 1);
+            st = launch_adj(p, 21, d2, flag, s, &d1);
             cur ^= 1;
         }
+        if (st == CRYO_OK) st = launch_adj(p, 2, args(a, cur), flag, s);
+        if (st != CRYO_OK) return st;
+        cur ^= 1;
     }
     return CRYO_OK;
 }
