@@ -82,8 +82,10 @@ __device__ inline AdjLds adj_stage(const StepArgs<double> &a, unsigned char *sme
 
 // Pass 1 of one step over this workgroup's line groups (tables staged).
 template <int RPL, int G, bool CUBE>
+// (keep: lam^{n+1} of the group's single line comes in lamR, not from memory)
 __device__ inline void adj1_body(const StepArgs<double> &a, const AdjArgs &d,
-                                 unsigned char *smem, const AdjLds &tb) {
+                                 unsigned char *smem, const AdjLds &tb,
+                                 const double (&lamR)[RPL], bool keep) {
     constexpr int NL = WAVE * G, NG = ADJ_WAVES / G;
     __shared__ double xchg[NG][9 * G];
     __shared__ double xb[NG][2 * G];
@@ -115,7 +117,7 @@ __device__ inline void adj1_body(const StepArgs<double> &a, const AdjArgs &d,
         for (int r = 0; r < RPL; ++r) {
             const int q = r * NL + lg;
             T[r] = d.T[base + q];
-            MU[r] = d.lam_in[base + q];
+            MU[r] = keep ? lamR[r] : d.lam_in[base + q];
         }
         // boundary-copy lines feed their sensitivity back to the copied line
         if (j == 1 && !a.held[2]) {
@@ -313,15 +315,19 @@ template <int RPL, int G, bool CUBE>
 __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj1(StepArgs<double> a, AdjArgs d) {
     extern __shared__ __align__(16) unsigned char smem[];
     const AdjLds tb = adj_stage(a, smem);
-    adj1_body<RPL, G, CUBE>(a, d, smem, tb);
+    const double none[RPL] = {};
+    adj1_body<RPL, G, CUBE>(a, d, smem, tb, none, false);
 }
 
 // Pass 2: axial faces.  Each interior line j adds the terms of its two
 // axial faces (capacity rows), and the lines next to the z-boundaries write
 // the boundary lines' lam^n.
 template <int RPL, int G>
+// (keep: lam^n of the group's single line goes to lamR, not to memory; the
+// boundary lines' lam^n is always written)
 __device__ inline void adj2_body(const StepArgs<double> &a, const AdjArgs &d,
-                                 unsigned char *smem, const AdjLds &tb) {
+                                 unsigned char *smem, const AdjLds &tb, double (&lamR)[RPL],
+                                 bool keep) {
     constexpr int NL = WAVE * G, NG = ADJ_WAVES / G;
     const uint32_t *sinf = tb.sinf;
     const LawLds<double> &law = tb.law;
@@ -402,7 +408,8 @@ __device__ inline void adj2_body(const StepArgs<double> &a, const AdjArgs &d,
                 if (lg == a.surf_lane && r == a.surf_reg) le_ += d.cS * a.wz_end;
                 d.lam_out[(size_t)(a.nz - 1) * LS + q] = le_;
             }
-            d.lam_out[base + q] = lam;
+            if (keep) lamR[r] = lam;
+            else d.lam_out[base + q] = lam;
             // one row at a time (register pressure)
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -432,22 +439,27 @@ template <int RPL, int G>
 __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj2(StepArgs<double> a, AdjArgs d) {
     extern __shared__ __align__(16) unsigned char smem[];
     const AdjLds tb = adj_stage(a, smem);
-    adj2_body<RPL, G>(a, d, smem, tb);
+    double lamR[RPL];
+    adj2_body<RPL, G>(a, d, smem, tb, lamR, false);
 }
 
 // Pass 2 of step k and pass 1 of step k - 1 in one launch: each line group
-// finishes lam^k of its lines (written to memory, read back by the same
-// lanes), then runs the next step's line solves on it.  Every value that
+// finishes lam^k of its lines (in registers for one line per group, else
+// written to memory and read back by the same lanes), then runs the next
+// step's line solves on it.  Every value that
 // crosses line groups (y^k of the neighbouring lines) is read in the first
 // phase and written only to the other buffer in the second.
-template <int RPL, int G, bool CUBE>
+template <int RPL, int G, bool CUBE, bool KEEP>
 __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj21(StepArgs<double> a, AdjArgs d2,
                                                            AdjArgs d1) {
     extern __shared__ __align__(16) unsigned char smem[];
     const AdjLds tb = adj_stage(a, smem);
-    adj2_body<RPL, G>(a, d2, smem, tb);
+    // one line per group: lam^k stays in registers between the phases (no
+    // other group reads it)
+    double lamR[RPL] = {};
+    adj2_body<RPL, G>(a, d2, smem, tb, lamR, KEEP);
     __syncthreads();           // the LDS row sums area passes to the next phase
-    adj1_body<RPL, G, CUBE>(a, d1, smem, tb);
+    adj1_body<RPL, G, CUBE>(a, d1, smem, tb, lamR, KEEP);
 }
 
 // lam^N = dJ_N / dT^N: the surface weights on the outer row
@@ -499,10 +511,14 @@ cryo_status launch_adj(const cryo_plan *p, int pass, const AdjArgs &d, int *flag
     case R_ * 10 + G_:                                                                    \
         if (pass == 2)                                                                    \
             hipLaunchKernelGGL((k_adj2<R_, G_>), g, b, lds, s, a, d);                     \
+        else if (pass == 21 && a.laws.cube && a.lpw == 1)                                 \
+            hipLaunchKernelGGL((k_adj21<R_, G_, true, true>), g, b, lds, s, a, d, *d1);   \
         else if (pass == 21 && a.laws.cube)                                               \
-            hipLaunchKernelGGL((k_adj21<R_, G_, true>), g, b, lds, s, a, d, *d1);         \
+            hipLaunchKernelGGL((k_adj21<R_, G_, true, false>), g, b, lds, s, a, d, *d1);  \
+        else if (pass == 21 && a.lpw == 1)                                                \
+            hipLaunchKernelGGL((k_adj21<R_, G_, false, true>), g, b, lds, s, a, d, *d1);  \
         else if (pass == 21)                                                              \
-            hipLaunchKernelGGL((k_adj21<R_, G_, false>), g, b, lds, s, a, d, *d1);        \
+            hipLaunchKernelGGL((k_adj21<R_, G_, false, false>), g, b, lds, s, a, d, *d1); \
         else if (a.laws.cube)                                                             \
             hipLaunchKernelGGL((k_adj1<R_, G_, true>), g, b, lds, s, a, d);               \
         else                                                                              \
