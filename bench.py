@@ -192,6 +192,9 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the timed region, copy this many MiB device to device once "
                          "(a kernel of known traffic that calibrates the HBM byte counters)")
+    ap.add_argument("--gradient-only", type=int, default=0, metavar="N",
+                    help="profiling aid: time only a forward and a gradient of N steps on the "
+                         "adjoint cell and print that result")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: the stepper runs on exactly one GPU; --gpus %d is not supported"
@@ -204,6 +207,10 @@ def main():
     import paper_1408_5853_amd as P
 
     stream = torch.cuda.current_stream()
+    if args.gradient_only:
+        gradient_extra(P, 50, stream)                       # warm
+        print(json.dumps({"gradient": gradient_extra(P, args.gradient_only, stream)}), flush=True)
+        return
     cell = cellgen.device_cell(0)
     cells = cell["nr"] * cell["nz"]
     log("bench: device cell 1024x4096 FP64, %d steps after %d warmup" % (args.steps, args.warmup))
