@@ -142,7 +142,7 @@ __device__ inline void adj1_body(const StepArgs<double> &a, const AdjArgs &d,
             const bool cap = kind == K_CAP, ifc = kind == K_IFACE;
             const double t = T[r], Te = (r < RPL - 1) ? T[r + 1] : TeL;
             const int le = (inf_r >> 6) & 63, l2 = (inf_r >> 12) & 63;
-            const int l3 = (inf_r >> 18) & 63, lc = (inf_r >> 24) & 63;
+            const int lc = (inf_r >> 24) & 63;
             const double lamE = law.lawc(le, 0.5 * (t + Te));
             // rows in the stepping kernel's scaled form: an interface row's
             // west coefficient is the ratio law at the node and its east one
@@ -153,7 +153,6 @@ __device__ inline void adj1_body(const StepArgs<double> &a, const AdjArgs &d,
                 const double va = law.lawc(l2, t);
                 if (ifc) l2v = va;
             }
-            (void)l3;
             double rc;
             if constexpr (CUBE) rc = law.cube(lc, t);
             else rc = law.lawc(lc, t);
