@@ -12,6 +12,10 @@
 // boundary rows) and the right-hand side is the explicit residual, so the
 // unknown is the increment dT = T^ - T:
 //   A dT_{i-1} + B dT_i + C dT_{i+1} = Lambda_i[T] + Lambda_j[T] + X.
+// The rows are solved in scaled form (same solution): capacity rows times
+// eta^2, so the axial faces take the radial law, and interface rows divided
+// by the outer layer's law at the node, so they need one ratio law; the
+// plan's forward tables (fgw, fge, finfo, flaws) hold that form.
 // The tridiagonal system is solved by partition: every lane eliminates its
 // chunk down to two unknowns (first and last row), the 128 chunk-end unknowns
 // are reduced to one per lane, and parallel cyclic reduction across the wave
