@@ -29,11 +29,12 @@ namespace cryo {
 
 // One step of eq. (8).  A line is spread over G waves (NL = 64 G lanes, each
 // lane a chunk of RPL rows); a workgroup of STEP_WAVES waves runs
-// STEP_WAVES / G lines side by side.  Each line group marches up a block of
-// lpw consecutive interior lines, keeping the flux through the face between
-// the current and the next line: the north-face flux of line j is the
-// south-face flux of line j+1 (eq. (11)), so a capacity row evaluates two
-// conductivities per line (east r-face, north z-face) instead of three.
+// STEP_WAVES / G lines side by side.  Each line group marches through a
+// block of lpw consecutive interior lines (up or down), keeping the flux
+// through the face between the current and the next line: the flux into
+// line j from line j+1 is minus the flux into line j+1 from line j (eq. (11)),
+// so a capacity row evaluates two conductivities per line (east r-face, the
+// face towards the next line) instead of three.
 // CUBE: every capacity law has exponent 3 (c(T) by multiplication).
 template <typename R, int RPL, int G, bool CUBE>
 __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *__restrict__ Tin,
@@ -62,6 +63,18 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
     const int L = a.laws.L;
     const int j0 = 1 + (blk * NG + grp) * a.lpw;
     const int j1 = min(j0 + a.lpw, a.nz - 1);             // exclusive
+    // Line order: even line groups march up, odd ones down, so that the
+    // halo line two neighbouring groups share is read by both at about the
+    // same time (both at their start or both at their end) and stays in L2.
+    // The LDS line ring marches up only.  dir is uniform.
+    constexpr bool RING_ = ring_used<R>(RPL);
+    const int dir = (!RING_ && ((blk * NG + grp) & 1)) ? -1 : 1;
+    // line of iteration it, clamped: active iterations first (it < j1 - j0),
+    // then inactive ones on real lines (results discarded)
+    auto line_at = [&](int it) {
+        const int jr = dir > 0 ? j0 + it : j1 - 1 - it;
+        return min(max(jr, 1), a.nz - 2);
+    };
     const size_t LS = (size_t)a.np * NPL;                 // line stride
     const size_t LO = PAIR ? (size_t)a.np : 0;            // offset of the low plane
     R *xch = xchg[grp];
@@ -110,8 +123,9 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
     R Tc[RPL], Lc[RPL];
     R TwF, TeL, LwF = 0, LeL = 0;
     {
-        const int jb = min(j0, a.nz - 2);
+        const int jb = line_at(0);
         const size_t bc = (size_t)jb * LS;
+        const size_t bp = (size_t)(jb - dir) * LS;       // the line before it
         prefetch(1, bc + LS);
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
@@ -125,13 +139,13 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
             LwF = Tin[bc + LO + qW];
             LeL = Tin[bc + LO + qE];
         }
-        // south-face flux of the block's first line (capacity rows); the line
-        // below is loaded up front
+        // axial flux into the block's first line from the line before it
+        // (capacity rows); that line is loaded up front
         R Tpv[RPL], Tplv[RPL];
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
-            Tpv[r] = Tin[bc - LS + r * NL + lg];
-            Tplv[r] = PAIR ? Tin[bc - LS + LO + r * NL + lg] : (R)0;
+            Tpv[r] = Tin[bp + r * NL + lg];
+            Tplv[r] = PAIR ? Tin[bp + LO + r * NL + lg] : (R)0;
         }
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
@@ -142,7 +156,7 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
             const int l2 = (inf_r >> 12) & 63;
             if constexpr (!PAIR) bad |= !LawLds<R>::in_range(Tp);
             const R lamS = law.lawm(cap ? l2 : law_zero(L), Tc[r] + Tp);
-            fs_set(r, lamS * dif<R>(Tc[r], Lc[r], Tp, Tpl));
+            fs_set(r, lamS * dif<R>(Tp, Tpl, Tc[r], Lc[r]));
             if (r & 1) __builtin_amdgcn_sched_barrier(0);      // register pressure
         }
         // the next line's slot must have landed before the first row reads it
@@ -152,7 +166,7 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
     constexpr int PF = 2;
     R TnQ[PF], LnQ[PF];
     if constexpr (!RING) {
-        const size_t bq = (size_t)(min(j0, a.nz - 2) + 1) * LS;
+        const size_t bq = (size_t)(line_at(0) + dir) * LS;
 #pragma unroll
         for (int r = 0; r < PF && r < RPL; ++r) {
             TnQ[r] = Tin[bq + r * NL + lg];
@@ -160,10 +174,10 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
         }
     }
     for (int it = 0; it < a.lpw; ++it) {
-        const int jr = j0 + it;
-        const bool active = jr < j1;
-        const int j = min(jr, a.nz - 2);
+        const bool active = it < j1 - j0;
+        const int j = line_at(it);
         const size_t base = (size_t)j * LS;
+        const size_t bo = (size_t)(j + dir) * LS;        // the other line: the next one
         const R *sn = ring + ((it + 1) & 1) * SLOT;      // line j+1
         // the other slot (line j, already read into registers) takes line j+2;
         // its reads must have completed before the load overwrites it
@@ -173,7 +187,7 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
         }
         R TwP, TeP, LwP = 0, LeP = 0;                      // next line's chunk-end neighbours
         {
-            const size_t bn = (size_t)min(j + 1, a.nz - 2) * LS;
+            const size_t bn = (size_t)line_at(it + 1) * LS;
             TwP = Tin[bn + qW];
             TeP = Tin[bn + qE];
             if constexpr (PAIR) {
@@ -206,8 +220,8 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
             if (r + 1 < RPL) infn = sinf[q + NL];
             if constexpr (!RING) {
                 if (r + PF < RPL) {
-                    TnP[r + PF] = Tin[base + LS + q + PF * NL];
-                    LnP[r + PF] = PAIR ? Tin[base + LS + LO + q + PF * NL] : (R)0;
+                    TnP[r + PF] = Tin[bo + q + PF * NL];
+                    LnP[r + PF] = PAIR ? Tin[bo + LO + q + PF * NL] : (R)0;
                 }
             }
             const uint32_t kind = inf_r & 7;
@@ -221,9 +235,10 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
                 Tnr = TnP[r];
                 if constexpr (PAIR) Lnr = LnP[r];
             }
-            // read unconditionally at the row's start: a read under the
-            // capacity test becomes a branch that waits for it at once
-            const R FS = fs_get(r);
+            // the carried flux into this line from the previous line, read
+            // unconditionally at the row's start (a read under the capacity
+            // test becomes a branch that waits for it at once)
+            const R Fc = fs_get(r);
             const R Tw = (r > 0) ? Tc[r - 1] : TwF;
             const R Te = (r < RPL - 1) ? Tc[r + 1] : TeL;
             const R Lw = (r > 0) ? Lc[r - 1] : LwF;
@@ -244,15 +259,16 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
             else rc = law.lawm(lc, T + T);
             const R fw = sgw[q] * (cap ? lamW : lam2);
             const R fe = sge[q] * (cap ? lamE : (R)1);
-            const R FN = lam2 * dif<R>(Tnr, Lnr, T, Tl);
+            // flux into this line from the next one (carried on, negated)
+            const R Fo = lam2 * dif<R>(Tnr, Lnr, T, Tl);
             R dd = fw * dif<R>(Tw, Lw, T, Tl) + fe * dif<R>(Te, Le, T, Tl);
-            dd += cap ? FN - FS : (R)0;
+            dd += cap ? Fo + Fc : (R)0;
             dd += (R)((inf_r >> 3) & 1) * X;                // heater capacity rows
             // held walls: rows 0 and nr - 1 are unit rows with dT = value - T
             if (r == 0 && a.held[0]) dd = lg == 0 ? dif<R>(a.val[0], (R)0, T, Tl) : dd;
             if (r == a.surf_reg && a.held[1])
                 dd = lg == a.surf_lane ? dif<R>(a.val[1], (R)0, T, Tl) : dd;
-            fs_set(r, FN);
+            fs_set(r, -Fo);
             lamW = lamE;
             const R aa = -fw, bb = fw + fe + rc, cc = -fe;
             if (r == 0) {
@@ -271,9 +287,9 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
             if (RPL >= 10 || (r & 1)) __builtin_amdgcn_sched_barrier(0);
         }
         if constexpr (!RING) {
-            // the next iteration's first rows above (its line is min(jr + 1,
-            // nz - 2), one past the last interior line only when inactive)
-            const size_t bq = (size_t)(min(jr + 1, a.nz - 2) + 1) * LS;
+            // the next iteration's first rows of its other line (a boundary
+            // line only for inactive iterations)
+            const size_t bq = (size_t)(line_at(it + 1) + dir) * LS;
 #pragma unroll
             for (int r = 0; r < PF && r < RPL; ++r) {
                 TnQ[r] = Tin[bq + r * NL + lg];

@@ -278,7 +278,7 @@ extern "C" {
 
 const char *cryo_last_error(void) { return g_err.c_str(); }
 
-const char *cryo_version(void) { return "cryocell 0.6 (gfx950)"; }
+const char *cryo_version(void) { return "cryocell 0.7 (gfx950)"; }
 
 cryo_status cryo_validate(const cryo_problem *prob) { return check_problem(prob); }
 
