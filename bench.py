@@ -38,7 +38,8 @@ BYTES_PER_CELL_STEP = 16          # read T, write T^ (FP64; an FP32 pair is also
 # keyed by library version and kernel shape: any other build reports null.
 # (0.6 changed only the adjoint kernels: its k_step is the code measured on 0.5.)
 MEASURED_TRAFFIC = {("cryocell 0.5 (gfx950)", (16, 1, 2)): 84.65e6,
-                    ("cryocell 0.6 (gfx950)", (16, 1, 2)): 84.65e6}
+                    ("cryocell 0.6 (gfx950)", (16, 1, 2)): 84.65e6,
+                    ("cryocell 0.7 (gfx950)", (16, 1, 2)): 75.23e6}
 
 
 def log(*a):
@@ -244,7 +245,7 @@ def main():
                      "note": "algorithmic 16 B/cell-step; traffic = rocprofv3 FETCH_SIZE and "
                              "WRITE_SIZE scaled by a 256 MiB copy; the 64 MiB ping-pong "
                              "state stays in L2/MALL and the kernel is bound by FP64 VALU "
-                             "issue and LDS latency (45 % VALU busy), not by HBM"},
+                             "issue and LDS latency (46 % VALU busy), not by HBM"},
     }
     if args.copy_mib:
         n = args.copy_mib * (1 << 20) // 8
