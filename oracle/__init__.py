@@ -42,7 +42,7 @@ class _OCell(C.Structure):
         ("amplitude", C.c_double), ("width", C.c_double),
         ("period", C.c_double), ("t_on", C.c_double),
         ("bc_kind", C.c_int * 4), ("bc_value", C.c_double * 4),
-        ("dt", C.c_double),
+        ("dt", C.c_double), ("turn_on", C.c_int),
     ]
 
 
@@ -60,6 +60,8 @@ def lib():
         L.oc_radii.argtypes = [cp, dp]
         L.oc_source_fraction.argtypes = [cp, C.c_long]
         L.oc_source_fraction.restype = C.c_double
+        L.oc_turn_on_source.argtypes = [cp, C.c_long, C.c_int]
+        L.oc_turn_on_source.restype = C.c_double
         L.oc_source_fraction_dwidth.argtypes = [cp, C.c_long]
         L.oc_source_fraction_dwidth.restype = C.c_double
         L.oc_line_rows.argtypes = [cp, dp, C.c_long, C.c_int, dp, dp, dp, dp]
@@ -101,6 +103,7 @@ class _Cell:
             s.bc_kind[q] = int(cell["bc"][q][0])
             s.bc_value[q] = float(cell["bc"][q][1])
         s.dt = cell["dt"]
+        s.turn_on = int(bool(cell.get("turn_on", False)))
         self.s = s
 
     def ref(self):
@@ -129,6 +132,11 @@ def radii(cell):
 
 def source_fraction(cell, k):
     return lib().oc_source_fraction(_Cell(cell).ref(), int(k))
+
+
+def turn_on_source(cell, k, i):
+    """Source factor of sub-step i of pulse-start step k, eq. (22)."""
+    return lib().oc_turn_on_source(_Cell(cell).ref(), int(k), int(i))
 
 
 def source_fraction_dwidth(cell, k):

@@ -22,6 +22,14 @@
  *    nearest integer when within 1e-9 relative.  The source is the amplitude
  *    times that average on the heater layer's capacity nodes (p(t) = 1).
  *  - Axial spacing is uniform, eta = height / (nz - 1).
+ *  - Transient turn-on model (Sec. 3.2, eq. (22)), when enabled: the
+ *    exponential is taken decaying, p^2(t) = 1 - exp(-(t - t_n) / (7 tau*)),
+ *    so that p^2 rises from 0 towards 1 as the text describes (as printed
+ *    it is negative).  Pulse n starts at t_n = t_on + n P, which must fall on
+ *    a step boundary; the step [t_n, t_n + tau) is taken as 100 sub-steps of
+ *    tau* = tau / 100, sub-step i with the gate averaged over the sub-step
+ *    times p^2 at its start, 1 - exp(-i / 7).  All other steps are unchanged
+ *    (p^2 = 1), and the surface mean is reported once per step.
  */
 #include "oracle.h"
 
@@ -139,13 +147,14 @@ static double snap(double x)
     return fabs(x - n) <= 1e-9 * fmax(1.0, fabs(x)) ? n : x;
 }
 
-/* eq. (4): nu(t) = 1 on [t_on + nP, t_on + nP + w), averaged over one step */
-double oc_source_fraction(const ocell *c, long k)
+/* eq. (4): time the gate nu(t) = 1 on [t_on + nP, t_on + nP + w) is open
+ * within [lo, hi), all in step units */
+static double gate_overlap(const ocell *c, double lo, double hi)
 {
     if (!(c->width > 0)) return 0.0;
     double b0 = snap(c->t_on / c->dt), W = snap(c->width / c->dt);
     double P = snap(c->period / c->dt);
-    double lo = (double)k, hi = (double)k + 1.0, s = 0.0;
+    double s = 0.0;
     long n = (long)floor((lo - b0 - W) / P);
     if (n < 0) n = 0;
     for (;; n++) {
@@ -155,6 +164,30 @@ double oc_source_fraction(const ocell *c, long k)
         if (o > 0) s += o;
     }
     return s;
+}
+
+/* eq. (4) averaged over step k */
+double oc_source_fraction(const ocell *c, long k)
+{
+    return gate_overlap(c, (double)k, (double)k + 1.0);
+}
+
+/* eq. (22): does step k start a pulse (t_on + n P = k dt)?  -1 when the
+ * model is on but pulse starts do not fall on step boundaries */
+static int pulse_start(const ocell *c, long k)
+{
+    double b0 = snap(c->t_on / c->dt), P = snap(c->period / c->dt);
+    if (b0 != floor(b0) || P != floor(P) || !(P >= 1)) return -1;
+    long kb = (long)b0, kp = (long)P;
+    return k >= kb && (k - kb) % kp == 0;
+}
+
+/* source factor of sub-step i of a pulse-start step k: the gate's average
+ * over [k + i/100, k + (i+1)/100) times p^2 = 1 - exp(-i/7) (eq. (22)) */
+double oc_turn_on_source(const ocell *c, long k, int i)
+{
+    double lo = (double)k + (double)i / 100.0, hi = (double)k + (double)(i + 1) / 100.0;
+    return gate_overlap(c, lo, hi) / (hi - lo) * (1.0 - exp(-(double)i / 7.0));
 }
 
 /* d/d(width) of the step average: 1/dt while a pulse ends inside the step,
@@ -179,11 +212,11 @@ double oc_source_fraction_dwidth(const ocell *c, long k)
 
 /* Rows of eq. (13) for line j (capacity), eq. (18) (interface), eq. (15)
  * (r boundaries); the explicit z operator eq. (11) sits in F. */
-static void line_rows(const ocell *c, const geom *g, const double *T, double s,
-                      int j, double *A, double *B, double *C, double *F)
+static void line_rows(const ocell *c, const geom *g, const double *T, double tau,
+                      double s, int j, double *A, double *B, double *C, double *F)
 {
     int nr = c->nr;
-    double tau = c->dt, eta = c->height / (c->nz - 1);
+    double eta = c->height / (c->nz - 1);
     const double *Tj = T + (size_t)j * nr;
     const double *Tn = Tj + nr, *Ts = Tj - nr;
     const double *r = g->r, *h = g->h;
@@ -226,7 +259,7 @@ int oc_line_rows(const ocell *c, const double *T, long k, int j,
 {
     geom g;
     if (check_cell(c) || j < 1 || j > c->nz - 2 || geom_build(c, &g)) return 1;
-    line_rows(c, &g, T, oc_source_fraction(c, k), j, A, B, C, F);
+    line_rows(c, &g, T, c->dt, oc_source_fraction(c, k), j, A, B, C, F);
     geom_free(&g);
     return 0;
 }
@@ -267,7 +300,7 @@ int oc_line_paper_sweep(const ocell *c, const double *T, long k, int j, double *
     double *A = malloc(sizeof(double) * 6 * nr);
     if (!A) { geom_free(&g); return 1; }
     double *B = A + nr, *C = B + nr, *F = C + nr, *al = F + nr, *be = al + nr;
-    line_rows(c, &g, T, oc_source_fraction(c, k), j, A, B, C, F);
+    line_rows(c, &g, T, c->dt, oc_source_fraction(c, k), j, A, B, C, F);
     const double *Tj = T + (size_t)j * nr;
     al[0] = 1.0; be[0] = 0.0;                                   /* eq. (16) */
     for (int i = 1; i < nr - 1; i++) {
@@ -335,19 +368,26 @@ static int thread_id(void)
 #endif
 }
 
-/* one step of eq. (8): T (old, step k) -> Tn (new); scratch per thread */
-static void step(const ocell *c, const geom *g, const double *T, double *Tn,
-                 long k, rows_t *scr, int nth)
+/* one step of eq. (8) of length tau with gate factor s: T (old) -> Tn (new);
+ * scratch per thread */
+static void step_tau(const ocell *c, const geom *g, const double *T, double *Tn,
+                     double tau, double s, rows_t *scr, int nth)
 {
     int nr = c->nr, nz = c->nz;
-    double s = oc_source_fraction(c, k);
 #pragma omp parallel for num_threads(nth) schedule(static)
     for (int j = 1; j < nz - 1; j++) {
         rows_t *w = &scr[thread_id()];
-        line_rows(c, g, T, s, j, w->A, w->B, w->C, w->F);
+        line_rows(c, g, T, tau, s, j, w->A, w->B, w->C, w->F);
         thomas(nr, w->A, w->B, w->C, w->F, w->al, w->be, Tn + (size_t)j * nr);
     }
     z_boundaries(c, Tn);
+}
+
+/* step k (p^2 = 1) */
+static void step(const ocell *c, const geom *g, const double *T, double *Tn,
+                 long k, rows_t *scr, int nth)
+{
+    step_tau(c, g, T, Tn, c->dt, oc_source_fraction(c, k), scr, nth);
 }
 
 static rows_t *scratch_alloc(int nth, int nr)
@@ -375,15 +415,26 @@ int oc_forward(const ocell *c, double *T, long k0, long nsteps, double *surf,
                int nthreads)
 {
     geom g;
-    if (check_cell(c) || nsteps < 0 || geom_build(c, &g)) return 1;
+    if (check_cell(c) || nsteps < 0) return 1;
+    if (c->turn_on && c->width > 0 && pulse_start(c, 0) < 0) return 1;
+    if (geom_build(c, &g)) return 1;
     size_t n = (size_t)c->nr * c->nz;
     int nth = nthreads_of(nthreads);
     double *Tn = malloc(sizeof(double) * n);
     rows_t *scr = scratch_alloc(nth, c->nr);
     if (!Tn || !scr) { free(Tn); scratch_free(scr, nth); geom_free(&g); return 1; }
     for (long s = 0; s < nsteps; s++) {
-        step(c, &g, T, Tn, k0 + s, scr, nth);
-        memcpy(T, Tn, sizeof(double) * n);
+        long k = k0 + s;
+        if (c->turn_on && c->width > 0 && pulse_start(c, k) == 1) {
+            /* eq. (22): the pulse's first step as 100 sub-steps */
+            for (int i = 0; i < 100; i++) {
+                step_tau(c, &g, T, Tn, c->dt / 100.0, oc_turn_on_source(c, k, i), scr, nth);
+                memcpy(T, Tn, sizeof(double) * n);
+            }
+        } else {
+            step(c, &g, T, Tn, k, scr, nth);
+            memcpy(T, Tn, sizeof(double) * n);
+        }
         if (surf) surf[s] = surface_mean(c, T);
     }
     free(Tn);
@@ -487,7 +538,7 @@ int oc_gradient(const ocell *c, const double *T0, long N, const double *target,
                 int nthreads)
 {
     geom g;
-    if (check_cell(c) || N < 1 || geom_build(c, &g)) return 1;
+    if (check_cell(c) || N < 1 || c->turn_on || geom_build(c, &g)) return 1;
     int nr = c->nr, nz = c->nz, L = c->n_layers, ng = 2 + 2 * L;
     size_t n = (size_t)nr * nz;
     long K = ckpt > 0 ? ckpt : N;
@@ -544,7 +595,7 @@ int oc_gradient(const ocell *c, const double *T0, long N, const double *target,
 #pragma omp parallel for num_threads(nth) schedule(static)
             for (int j = 1; j < nz - 1; j++) {
                 rows_t *w = &scr[thread_id()];
-                line_rows(c, &g, T, s, j, w->A, w->B, w->C, w->F);
+                line_rows(c, &g, T, c->dt, s, j, w->A, w->B, w->C, w->F);
                 /* A^T: sub-diagonal C_{i-1}, diagonal B_i, super-diagonal A_{i+1} */
                 double *sub = w->F, *sup = w->al;
                 sub[0] = 0.0;

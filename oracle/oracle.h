@@ -32,12 +32,16 @@ typedef struct {
     int bc_kind[4];           /* r_inner, r_outer, z_low, z_high: 0 insulated, 1 fixed */
     double bc_value[4];
     double dt;
+    int turn_on;              /* eq. (22) turn-on model: 0 off, 1 on */
 } ocell;
 
 /* node radii r_0..r_{nr-1}, eq. (9) */
 int oc_radii(const ocell *c, double *r);
 /* step-averaged pulse gate over [k dt, (k+1) dt), eq. (4) */
 double oc_source_fraction(const ocell *c, long k);
+/* source factor of sub-step i (0..99) of a pulse-start step k under the
+ * turn-on model, eq. (22): gate average over the sub-step times p^2 */
+double oc_turn_on_source(const ocell *c, long k, int i);
 /* derivative of oc_source_fraction with respect to the pulse width [1/s] */
 double oc_source_fraction_dwidth(const ocell *c, long k);
 /* rows A,B,C,F (length nr) of line j for step k, from old field T [nz][nr] */
@@ -52,10 +56,13 @@ int oc_thomas(int n, const double *A, const double *B, const double *C,
 int oc_line_paper_sweep(const ocell *c, const double *T, long k, int j,
                         double *x);
 /* advance T [nz][nr] from step k0 by nsteps steps; surf (nullable) receives
- * the surface mean after each step */
+ * the surface mean after each step.  With turn_on set, each step that starts
+ * a pulse runs as 100 sub-steps of dt/100 (eq. (22)); pulse starts must then
+ * fall on step boundaries, else the call fails */
 int oc_forward(const ocell *c, double *T, long k0, long nsteps, double *surf,
                int nthreads);
-/* J = sum_{n=1..N} (S_n - target_n)^2 and its gradient
+/* (fails when turn_on is set)
+ * J = sum_{n=1..N} (S_n - target_n)^2 and its gradient
  * grad = [dJ/dQ, dJ/dwidth, dJ/dthick[L], dJ/dkscale[L]] by the discrete
  * adjoint.  ckpt = 0 stores every state, else every ckpt-th with recompute.
  * lam0 (nullable, [nz][nr]) receives dJ/dT^0. */

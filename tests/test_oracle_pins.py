@@ -397,3 +397,134 @@ def test_maximum_principle_and_heating():
     T, S = oracle.forward(c, nsteps=3000, surf=True)
     assert T.min() > 28.0 - 1e-9
     assert np.all(np.diff(S[:900]) >= -1e-12)     # heating phase: surface rises
+
+
+# --------------------------------------------------------------------------
+# Transient turn-on model, Sec. 3.2, eq. (22) (decaying exponential reading)
+# --------------------------------------------------------------------------
+
+def _p2_sum(m):
+    # sum_{i<m} (1 - exp(-i/7)) by the geometric series
+    return m - (1.0 - math.exp(-m / 7.0)) / (1.0 - math.exp(-1.0 / 7.0))
+
+
+@pytest.mark.parametrize("w_steps,open_frac", [
+    # gate open over the whole step: all 100 sub-steps
+    (3.0, _p2_sum(100) / 100.0),
+    # gate closing at 0.375 of the step: sub-steps 0..36 open, 37 half open
+    (0.375, (_p2_sum(37) + 0.5 * (1.0 - math.exp(-37.0 / 7.0))) / 100.0),
+])
+def test_turn_on_heat_balance_closed_form(w_steps, open_frac):
+    # constant capacity, nonlinear conductivity, insulated on all sides: over
+    # the 100 sub-steps the fluxes telescope and the capacity-weighted content
+    # grows by exactly Q tau* sum_i (gate_i p2_i)
+    dt = 2e-7
+    Ls = [layer(1e-3, 30, k0=3.0, p=1.3, c0=80.0, q=0.0, rho=4e3)]
+    c = cell(Ls, nz=8, height=5e-3, dt=dt, amplitude=3e9, width=w_steps * dt,
+             period=50 * dt, heater=0)
+    c["turn_on"] = True
+    T = _random_field(c, 5, 28.0, 34.0)
+    T[0], T[-1] = T[1], T[-2]
+    Tn = oracle.forward(c, T, k0=50, nsteps=1)          # step 50 starts pulse 1
+    r = oracle.radii(c)
+    h = np.diff(r)
+    w = r[1:-1] * 0.5 * (h[:-1] + h[1:]) * (c["height"] / (c["nz"] - 1))
+    wc = w * Ls[0]["rho"] * Ls[0]["c0"] * np.ones((c["nz"] - 2, 1))
+    lhs = np.sum(wc * (Tn[1:-1, 1:-1] - T[1:-1, 1:-1]))
+    rhs = dt * c["amplitude"] * open_frac * np.sum(w * np.ones((c["nz"] - 2, 1)))
+    # rounding: each of the 100 sub-steps stores every temperature (<= 40 K)
+    # to within 2 ulp
+    rnd = 100 * 2 * np.finfo(float).eps * 40.0 * np.sum(wc)
+    assert abs(lhs - rhs) <= 1e-12 * abs(rhs) + rnd
+    assert rnd < 1e-8 * abs(rhs)
+    # without the model the same step injects the plain step average
+    c["turn_on"] = False
+    Tp = oracle.forward(c, T, k0=50, nsteps=1)
+    lhs_p = np.sum(w * Ls[0]["rho"] * Ls[0]["c0"] * (Tp[1:-1, 1:-1] - T[1:-1, 1:-1]))
+    rhs_p = dt * c["amplitude"] * min(w_steps, 1.0) * np.sum(w * np.ones((c["nz"] - 2, 1)))
+    assert abs(lhs_p - rhs_p) <= 1e-11 * abs(rhs_p)
+    assert abs(lhs - lhs_p) > 0.05 * abs(lhs_p)
+
+
+def test_turn_on_leaves_other_steps_alone():
+    c = cellgen.with_nz(cellgen.small_cell(1), 4)
+    dt = c["dt"]
+    c.update(t_on=3 * dt, width=5 * dt, period=20 * dt)
+    on = dict(c, turn_on=True)
+    T = oracle.forward(c, nsteps=3)                      # steps 0..2: no pulse starts
+    assert np.array_equal(oracle.forward(on, nsteps=3), T)
+    # steps 4..22 start no pulse either
+    T5 = oracle.forward(c, T, k0=3, nsteps=1)
+    assert np.array_equal(oracle.forward(on, T5, k0=4, nsteps=19),
+                          oracle.forward(c, T5, k0=4, nsteps=19))
+    # the pulse-start step 3 does change
+    assert not np.array_equal(oracle.forward(on, T, k0=3, nsteps=1), T5)
+
+
+def test_turn_on_substeps_are_hundredth_steps():
+    # with no source a pulse-start step is 100 plain steps of dt / 100
+    c = cellgen.with_nz(cellgen.small_cell(2, z_active=True), 6)
+    c["amplitude"] = 0.0
+    T0 = _random_field(c, 9, 28.0, 31.0)
+    on = dict(c, turn_on=True)
+    fine = dict(c, dt=c["dt"] / 100.0)
+    k = int(round(c["t_on"] / c["dt"]))
+    assert np.array_equal(oracle.forward(on, T0, k0=k, nsteps=1),
+                          oracle.forward(fine, T0, k0=0, nsteps=100))
+
+
+def test_turn_on_factor_shape():
+    # p^2 starts at zero, rises, and is saturated about halfway through the
+    # step (Sec. 3.2, Fig. 2)
+    c = cellgen.small_cell(0)
+    c.update(turn_on=True, width=10 * c["dt"])
+    f = np.array([oracle.turn_on_source(c, 0, i) for i in range(100)])
+    assert f[0] == 0.0
+    assert np.all(np.diff(f) > 0)
+    assert 0.999 < f[50] < 1.0 and f[99] < 1.0
+    assert f[10] < 0.8
+
+
+def test_turn_on_needs_pulse_starts_on_steps():
+    c = cellgen.with_nz(cellgen.small_cell(0), 4)
+    c.update(turn_on=True, t_on=2.5 * c["dt"])
+    with pytest.raises(ValueError):
+        oracle.forward(c, nsteps=2)
+    c.update(t_on=0.0, period=1000.5 * c["dt"])
+    with pytest.raises(ValueError):
+        oracle.forward(c, nsteps=2)
+    with pytest.raises(ValueError):
+        oracle.gradient(dict(c, period=1000 * c["dt"]), np.zeros(2), nsteps=2)
+
+
+def fig3_cell(mult, turn_on):
+    """A cold start (4.2 K, inner wall held there) with a strong pulse, the
+    setting of the paper's Fig. 3: steps of mult x 1 us."""
+    c = cellgen.with_nz(cellgen.small_cell(0), 4)
+    c.update(T_init=4.2, amplitude=3e9, dt=1e-6 * mult, turn_on=turn_on)
+    c["bc"][0] = [1, 4.2]
+    return c
+
+
+def _heater_trace(c, t_end=1e-3):
+    T = oracle.initial_field(c)
+    out = []
+    for k in range(int(round(t_end / c["dt"]))):
+        T = oracle.forward(c, T, k0=k, nsteps=1)
+        out.append(T[1].max())
+    return np.array(out)
+
+
+def test_turn_on_removes_start_jump_fig3():
+    # Fig. 3: with long steps and no turn-on model the first step overshoots
+    # and the cell then cools while the heater is still on; with the model it
+    # heats monotonically and ends near the short-step solution
+    ref = _heater_trace(fig3_cell(1, False))[-1]
+    for mult in (20, 100):
+        off = _heater_trace(fig3_cell(mult, False))
+        on = _heater_trace(fig3_cell(mult, True))
+        assert np.any(np.diff(off) < -0.1)
+        assert off[0] > ref * 0.5 and off.max() > on.max()
+        assert np.all(np.diff(on) >= 0)
+        assert abs(on[-1] - ref) < abs(off[-1] - ref)
+        assert abs(on[-1] - ref) < 0.03 * ref
