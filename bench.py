@@ -182,6 +182,32 @@ def paper_shape_extra(P, steps, stream):
                                     "(0.098 Gcell-steps/s), 64.0 min on its CPU"}
 
 
+def turn_on_extra(P, steps, stream):
+    """The transient turn-on model (eq. (22)) on the device cell: a run that
+    starts on a pulse start (its first step as 100 sub-steps of dt/100) timed
+    with and without the model; one pulse start per 100,000 steps at this
+    cell's period and dt."""
+    import cellgen
+    c = cellgen.device_cell(0)
+    per_period = int(round(c["period"] / c["dt"]))
+    out = {"workload": "device cell 1024x4096, FP64, %d steps from a pulse start" % steps}
+    for on in (False, True):
+        plan = P.Plan(dict(c, turn_on=on), "f64")
+        T = plan.init()
+        ws = plan.workspace(steps)
+        plan.forward(T, 0, steps, ws=ws)                  # warm (device tables)
+        T = plan.init()
+        secs = timed(stream, lambda: plan.forward(T, 0, steps, ws=ws))
+        plan.poll(ws)
+        out["with_model_s" if on else "without_model_s"] = round(secs, 5)
+    extra = out["with_model_s"] - out["without_model_s"]
+    plain = out["without_model_s"] / steps
+    out["turn_on_step_ms"] = round(1e3 * (plain + extra), 4)
+    out["plain_step_ms"] = round(1e3 * plain, 4)
+    out["overhead_per_period_pct"] = round(100 * extra / (per_period * plain), 4)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -265,6 +291,8 @@ def main():
         out["extra"]["gradient"] = gradient_extra(P, 50_000, stream)
         log("bench: paper shape")
         out["extra"]["paper_shape"] = paper_shape_extra(P, 10_000, stream)
+        log("bench: turn-on model")
+        out["extra"]["turn_on"] = turn_on_extra(P, 1000, stream)
         log("bench: design loop")
         out["extra"]["design_loop"] = design_extra(P, 500, 2, stream)
     if not args.no_cpu:

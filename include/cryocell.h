@@ -183,6 +183,21 @@ cryo_status cryo_forward(const cryo_plan *plan, void *T, int64_t k0,
                          int64_t nsteps, void *ws, size_t ws_bytes,
                          double *surf, void *stream);
 
+/* Transient turn-on model of the source, Sec. 3.2, eq. (22), read with a
+ * decaying exponential (p^2 = 1 - exp(-(t - t_n) / (7 tau*)), tau* = dt/100,
+ * rising from 0 towards 1).  With on != 0, every step k of cryo_forward whose
+ * interval starts a pulse (k dt = t_on + n period) runs as 100 sub-steps of
+ * dt/100; sub-step i takes the gate of eq. (4) averaged over the sub-step
+ * times 1 - exp(-i/7), the value of p^2 at its start.  Other steps are
+ * unchanged, and `surf` keeps one value per step (after its last sub-step).
+ * Requires t_on and period to be whole multiples of dt (CRYO_ERR_UNSUPPORTED
+ * otherwise).  The plan builds host tables for dt/100 here (device tables at
+ * its next forward call), follows later cryo_plan_set_shape calls, and frees
+ * them with on = 0 or cryo_plan_destroy.  cryo_gradient and
+ * cryo_gradient_many reject a plan with the model on (CRYO_ERR_UNSUPPORTED);
+ * batches do not offer it. */
+cryo_status cryo_plan_set_turn_on(cryo_plan *plan, int32_t on);
+
 /* After the stream has finished a cryo_forward that used `ws`: returns
  * CRYO_ERR_NONFINITE if that call produced a non-finite temperature, else
  * CRYO_OK.  Synchronises `stream`. */

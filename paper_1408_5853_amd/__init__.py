@@ -63,6 +63,8 @@ class Plan:
                                      C.byref(h)))
         self._h = h
         self.nr, self.nz = int(cell["nr"]), int(cell["nz"])
+        if cell.get("turn_on"):
+            self.set_turn_on(True)
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
@@ -89,6 +91,11 @@ class Plan:
     def set_shape(self, rows_per_lane, waves_per_line, lines_per_wave):
         check(lib().cryo_plan_set_shape(self._h, int(rows_per_lane), int(waves_per_line),
                                         int(lines_per_wave)))
+
+    def set_turn_on(self, on=True):
+        """Switch the transient turn-on model of eq. (22) on or off: each
+        pulse's first step then runs as 100 sub-steps of dt/100."""
+        check(lib().cryo_plan_set_turn_on(self._h, int(bool(on))))
 
     def radii(self):
         r = np.zeros(self.nr)

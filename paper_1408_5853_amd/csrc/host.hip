@@ -25,11 +25,11 @@ static double snap(double x) {
     return fabs(x - n) <= 1e-9 * fmax(1.0, fabs(x)) ? n : x;
 }
 
-// Average of the rectangular gate of eq. (4) over step k, all times in step
-// units: pulses occupy [b0 + n P, b0 + n P + W), n >= 0.
-double source_fraction(const Pulse &p, int64_t k) {
+// Time the rectangular gate of eq. (4) is open within [lo, hi), all times in
+// step units: pulses occupy [b0 + n P, b0 + n P + W), n >= 0.
+static double gate_open(const Pulse &p, double lo, double hi) {
     if (!(p.W > 0)) return 0.0;
-    double lo = (double)k, hi = lo + 1.0, s = 0.0;
+    double s = 0.0;
     int64_t n = (int64_t)floor((lo - p.b0 - p.W) / p.P);
     if (n < 0) n = 0;
     for (;; ++n) {
@@ -40,6 +40,28 @@ double source_fraction(const Pulse &p, int64_t k) {
         if (o > 0) s += o;
     }
     return s;
+}
+
+// the gate's average over step k
+double source_fraction(const Pulse &p, int64_t k) {
+    return gate_open(p, (double)k, (double)k + 1.0);
+}
+
+// Turn-on model, eq. (22): pulse n starts at step b0 + n P, which needs b0
+// and P whole.  Sub-step i (of 100) of a pulse-start step k spans
+// [k + i/100, k + (i+1)/100) and starts i tau* after the pulse, where
+// p^2 = 1 - exp(-i tau* / (7 tau*)).
+bool pulse_starts_on_steps(const Pulse &p) {
+    return p.b0 == floor(p.b0) && p.P == floor(p.P) && p.P >= 1.0;
+}
+bool pulse_start(const Pulse &p, int64_t k) {
+    if (!(p.W > 0) || !pulse_starts_on_steps(p)) return false;
+    const int64_t kb = (int64_t)p.b0, kp = (int64_t)p.P;
+    return k >= kb && (k - kb) % kp == 0;
+}
+double turn_on_source(const Pulse &p, int64_t k, int i) {
+    const double lo = (double)k + (double)i / 100.0, hi = (double)k + (double)(i + 1) / 100.0;
+    return gate_open(p, lo, hi) / (hi - lo) * (1.0 - exp(-(double)i / 7.0));
 }
 
 // FP64 power tables (see POW_*): one block per law id, then the cube path's
@@ -401,6 +423,7 @@ cryo_status cryo_plan_create(const cryo_problem *prob, cryo_dtype dtype, cryo_pl
 
 void cryo_plan_destroy(cryo_plan *p) {
     if (!p) return;
+    cryo_plan_destroy(p->sub);
     if (p->d_rows) (void)hipFree(p->d_rows);
     if (p->d_info) (void)hipFree(p->d_info);
     if (p->d_pow) (void)hipFree(p->d_pow);
@@ -440,6 +463,32 @@ cryo_status cryo_plan_set_shape(cryo_plan *p, int32_t rows_per_lane, int32_t wav
         }
         build_row_tables(p);
     }
+    if (p->sub) return cryo_plan_set_shape(p->sub, rows_per_lane, waves_per_line, lines_per_wave);
+    return CRYO_OK;
+}
+
+cryo_status cryo_plan_set_turn_on(cryo_plan *p, int32_t on) {
+    if (!p) return fail(CRYO_ERR_ARG, "null plan");
+    if (!on) {
+        cryo_plan_destroy(p->sub);
+        p->sub = nullptr;
+        return CRYO_OK;
+    }
+    if (p->sub) return CRYO_OK;
+    if (p->pulse.W > 0 && !pulse_starts_on_steps(p->pulse))
+        return fail(CRYO_ERR_UNSUPPORTED, "the turn-on model needs t_on and period to be "
+                                          "whole multiples of dt");
+    cryo_problem q = p->prob;
+    q.dt = p->prob.dt / 100.0;
+    cryo_plan *s = nullptr;
+    cryo_status st = cryo_plan_create(&q, p->dtype, &s);
+    if (st != CRYO_OK) return st;
+    st = cryo_plan_set_shape(s, p->rpl, p->wpl, p->lpw);
+    if (st != CRYO_OK) {
+        cryo_plan_destroy(s);
+        return st;
+    }
+    p->sub = s;
     return CRYO_OK;
 }
 
@@ -482,6 +531,7 @@ cryo_status cryo_forward(const cryo_plan *p, void *T, int64_t k0, int64_t nsteps
         return fail(CRYO_ERR_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes");
     if (((uintptr_t)ws & 255) != 0) return fail(CRYO_ERR_WORKSPACE, "workspace must be 256-aligned");
     cryo_status st0 = ensure_device(const_cast<cryo_plan *>(p));
+    if (st0 == CRYO_OK && p->sub) st0 = ensure_device(p->sub);
     if (st0 != CRYO_OK) return st0;
     hipStream_t s = (hipStream_t)stream;
     char *w = (char *)ws;
@@ -493,10 +543,22 @@ cryo_status cryo_forward(const cryo_plan *p, void *T, int64_t k0, int64_t nsteps
     if (st != CRYO_OK) return st;
     int G = step_grid(p);
     int64_t done_surf = 0;
+    int cur = 0;
     for (int64_t n = 0; n < nsteps; ++n) {
-        double X = p->pulse.amplitude * source_fraction(p->pulse, k0 + n);
         double *pp = surf ? part + (size_t)(n % SURF_CHUNK) * G : nullptr;
-        st = launch_step(p, buf[n & 1], buf[(n + 1) & 1], X, pp, flag, s);
+        if (p->sub && pulse_start(p->pulse, k0 + n)) {
+            // eq. (22): the pulse's first step as 100 sub-steps of dt / 100
+            // (same layout and launch shape; the last one reports the surface)
+            for (int i = 0; i < 100 && st == CRYO_OK; ++i) {
+                double X = p->pulse.amplitude * turn_on_source(p->pulse, k0 + n, i);
+                st = launch_step(p->sub, buf[cur], buf[cur ^ 1], X, i == 99 ? pp : nullptr, flag, s);
+                cur ^= 1;
+            }
+        } else {
+            double X = p->pulse.amplitude * source_fraction(p->pulse, k0 + n);
+            st = launch_step(p, buf[cur], buf[cur ^ 1], X, pp, flag, s);
+            cur ^= 1;
+        }
         if (st != CRYO_OK) return st;
         if (surf && ((n + 1) % SURF_CHUNK == 0 || n + 1 == nsteps)) {
             int cnt = (int)(n + 1 - done_surf);
@@ -505,7 +567,7 @@ cryo_status cryo_forward(const cryo_plan *p, void *T, int64_t k0, int64_t nsteps
             done_surf = n + 1;
         }
     }
-    return launch_from_internal(p, buf[nsteps & 1], T, flag, s);
+    return launch_from_internal(p, buf[cur], T, flag, s);
 }
 
 cryo_status cryo_poll(const cryo_plan *p, const void *ws, void *stream) {

@@ -155,12 +155,18 @@ struct cryo_plan {
     uint32_t *d_info = nullptr;       // [2][np]: info, finfo
     double *d_pow = nullptr;          // pow_blob, then fpow_blob
     int device = 0;
+    // transient turn-on model (eq. (22)): the same cell at dt / 100, whose
+    // tables step the sub-steps of each pulse-start step (null when off)
+    cryo_plan *sub = nullptr;
 };
 
 namespace cryo {
 void set_error(const std::string &msg);
 cryo_status fail(cryo_status st, const std::string &msg);
 double source_fraction(const Pulse &p, int64_t k);
+bool pulse_starts_on_steps(const Pulse &p);
+bool pulse_start(const Pulse &p, int64_t k);
+double turn_on_source(const Pulse &p, int64_t k, int i);
 
 // launchers (forward.hip)
 cryo_status launch_to_internal(const cryo_plan *p, const void *T, void *Ti, int *flag,

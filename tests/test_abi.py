@@ -94,3 +94,29 @@ def test_workspace_grows_with_grid():
     a = P.Plan(cellgen.small_cell(0)).workspace_bytes(100)
     b = P.Plan(cellgen.device_cell(0, nz=64)).workspace_bytes(100)
     assert 0 < a < b
+
+
+def test_turn_on_model_host_checks():
+    # eq. (22) needs pulse starts on step boundaries; host-only checks
+    c = cellgen.with_nz(cellgen.small_cell(0), 4)
+    dt = c["dt"]
+    P.Plan(dict(c, turn_on=True))                                   # t_on = 0
+    P.Plan(dict(c, turn_on=True, width=0.0, t_on=2.5 * dt))        # no pulse: nothing to expand
+    for bad in (dict(t_on=2.5 * dt), dict(period=1000.5 * dt)):
+        with pytest.raises(P.CryoError) as e:
+            P.Plan(dict(c, turn_on=True, **bad))
+        assert e.value.status == 6
+    plan = P.Plan(dict(c, turn_on=True))
+    plan.set_shape(4, 2, 1)                 # the sub-step tables follow
+    plan.set_turn_on(False)
+    plan.set_turn_on(True)
+    # the adjoint of the sub-steps is not built: refused before any device use
+    L = P.lib()
+    tgt = np.zeros(4)
+    J, g = ctypes.c_double(), np.zeros(2 + 2 * len(c["layers"]))
+    dp = ctypes.POINTER(ctypes.c_double)
+    st = L.cryo_gradient(plan._h, ctypes.c_void_p(256), 4, tgt.ctypes.data_as(dp), 0,
+                         ctypes.c_void_p(256), 1 << 40, ctypes.byref(J), g.ctypes.data_as(dp),
+                         None, None)
+    assert st == 6
+    assert "turn-on" in P.lib().cryo_last_error().decode()
