@@ -1,0 +1,53 @@
+"""Stored expected values (tests/golden/oracle_runs.json, written by
+tests/golden/make_golden.py from the CPU oracle only).
+
+On the CPU the oracle must reproduce them bit for bit, on any thread count
+(a change to its arithmetic shows up here and needs a reason).  On the GPU the
+library must match them to the FP64 parity bound, 1e-10 relative.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.join(HERE, "golden"))
+
+import make_golden  # noqa: E402
+import oracle  # noqa: E402
+
+with open(os.path.join(HERE, "golden", "oracle_runs.json")) as f:
+    GOLDEN = json.load(f)
+CASES = {name: (cell, n) for name, _, cell, n in make_golden.cases()}
+
+
+def test_golden_covers_every_case():
+    assert sorted(GOLDEN) == sorted(CASES)
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_oracle_reproduces_golden(name):
+    cell, n = CASES[name]
+    rec = GOLDEN[name]
+    assert rec["steps"] == n
+    T, S = oracle.forward(cell, nsteps=n, surf=True)       # all host threads
+    for k, v in rec["surface"].items():
+        assert S[int(k) - 1] == float(v)
+    for j, i, v in rec["field"]:
+        assert T[j, i] == float(v)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_gpu_matches_golden(name):
+    from gpu_util import run_gpu, say
+    cell, n = CASES[name]
+    rec = GOLDEN[name]
+    say("case golden %s, %d steps" % (name, n))
+    T, S = run_gpu(cell, n)
+    for k, v in rec["surface"].items():
+        assert abs(S[int(k) - 1] - float(v)) <= 1e-10 * abs(float(v))
+    for j, i, v in rec["field"]:
+        assert abs(T[j, i] - float(v)) <= 1e-10 * abs(float(v))
