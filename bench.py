@@ -284,7 +284,9 @@ def main():
     if not args.no_extra:
         log("bench: FP32 pair rate")
         s32, _ = rate(P.Plan, cell, "f32", 20_000, 500, stream)
-        out["extra"] = {"f32_pair_gcell_steps_s": round(cells * 20_000 / s32 / 1e9, 3)}
+        r32 = cells * 20_000 / s32 / 1e9
+        out["extra"] = {"f32_pair_gcell_steps_s": round(r32, 3),
+                        "f32_pair_hbm_frac": round(r32 * BYTES_PER_CELL_STEP / HBM_PEAK_GBS, 4)}
         log("bench: batched sweep")
         out["extra"]["batch"] = batch_extra(P, 2000, stream)
         log("bench: gradient")
