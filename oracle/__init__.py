@@ -43,6 +43,8 @@ class _OCell(C.Structure):
         ("period", C.c_double), ("t_on", C.c_double),
         ("bc_kind", C.c_int * 4), ("bc_value", C.c_double * 4),
         ("dt", C.c_double), ("turn_on", C.c_int),
+        ("poly_a", C.POINTER(C.c_double)), ("poly_b", C.POINTER(C.c_double)),
+        ("joule_tref", C.c_double),
     ]
 
 
@@ -104,6 +106,14 @@ class _Cell:
             s.bc_value[q] = float(cell["bc"][q][1])
         s.dt = cell["dt"]
         s.turn_on = int(bool(cell.get("turn_on", False)))
+        if cell.get("poly"):
+            # eqs. (23), (24): per layer poly_a (4 values) and poly_b (5)
+            self.pa = np.ascontiguousarray([float(x) for l in Ls for x in l["poly_a"]])
+            self.pb = np.ascontiguousarray([float(x) for l in Ls for x in l["poly_b"]])
+            assert self.pa.size == 4 * len(Ls) and self.pb.size == 5 * len(Ls)
+            s.poly_a = self.pa.ctypes.data_as(dp)
+            s.poly_b = self.pb.ctypes.data_as(dp)
+        s.joule_tref = float(cell.get("joule_tref", 0.0))
         self.s = s
 
     def ref(self):

@@ -30,6 +30,10 @@
  *    tau* = tau / 100, sub-step i with the gate averaged over the sub-step
  *    times p^2 at its start, 1 - exp(-i / 7).  All other steps are unchanged
  *    (p^2 = 1), and the surface mean is reported once per step.
+ *  - Polynomial laws (eqs. (23), (24)), when given, replace the power laws
+ *    term for term (lambda still times the layer's conductivity scale); the
+ *    Joule source (eqs. (2), (25)), when enabled, multiplies the heater's
+ *    source by sqrt(joule_tref / T) at the node's old temperature.
  */
 #include "oracle.h"
 
@@ -114,9 +118,23 @@ static int geom_build(const ocell *c, geom *g)
     return 0;
 }
 
-/* material laws of the workloads: lambda_m(T), c_m(T) and their T-derivatives */
+/* sum_{k<n} coef[k] T^k, term by term */
+static double poly(const double *coef, int n, double T)
+{
+    double s = 0.0, Tk = 1.0;
+    for (int k = 0; k < n; k++) {
+        s += coef[k] * Tk;
+        Tk *= T;
+    }
+    return s;
+}
+
+/* material laws: the workloads' power laws, or the polynomial fits of
+ * eqs. (23) (c, cubic) and (24) (lambda, quartic) when given; and the
+ * T-derivatives of the power laws (the adjoint takes power laws only) */
 static double lam(const ocell *c, int m, double T)
 {
+    if (c->poly_b) return c->kscale[m] * poly(c->poly_b + 5 * m, 5, T);
     return c->kscale[m] * c->k0[m] * pow(T / c->tref[m], c->p[m]);
 }
 static double dlam(const ocell *c, int m, double T)
@@ -125,6 +143,7 @@ static double dlam(const ocell *c, int m, double T)
 }
 static double cap(const ocell *c, int m, double T)
 {
+    if (c->poly_a) return poly(c->poly_a + 4 * m, 4, T);
     return c->c0[m] * pow(T / c->tref[m], c->q[m]);
 }
 static double dcap(const ocell *c, int m, double T)
@@ -236,6 +255,9 @@ static void line_rows(const ocell *c, const geom *g, const double *T, double tau
             double ls = lam(c, m, 0.5 * (Tj[i] + Ts[i]));       /* lambda_{i,j-1/2} */
             double Lz = (ln * (Tn[i] - Tj[i]) / eta - ls * (Tj[i] - Ts[i]) / eta) / eta;
             double X = (m == c->heater) ? c->amplitude * s : 0.0;
+            /* Joule heating, eqs. (2), (25): resistivity proportional to
+             * T^(-1/2), taken at the old level like every coefficient */
+            if (c->joule_tref > 0) X *= sqrt(c->joule_tref / Tj[i]);
             F[i] = rc * Tj[i] + Lz + X;
         } else {
             int a = g->mat[i], b = a + 1;
@@ -538,7 +560,9 @@ int oc_gradient(const ocell *c, const double *T0, long N, const double *target,
                 int nthreads)
 {
     geom g;
-    if (check_cell(c) || N < 1 || c->turn_on || geom_build(c, &g)) return 1;
+    if (check_cell(c) || N < 1 || c->turn_on || c->poly_a || c->poly_b || c->joule_tref > 0 ||
+        geom_build(c, &g))
+        return 1;
     int nr = c->nr, nz = c->nz, L = c->n_layers, ng = 2 + 2 * L;
     size_t n = (size_t)nr * nz;
     long K = ckpt > 0 ? ckpt : N;

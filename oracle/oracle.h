@@ -33,6 +33,9 @@ typedef struct {
     double bc_value[4];
     double dt;
     int turn_on;              /* eq. (22) turn-on model: 0 off, 1 on */
+    const double *poly_a;     /* NULL, or [n_layers][4]: c_m(T) = sum a_k T^k, eq. (23) */
+    const double *poly_b;     /* NULL, or [n_layers][5]: lambda_m(T) = kscale sum b_k T^k, eq. (24) */
+    double joule_tref;        /* > 0: heater source times sqrt(joule_tref / T), eq. (25) */
 } ocell;
 
 /* node radii r_0..r_{nr-1}, eq. (9) */
@@ -61,7 +64,7 @@ int oc_line_paper_sweep(const ocell *c, const double *T, long k, int j,
  * fall on step boundaries, else the call fails */
 int oc_forward(const ocell *c, double *T, long k0, long nsteps, double *surf,
                int nthreads);
-/* (fails when turn_on is set)
+/* (fails when turn_on, polynomial laws or the Joule source are set)
  * J = sum_{n=1..N} (S_n - target_n)^2 and its gradient
  * grad = [dJ/dQ, dJ/dwidth, dJ/dthick[L], dJ/dkscale[L]] by the discrete
  * adjoint.  ckpt = 0 stores every state, else every ckpt-th with recompute.

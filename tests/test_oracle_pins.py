@@ -12,6 +12,7 @@ from fractions import Fraction
 import numpy as np
 import pytest
 import scipy.integrate as si
+import scipy.optimize as sp_opt
 import scipy.special as sp
 
 import cellgen
@@ -528,3 +529,144 @@ def test_turn_on_removes_start_jump_fig3():
         assert np.all(np.diff(on) >= 0)
         assert abs(on[-1] - ref) < abs(off[-1] - ref)
         assert abs(on[-1] - ref) < 0.03 * ref
+
+
+# --------------------------------------------------------------------------
+# Polynomial laws (eqs. (23), (24)) and the Joule source (eqs. (2), (25))
+# --------------------------------------------------------------------------
+
+def poly_layer(thickness, intervals, a, b, rho=5e3):
+    l = layer(thickness, intervals, rho=rho)
+    l.update(poly_a=[float(x) for x in a], poly_b=[float(x) for x in b])
+    return l
+
+
+def poly_cell(Ls, **kw):
+    c = cell(Ls, **kw)
+    c["poly"] = True
+    return c
+
+
+def test_polynomial_laws_reduce_to_power_laws():
+    # integer exponents: lambda = k0 (T/tref)^p and c = c0 (T/tref)^3 are
+    # polynomials; both law paths must give the same run to rounding
+    ps, k0s, c0s = [0, 1, 2], [3.0, 40.0, 0.7], [50.0, 120.0, 30.0]
+    Ls = [layer(t, n, k0=k, p=float(p), c0=c0, q=3.0, rho=4e3)
+          for t, n, k, p, c0 in zip([4e-4, 3e-4, 5e-4], [12, 10, 14], k0s, ps, c0s)]
+    c = cell(Ls, nz=7, height=4e-3, dt=2e-7, heater=1, amplitude=2e9, width=2e-6,
+             period=1e-5, bc=[[1, 28.0], [0, 0.0], [0, 0.0], [1, 30.0]])
+    T0 = _random_field(c, 4, 28.0, 33.0)
+    Tp = oracle.forward(c, T0, nsteps=150)
+    Pl = []
+    for l, k, p, c0 in zip(Ls, k0s, ps, c0s):
+        b = [0.0] * 5
+        b[p] = k / 30.0 ** p
+        Pl.append(poly_layer(l["thickness"], l["intervals"], [0, 0, 0, c0 / 30.0 ** 3], b,
+                             rho=l["rho"]))
+    cp = dict(c, layers=Pl, poly=True)
+    Tq = oracle.forward(cp, T0, nsteps=150)
+    assert np.max(np.abs(Tq - Tp) / Tp) < 1e-12
+    assert np.max(np.abs(Tp - T0)) > 0.1
+
+
+def _poly_U(b, T):
+    # Kirchhoff transform of a polynomial conductivity: int_0^T lambda
+    return sum(bk * T ** (k + 1) / (k + 1) for k, bk in enumerate(b))
+
+
+def _poly_Uinv(b, U):
+    return sp_opt.brentq(lambda T: _poly_U(b, T) - U, 1e-3, 1e4, xtol=1e-14, rtol=1e-15)
+
+
+def test_polynomial_layered_steady_state():
+    # the layered logarithmic steady state of a held-wall cell with the heater
+    # on all the time, for quartic conductivities (Kirchhoff transform of each
+    # layer's polynomial, inverted numerically): first-order convergence
+    th = [0.4e-3, 0.3e-3, 0.2e-3, 0.5e-3]
+    bs = [[4.0, 0.03, 2e-4, 1e-6, 3e-9], [0.3, 0.01, 1e-4, 0.0, 1e-9],
+          [1.5, 0.0, 5e-4, 2e-6, 0.0], [0.6, 0.02, 0.0, 1e-6, 2e-9]]
+    a = [20.0, 1.0, 0.05, 1e-3]
+    errs = []
+    for base in (16, 32, 64):
+        Ls = [poly_layer(t, base * w, a, b) for t, w, b in zip(th, (2, 2, 1, 2), bs)]
+        c = poly_cell(Ls, r_inner=1.2e-3, heater=2, amplitude=2e8, width=1.0,
+                      period=1.0, dt=5.0, height=1.0,
+                      bc=[[1, 28.0], [0, 0.0], [0, 0.0], [0, 0.0]])
+        T = oracle.forward(c, nsteps=800)
+        T2 = oracle.forward(c, T, k0=800, nsteps=1)
+        assert np.max(np.abs(T2 - T)) < 1e-9
+        r = oracle.radii(c)
+        R = [c["r_inner"]]
+        for l in Ls:
+            R.append(R[-1] + l["thickness"])
+        h0, h1, Q = R[2], R[3], c["amplitude"]
+
+        def G(x0, x1):
+            tot = 0.0
+            lo, hi = x0, min(x1, h0)
+            if hi > lo:
+                tot += Q * (h1 ** 2 - h0 ** 2) / 2 * math.log(hi / lo)
+            lo, hi = max(x0, h0), min(x1, h1)
+            if hi > lo:
+                tot += Q / 2 * (h1 ** 2 * math.log(hi / lo) - (hi ** 2 - lo ** 2) / 2)
+            return tot
+
+        Tb = [28.0]
+        for m in range(4):
+            Tb.append(_poly_Uinv(bs[m], _poly_U(bs[m], Tb[-1]) + G(R[m], R[m + 1])))
+        ex = np.array([_poly_Uinv(bs[m], _poly_U(bs[m], Tb[m]) + G(R[m], x))
+                       for x in r for m in [min(np.searchsorted(R, x, side="right") - 1, 3)]])
+        errs.append(np.max(np.abs(T[1] - ex)) / (ex.max() - 28.0))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert errs[-1] < 2e-2, errs
+    assert min(orders) > 0.9, (errs, orders)
+
+
+def test_polynomial_heat_balance_with_joule_source():
+    # insulated single layer, polynomial capacity, Joule source: per step the
+    # capacity-weighted content (c at the old level) grows by exactly
+    # dt A s sum w sqrt(T_J / T_old)
+    Ls = [poly_layer(1e-3, 36, [15.0, 0.8, 0.03, 2e-4], [2.0, 0.05, 1e-3, 0.0, 1e-8], rho=3e3)]
+    c = poly_cell(Ls, nz=10, height=5e-3, dt=2e-7, amplitude=3e8, width=4e-6,
+                  period=1e-5, heater=0)
+    c["joule_tref"] = 30.0
+    T = _random_field(c, 7, 28.0, 36.0)
+    T[0], T[-1] = T[1], T[-2]
+    r = oracle.radii(c)
+    h = np.diff(r)
+    w = r[1:-1] * 0.5 * (h[:-1] + h[1:]) * (c["height"] / (c["nz"] - 1))
+    a = Ls[0]["poly_a"]
+    for k in range(0, 40, 9):
+        Tn = oracle.forward(c, T, k0=k, nsteps=1)
+        Ti = T[1:-1, 1:-1]
+        cap = a[0] + a[1] * Ti + a[2] * Ti ** 2 + a[3] * Ti ** 3
+        lhs = np.sum(w * Ls[0]["rho"] * cap * (Tn[1:-1, 1:-1] - Ti))
+        s = oracle.source_fraction(c, k)
+        rhs = c["dt"] * c["amplitude"] * s * np.sum(w * np.sqrt(30.0 / Ti))
+        if s > 0:
+            assert abs(lhs - rhs) <= 1e-11 * abs(rhs)
+        else:
+            assert abs(lhs) <= 1e-11 * np.sum(w * Ls[0]["rho"] * cap * np.abs(Tn[1:-1, 1:-1] - Ti)) + 1e-30
+        T = Tn
+
+
+def test_joule_uniform_field_converges_to_closed_form():
+    # a uniform, insulated, all-heater cell with constant c: the field stays
+    # uniform and follows dT/dt = A sqrt(T_J / T) / (rho c), whose solution is
+    # T^(3/2) = T0^(3/2) + (3/2) A sqrt(T_J) t / (rho c); the lagged source
+    # makes the scheme first order in dt
+    t_end, A, TJ, rho, c0, T0 = 2e-3, 4e7, 30.0, 2e3, 5.0, 28.0
+    exact = (T0 ** 1.5 + 1.5 * A * math.sqrt(TJ) * t_end / (rho * c0)) ** (2.0 / 3.0)
+    errs = []
+    for n in (50, 100, 200):
+        Ls = [poly_layer(1e-3, 12, [c0, 0, 0, 0], [1.0, 0.01, 0, 0, 0], rho=rho)]
+        c = poly_cell(Ls, nz=5, height=2e-3, dt=t_end / n, amplitude=A, width=1.0,
+                      period=1.0, heater=0, T_init=T0)
+        c["joule_tref"] = TJ
+        T = oracle.forward(c, nsteps=n)
+        assert np.ptp(T) <= 1e-12 * T.max()
+        errs.append(abs(T[2, 5] - exact))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert exact - T0 > 5.0
+    assert errs[-1] < 5e-3 * (exact - T0), errs
+    assert min(orders) > 0.9, (errs, orders)
