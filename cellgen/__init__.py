@@ -239,3 +239,24 @@ def tiny(seed=0, nr=12, nz=6, n_layers=3, nsteps=20, z_active=True,
                 width=float(rng.uniform(0.3, 0.7) * nsteps * dt),
                 period=float(nsteps * dt * 0.9), t_on=float(2.5 * dt),
                 bc=_bc(z_active), dt=dt, T_init=T0, nsteps=nsteps)
+
+
+def poly_variant(cell, seed=0, joule_tref=0.0):
+    """Copy of `cell` with polynomial laws (the form of the paper's fits,
+    Sec. 5: cubic capacity, quartic conductivity) drawn around each layer's
+    power laws: c(T) = sum_k a_k T^k and lambda(T) = sum_k b_k T^k with
+    positive coefficients whose terms share the power law's value at tref,
+    lambda scaled by 0.8 so that it stays below the power law (and within
+    the explicit-z bound the power law was drawn for) near T0.  joule_tref
+    > 0 switches on the T^(-1/2) Joule source."""
+    rng = np.random.default_rng([11, seed])
+    c = copy.deepcopy(cell)
+    for l in c["layers"]:
+        wa = rng.dirichlet(np.ones(4)) * np.array([0.05, 0.1, 0.25, 1.0])
+        wa /= wa.sum()
+        wb = rng.dirichlet(np.ones(5))
+        l["poly_a"] = [float(l["c0"] * wa[k] / l["tref"] ** k) for k in range(4)]
+        l["poly_b"] = [float(0.8 * l["k0"] * wb[k] / l["tref"] ** k) for k in range(5)]
+    c["poly"] = True
+    c["joule_tref"] = float(joule_tref)
+    return c

@@ -183,6 +183,23 @@ cryo_status cryo_forward(const cryo_plan *plan, void *T, int64_t k0,
                          int64_t nsteps, void *ws, size_t ws_bytes,
                          double *surf, void *stream);
 
+/* Polynomial material laws of eqs. (23) and (24) in place of the power laws,
+ * and optionally the Joule source of eqs. (2) and (25).  FP64 plans only
+ * (CRYO_ERR_UNSUPPORTED otherwise); must precede the plan's first device
+ * call.  `a` holds 4 coefficients per layer (inner to outer):
+ * c_m(T) = sum_{k=0..3} a[4m+k] T^k [J/(kg K)]; `b` holds 5 per layer:
+ * lambda_m(T) = k_scale_m sum_{k=0..4} b[5m+k] T^k [W/(m K)]; rho and
+ * k_scale come from the layers' cryo_material, whose power-law fields are
+ * then unused.  joule_tref > 0 makes the heater's source
+ * amplitude * (gate average) * sqrt(joule_tref / T) at each node's old
+ * temperature (a resistivity proportional to T^(-1/2), eq. (25)); 0 keeps it
+ * temperature-independent.  Both laws must be positive, and dt within
+ * eq. (21)'s bound, at the coldest prescribed temperature (checked there
+ * only: CRYO_ERR_ARG, CRYO_ERR_UNSTABLE).  Arrays are copied.  Gradients
+ * refuse such a plan (CRYO_ERR_UNSUPPORTED); batches do not offer it. */
+cryo_status cryo_plan_set_poly_laws(cryo_plan *plan, const double *a, const double *b,
+                                    double joule_tref);
+
 /* Transient turn-on model of the source, Sec. 3.2, eq. (22), read with a
  * decaying exponential (p^2 = 1 - exp(-(t - t_n) / (7 tau*)), tau* = dt/100,
  * rising from 0 towards 1).  With on != 0, every step k of cryo_forward whose

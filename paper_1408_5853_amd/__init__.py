@@ -63,6 +63,10 @@ class Plan:
                                      C.byref(h)))
         self._h = h
         self.nr, self.nz = int(cell["nr"]), int(cell["nz"])
+        if cell.get("poly"):
+            Ls = cell["layers"]
+            self.set_poly_laws([l["poly_a"] for l in Ls], [l["poly_b"] for l in Ls],
+                               cell.get("joule_tref", 0.0))
         if cell.get("turn_on"):
             self.set_turn_on(True)
 
@@ -96,6 +100,19 @@ class Plan:
         """Switch the transient turn-on model of eq. (22) on or off: each
         pulse's first step then runs as 100 sub-steps of dt/100."""
         check(lib().cryo_plan_set_turn_on(self._h, int(bool(on))))
+
+    def set_poly_laws(self, a, b, joule_tref=0.0):
+        """Polynomial laws of eqs. (23), (24): a[m] = 4 capacity coefficients,
+        b[m] = 5 conductivity coefficients per layer (ascending powers of T);
+        joule_tref > 0 adds the T^(-1/2) Joule source of eq. (25)."""
+        aa = np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(-1))
+        bb = np.ascontiguousarray(np.asarray(b, dtype=np.float64).reshape(-1))
+        L = len(self.cell["layers"])
+        if aa.size != 4 * L or bb.size != 5 * L:
+            raise ValueError("need 4 capacity and 5 conductivity coefficients per layer")
+        dp = C.POINTER(C.c_double)
+        check(lib().cryo_plan_set_poly_laws(self._h, aa.ctypes.data_as(dp), bb.ctypes.data_as(dp),
+                                            float(joule_tref)))
 
     def radii(self):
         r = np.zeros(self.nr)

@@ -89,6 +89,23 @@ struct LawLds<double> {
     }
 };
 
+// Polynomial laws (eqs. (23), (24)): sum_k c_k x^k, k <= 4, by Horner's
+// rule, from POLY_BLK doubles per law id staged in LDS in place of the power
+// tables (c_0 .. c_4, one pad).  Interface rows need a quotient of two laws,
+// which callers form.
+struct LawPoly {
+    const double *c;
+    static __device__ inline bool in_range(double x) { return LawLds<double>::in_range(x); }
+    __device__ inline double lawc(int id, double x) const {
+        const double2 k01 = *(const double2 *)(c + POLY_BLK * id);
+        const double2 k23 = *(const double2 *)(c + POLY_BLK * id + 2);
+        const double k4 = c[POLY_BLK * id + 4];
+        return fma(fma(fma(fma(k4, x, k23.y), x, k23.x), x, k01.y), x, k01.x);
+    }
+    // the law at the mean of two values given their sum
+    __device__ inline double lawm(int id, double s) const { return lawc(id, 0.5 * s); }
+};
+
 // FP32: 2^(e log2 s + lk); the stepping kernel's tables hold lk = log2 K - e,
 // so that s is the sum of the two values whose mean the law is taken at
 template <>
@@ -124,6 +141,7 @@ struct StepArgs {
     int surf_lane, surf_reg;
     int groups;               // workgroups of one step of this instance
     Pulse pulse;              // batch: schedule evaluated on the device
+    int joule;                // heater source times X / sqrt(T) (eq. (25)), X holding sqrt(T_J)
 };
 
 constexpr int STEP_WAVES = STEP_WAVES_HOST;

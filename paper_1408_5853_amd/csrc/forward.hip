@@ -36,7 +36,15 @@ namespace cryo {
 // so a capacity row evaluates two conductivities per line (east r-face, the
 // face towards the next line) instead of three.
 // CUBE: every capacity law has exponent 3 (c(T) by multiplication).
-template <typename R, int RPL, int G, bool CUBE>
+// POLY (FP64 only): polynomial laws (eqs. (23), (24)), interface rows as the
+// quotient of two laws, and the optional Joule source (eq. (25)).
+template <typename R, bool POLY>
+__device__ inline auto law_of(const LawLds<R> &t) {
+    if constexpr (POLY) return LawPoly{t.blk};
+    else return t;
+}
+
+template <typename R, int RPL, int G, bool CUBE, bool POLY = false>
 __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *__restrict__ Tin,
                                  R *__restrict__ Tout, const R X, double *partial) {
     constexpr bool PAIR = Pair<R>::on;
@@ -55,7 +63,7 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
         sge[i] = a.ge[i];
         sinf[i] = a.info[i];
     }
-    const LawLds<R> law = stage_laws<R>(a, smem);       // ends with a barrier
+    const auto law = law_of<R, POLY>(stage_laws<R>(a, smem));   // ends with a barrier
     const int t = threadIdx.x;
     // the wave index is uniform: line indices and bases live in scalar registers
     const int lane = t & (WAVE - 1), wv = __builtin_amdgcn_readfirstlane(t / WAVE);
@@ -253,7 +261,8 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
             // law: capacity rows are scaled by eta^2), the ratio of the inner
             // to the outer layer's law at an interface node (its row divided
             // by the outer law), or unit / zero (boundary, padding)
-            const R lam2 = law.lawm(l2, T + (cap ? Tnr : T));
+            R lam2 = law.lawm(l2, T + (cap ? Tnr : T));
+            if constexpr (POLY) lam2 = lam2 / law.lawm((inf_r >> 18) & 63, T + T);
             R rc;
             if constexpr (CUBE) rc = law.cube(lc, T);
             else rc = law.lawm(lc, T + T);
@@ -263,7 +272,10 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
             const R Fo = lam2 * dif<R>(Tnr, Lnr, T, Tl);
             R dd = fw * dif<R>(Tw, Lw, T, Tl) + fe * dif<R>(Te, Le, T, Tl);
             dd += cap ? Fo + Fc : (R)0;
-            dd += (R)((inf_r >> 3) & 1) * X;                // heater capacity rows
+            if constexpr (POLY)                                 // heater rows, eq. (25)
+                dd += (R)((inf_r >> 3) & 1) * (a.joule ? X * rsqrt(T) : X);
+            else
+                dd += (R)((inf_r >> 3) & 1) * X;                // heater capacity rows
             // held walls: rows 0 and nr - 1 are unit rows with dT = value - T
             if (r == 0 && a.held[0]) dd = lg == 0 ? dif<R>(a.val[0], (R)0, T, Tl) : dd;
             if (r == a.surf_reg && a.held[1])
@@ -389,10 +401,10 @@ __device__ inline int xcd_block(int b, int nb) {
     return x * per + min(x, rem) + i;
 }
 
-template <typename R, int RPL, int G, bool CUBE>
+template <typename R, int RPL, int G, bool CUBE, bool POLY = false>
 __global__ __launch_bounds__(STEP_WAVES *WAVE) void k_step(StepArgs<R> a) {
-    step_body<R, RPL, G, CUBE>(a, xcd_block(blockIdx.x, gridDim.x), a.Tin, a.Tout, a.X,
-                               a.partial);
+    step_body<R, RPL, G, CUBE, POLY>(a, xcd_block(blockIdx.x, gridDim.x), a.Tin, a.Tout, a.X,
+                                     a.partial);
 }
 
 // Pulse average over step k (eq. (4)), step units; the host's schedule.
@@ -554,7 +566,8 @@ static StepArgs<R> step_args(const cryo_plan *p, const void *Tin, void *Tout, do
     a.nz = p->nz;
     a.np = p->np;
     a.lpw = p->lpw;
-    a.X = (R)(X * xs);
+    a.joule = p->poly && p->joule_tref > 0;
+    a.X = (R)(X * xs * (a.joule ? sqrt(p->joule_tref) : 1.0));
     for (int s = 0; s < 4; ++s) {
         a.held[s] = p->prob.bc.kind[s] == CRYO_HELD;
         a.val[s] = (R)p->prob.bc.value[s];
@@ -581,6 +594,11 @@ static cryo_status step_t(const cryo_plan *p, const void *Tin, void *Tout, doubl
     switch (key) {
 #define STEP_CASE(RP, GW) \
     case RP * 10 + GW: \
+        if constexpr (sizeof(R) == 8) \
+            if (p->poly) { \
+                hipLaunchKernelGGL((k_step<R, RP, GW, false, true>), g, b, lds, s, a); \
+                break; \
+            } \
         if (a.laws.cube) hipLaunchKernelGGL((k_step<R, RP, GW, true>), g, b, lds, s, a); \
         else hipLaunchKernelGGL((k_step<R, RP, GW, false>), g, b, lds, s, a); \
         break;

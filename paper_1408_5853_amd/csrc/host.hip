@@ -233,7 +233,8 @@ static void build_row_tables(cryo_plan *p) {
     p->info.assign(np, info_pack(K_PAD, 0, 0, 0, ZERO, ZERO, ZERO, UNIT));
     p->fgw.assign(np, 0.0);
     p->fge.assign(np, 0.0);
-    p->finfo = p->info;
+    // polynomial laws divide slot 2 by slot 3 on every row: unit by default
+    p->finfo.assign(np, info_pack(K_PAD, 0, 0, 0, ZERO, ZERO, p->poly ? UNIT : ZERO, UNIT));
     const int *bk = prob->bc.kind;
     for (i = 0; i < nr; ++i) {
         int idx = (i % rpl) * (WAVE * p->wpl) + i / rpl;
@@ -284,9 +285,19 @@ static void build_row_tables(cryo_plan *p) {
             fge = law3 == (uint32_t)UNIT ? ge : 0.0;
             f2 = UNIT;
         }
+        // polynomial laws: an interface row's quotient is formed in the
+        // kernel from the inner (slot 2) and outer (slot 3) layer laws
+        uint32_t f3 = ZERO;
+        if (p->poly) {
+            f3 = UNIT;
+            if (kind == K_IFACE) {
+                f2 = p->lay[i];
+                f3 = p->lay[i + 1];
+            }
+        }
         p->fgw[idx] = fgw;
         p->fge[idx] = fge;
-        p->finfo[idx] = info_pack(kind, heat, held, side, lawE, f2, ZERO, lawC);
+        p->finfo[idx] = info_pack(kind, heat, held, side, lawE, f2, f3, lawC);
     }
     p->surf_lane = (nr - 1) / rpl;
     p->surf_reg = (nr - 1) % rpl;
@@ -467,6 +478,63 @@ cryo_status cryo_plan_set_shape(cryo_plan *p, int32_t rows_per_lane, int32_t wav
     return CRYO_OK;
 }
 
+// sum_k c_k T^k
+static double poly_at(const double *c, int n, double T) {
+    double s = 0.0;
+    for (int k = n - 1; k >= 0; --k) s = s * T + c[k];
+    return s;
+}
+
+cryo_status cryo_plan_set_poly_laws(cryo_plan *p, const double *a, const double *b,
+                                    double joule_tref) {
+    if (!p || !a || !b) return fail(CRYO_ERR_ARG, "null argument");
+    if (p->d_info) return fail(CRYO_ERR_ARG, "laws must be set before the plan's first run");
+    if (p->dtype != CRYO_F64) return fail(CRYO_ERR_UNSUPPORTED, "polynomial laws need an FP64 plan");
+    const int L = p->L;
+    for (int i = 0; i < 4 * L; ++i)
+        if (!std::isfinite(a[i])) return fail(CRYO_ERR_ARG, "capacity coefficient not finite");
+    for (int i = 0; i < 5 * L; ++i)
+        if (!std::isfinite(b[i])) return fail(CRYO_ERR_ARG, "conductivity coefficient not finite");
+    if (!(joule_tref >= 0) || !std::isfinite(joule_tref))
+        return fail(CRYO_ERR_ARG, "Joule reference temperature must be >= 0");
+    // positive laws and eq. (21)'s bound at the coldest prescribed temperature
+    const cryo_problem *pr = &p->prob;
+    double Tm = pr->T_init;
+    for (int s = 0; s < 4; ++s)
+        if (pr->bc.kind[s] == CRYO_HELD) Tm = std::min(Tm, pr->bc.value[s]);
+    double best = INFINITY;
+    for (int m = 0; m < L; ++m) {
+        const cryo_material &mt = p->layers[m].mat;
+        const double c = poly_at(a + 4 * m, 4, Tm), lam = mt.k_scale * poly_at(b + 5 * m, 5, Tm);
+        if (!(c > 0) || !(lam > 0))
+            return fail(CRYO_ERR_ARG, "polynomial law not positive at T = " + std::to_string(Tm));
+        best = std::min(best, mt.rho * c / lam);
+    }
+    const double bound = 0.5 * p->eta * p->eta * best;
+    if (pr->dt > bound * (1 + 1e-12))
+        return fail(CRYO_ERR_UNSTABLE, "dt exceeds the explicit z bound " + std::to_string(bound) +
+                                           " of the polynomial laws at T = " + std::to_string(Tm));
+    p->poly = true;
+    p->poly_a.assign(a, a + 4 * L);
+    p->poly_b.assign(b, b + 5 * L);
+    p->joule_tref = joule_tref;
+    p->flaws.cube = 0;
+    // the stepping kernel's law blob: POLY_BLK coefficients per law id
+    std::vector<double> &B = p->fpow_blob;
+    B.assign(pow_blob_doubles(L), 0.0);
+    const double e2 = p->eta * p->eta;
+    for (int m = 0; m < L; ++m) {
+        const cryo_material &mt = p->layers[m].mat;
+        for (int k = 0; k < 5; ++k) B[(size_t)POLY_BLK * m + k] = mt.k_scale * b[5 * m + k];
+        for (int k = 0; k < 4; ++k)
+            B[(size_t)POLY_BLK * (2 * L + m) + k] = e2 * mt.rho * a[4 * m + k] / pr->dt;
+    }
+    B[(size_t)POLY_BLK * law_unit(L)] = 1.0;
+    build_row_tables(p);
+    if (p->sub) return cryo_plan_set_poly_laws(p->sub, a, b, joule_tref);
+    return CRYO_OK;
+}
+
 cryo_status cryo_plan_set_turn_on(cryo_plan *p, int32_t on) {
     if (!p) return fail(CRYO_ERR_ARG, "null plan");
     if (!on) {
@@ -484,6 +552,8 @@ cryo_status cryo_plan_set_turn_on(cryo_plan *p, int32_t on) {
     cryo_status st = cryo_plan_create(&q, p->dtype, &s);
     if (st != CRYO_OK) return st;
     st = cryo_plan_set_shape(s, p->rpl, p->wpl, p->lpw);
+    if (st == CRYO_OK && p->poly)
+        st = cryo_plan_set_poly_laws(s, p->poly_a.data(), p->poly_b.data(), p->joule_tref);
     if (st != CRYO_OK) {
         cryo_plan_destroy(s);
         return st;

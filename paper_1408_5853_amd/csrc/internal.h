@@ -96,6 +96,12 @@ constexpr double POW_TLO = 0.0625, POW_THI = 1048576.0;   // 2^EMIN, 2^(EMIN+NE)
 constexpr int POW_BX = 2 * POW_NM;                 // binade multipliers
 constexpr int POW_BE = POW_BX + POW_NE;            // exponent, then binomials from +2
 constexpr int POW_BLK = POW_BE + 2 + (POW_DEG - 1) + 2;
+// Polynomial laws (eqs. (23), (24)) use the same blob size with POLY_BLK
+// doubles per law id in the stepping kernel's id scheme: ids 0..L-1 hold
+// k_scale b_k of layer m, ids 2L..3L-1 eta^2 rho a_k / dt, the zero and unit
+// laws 0 and 1; the ratio ids are unused (an interface row divides its
+// inner layer's law, slot 2, by its outer layer's, slot 3).
+constexpr int POLY_BLK = 6;
 // blob: (3L+2) law blocks, then {cube multiplier, addend} pairs per law id
 __host__ __device__ inline size_t pow_blob_doubles(int L) {
     return (size_t)(3 * L + 2) * (POW_BLK + 2);
@@ -158,6 +164,13 @@ struct cryo_plan {
     // transient turn-on model (eq. (22)): the same cell at dt / 100, whose
     // tables step the sub-steps of each pulse-start step (null when off)
     cryo_plan *sub = nullptr;
+    // polynomial laws (eqs. (23), (24)) and the Joule source (eq. (25)):
+    // when set, fpow_blob holds the polynomial coefficients (see POLY_BLK)
+    // and finfo's slot 3 the denominator law of each row (the outer layer's
+    // law on interface rows, the unit law elsewhere)
+    bool poly = false;
+    std::vector<double> poly_a, poly_b;   // [L][4], [L][5] as given
+    double joule_tref = 0.0;
 };
 
 namespace cryo {

@@ -120,3 +120,32 @@ def test_turn_on_model_host_checks():
                          None, None)
     assert st == 6
     assert "turn-on" in P.lib().cryo_last_error().decode()
+
+
+def test_polynomial_laws_host_checks():
+    c = cellgen.poly_variant(cellgen.with_nz(cellgen.small_cell(0), 4), 0, joule_tref=30.0)
+    plan = P.Plan(c)                                        # FP64, laws accepted
+    with pytest.raises(P.CryoError) as e:
+        P.Plan(c, "f32")
+    assert e.value.status == 6
+    Ls = c["layers"]
+    a = [l["poly_a"] for l in Ls]
+    zero_b = [[0.0] * 5 for _ in Ls]
+    with pytest.raises(P.CryoError) as e:
+        P.Plan(dict(c, poly=False)).set_poly_laws(a, zero_b)          # lambda = 0
+    assert e.value.status == 1
+    big_b = [[1e6 * x for x in l["poly_b"]] for l in Ls]
+    with pytest.raises(P.CryoError) as e:
+        P.Plan(dict(c, poly=False)).set_poly_laws(a, big_b)           # eq. (21) bound
+    assert e.value.status == 2
+    with pytest.raises(ValueError):
+        plan.set_poly_laws(a[:-1], zero_b)
+    P.Plan(dict(c, turn_on=True))                           # with the turn-on model
+    L = P.lib()
+    tgt = np.zeros(4)
+    J, g = ctypes.c_double(), np.zeros(2 + 2 * len(Ls))
+    dp = ctypes.POINTER(ctypes.c_double)
+    st = L.cryo_gradient(plan._h, ctypes.c_void_p(256), 4, tgt.ctypes.data_as(dp), 0,
+                         ctypes.c_void_p(256), 1 << 40, ctypes.byref(J), g.ctypes.data_as(dp),
+                         None, None)
+    assert st == 6 and "polynomial" in P.lib().cryo_last_error().decode()
