@@ -208,6 +208,19 @@ def turn_on_extra(P, steps, stream):
     return out
 
 
+def poly_extra(P, steps, stream):
+    """The polynomial laws (eqs. (23), (24)) with the Joule source (eq. (25))
+    on the device cell (seeded coefficients around its power laws)."""
+    import cellgen
+    c = cellgen.poly_variant(cellgen.device_cell(0), 0, joule_tref=30.0)
+    secs, plan = rate(P.Plan, c, "f64", steps, 200, stream)
+    r = c["nr"] * c["nz"] * steps / secs / 1e9
+    return {"workload": "device cell 1024x4096, FP64, polynomial laws + Joule source",
+            "steps": steps, "kernel_shape": list(plan.shape()),
+            "gcell_steps_s": round(r, 2),
+            "hbm_frac": round(r * BYTES_PER_CELL_STEP / HBM_PEAK_GBS, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -222,6 +235,9 @@ def main():
     ap.add_argument("--gradient-only", type=int, default=0, metavar="N",
                     help="profiling aid: time only a forward and a gradient of N steps on the "
                          "adjoint cell and print that result")
+    ap.add_argument("--poly-only", type=int, default=0, metavar="N",
+                    help="profiling aid: time only N steps of the polynomial-law path on the "
+                         "device cell and print that result")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: the stepper runs on exactly one GPU; --gpus %d is not supported"
@@ -237,6 +253,9 @@ def main():
     if args.gradient_only:
         gradient_extra(P, 50, stream)                       # warm
         print(json.dumps({"gradient": gradient_extra(P, args.gradient_only, stream)}), flush=True)
+        return
+    if args.poly_only:
+        print(json.dumps({"poly_laws": poly_extra(P, args.poly_only, stream)}), flush=True)
         return
     cell = cellgen.device_cell(0)
     cells = cell["nr"] * cell["nz"]
@@ -295,6 +314,8 @@ def main():
         out["extra"]["paper_shape"] = paper_shape_extra(P, 10_000, stream)
         log("bench: turn-on model")
         out["extra"]["turn_on"] = turn_on_extra(P, 1000, stream)
+        log("bench: polynomial laws")
+        out["extra"]["poly_laws"] = poly_extra(P, 5000, stream)
         log("bench: design loop")
         out["extra"]["design_loop"] = design_extra(P, 500, 2, stream)
     if not args.no_cpu:
