@@ -45,6 +45,7 @@ class _OCell(C.Structure):
         ("dt", C.c_double), ("turn_on", C.c_int),
         ("poly_a", C.POINTER(C.c_double)), ("poly_b", C.POINTER(C.c_double)),
         ("joule_tref", C.c_double),
+        ("z_full", C.c_int), ("nr_top", C.c_int),
     ]
 
 
@@ -114,6 +115,10 @@ class _Cell:
             s.poly_a = self.pa.ctypes.data_as(dp)
             s.poly_b = self.pb.ctypes.data_as(dp)
         s.joule_tref = float(cell.get("joule_tref", 0.0))
+        # eq. (9), stepped domain: {"z_full": j0, "nr_top": N_t}
+        st = cell.get("stepped")
+        if st:
+            s.z_full, s.nr_top = int(st["z_full"]), int(st["nr_top"])
         self.s = s
 
     def ref(self):

@@ -30,6 +30,15 @@
  *    tau* = tau / 100, sub-step i with the gate averaged over the sub-step
  *    times p^2 at its start, 1 - exp(-i / 7).  All other steps are unchanged
  *    (p^2 = 1), and the surface mean is reported once per step.
+ *  - Stepped domain (eq. (9): N_j radial nodes on line j), when set: lines
+ *    j <= z_full span all nr nodes (the layered section up to z_0), lines
+ *    above span nodes 0..nr_top-1 only (the terminal up to z_max).  The
+ *    terminal's outer wall and the step face are insulated: a node of line
+ *    z_full exchanges axial heat only with a capacity node above it, so the
+ *    face is closed from node nr_top - 1 on (above that node sits the
+ *    terminal's wall node, which only copies its neighbour); nodes outside
+ *    the domain are not solved and keep their values; the surface mean runs
+ *    over the lines of the layered section, z in [0, z_0].
  *  - Polynomial laws (eqs. (23), (24)), when given, replace the power laws
  *    term for term (lambda still times the layer's conductivity scale); the
  *    Joule source (eqs. (2), (25)), when enabled, multiplies the heater's
@@ -76,6 +85,8 @@ static int check_cell(const ocell *c)
     }
     if (tot != c->nr - 1) return 1;
     if (c->r_inner == 0 && c->bc_kind[0] != 0) return 1;
+    if (c->z_full < 0 || c->z_full > c->nz - 2) return 1;
+    if (c->z_full > 0 && (c->nr_top < 3 || c->nr_top > c->nr)) return 1;
     return 0;
 }
 
@@ -229,17 +240,23 @@ double oc_source_fraction_dwidth(const ocell *c, long k)
     return d / c->dt;
 }
 
+/* radial node count N_j of line j (eq. (9)) */
+static int line_len(const ocell *c, int j)
+{
+    return (c->z_full > 0 && j > c->z_full) ? c->nr_top : c->nr;
+}
+
 /* Rows of eq. (13) for line j (capacity), eq. (18) (interface), eq. (15)
  * (r boundaries); the explicit z operator eq. (11) sits in F. */
 static void line_rows(const ocell *c, const geom *g, const double *T, double tau,
                       double s, int j, double *A, double *B, double *C, double *F)
 {
-    int nr = c->nr;
+    int nr = c->nr, n = line_len(c, j);
     double eta = c->height / (c->nz - 1);
     const double *Tj = T + (size_t)j * nr;
     const double *Tn = Tj + nr, *Ts = Tj - nr;
     const double *r = g->r, *h = g->h;
-    for (int i = 1; i < nr - 1; i++) {
+    for (int i = 1; i < n - 1; i++) {
         if (g->kind[i] == ROW_CAP) {
             int m = g->mat[i];
             double lw = lam(c, m, 0.5 * (Tj[i] + Tj[i - 1]));   /* lambda_{i-1/2,j} */
@@ -252,6 +269,8 @@ static void line_rows(const ocell *c, const geom *g, const double *T, double tau
             C[i] = -re * le / (r[i] * hb * h[i + 1]);
             B[i] = (rw * lw / h[i] + re * le / h[i + 1]) / (r[i] * hb) + rc;
             double ln = lam(c, m, 0.5 * (Tj[i] + Tn[i]));       /* lambda_{i,j+1/2} */
+            /* the step face: no capacity node above */
+            if (c->z_full > 0 && j == c->z_full && i >= c->nr_top - 1) ln = 0.0;
             double ls = lam(c, m, 0.5 * (Tj[i] + Ts[i]));       /* lambda_{i,j-1/2} */
             double Lz = (ln * (Tn[i] - Tj[i]) / eta - ls * (Tj[i] - Ts[i]) / eta) / eta;
             double X = (m == c->heater) ? c->amplitude * s : 0.0;
@@ -271,9 +290,9 @@ static void line_rows(const ocell *c, const geom *g, const double *T, double tau
     A[0] = 0.0; B[0] = 1.0;
     if (c->bc_kind[0] == 0) { C[0] = -1.0; F[0] = 0.0; }
     else { C[0] = 0.0; F[0] = c->bc_value[0]; }
-    C[nr - 1] = 0.0; B[nr - 1] = 1.0;
-    if (c->bc_kind[1] == 0) { A[nr - 1] = -1.0; F[nr - 1] = 0.0; }
-    else { A[nr - 1] = 0.0; F[nr - 1] = c->bc_value[1]; }
+    C[n - 1] = 0.0; B[n - 1] = 1.0;
+    if (c->bc_kind[1] == 0 || n < nr) { A[n - 1] = -1.0; F[n - 1] = 0.0; }
+    else { A[n - 1] = 0.0; F[n - 1] = c->bc_value[1]; }
 }
 
 int oc_line_rows(const ocell *c, const double *T, long k, int j,
@@ -357,16 +376,17 @@ static void z_boundaries(const ocell *c, double *T)
     else for (int i = 0; i < nr; i++) top[i] = c->bc_value[3];
 }
 
-/* trapezoid weights along the outer surface r = r_max, normalised to 1 */
+/* trapezoid weights along the outer surface r = r_max (lines 0..J, J the
+ * last line of the layered section), normalised to 1 */
 static double surface_mean(const ocell *c, const double *T)
 {
-    int nr = c->nr, nz = c->nz;
+    int nr = c->nr, J = c->z_full > 0 ? c->z_full : c->nz - 1;
     double s = 0.0;
-    for (int j = 0; j < nz; j++) {
-        double w = (j == 0 || j == nz - 1) ? 0.5 : 1.0;
+    for (int j = 0; j <= J; j++) {
+        double w = (j == 0 || j == J) ? 0.5 : 1.0;
         s += w * T[(size_t)j * nr + nr - 1];
     }
-    return s / (nz - 1);
+    return s / J;
 }
 
 typedef struct { double *A, *B, *C, *F, *al, *be, *wa, *wb; } rows_t;
@@ -399,8 +419,10 @@ static void step_tau(const ocell *c, const geom *g, const double *T, double *Tn,
 #pragma omp parallel for num_threads(nth) schedule(static)
     for (int j = 1; j < nz - 1; j++) {
         rows_t *w = &scr[thread_id()];
+        int n = line_len(c, j);
         line_rows(c, g, T, tau, s, j, w->A, w->B, w->C, w->F);
-        thomas(nr, w->A, w->B, w->C, w->F, w->al, w->be, Tn + (size_t)j * nr);
+        thomas(n, w->A, w->B, w->C, w->F, w->al, w->be, Tn + (size_t)j * nr);
+        for (int i = n; i < nr; i++) Tn[(size_t)j * nr + i] = T[(size_t)j * nr + i];
     }
     z_boundaries(c, Tn);
 }
@@ -561,7 +583,7 @@ int oc_gradient(const ocell *c, const double *T0, long N, const double *target,
 {
     geom g;
     if (check_cell(c) || N < 1 || c->turn_on || c->poly_a || c->poly_b || c->joule_tref > 0 ||
-        geom_build(c, &g))
+        c->z_full > 0 || geom_build(c, &g))
         return 1;
     int nr = c->nr, nz = c->nz, L = c->n_layers, ng = 2 + 2 * L;
     size_t n = (size_t)nr * nz;

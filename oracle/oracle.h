@@ -36,6 +36,7 @@ typedef struct {
     const double *poly_a;     /* NULL, or [n_layers][4]: c_m(T) = sum a_k T^k, eq. (23) */
     const double *poly_b;     /* NULL, or [n_layers][5]: lambda_m(T) = kscale sum b_k T^k, eq. (24) */
     double joule_tref;        /* > 0: heater source times sqrt(joule_tref / T), eq. (25) */
+    int z_full, nr_top;       /* z_full > 0: lines j > z_full span nodes 0..nr_top-1 (eq. (9)) */
 } ocell;
 
 /* node radii r_0..r_{nr-1}, eq. (9) */
@@ -64,7 +65,7 @@ int oc_line_paper_sweep(const ocell *c, const double *T, long k, int j,
  * fall on step boundaries, else the call fails */
 int oc_forward(const ocell *c, double *T, long k0, long nsteps, double *surf,
                int nthreads);
-/* (fails when turn_on, polynomial laws or the Joule source are set)
+/* (fails when turn_on, polynomial laws, the Joule source or a stepped domain are set)
  * J = sum_{n=1..N} (S_n - target_n)^2 and its gradient
  * grad = [dJ/dQ, dJ/dwidth, dJ/dthick[L], dJ/dkscale[L]] by the discrete
  * adjoint.  ckpt = 0 stores every state, else every ckpt-th with recompute.

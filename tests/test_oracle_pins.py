@@ -670,3 +670,62 @@ def test_joule_uniform_field_converges_to_closed_form():
     assert exact - T0 > 5.0
     assert errs[-1] < 5e-3 * (exact - T0), errs
     assert min(orders) > 0.9, (errs, orders)
+
+
+# --------------------------------------------------------------------------
+# Stepped domain (eq. (9): N_j radial nodes on line j)
+# --------------------------------------------------------------------------
+
+def test_stepped_domain_full_radius_is_rectangular():
+    # the terminal spanning every radial node leaves the field unchanged bit
+    # for bit; only the surface mean is restricted to the layered section
+    c = cellgen.with_nz(cellgen.small_cell(2, z_active=True), 14)
+    T0 = _random_field(c, 3, 28.0, 32.0)
+    Tr = oracle.forward(c, T0, nsteps=120)
+    st = dict(c, stepped=dict(z_full=8, nr_top=c["nr"]))
+    Ts, S = oracle.forward(st, T0, nsteps=120, surf=True)
+    assert np.array_equal(Ts, Tr)
+    w = np.ones(9)
+    w[0] = w[-1] = 0.5
+    assert S[-1] == pytest.approx(np.dot(w, Tr[:9, -1]) / 8, rel=1e-15)
+
+
+def test_stepped_domain_heat_balance_exact():
+    # insulated everywhere, random field: over the domain's capacity nodes the
+    # content changes by exactly the injected source each step, so the step
+    # face and the terminal's outer wall pass no heat; nodes outside the
+    # domain are left alone
+    Ls = [layer(1e-3, 40, k0=3.0, p=1.3, c0=80.0, q=3.0, rho=4e3)]
+    c = cell(Ls, nz=12, height=5e-3, dt=2e-7, amplitude=3e8, width=4e-6,
+             period=1e-5, heater=0)
+    j0, nt = 5, 15
+    c["stepped"] = dict(z_full=j0, nr_top=nt)
+    T = _random_field(c, 11, 28.0, 34.0)
+    T[0], T[-1] = T[1], T[-2]
+    r = oracle.radii(c)
+    h = np.diff(r)
+    w = r[1:-1] * 0.5 * (h[:-1] + h[1:]) * (c["height"] / (c["nz"] - 1))
+    mask = np.zeros((c["nz"], c["nr"]), bool)
+    mask[1:j0 + 1, 1:-1] = True
+    mask[j0 + 1:-1, 1:nt - 1] = True
+    W = np.zeros_like(T)
+    W[:, 1:-1] = w
+    l = Ls[0]
+    for k in range(0, 40, 9):
+        Tn = oracle.forward(c, T, k0=k, nsteps=1)
+        rc = l["rho"] * l["c0"] * (T / l["tref"]) ** l["q"]
+        lhs = np.sum((W * rc * (Tn - T))[mask])
+        rhs = c["dt"] * c["amplitude"] * oracle.source_fraction(c, k) * np.sum(W[mask])
+        scale = np.sum((W * rc * np.abs(Tn - T))[mask])
+        assert abs(lhs - rhs) <= 1e-11 * max(abs(rhs), scale)
+        assert np.array_equal(Tn[j0 + 1:-1, nt:], T[j0 + 1:-1, nt:])
+        assert scale > 0
+        T = Tn
+
+
+def test_stepped_domain_rejects_bad_steps():
+    c = cellgen.with_nz(cellgen.small_cell(0), 6)
+    for bad in (dict(z_full=5, nr_top=10), dict(z_full=2, nr_top=2),
+                dict(z_full=2, nr_top=c["nr"] + 1)):
+        with pytest.raises(ValueError):
+            oracle.forward(dict(c, stepped=bad), nsteps=1)
