@@ -183,6 +183,22 @@ cryo_status cryo_forward(const cryo_plan *plan, void *T, int64_t k0,
                          int64_t nsteps, void *ws, size_t ws_bytes,
                          double *surf, void *stream);
 
+/* Stepped domain of eq. (9) (N_j radial nodes on line j): lines
+ * j <= z_full span all nr radial nodes (the layered section, z <= z_0), lines
+ * above span nodes 0..nr_top-1 only (the terminal, z_0 < z <= z_max).  The
+ * terminal's outer wall (node nr_top - 1) and the step face are insulated: a
+ * node of line z_full exchanges axial heat only with a capacity node above
+ * it (nodes nr_top - 1 and beyond see a closed face).  The held or insulated
+ * outer wall of the problem applies to the layered section, the inner wall
+ * and the z-boundaries to every line.  Nodes outside the domain are not
+ * solved: their values are whatever the field held (a z-boundary copy or
+ * hold still writes them).  The surface output becomes the trapezoid mean of
+ * T on r = r_max over z in [0, z_0] (lines 0..z_full).  1 <= z_full <= nz-2,
+ * 3 <= nr_top <= nr (CRYO_ERR_ARG otherwise); must precede the plan's first
+ * device call; FP64 and FP32.  Gradients refuse such a plan, and polynomial
+ * laws cannot be combined with it (CRYO_ERR_UNSUPPORTED). */
+cryo_status cryo_plan_set_stepped(cryo_plan *plan, int32_t z_full, int32_t nr_top);
+
 /* Polynomial material laws of eqs. (23) and (24) in place of the power laws,
  * and optionally the Joule source of eqs. (2) and (25).  FP64 plans only
  * (CRYO_ERR_UNSUPPORTED otherwise); must precede the plan's first device

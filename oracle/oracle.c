@@ -291,7 +291,8 @@ static void line_rows(const ocell *c, const geom *g, const double *T, double tau
     if (c->bc_kind[0] == 0) { C[0] = -1.0; F[0] = 0.0; }
     else { C[0] = 0.0; F[0] = c->bc_value[0]; }
     C[n - 1] = 0.0; B[n - 1] = 1.0;
-    if (c->bc_kind[1] == 0 || n < nr) { A[n - 1] = -1.0; F[n - 1] = 0.0; }
+    /* the terminal's wall is insulated; the layered section's as given */
+    if (c->bc_kind[1] == 0 || (c->z_full > 0 && j > c->z_full)) { A[n - 1] = -1.0; F[n - 1] = 0.0; }
     else { A[n - 1] = 0.0; F[n - 1] = c->bc_value[1]; }
 }
 

@@ -67,6 +67,8 @@ class Plan:
             Ls = cell["layers"]
             self.set_poly_laws([l["poly_a"] for l in Ls], [l["poly_b"] for l in Ls],
                                cell.get("joule_tref", 0.0))
+        if cell.get("stepped"):
+            self.set_stepped(cell["stepped"]["z_full"], cell["stepped"]["nr_top"])
         if cell.get("turn_on"):
             self.set_turn_on(True)
 
@@ -100,6 +102,11 @@ class Plan:
         """Switch the transient turn-on model of eq. (22) on or off: each
         pulse's first step then runs as 100 sub-steps of dt/100."""
         check(lib().cryo_plan_set_turn_on(self._h, int(bool(on))))
+
+    def set_stepped(self, z_full, nr_top):
+        """Stepped domain of eq. (9): lines above z_full span the inner nr_top
+        radial nodes (the terminal); the surface mean covers lines 0..z_full."""
+        check(lib().cryo_plan_set_stepped(self._h, int(z_full), int(nr_top)))
 
     def set_poly_laws(self, a, b, joule_tref=0.0):
         """Polynomial laws of eqs. (23), (24): a[m] = 4 capacity coefficients,

@@ -142,6 +142,11 @@ struct StepArgs {
     int groups;               // workgroups of one step of this instance
     Pulse pulse;              // batch: schedule evaluated on the device
     int joule;                // heater source times X / sqrt(T) (eq. (25)), X holding sqrt(T_J)
+    // stepped domain (eq. (9)): lines above z_full take the terminal's row
+    // tables (nz - 1 when there is none)
+    int z_full;
+    const R *gw2, *ge2;
+    const uint32_t *info2;
 };
 
 constexpr int STEP_WAVES = STEP_WAVES_HOST;
@@ -388,6 +393,11 @@ template <typename R>
 __host__ __device__ inline size_t ring_lds_offset(int L, int np) {
     size_t b = (law_lds_bytes<R>(L) + 15) & ~(size_t)15;
     return (b + (2 * sizeof(R) + sizeof(uint32_t)) * (size_t)np + 15) & ~(size_t)15;
+}
+// one set of per-row tables (gw, ge, info) of an np-row line, 16-aligned
+template <typename R>
+__host__ __device__ inline size_t step_tables_bytes(int np) {
+    return ((2 * sizeof(R) + sizeof(uint32_t)) * (size_t)np + 15) & ~(size_t)15;
 }
 template <typename R>
 __host__ __device__ inline size_t ring_slot_elems(int rpl) {

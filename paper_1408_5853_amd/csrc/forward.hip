@@ -44,7 +44,12 @@ __device__ inline auto law_of(const LawLds<R> &t) {
     else return t;
 }
 
-template <typename R, int RPL, int G, bool CUBE, bool POLY = false>
+// STEPPED: the stepped domain of eq. (9).  Lines above z_full use the
+// terminal's row tables (rows past its wall are identity rows), the axial
+// face between lines z_full and z_full + 1 is closed where the terminal's row
+// is not a capacity row, the held outer wall belongs to the layered lines,
+// and the surface mean covers lines 0..z_full.
+template <typename R, int RPL, int G, bool CUBE, bool POLY = false, bool STEPPED = false>
 __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *__restrict__ Tin,
                                  R *__restrict__ Tout, const R X, double *partial) {
     constexpr bool PAIR = Pair<R>::on;
@@ -58,10 +63,21 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
     R *sgw = (R *)(smem + ((law_lds_bytes<R>(a.laws.L) + 15) & ~(size_t)15));
     R *sge = sgw + a.np;
     uint32_t *sinf = (uint32_t *)(sge + a.np);
+    // STEPPED: the terminal's tables next, where the ring or carried fluxes
+    // would otherwise start (those move up by tbytes)
+    const size_t tbytes = STEPPED ? step_tables_bytes<R>(a.np) : 0;
+    R *sgw2 = (R *)(smem + ring_lds_offset<R>(a.laws.L, a.np));
+    R *sge2 = sgw2 + a.np;
+    uint32_t *sinf2 = (uint32_t *)(sge2 + a.np);
     for (int i = threadIdx.x; i < a.np; i += blockDim.x) {
         sgw[i] = a.gw[i];
         sge[i] = a.ge[i];
         sinf[i] = a.info[i];
+        if constexpr (STEPPED) {
+            sgw2[i] = a.gw2[i];
+            sge2[i] = a.ge2[i];
+            sinf2[i] = a.info2[i];
+        }
     }
     const auto law = law_of<R, POLY>(stage_laws<R>(a, smem));   // ends with a barrier
     const int t = threadIdx.x;
@@ -101,7 +117,7 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
     constexpr bool RING = ring_used<R>(RPL);
     constexpr int EPL = 16 / (int)sizeof(R);              // elements per lane per load
     constexpr int LPS = WAVE / EPL;                       // lanes per row-plane
-    R *ring = (R *)(smem + ring_lds_offset<R>(L, a.np)) + (size_t)wv * 2 * SLOT;
+    R *ring = (R *)(smem + ring_lds_offset<R>(L, a.np) + tbytes) + (size_t)wv * 2 * SLOT;
     auto prefetch = [&](int slot, size_t lbase) {
         if constexpr (!RING) return;
         R *dst = ring + slot * SLOT;
@@ -119,7 +135,7 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
     // carried south-face fluxes: registers, or (FP64, 10+ rows per lane) LDS
     constexpr bool FS_LDS = fs_in_lds<R>(RPL);
     R FSr[FS_LDS ? 1 : RPL];
-    R *fsl = (R *)(smem + ring_lds_offset<R>(L, a.np)) + (size_t)wv * RPL * WAVE + lane;
+    R *fsl = (R *)(smem + ring_lds_offset<R>(L, a.np) + tbytes) + (size_t)wv * RPL * WAVE + lane;
     auto fs_get = [&](int r) -> R {
         if constexpr (FS_LDS) return fsl[r * WAVE];
         else return FSr[r];
@@ -134,6 +150,8 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
         const int jb = line_at(0);
         const size_t bc = (size_t)jb * LS;
         const size_t bp = (size_t)(jb - dir) * LS;       // the line before it
+        const uint32_t *tinf = (STEPPED && jb > a.z_full) ? sinf2 : sinf;
+        const bool trans = STEPPED && min(jb, jb - dir) == a.z_full;
         prefetch(1, bc + LS);
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
@@ -159,12 +177,15 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
         for (int r = 0; r < RPL; ++r) {
             const int q = r * NL + lg;
             const R Tp = Tpv[r], Tpl = Tplv[r];
-            const uint32_t inf_r = sinf[q];
+            const uint32_t inf_r = tinf[q];
             const bool cap = (inf_r & 7) == K_CAP;
             const int l2 = (inf_r >> 12) & 63;
             if constexpr (!PAIR) bad |= !LawLds<R>::in_range(Tp);
             const R lamS = law.lawm(cap ? l2 : law_zero(L), Tc[r] + Tp);
-            fs_set(r, lamS * dif<R>(Tp, Tpl, Tc[r], Lc[r]));
+            R Fs = lamS * dif<R>(Tp, Tpl, Tc[r], Lc[r]);
+            if constexpr (STEPPED)                          // the step face
+                if (trans && (sinf2[q] & 7) != K_CAP) Fs = (R)0;
+            fs_set(r, Fs);
             if (r & 1) __builtin_amdgcn_sched_barrier(0);      // register pressure
         }
         // the next line's slot must have landed before the first row reads it
@@ -186,6 +207,12 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
         const int j = line_at(it);
         const size_t base = (size_t)j * LS;
         const size_t bo = (size_t)(j + dir) * LS;        // the other line: the next one
+        // stepped domain: this line's tables, and whether its face with the
+        // other line is the one at the step
+        const bool up = STEPPED && j > a.z_full;
+        const bool trans = STEPPED && min(j, j + dir) == a.z_full;
+        const R *tgw = up ? sgw2 : sgw, *tge = up ? sge2 : sge;
+        const uint32_t *tinf = up ? sinf2 : sinf;
         const R *sn = ring + ((it + 1) & 1) * SLOT;      // line j+1
         // the other slot (line j, already read into registers) takes line j+2;
         // its reads must have completed before the load overwrites it
@@ -204,7 +231,7 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
             }
         }
         // west face of the chunk's first row: east face of the previous row
-        R lamW = law.lawm((sinf[qW] >> 6) & 63, TwF + Tc[0]);
+        R lamW = law.lawm((tinf[qW] >> 6) & 63, TwF + Tc[0]);
         R a0 = 0, b0 = 1, c0 = 0, d0 = 0;
         R al[RPL], ga[RPL], de[RPL];
         // without the ring: the next line's values come from memory two rows
@@ -220,12 +247,12 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
         }
         // the rows' info words, one row ahead (they head each row's chain of
         // table lookups)
-        uint32_t infn = sinf[lg];
+        uint32_t infn = tinf[lg];
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
             const int q = r * NL + lg;
             const uint32_t inf_r = infn;
-            if (r + 1 < RPL) infn = sinf[q + NL];
+            if (r + 1 < RPL) infn = tinf[q + NL];
             if constexpr (!RING) {
                 if (r + PF < RPL) {
                     TnP[r + PF] = Tin[bo + q + PF * NL];
@@ -266,10 +293,12 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
             R rc;
             if constexpr (CUBE) rc = law.cube(lc, T);
             else rc = law.lawm(lc, T + T);
-            const R fw = sgw[q] * (cap ? lamW : lam2);
-            const R fe = sge[q] * (cap ? lamE : (R)1);
+            const R fw = tgw[q] * (cap ? lamW : lam2);
+            const R fe = tge[q] * (cap ? lamE : (R)1);
             // flux into this line from the next one (carried on, negated)
-            const R Fo = lam2 * dif<R>(Tnr, Lnr, T, Tl);
+            R Fo = lam2 * dif<R>(Tnr, Lnr, T, Tl);
+            if constexpr (STEPPED)                          // the step face
+                if (trans && (sinf2[q] & 7) != K_CAP) Fo = (R)0;
             R dd = fw * dif<R>(Tw, Lw, T, Tl) + fe * dif<R>(Te, Le, T, Tl);
             dd += cap ? Fo + Fc : (R)0;
             if constexpr (POLY)                                 // heater rows, eq. (25)
@@ -278,7 +307,7 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
                 dd += (R)((inf_r >> 3) & 1) * X;                // heater capacity rows
             // held walls: rows 0 and nr - 1 are unit rows with dT = value - T
             if (r == 0 && a.held[0]) dd = lg == 0 ? dif<R>(a.val[0], (R)0, T, Tl) : dd;
-            if (r == a.surf_reg && a.held[1])
+            if (r == a.surf_reg && a.held[1] && !up)
                 dd = lg == a.surf_lane ? dif<R>(a.val[1], (R)0, T, Tl) : dd;
             fs_set(r, -Fo);
             lamW = lamE;
@@ -356,9 +385,14 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
 #pragma unroll
                 for (int r = 1; r < RPL; ++r)
                     if (r == sreg) v = (double)Hn[r] + (double)Lnw[r];
-                sv += a.wz_mid * v;
-                if (j == 1) sv += a.wz_end * (a.held[2] ? (double)a.val[2] : v);
-                if (j == a.nz - 2) sv += a.wz_end * (a.held[3] ? (double)a.val[3] : v);
+                if constexpr (STEPPED) {                    // lines 0..z_full
+                    sv += j < a.z_full ? a.wz_mid * v : j == a.z_full ? a.wz_end * v : 0.0;
+                    if (j == 1) sv += a.wz_end * (a.held[2] ? (double)a.val[2] : v);
+                } else {
+                    sv += a.wz_mid * v;
+                    if (j == 1) sv += a.wz_end * (a.held[2] ? (double)a.val[2] : v);
+                    if (j == a.nz - 2) sv += a.wz_end * (a.held[3] ? (double)a.val[3] : v);
+                }
             }
         }
         // next line: registers from its ring slot, or the values the rows
@@ -401,10 +435,10 @@ __device__ inline int xcd_block(int b, int nb) {
     return x * per + min(x, rem) + i;
 }
 
-template <typename R, int RPL, int G, bool CUBE, bool POLY = false>
+template <typename R, int RPL, int G, bool CUBE, bool POLY = false, bool STEPPED = false>
 __global__ __launch_bounds__(STEP_WAVES *WAVE) void k_step(StepArgs<R> a) {
-    step_body<R, RPL, G, CUBE, POLY>(a, xcd_block(blockIdx.x, gridDim.x), a.Tin, a.Tout, a.X,
-                                     a.partial);
+    step_body<R, RPL, G, CUBE, POLY, STEPPED>(a, xcd_block(blockIdx.x, gridDim.x), a.Tin, a.Tout,
+                                              a.X, a.partial);
 }
 
 // Pulse average over step k (eq. (4)), step units; the host's schedule.
@@ -577,6 +611,16 @@ static StepArgs<R> step_args(const cryo_plan *p, const void *Tin, void *Tout, do
     a.wz_end = 0.5 / (p->nz - 1);
     a.surf_lane = p->surf_lane;
     a.surf_reg = p->surf_reg;
+    // stepped domain: the terminal's tables, and the surface over lines
+    // 0..z_full
+    a.z_full = p->stepped ? p->z_full : p->nz - 1;
+    a.gw2 = p->stepped ? (const R *)p->d_rows2 : a.gw;
+    a.ge2 = p->stepped ? a.gw2 + p->np : a.ge;
+    a.info2 = p->stepped ? p->d_info2 : a.info;
+    if (p->stepped) {
+        a.wz_mid = 1.0 / p->z_full;
+        a.wz_end = 0.5 / p->z_full;
+    }
     a.groups = step_grid(p);
     a.pulse = p->pulse;
     a.pulse.amplitude *= xs;
@@ -589,11 +633,16 @@ static cryo_status step_t(const cryo_plan *p, const void *Tin, void *Tout, doubl
                           double *partial, int *flag, hipStream_t s) {
     StepArgs<R> a = step_args<R>(p, Tin, Tout, X, partial, flag);
     dim3 g(step_grid(p)), b(STEP_WAVES * WAVE);
-    const size_t lds = step_lds_bytes<R>(p->L, p->np, p->rpl);
+    const size_t lds = step_lds(p);
     const int key = p->rpl * 10 + p->wpl;
     switch (key) {
 #define STEP_CASE(RP, GW) \
     case RP * 10 + GW: \
+        if (p->stepped) { \
+            if (a.laws.cube) hipLaunchKernelGGL((k_step<R, RP, GW, true, false, true>), g, b, lds, s, a); \
+            else hipLaunchKernelGGL((k_step<R, RP, GW, false, false, true>), g, b, lds, s, a); \
+            break; \
+        } \
         if constexpr (sizeof(R) == 8) \
             if (p->poly) { \
                 hipLaunchKernelGGL((k_step<R, RP, GW, false, true>), g, b, lds, s, a); \
@@ -632,8 +681,12 @@ size_t step_desc_bytes(cryo_dtype dt) {
 }
 
 size_t step_lds(const cryo_plan *p) {
-    return p->dtype == CRYO_F64 ? step_lds_bytes<double>(p->L, p->np, p->rpl)
-                                : step_lds_bytes<float>(p->L, p->np, p->rpl);
+    // a stepped domain stages the terminal's tables too
+    return p->dtype == CRYO_F64
+               ? step_lds_bytes<double>(p->L, p->np, p->rpl) +
+                     (p->stepped ? step_tables_bytes<double>(p->np) : 0)
+               : step_lds_bytes<float>(p->L, p->np, p->rpl) +
+                     (p->stepped ? step_tables_bytes<float>(p->np) : 0);
 }
 
 void step_desc_fill(const cryo_plan *p, void *out, void *buf0, void *buf1, int *flag) {

@@ -96,6 +96,7 @@ static cryo_status grad_check(const cryo_plan *p, int64_t N, const double *targe
     if (p->dtype != CRYO_F64) return fail(CRYO_ERR_UNSUPPORTED, "the adjoint needs an FP64 plan");
     if (p->sub) return fail(CRYO_ERR_UNSUPPORTED, "no adjoint of the turn-on model's sub-steps");
     if (p->poly) return fail(CRYO_ERR_UNSUPPORTED, "no adjoint of the polynomial laws");
+    if (p->stepped) return fail(CRYO_ERR_UNSUPPORTED, "no adjoint of the stepped domain");
     const int key = p->rpl * 10 + p->wpl;
     if (!(key == 21 || key == 41 || key == 81 || key == 42 || key == 82 || key == 44 || key == 84))
         return fail(CRYO_ERR_UNSUPPORTED, "the adjoint kernels take 2, 4 or 8 rows per lane; set "

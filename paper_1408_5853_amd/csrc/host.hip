@@ -208,12 +208,33 @@ cryo_status ensure_device(cryo_plan *p) {
     if (e == hipSuccess)
         e = hipMemcpy(p->d_pow, blobs.data(), sizeof(double) * blobs.size(),
                       hipMemcpyHostToDevice);
+    if (e == hipSuccess && p->stepped) {
+        std::vector<double> t(p->tfgw);
+        t.insert(t.end(), p->tfge.begin(), p->tfge.end());
+        e = hipMalloc(&p->d_rows2, es * 2 * np);
+        if (e == hipSuccess) {
+            if (p->dtype == CRYO_F64) {
+                e = hipMemcpy(p->d_rows2, t.data(), es * 2 * np, hipMemcpyHostToDevice);
+            } else {
+                std::vector<float> f(t.begin(), t.end());
+                e = hipMemcpy(p->d_rows2, f.data(), es * 2 * np, hipMemcpyHostToDevice);
+            }
+        }
+        if (e == hipSuccess) e = hipMalloc((void **)&p->d_info2, sizeof(uint32_t) * np);
+        if (e == hipSuccess)
+            e = hipMemcpy(p->d_info2, p->tfinfo.data(), sizeof(uint32_t) * np,
+                          hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) {
         if (p->d_rows) (void)hipFree(p->d_rows);
         if (info) (void)hipFree(info);
         if (p->d_pow) (void)hipFree(p->d_pow);
+        if (p->d_rows2) (void)hipFree(p->d_rows2);
+        if (p->d_info2) (void)hipFree(p->d_info2);
         p->d_rows = nullptr;
         p->d_pow = nullptr;
+        p->d_rows2 = nullptr;
+        p->d_info2 = nullptr;
         return fail(CRYO_ERR_DEVICE, std::string("device table upload: ") + hipGetErrorString(e));
     }
     p->d_info = info;
@@ -222,25 +243,22 @@ cryo_status ensure_device(cryo_plan *p) {
 
 // Lane-major per-row tables: row i = lg * rpl + reg of a line sits at
 // reg * (64 wpl) + lg, lg the lane within the line.
-static void build_row_tables(cryo_plan *p) {
+// One line's rows: nodes 0..n-1 of the grid, row n-1 the outer wall
+// (insulated when `terminal`, else as the problem says).  Writes the rows as
+// written (gw, ge, info; may be null) and the stepping kernel's form (fgw,
+// fge, finfo) at the lane-major positions.
+static void fill_rows(cryo_plan *p, int n, bool terminal, double *gwo, double *geo,
+                      uint32_t *info, double *fgwo, double *fgeo, uint32_t *finfo) {
     const cryo_problem *prob = &p->prob;
-    const int nr = p->nr, L = p->L, np = p->np, rpl = p->rpl;
+    const int nr = p->nr, L = p->L, rpl = p->rpl;
     const int ZERO = law_zero(L), UNIT = law_unit(L);
-    int i;
     const double e2 = p->eta * p->eta;
-    p->gw.assign(np, 0.0);
-    p->ge.assign(np, 0.0);
-    p->info.assign(np, info_pack(K_PAD, 0, 0, 0, ZERO, ZERO, ZERO, UNIT));
-    p->fgw.assign(np, 0.0);
-    p->fge.assign(np, 0.0);
-    // polynomial laws divide slot 2 by slot 3 on every row: unit by default
-    p->finfo.assign(np, info_pack(K_PAD, 0, 0, 0, ZERO, ZERO, p->poly ? UNIT : ZERO, UNIT));
     const int *bk = prob->bc.kind;
-    for (i = 0; i < nr; ++i) {
+    for (int i = 0; i < n; ++i) {
         int idx = (i % rpl) * (WAVE * p->wpl) + i / rpl;
-        uint32_t kind = p->kind[i];
+        uint32_t kind = (i == n - 1 && n < nr) ? (uint32_t)K_HI : (uint32_t)p->kind[i];
         uint32_t m = p->lay[i];
-        uint32_t lawE = (i < nr - 1) ? p->lay[i + 1] : ZERO;     // radial law of interval i+1
+        uint32_t lawE = (i < n - 1) ? p->lay[i + 1] : ZERO;      // radial law of interval i+1
         uint32_t law2 = ZERO, law3 = ZERO, lawC = ZERO, heat = 0, held = 0, side = 0;
         double gw = 0.0, ge = 0.0;
         if (kind == K_CAP) {
@@ -262,12 +280,14 @@ static void build_row_tables(cryo_plan *p) {
             if (bk[0] == CRYO_HELD) { lawC = UNIT; held = 1; }
             else { ge = 1.0; law3 = UNIT; }
         } else {  // K_HI: eq. (15)/(17): T_{N} = T_{N-1}, or the held wall value
-            if (bk[1] == CRYO_HELD) { lawC = UNIT; held = 1; side = 1; }
+            if (bk[1] == CRYO_HELD && !terminal) { lawC = UNIT; held = 1; side = 1; }
             else { gw = 1.0; law2 = UNIT; side = 1; }
         }
-        p->gw[idx] = gw;
-        p->ge[idx] = ge;
-        p->info[idx] = info_pack(kind, heat, held, side, lawE, law2, law3, lawC);
+        if (gwo) {
+            gwo[idx] = gw;
+            geo[idx] = ge;
+            info[idx] = info_pack(kind, heat, held, side, lawE, law2, law3, lawC);
+        }
         // the stepping kernel's form: capacity rows times eta^2 (slot 2 then
         // takes the radial law), interface rows divided by the outer law
         // (slot 2 the ratio law, slot 3 one); boundary rows fold their unit or
@@ -295,12 +315,35 @@ static void build_row_tables(cryo_plan *p) {
                 f3 = p->lay[i + 1];
             }
         }
-        p->fgw[idx] = fgw;
-        p->fge[idx] = fge;
-        p->finfo[idx] = info_pack(kind, heat, held, side, lawE, f2, f3, lawC);
+        fgwo[idx] = fgw;
+        fgeo[idx] = fge;
+        finfo[idx] = info_pack(kind, heat, held, side, lawE, f2, f3, lawC);
     }
-    p->surf_lane = (nr - 1) / rpl;
-    p->surf_reg = (nr - 1) % rpl;
+}
+
+static void build_row_tables(cryo_plan *p) {
+    const int nr = p->nr, L = p->L, np = p->np;
+    const int ZERO = law_zero(L), UNIT = law_unit(L);
+    // padding rows: identity; polynomial laws divide slot 2 by slot 3 on
+    // every row, so slot 3 is the unit law there
+    const uint32_t pad = info_pack(K_PAD, 0, 0, 0, ZERO, ZERO, p->poly ? UNIT : ZERO, UNIT);
+    p->gw.assign(np, 0.0);
+    p->ge.assign(np, 0.0);
+    p->info.assign(np, info_pack(K_PAD, 0, 0, 0, ZERO, ZERO, ZERO, UNIT));
+    p->fgw.assign(np, 0.0);
+    p->fge.assign(np, 0.0);
+    p->finfo.assign(np, pad);
+    fill_rows(p, nr, false, p->gw.data(), p->ge.data(), p->info.data(), p->fgw.data(),
+              p->fge.data(), p->finfo.data());
+    // stepped domain (eq. (9)): the terminal's lines, nodes 0..nr_top-1
+    p->tfgw.assign(np, 0.0);
+    p->tfge.assign(np, 0.0);
+    p->tfinfo.assign(np, pad);
+    if (p->stepped)
+        fill_rows(p, p->nr_top, true, nullptr, nullptr, nullptr, p->tfgw.data(), p->tfge.data(),
+                  p->tfinfo.data());
+    p->surf_lane = (nr - 1) / p->rpl;
+    p->surf_reg = (nr - 1) % p->rpl;
 }
 
 }  // namespace cryo
@@ -438,6 +481,8 @@ void cryo_plan_destroy(cryo_plan *p) {
     if (p->d_rows) (void)hipFree(p->d_rows);
     if (p->d_info) (void)hipFree(p->d_info);
     if (p->d_pow) (void)hipFree(p->d_pow);
+    if (p->d_rows2) (void)hipFree(p->d_rows2);
+    if (p->d_info2) (void)hipFree(p->d_info2);
     delete p;
 }
 
@@ -490,6 +535,8 @@ cryo_status cryo_plan_set_poly_laws(cryo_plan *p, const double *a, const double 
     if (!p || !a || !b) return fail(CRYO_ERR_ARG, "null argument");
     if (p->d_info) return fail(CRYO_ERR_ARG, "laws must be set before the plan's first run");
     if (p->dtype != CRYO_F64) return fail(CRYO_ERR_UNSUPPORTED, "polynomial laws need an FP64 plan");
+    if (p->stepped)
+        return fail(CRYO_ERR_UNSUPPORTED, "polynomial laws on a stepped domain are not built");
     const int L = p->L;
     for (int i = 0; i < 4 * L; ++i)
         if (!std::isfinite(a[i])) return fail(CRYO_ERR_ARG, "capacity coefficient not finite");
@@ -535,6 +582,25 @@ cryo_status cryo_plan_set_poly_laws(cryo_plan *p, const double *a, const double 
     return CRYO_OK;
 }
 
+cryo_status cryo_plan_set_stepped(cryo_plan *p, int32_t z_full, int32_t nr_top) {
+    if (!p) return fail(CRYO_ERR_ARG, "null plan");
+    if (p->d_info) return fail(CRYO_ERR_ARG, "the domain must be set before the plan's first run");
+    if (p->poly)
+        return fail(CRYO_ERR_UNSUPPORTED, "polynomial laws on a stepped domain are not built");
+    if (z_full < 1 || z_full > p->nz - 2) return fail(CRYO_ERR_ARG, "z_full must be 1..nz-2");
+    if (nr_top < 3 || nr_top > p->nr) return fail(CRYO_ERR_ARG, "nr_top must be 3..nr");
+    p->stepped = true;
+    p->z_full = z_full;
+    p->nr_top = nr_top;
+    if (step_lds(p) > MAX_STEP_LDS) {
+        p->stepped = false;
+        return fail(CRYO_ERR_UNSUPPORTED, "the terminal's tables exceed a workgroup's LDS");
+    }
+    build_row_tables(p);
+    if (p->sub) return cryo_plan_set_stepped(p->sub, z_full, nr_top);
+    return CRYO_OK;
+}
+
 cryo_status cryo_plan_set_turn_on(cryo_plan *p, int32_t on) {
     if (!p) return fail(CRYO_ERR_ARG, "null plan");
     if (!on) {
@@ -554,6 +620,7 @@ cryo_status cryo_plan_set_turn_on(cryo_plan *p, int32_t on) {
     st = cryo_plan_set_shape(s, p->rpl, p->wpl, p->lpw);
     if (st == CRYO_OK && p->poly)
         st = cryo_plan_set_poly_laws(s, p->poly_a.data(), p->poly_b.data(), p->joule_tref);
+    if (st == CRYO_OK && p->stepped) st = cryo_plan_set_stepped(s, p->z_full, p->nr_top);
     if (st != CRYO_OK) {
         cryo_plan_destroy(s);
         return st;

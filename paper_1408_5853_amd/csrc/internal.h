@@ -171,6 +171,14 @@ struct cryo_plan {
     bool poly = false;
     std::vector<double> poly_a, poly_b;   // [L][4], [L][5] as given
     double joule_tref = 0.0;
+    // stepped domain (eq. (9)): lines above z_full span nodes 0..nr_top-1
+    // (the terminal); its lines' tables in the stepping kernel's form
+    bool stepped = false;
+    int z_full = 0, nr_top = 0;
+    std::vector<double> tfgw, tfge;
+    std::vector<uint32_t> tfinfo;
+    void *d_rows2 = nullptr;          // [2][np]: tfgw, tfge
+    uint32_t *d_info2 = nullptr;      // [np]: tfinfo
 };
 
 namespace cryo {

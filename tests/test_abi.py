@@ -149,3 +149,28 @@ def test_polynomial_laws_host_checks():
                          ctypes.c_void_p(256), 1 << 40, ctypes.byref(J), g.ctypes.data_as(dp),
                          None, None)
     assert st == 6 and "polynomial" in P.lib().cryo_last_error().decode()
+
+
+def test_stepped_domain_host_checks():
+    c = cellgen.with_nz(cellgen.small_cell(0), 10)
+    P.Plan(dict(c, stepped=dict(z_full=4, nr_top=20)))
+    P.Plan(dict(c, stepped=dict(z_full=4, nr_top=20)), "f32")
+    for bad in (dict(z_full=0, nr_top=20), dict(z_full=9, nr_top=20),
+                dict(z_full=4, nr_top=2), dict(z_full=4, nr_top=c["nr"] + 1)):
+        with pytest.raises(P.CryoError) as e:
+            P.Plan(dict(c, stepped=bad))
+        assert e.value.status == 1
+    pc = cellgen.poly_variant(c, 0)
+    with pytest.raises(P.CryoError) as e:
+        P.Plan(dict(pc, stepped=dict(z_full=4, nr_top=20)))
+    assert e.value.status == 6
+    plan = P.Plan(dict(c, stepped=dict(z_full=4, nr_top=20), turn_on=True))
+    L = P.lib()
+    tgt = np.zeros(4)
+    J, g = ctypes.c_double(), np.zeros(2 + 2 * len(c["layers"]))
+    dp = ctypes.POINTER(ctypes.c_double)
+    plan.set_turn_on(False)
+    st = L.cryo_gradient(plan._h, ctypes.c_void_p(256), 4, tgt.ctypes.data_as(dp), 0,
+                         ctypes.c_void_p(256), 1 << 40, ctypes.byref(J), g.ctypes.data_as(dp),
+                         None, None)
+    assert st == 6 and "stepped" in P.lib().cryo_last_error().decode()
