@@ -221,6 +221,23 @@ def poly_extra(P, steps, stream):
             "hbm_frac": round(r * BYTES_PER_CELL_STEP / HBM_PEAK_GBS, 4)}
 
 
+def stepped_extra(P, steps, stream):
+    """The stepped domain of eq. (9) on the device cell: a layered section
+    over the lower 80 % of the axis, a terminal of the inner 256 radial nodes
+    above it."""
+    import cellgen
+    c = cellgen.device_cell(0)
+    zf, nt = int(0.8 * (c["nz"] - 1)), 256
+    c["stepped"] = dict(z_full=zf, nr_top=nt)
+    secs, plan = rate(P.Plan, c, "f64", steps, 200, stream)
+    nodes = c["nr"] * c["nz"]
+    inside = c["nr"] * (zf + 1) + nt * (c["nz"] - 1 - zf)
+    return {"workload": "device cell 1024x4096, FP64, terminal of 256 radial nodes above "
+                        "line %d" % zf, "steps": steps, "kernel_shape": list(plan.shape()),
+            "grid_gcell_steps_s": round(nodes * steps / secs / 1e9, 2),
+            "domain_gcell_steps_s": round(inside * steps / secs / 1e9, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -316,6 +333,8 @@ def main():
         out["extra"]["turn_on"] = turn_on_extra(P, 1000, stream)
         log("bench: polynomial laws")
         out["extra"]["poly_laws"] = poly_extra(P, 5000, stream)
+        log("bench: stepped domain")
+        out["extra"]["stepped_domain"] = stepped_extra(P, 5000, stream)
         log("bench: design loop")
         out["extra"]["design_loop"] = design_extra(P, 500, 2, stream)
     if not args.no_cpu:
