@@ -200,9 +200,9 @@ cryo_status cryo_forward(const cryo_plan *plan, void *T, int64_t k0,
 cryo_status cryo_plan_set_stepped(cryo_plan *plan, int32_t z_full, int32_t nr_top);
 
 /* Polynomial material laws of eqs. (23) and (24) in place of the power laws,
- * and optionally the Joule source of eqs. (2) and (25).  FP64 plans only
- * (CRYO_ERR_UNSUPPORTED otherwise); must precede the plan's first device
- * call.  `a` holds 4 coefficients per layer (inner to outer):
+ * and optionally the Joule source of eqs. (2) and (25).  FP64 and FP32
+ * plans (FP32 evaluates the laws in float); must precede the plan's first
+ * device call.  `a` holds 4 coefficients per layer (inner to outer):
  * c_m(T) = sum_{k=0..3} a[4m+k] T^k [J/(kg K)]; `b` holds 5 per layer:
  * lambda_m(T) = k_scale_m sum_{k=0..4} b[5m+k] T^k [W/(m K)]; rho and
  * k_scale come from the layers' cryo_material, whose power-law fields are

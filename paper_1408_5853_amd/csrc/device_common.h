@@ -93,7 +93,10 @@ struct LawLds<double> {
 // rule, from POLY_BLK doubles per law id staged in LDS in place of the power
 // tables (c_0 .. c_4, one pad).  Interface rows need a quotient of two laws,
 // which callers form.
-struct LawPoly {
+template <typename R>
+struct LawPoly;
+template <>
+struct LawPoly<double> {
     const double *c;
     static __device__ inline bool in_range(double x) { return LawLds<double>::in_range(x); }
     __device__ inline double lawc(int id, double x) const {
@@ -104,6 +107,18 @@ struct LawPoly {
     }
     // the law at the mean of two values given their sum
     __device__ inline double lawm(int id, double s) const { return lawc(id, 0.5 * s); }
+};
+// FP32 pairs: the same coefficients rounded to float, Horner's rule in float
+template <>
+struct LawPoly<float> {
+    const float *c;
+    __device__ inline float lawc(int id, float x) const {
+        const float2 k01 = *(const float2 *)(c + POLY_BLK * id);
+        const float2 k23 = *(const float2 *)(c + POLY_BLK * id + 2);
+        const float k4 = c[POLY_BLK * id + 4];
+        return fmaf(fmaf(fmaf(fmaf(k4, x, k23.y), x, k23.x), x, k01.y), x, k01.x);
+    }
+    __device__ inline float lawm(int id, float s) const { return lawc(id, 0.5f * s); }
 };
 
 // FP32: 2^(e log2 s + lk); the stepping kernel's tables hold lk = log2 K - e,
@@ -383,8 +398,8 @@ __host__ __device__ inline size_t law_lds_bytes(int L) {
     const int nlaw = 3 * L + 2;
     if constexpr (sizeof(R) == 8)
         return sizeof(double) * pow_blob_doubles(L);
-    else
-        return sizeof(float) * 4 * nlaw;
+    else    // room for POLY_BLK floats per law id (polynomial laws)
+        return sizeof(float) * POLY_BLK * nlaw;
 }
 // The stepping kernel also keeps a two-slot ring of line buffers per wave
 // (the lines after the current one, loaded straight into LDS): a slot is
@@ -453,6 +468,17 @@ __device__ inline LawLds<R> stage_laws(const StepArgs<R> &a, unsigned char *smem
     }
     __syncthreads();
     return v;
+}
+
+// Polynomial laws: the stepping kernel's coefficient blob (POLY_BLK doubles
+// per law id) staged in LDS in the field's type; all threads call it.
+template <typename R>
+__device__ inline LawPoly<R> stage_poly(const StepArgs<R> &a, unsigned char *smem) {
+    const int n = POLY_BLK * (3 * a.laws.L + 2);
+    R *d = (R *)smem;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) d[i] = (R)a.pow_blob[i];
+    __syncthreads();
+    return LawPoly<R>{d};
 }
 
 }  // namespace cryo

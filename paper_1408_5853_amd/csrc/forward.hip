@@ -36,12 +36,12 @@ namespace cryo {
 // so a capacity row evaluates two conductivities per line (east r-face, the
 // face towards the next line) instead of three.
 // CUBE: every capacity law has exponent 3 (c(T) by multiplication).
-// POLY (FP64 only): polynomial laws (eqs. (23), (24)), interface rows as the
-// quotient of two laws, and the optional Joule source (eq. (25)).
+// POLY: polynomial laws (eqs. (23), (24)), interface rows as the quotient
+// of two laws, and the optional Joule source (eq. (25)).
 template <typename R, bool POLY>
-__device__ inline auto law_of(const LawLds<R> &t) {
-    if constexpr (POLY) return LawPoly{t.blk};
-    else return t;
+__device__ inline auto stage_law_of(const StepArgs<R> &a, unsigned char *smem) {
+    if constexpr (POLY) return stage_poly<R>(a, smem);
+    else return stage_laws<R>(a, smem);
 }
 
 // STEPPED: the stepped domain of eq. (9).  Lines above z_full use the
@@ -79,7 +79,7 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
             sinf2[i] = a.info2[i];
         }
     }
-    const auto law = law_of<R, POLY>(stage_laws<R>(a, smem));   // ends with a barrier
+    const auto law = stage_law_of<R, POLY>(a, smem);   // ends with a barrier
     const int t = threadIdx.x;
     // the wave index is uniform: line indices and bases live in scalar registers
     const int lane = t & (WAVE - 1), wv = __builtin_amdgcn_readfirstlane(t / WAVE);
@@ -643,11 +643,10 @@ static cryo_status step_t(const cryo_plan *p, const void *Tin, void *Tout, doubl
             else hipLaunchKernelGGL((k_step<R, RP, GW, false, false, true>), g, b, lds, s, a); \
             break; \
         } \
-        if constexpr (sizeof(R) == 8) \
-            if (p->poly) { \
-                hipLaunchKernelGGL((k_step<R, RP, GW, false, true>), g, b, lds, s, a); \
-                break; \
-            } \
+        if (p->poly) { \
+            hipLaunchKernelGGL((k_step<R, RP, GW, false, true>), g, b, lds, s, a); \
+            break; \
+        } \
         if (a.laws.cube) hipLaunchKernelGGL((k_step<R, RP, GW, true>), g, b, lds, s, a); \
         else hipLaunchKernelGGL((k_step<R, RP, GW, false>), g, b, lds, s, a); \
         break;

@@ -534,7 +534,6 @@ cryo_status cryo_plan_set_poly_laws(cryo_plan *p, const double *a, const double 
                                     double joule_tref) {
     if (!p || !a || !b) return fail(CRYO_ERR_ARG, "null argument");
     if (p->d_info) return fail(CRYO_ERR_ARG, "laws must be set before the plan's first run");
-    if (p->dtype != CRYO_F64) return fail(CRYO_ERR_UNSUPPORTED, "polynomial laws need an FP64 plan");
     if (p->stepped)
         return fail(CRYO_ERR_UNSUPPORTED, "polynomial laws on a stepped domain are not built");
     const int L = p->L;

@@ -125,9 +125,7 @@ def test_turn_on_model_host_checks():
 def test_polynomial_laws_host_checks():
     c = cellgen.poly_variant(cellgen.with_nz(cellgen.small_cell(0), 4), 0, joule_tref=30.0)
     plan = P.Plan(c)                                        # FP64, laws accepted
-    with pytest.raises(P.CryoError) as e:
-        P.Plan(c, "f32")
-    assert e.value.status == 6
+    P.Plan(c, "f32")                                        # and FP32
     Ls = c["layers"]
     a = [l["poly_a"] for l in Ls]
     zero_b = [[0.0] * 5 for _ in Ls]

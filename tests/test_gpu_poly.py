@@ -1,6 +1,7 @@
 """Parity of the polynomial-law path (eqs. (23), (24)) and the Joule source
 (eqs. (2), (25)) on the GPU with the FP64 CPU oracle, element by element:
-1e-10 relative on the field and the surface trace, over seeded cells with
+1e-10 relative on the field and the surface trace in FP64 (1e-4 K in FP32),
+over seeded cells with
 interfaces, ragged radial lengths from 5 to 1024 nodes (every chunk length
 the default shapes pick, the 16-row one included), a non-default launch shape
 and the turn-on model.
@@ -45,6 +46,19 @@ def test_poly_ragged_shapes_random_fields_f64(nr, nz):
     rng = np.random.default_rng(nr)
     T0 = 28.0 + rng.uniform(0, 6, size=(nz, nr))
     _check(c, 40, T0=T0, k0=3)
+
+
+@pytest.mark.parametrize("seed,joule", [(1, 30.0), (2, 0.0)])
+def test_poly_f32(seed, joule):
+    c = cellgen.poly_variant(cellgen.with_nz(cellgen.small_cell(seed, z_active=True), 12), seed,
+                             joule_tref=joule)
+    say("case poly f32 nr=%d nz=%d joule=%g" % (c["nr"], c["nz"], joule))
+    Tg, Sg = run_gpu(c, 1500, dtype="f32")
+    To, So = oracle.forward(c, nsteps=1500, surf=True)
+    e, es = np.max(np.abs(Tg - To)), np.max(np.abs(Sg - So))
+    say("  max abs err field %.3e K surface %.3e K" % (e, es))
+    assert e < 1e-4 and es < 1e-4
+    assert To.max() > 28.05
 
 
 def test_poly_non_default_shape_and_turn_on():
