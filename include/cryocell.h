@@ -195,8 +195,8 @@ cryo_status cryo_forward(const cryo_plan *plan, void *T, int64_t k0,
  * hold still writes them).  The surface output becomes the trapezoid mean of
  * T on r = r_max over z in [0, z_0] (lines 0..z_full).  1 <= z_full <= nz-2,
  * 3 <= nr_top <= nr (CRYO_ERR_ARG otherwise); must precede the plan's first
- * device call; FP64 and FP32.  Gradients refuse such a plan, and polynomial
- * laws cannot be combined with it (CRYO_ERR_UNSUPPORTED). */
+ * device call; FP64 and FP32; combines with the polynomial laws and the
+ * turn-on model.  Gradients refuse such a plan (CRYO_ERR_UNSUPPORTED). */
 cryo_status cryo_plan_set_stepped(cryo_plan *plan, int32_t z_full, int32_t nr_top);
 
 /* Polynomial material laws of eqs. (23) and (24) in place of the power laws,

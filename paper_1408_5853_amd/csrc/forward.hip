@@ -638,6 +638,10 @@ static cryo_status step_t(const cryo_plan *p, const void *Tin, void *Tout, doubl
     switch (key) {
 #define STEP_CASE(RP, GW) \
     case RP * 10 + GW: \
+        if (p->stepped && p->poly) { \
+            hipLaunchKernelGGL((k_step<R, RP, GW, false, true, true>), g, b, lds, s, a); \
+            break; \
+        } \
         if (p->stepped) { \
             if (a.laws.cube) hipLaunchKernelGGL((k_step<R, RP, GW, true, false, true>), g, b, lds, s, a); \
             else hipLaunchKernelGGL((k_step<R, RP, GW, false, false, true>), g, b, lds, s, a); \

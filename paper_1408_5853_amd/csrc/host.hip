@@ -534,8 +534,6 @@ cryo_status cryo_plan_set_poly_laws(cryo_plan *p, const double *a, const double 
                                     double joule_tref) {
     if (!p || !a || !b) return fail(CRYO_ERR_ARG, "null argument");
     if (p->d_info) return fail(CRYO_ERR_ARG, "laws must be set before the plan's first run");
-    if (p->stepped)
-        return fail(CRYO_ERR_UNSUPPORTED, "polynomial laws on a stepped domain are not built");
     const int L = p->L;
     for (int i = 0; i < 4 * L; ++i)
         if (!std::isfinite(a[i])) return fail(CRYO_ERR_ARG, "capacity coefficient not finite");
@@ -584,8 +582,6 @@ cryo_status cryo_plan_set_poly_laws(cryo_plan *p, const double *a, const double 
 cryo_status cryo_plan_set_stepped(cryo_plan *p, int32_t z_full, int32_t nr_top) {
     if (!p) return fail(CRYO_ERR_ARG, "null plan");
     if (p->d_info) return fail(CRYO_ERR_ARG, "the domain must be set before the plan's first run");
-    if (p->poly)
-        return fail(CRYO_ERR_UNSUPPORTED, "polynomial laws on a stepped domain are not built");
     if (z_full < 1 || z_full > p->nz - 2) return fail(CRYO_ERR_ARG, "z_full must be 1..nz-2");
     if (nr_top < 3 || nr_top > p->nr) return fail(CRYO_ERR_ARG, "nr_top must be 3..nr");
     p->stepped = true;

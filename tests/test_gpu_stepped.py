@@ -90,6 +90,20 @@ def test_stepped_ragged_shapes_f64(nr, nz):
     assert rel_err(Tg, To) < F64_TOL and rel_err(Sg, So) < F64_TOL
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_stepped_with_polynomial_laws(dtype):
+    c = cellgen.poly_variant(cellgen.with_nz(cellgen.small_cell(1, z_active=True), 15), 1,
+                             joule_tref=30.0)
+    c["amplitude"] *= 3
+    c["stepped"] = dict(z_full=8, nr_top=38)          # the wall on an interface node
+    Tg, Sg = _run(c, 800, dtype=dtype)
+    To, So = oracle.forward(c, nsteps=800, surf=True)
+    if dtype == "f64":
+        assert rel_err(Tg, To) < F64_TOL and rel_err(Sg, So) < F64_TOL
+    else:
+        assert np.max(np.abs(Tg - To)) < F32_TOL_K and np.max(np.abs(Sg - So)) < F32_TOL_K
+
+
 def test_stepped_with_turn_on():
     c = cellgen.with_nz(cellgen.small_cell(4, z_active=True), 12)
     dt = c["dt"]
