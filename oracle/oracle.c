@@ -220,6 +220,25 @@ double oc_turn_on_source(const ocell *c, long k, int i)
     return gate_overlap(c, lo, hi) / (hi - lo) * (1.0 - exp(-(double)i / 7.0));
 }
 
+/* its derivative with respect to the pulse width [1/s]: a pulse end inside
+ * the sub-step counts fully, one on its boundary half (as for whole steps) */
+static double turn_on_source_dwidth(const ocell *c, long k, int i)
+{
+    if (!(c->width > 0)) return 0.0;
+    double b0 = snap(c->t_on / c->dt), W = snap(c->width / c->dt);
+    double P = snap(c->period / c->dt);
+    double lo = (double)k + (double)i / 100.0, hi = (double)k + (double)(i + 1) / 100.0, d = 0.0;
+    long n = (long)floor((lo - b0 - W) / P);
+    if (n < 0) n = 0;
+    for (;; n++) {
+        double b = b0 + n * P, e = b + W;
+        if (b >= hi) break;
+        if (e > lo && e < hi) d += 1.0;
+        else if (e == lo || e == hi) d += 0.5;
+    }
+    return d / ((hi - lo) * c->dt) * (1.0 - exp(-(double)i / 7.0));
+}
+
 /* d/d(width) of the step average: 1/dt while a pulse ends inside the step,
  * half of that on each side when it ends exactly on a step boundary (the
  * mean of the one-sided derivatives, which a central difference sees) */
@@ -508,13 +527,13 @@ typedef struct {
 
 /* contributions of line j's rows; lamn rows j-1..j+1 updated; gl = grad part */
 static void adjoint_line(const adj_ctx *x, const double *T, const double *Tn,
-                         double s, double sd, int j, const double *y,
+                         double tau, double s, double sd, int j, const double *y,
                          double *lamn, double *gl)
 {
     const ocell *c = x->c;
     const geom *g = x->g;
     int nr = c->nr, L = x->L;
-    double tau = c->dt, eta = c->height / (c->nz - 1), e2 = eta * eta;
+    double eta = c->height / (c->nz - 1), e2 = eta * eta;
     const double *Tj = T + (size_t)j * nr, *Tnn = Tj + nr, *Tss = Tj - nr;
     const double *X = Tn + (size_t)j * nr;   /* new values of line j */
     double *lj = lamn + (size_t)j * nr, *ln_ = lj + nr, *ls_ = lj - nr;
@@ -578,18 +597,52 @@ static void adjoint_line(const adj_ctx *x, const double *T, const double *Tn,
     }
 }
 
+/* The launches of a run of N steps: one per step, or the 100 sub-steps of a
+ * pulse-start step under the turn-on model (eq. (22)).  Each has its time
+ * step, source factor, its width derivative, and the step whose surface is
+ * observed after it (1..N; 0 for none). */
+typedef struct { double tau, s, sd; long obs; } launch_t;
+
+static long launches(const ocell *c, long N, launch_t *out)
+{
+    long m = 0;
+    for (long k = 0; k < N; k++) {
+        if (c->turn_on && c->width > 0 && pulse_start(c, k) == 1) {
+            for (int i = 0; i < 100; i++, m++)
+                if (out) {
+                    out[m].tau = c->dt / 100.0;
+                    out[m].s = oc_turn_on_source(c, k, i);
+                    out[m].sd = turn_on_source_dwidth(c, k, i);
+                    out[m].obs = i == 99 ? k + 1 : 0;
+                }
+        } else {
+            if (out) {
+                out[m].tau = c->dt;
+                out[m].s = oc_source_fraction(c, k);
+                out[m].sd = oc_source_fraction_dwidth(c, k);
+                out[m].obs = k + 1;
+            }
+            m++;
+        }
+    }
+    return m;
+}
+
 int oc_gradient(const ocell *c, const double *T0, long N, const double *target,
                 long ckpt, double *J, double *grad, double *surf, double *lam0,
                 int nthreads)
 {
     geom g;
-    if (check_cell(c) || N < 1 || c->turn_on || c->poly_a || c->poly_b || c->joule_tref > 0 ||
+    if (check_cell(c) || N < 1 || c->poly_a || c->poly_b || c->joule_tref > 0 ||
         c->z_full > 0 || geom_build(c, &g))
         return 1;
+    if (c->turn_on && c->width > 0 && pulse_start(c, 0) < 0) { geom_free(&g); return 1; }
     int nr = c->nr, nz = c->nz, L = c->n_layers, ng = 2 + 2 * L;
     size_t n = (size_t)nr * nz;
-    long K = ckpt > 0 ? ckpt : N;
-    long nseg = (N + K - 1) / K;
+    long M = launches(c, N, NULL);
+    launch_t *lh = malloc(sizeof(launch_t) * M);
+    long K = ckpt > 0 ? ckpt : M;
+    long nseg = (M + K - 1) / K;
     int nth = nthreads_of(nthreads);
     int rc_ = 1;
     double *ck = malloc(sizeof(double) * n * nseg);
@@ -599,38 +652,42 @@ int oc_gradient(const ocell *c, const double *T0, long N, const double *target,
     double *mu = calloc(n, sizeof(double)), *Y = calloc(n, sizeof(double));
     double *gl = calloc((size_t)nz * ng, sizeof(double));
     rows_t *scr = scratch_alloc(nth, nr);
-    if (!ck || !seg || !S || !lam_ || !lamn || !mu || !Y || !gl || !scr) goto out;
+    if (!lh || !ck || !seg || !S || !lam_ || !lamn || !mu || !Y || !gl || !scr) goto out;
+    launches(c, N, lh);
 
-    /* forward sweep with checkpoints */
+    /* forward sweep over the launches with checkpoints */
     double *Tc = seg, *Tt = seg + n;
     memcpy(Tc, T0, sizeof(double) * n);
     double Jv = 0.0;
-    for (long k = 0; k < N; k++) {
-        if (k % K == 0) memcpy(ck + n * (k / K), Tc, sizeof(double) * n);
-        step(c, &g, Tc, Tt, k, scr, nth);
+    for (long l = 0; l < M; l++) {
+        if (l % K == 0) memcpy(ck + n * (l / K), Tc, sizeof(double) * n);
+        step_tau(c, &g, Tc, Tt, lh[l].tau, lh[l].s, scr, nth);
         memcpy(Tc, Tt, sizeof(double) * n);
-        S[k + 1] = surface_mean(c, Tc);
-        if (surf) surf[k] = S[k + 1];
-        double d = S[k + 1] - target[k];
-        Jv += d * d;
+        long o = lh[l].obs;
+        if (o > 0) {
+            S[o] = surface_mean(c, Tc);
+            if (surf) surf[o - 1] = S[o];
+            double d = S[o] - target[o - 1];
+            Jv += d * d;
+        }
     }
     *J = Jv;
     for (int q = 0; q < ng; q++) grad[q] = 0.0;
 
-    /* lam^N = dJ_N / dT^N */
+    /* lam^M = dJ_N / dT^M (the last launch observes step N) */
     for (int j = 0; j < nz; j++) {
         double w = ((j == 0 || j == nz - 1) ? 0.5 : 1.0) / (nz - 1);
         lam_[(size_t)j * nr + nr - 1] = 2.0 * (S[N] - target[N - 1]) * w;
     }
     adj_ctx ax = { c, &g, L, ng };
     for (long sg = nseg - 1; sg >= 0; sg--) {
-        long a = sg * K, b = (a + K < N) ? a + K : N;
+        long a = sg * K, b = (a + K < M) ? a + K : M;
         memcpy(seg, ck + n * sg, sizeof(double) * n);
-        for (long k = a; k < b; k++)
-            step(c, &g, seg + n * (k - a), seg + n * (k - a + 1), k, scr, nth);
-        for (long k = b - 1; k >= a; k--) {
-            const double *T = seg + n * (k - a), *Tn = seg + n * (k - a + 1);
-            double s = oc_source_fraction(c, k), sd = oc_source_fraction_dwidth(c, k);
+        for (long l = a; l < b; l++)
+            step_tau(c, &g, seg + n * (l - a), seg + n * (l - a + 1), lh[l].tau, lh[l].s, scr, nth);
+        for (long l = b - 1; l >= a; l--) {
+            const double *T = seg + n * (l - a), *Tn = seg + n * (l - a + 1);
+            double tau = lh[l].tau, s = lh[l].s, sd = lh[l].sd;
             /* move the copied boundary lines' sensitivities onto their sources */
             memcpy(mu, lam_, sizeof(double) * n);
             if (c->bc_kind[2] == 0)
@@ -642,7 +699,7 @@ int oc_gradient(const ocell *c, const double *T0, long N, const double *target,
 #pragma omp parallel for num_threads(nth) schedule(static)
             for (int j = 1; j < nz - 1; j++) {
                 rows_t *w = &scr[thread_id()];
-                line_rows(c, &g, T, c->dt, s, j, w->A, w->B, w->C, w->F);
+                line_rows(c, &g, T, tau, s, j, w->A, w->B, w->C, w->F);
                 /* A^T: sub-diagonal C_{i-1}, diagonal B_i, super-diagonal A_{i+1} */
                 double *sub = w->F, *sup = w->al;
                 sub[0] = 0.0;
@@ -652,18 +709,20 @@ int oc_gradient(const ocell *c, const double *T0, long N, const double *target,
                 thomas(nr, sub, w->B, sup, mu + (size_t)j * nr, w->wa, w->wb,
                        Y + (size_t)j * nr);
             }
+            /* the state before launch l is observed when launch l-1 ends a step */
             memset(lamn, 0, sizeof(double) * n);
-            if (k >= 1)
+            long o = l >= 1 ? lh[l - 1].obs : 0;
+            if (o > 0)
                 for (int j = 0; j < nz; j++) {
                     double w = ((j == 0 || j == nz - 1) ? 0.5 : 1.0) / (nz - 1);
-                    lamn[(size_t)j * nr + nr - 1] = 2.0 * (S[k] - target[k - 1]) * w;
+                    lamn[(size_t)j * nr + nr - 1] = 2.0 * (S[o] - target[o - 1]) * w;
                 }
             memset(gl, 0, sizeof(double) * nz * ng);
             /* lines three apart touch disjoint rows of lamn */
             for (int phase = 0; phase < 3; phase++) {
 #pragma omp parallel for num_threads(nth) schedule(static)
                 for (int j = 1 + phase; j < nz - 1; j += 3)
-                    adjoint_line(&ax, T, Tn, s, sd, j, Y + (size_t)j * nr, lamn,
+                    adjoint_line(&ax, T, Tn, tau, s, sd, j, Y + (size_t)j * nr, lamn,
                                  gl + (size_t)j * ng);
             }
             for (int j = 1; j < nz - 1; j++)
@@ -674,7 +733,7 @@ int oc_gradient(const ocell *c, const double *T0, long N, const double *target,
     if (lam0) memcpy(lam0, lam_, sizeof(double) * n);
     rc_ = 0;
 out:
-    free(ck); free(seg); free(S); free(lam_); free(lamn); free(mu); free(Y);
+    free(lh); free(ck); free(seg); free(S); free(lam_); free(lamn); free(mu); free(Y);
     free(gl);
     scratch_free(scr, nth);
     geom_free(&g);

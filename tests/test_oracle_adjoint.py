@@ -144,3 +144,28 @@ def test_gradient_threads_bitwise_deterministic():
     a = oracle.gradient(c, target, nthreads=1)
     b = oracle.gradient(c, target, nthreads=4)
     assert a[0] == b[0] and np.array_equal(a[1], b[1])
+
+
+def _turn_on_cell(seed, w_steps, nsteps=24):
+    c = cellgen.tiny(seed, nr=14, nz=6, n_layers=3, nsteps=nsteps, z_active=True,
+                     dt=2e-6, amplitude=4e9, heater=2)
+    dt = c["dt"]
+    c.update(t_on=3 * dt, period=20 * dt, width=w_steps * dt, turn_on=True)
+    return c
+
+
+@pytest.mark.parametrize("seed,w_steps", [(0, 7.3), (1, 0.374)])
+def test_turn_on_gradient_matches_central_differences(seed, w_steps):
+    # the turn-on model's sub-steps inside the adjoint sweep (eq. (22)); a
+    # pulse end inside a regular step, and one inside sub-step 37 of a pulse
+    # start (the width derivative of a sub-step's source factor)
+    _fd_check(_turn_on_cell(seed, w_steps), seed, 1e-6)
+
+
+def test_turn_on_checkpointing_over_sub_steps_bitwise():
+    c = _turn_on_cell(2, 4.6, nsteps=23)
+    target = _target(c, np.random.default_rng(3))
+    J0, g0, S0 = oracle.gradient(c, target, ckpt=0)
+    for K in (1, 7, 60, 217):                 # 23 steps + 2 x 99 sub-steps = 221 launches
+        J1, g1, S1 = oracle.gradient(c, target, ckpt=K)
+        assert J1 == J0 and np.array_equal(g1, g0) and np.array_equal(S1, S0)

@@ -495,7 +495,7 @@ def test_turn_on_needs_pulse_starts_on_steps():
     with pytest.raises(ValueError):
         oracle.forward(c, nsteps=2)
     with pytest.raises(ValueError):
-        oracle.gradient(dict(c, period=1000 * c["dt"]), np.zeros(2), nsteps=2)
+        oracle.gradient(c, np.zeros(2), nsteps=2)
 
 
 def fig3_cell(mult, turn_on):
