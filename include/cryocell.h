@@ -226,9 +226,8 @@ cryo_status cryo_plan_set_poly_laws(cryo_plan *plan, const double *a, const doub
  * Requires t_on and period to be whole multiples of dt (CRYO_ERR_UNSUPPORTED
  * otherwise).  The plan builds host tables for dt/100 here (device tables at
  * its next forward call), follows later cryo_plan_set_shape calls, and frees
- * them with on = 0 or cryo_plan_destroy.  cryo_gradient and
- * cryo_gradient_many reject a plan with the model on (CRYO_ERR_UNSUPPORTED);
- * batches do not offer it. */
+ * them with on = 0 or cryo_plan_destroy.  Gradients include the sub-steps
+ * in their sweep (see cryo_gradient); batches do not offer the model. */
 cryo_status cryo_plan_set_turn_on(cryo_plan *plan, int32_t on);
 
 /* After the stream has finished a cryo_forward that used `ws`: returns
@@ -256,10 +255,15 @@ cryo_status cryo_autotune(const cryo_problem *prob, cryo_dtype dtype, int32_t st
  * from T0 (steps 0..N-1): transposed line solves, the local stencil of the
  * lagged coefficients, the copied z-boundary lines, the radii that move with
  * the thicknesses, and the pulse-edge steps (a pulse end on a step boundary
- * takes the mean of the two one-sided derivatives).  States are checkpointed
- * every ckpt steps (0: ceil(sqrt(N))) and each segment is recomputed.
+ * takes the mean of the two one-sided derivatives).  With the turn-on model
+ * (cryo_plan_set_turn_on) the sweep runs over kernel steps, the 100
+ * sub-steps of each pulse-start step included, whose source factors carry
+ * p^2 and a width derivative of their own; the surface is still observed
+ * once per step.  States are checkpointed every ckpt kernel steps (0: the
+ * square root of their count, rounded up) and each segment is recomputed.
  * FP64 plans with one of the gradient's shapes only (CRYO_ERR_UNSUPPORTED
- * otherwise, see cryo_plan_set_shape).  T0 is a device field; target, J, grad and surf (nullable, N
+ * otherwise, see cryo_plan_set_shape); polynomial laws and stepped domains
+ * are refused (CRYO_ERR_UNSUPPORTED).  T0 is a device field; target, J, grad and surf (nullable, N
  * values) are host arrays.  Synchronous on `stream`. */
 cryo_status cryo_gradient_workspace_bytes(const cryo_plan *plan, int64_t nsteps, int64_t ckpt,
                                           size_t *bytes);

@@ -37,18 +37,71 @@ static double source_fraction_dwidth(const Pulse &p, double dt, int64_t k) {
     return d / dt;
 }
 
+// The kernel steps (launches) of a run of N steps: one per step, or, with
+// the turn-on model (eq. (22)), the 100 sub-steps of dt/100 of each
+// pulse-start step.  Each carries its source factor, that factor's width
+// derivative [1/s], and the step whose surface it completes (1..N, 0 none).
+struct Launch {
+    bool sub;
+    double s, ds;
+    int64_t obs;
+};
+
+// d/d(width) of sub-step i's factor: the gate average's derivative over the
+// sub-step (a pulse end inside counts fully, on its boundary half) times p^2
+static double turn_on_source_dwidth(const Pulse &p, double dt, int64_t k, int i) {
+    if (!(p.W > 0)) return 0.0;
+    const double lo = (double)k + (double)i / 100.0, hi = (double)k + (double)(i + 1) / 100.0;
+    double d = 0.0;
+    int64_t n = (int64_t)floor((lo - p.b0 - p.W) / p.P);
+    if (n < 0) n = 0;
+    for (;; ++n) {
+        const double b = p.b0 + (double)n * p.P;
+        if (b >= hi) break;
+        const double e = b + p.W;
+        if (e > lo && e < hi) d += 1.0;
+        else if (e == lo || e == hi) d += 0.5;
+    }
+    return d / ((hi - lo) * dt) * (1.0 - exp(-(double)i / 7.0));
+}
+
+static std::vector<Launch> launch_list(const cryo_plan *p, int64_t N) {
+    std::vector<Launch> v;
+    v.reserve((size_t)std::max<int64_t>(N, 0));
+    for (int64_t k = 0; k < N; ++k) {
+        if (p->sub && pulse_start(p->pulse, k)) {
+            for (int i = 0; i < 100; ++i)
+                v.push_back({true, turn_on_source(p->pulse, k, i),
+                             turn_on_source_dwidth(p->pulse, p->prob.dt, k, i), i == 99 ? k + 1 : 0});
+        } else {
+            v.push_back({false, source_fraction(p->pulse, k),
+                         source_fraction_dwidth(p->pulse, p->prob.dt, k), k + 1});
+        }
+    }
+    return v;
+}
+
+static int64_t launch_count(const cryo_plan *p, int64_t N) {
+    int64_t m = N;
+    if (p->sub)
+        for (int64_t k = 0; k < N; ++k) m += pulse_start(p->pulse, k) ? 99 : 0;
+    return m;
+}
+
 struct GradLayout {
     size_t flag, fwd_buf[2], part, ck, seg, lam[2], Y[2], lpart[2], acc, accg, surf, total;
     int64_t nck, K;
 };
 
+// checkpoints every K kernel steps (sub-steps of the turn-on model count)
 static GradLayout grad_layout(const cryo_plan *p, int64_t N, int64_t ckpt) {
     GradLayout g;
     const size_t F = al256(8 * (size_t)p->nz * p->np);
-    int64_t K = ckpt > 0 ? ckpt : (int64_t)ceil(sqrt((double)std::max<int64_t>(N, 1)));
-    K = std::max<int64_t>(1, std::min<int64_t>(K, std::max<int64_t>(N, 1)));
+    const int64_t M = launch_count(p, N);
+    int64_t K = ckpt > 0 ? ckpt : (int64_t)ceil(sqrt((double)std::max<int64_t>(M, 1)));
+    K = std::max<int64_t>(1, std::min<int64_t>(K, std::max<int64_t>(M, 1)));
     g.K = K;
-    g.nck = (N + K - 1) / K;
+    g.nck = (M + K - 1) / K;
     size_t o = 0;
     g.flag = o; o += 256;
     g.fwd_buf[0] = o; o += F;
@@ -88,13 +141,13 @@ struct GradRun {
     hipStream_t s;
     std::vector<double> S, cS;
     double J;
+    std::vector<Launch> L;    // the run's kernel steps
 };
 
 static cryo_status grad_check(const cryo_plan *p, int64_t N, const double *target, int64_t ckpt,
                               const void *T0, void *ws, size_t ws_bytes) {
     if (!p || !T0 || N < 1 || !target || ckpt < 0) return fail(CRYO_ERR_ARG, "bad argument");
     if (p->dtype != CRYO_F64) return fail(CRYO_ERR_UNSUPPORTED, "the adjoint needs an FP64 plan");
-    if (p->sub) return fail(CRYO_ERR_UNSUPPORTED, "no adjoint of the turn-on model's sub-steps");
     if (p->poly) return fail(CRYO_ERR_UNSUPPORTED, "no adjoint of the polynomial laws");
     if (p->stepped) return fail(CRYO_ERR_UNSUPPORTED, "no adjoint of the stepped domain");
     const int key = p->rpl * 10 + p->wpl;
@@ -115,7 +168,9 @@ static size_t field_f64(const cryo_plan *p) { return al256(8 * (size_t)p->nz * p
 static cryo_status grad_forward(GradRun &r) {
     cryo_plan *p = r.p;
     cryo_status st = ensure_device(p);
+    if (st == CRYO_OK && p->sub) st = ensure_device(p->sub);
     if (st != CRYO_OK) return st;
+    r.L = launch_list(p, r.N);
     const GradLayout &g = r.g;
     char *w = r.w;
     hipStream_t s = r.s;
@@ -127,20 +182,25 @@ static cryo_status grad_forward(GradRun &r) {
     st = launch_to_internal(p, r.T0, w + g.fwd_buf[0], flag, s);
     if (st != CRYO_OK) return st;
     int64_t done = 0;
-    for (int64_t k = 0; k < r.N; ++k) {
-        void *cur = w + g.fwd_buf[k & 1], *nxt = w + g.fwd_buf[(k + 1) & 1];
-        if (k % g.K == 0 && hipMemcpyAsync(w + g.ck + F * (k / g.K), cur, F,
+    const int64_t M = (int64_t)r.L.size();
+    for (int64_t l = 0; l < M; ++l) {
+        const Launch &ln = r.L[l];
+        void *cur = w + g.fwd_buf[l & 1], *nxt = w + g.fwd_buf[(l + 1) & 1];
+        if (l % g.K == 0 && hipMemcpyAsync(w + g.ck + F * (l / g.K), cur, F,
                                            hipMemcpyDeviceToDevice, s) != hipSuccess)
             return fail(CRYO_ERR_DEVICE, "checkpoint copy");
-        const double X = p->pulse.amplitude * source_fraction(p->pulse, k);
-        st = launch_step(p, cur, nxt, X, part + (size_t)(k % SURF_CHUNK) * G, flag, s);
+        const double X = p->pulse.amplitude * ln.s;
+        double *pp = ln.obs > 0 ? part + (size_t)((ln.obs - 1) % SURF_CHUNK) * G : nullptr;
+        st = launch_step(ln.sub ? p->sub : p, cur, nxt, X, pp, flag, s);
         if (st != CRYO_OK) return st;
-        if ((k + 1) % SURF_CHUNK == 0 || k + 1 == r.N) {
-            st = launch_surf_reduce(p, part, (int)(k + 1 - done), surf + done, s);
+        if (ln.obs > 0 && (ln.obs % SURF_CHUNK == 0 || ln.obs == r.N)) {
+            st = launch_surf_reduce(p, part, (int)(ln.obs - done), surf + done, s);
             if (st != CRYO_OK) return st;
-            done = k + 1;
+            done = ln.obs;
         }
     }
+    // the final state sits in fwd_buf[M & 1]: the surface trace is all the
+    // backward sweep needs from it
     return CRYO_OK;
 }
 
@@ -179,13 +239,16 @@ static cryo_status grad_backward(GradRun &r) {
     if (st == CRYO_OK) st = launch_adj_init(p, lam[0], r.cS[r.N], s);
     if (st != CRYO_OK) return st;
     int cur = 0;
+    const int64_t M = (int64_t)r.L.size();
+    // the plan whose tables step launch k (the turn-on sub-steps: dt / 100)
+    auto plan_of = [&](int64_t k) { return r.L[k].sub ? p->sub : p; };
     for (int64_t sg = g.nck - 1; sg >= 0; --sg) {
-        const int64_t a = sg * g.K, b = std::min<int64_t>(r.N, a + g.K);
+        const int64_t a = sg * g.K, b = std::min<int64_t>(M, a + g.K);
         if (hipMemcpyAsync(segp(0), ckp(sg), F, hipMemcpyDeviceToDevice, s) != hipSuccess)
             return fail(CRYO_ERR_DEVICE, "checkpoint restore");
         for (int64_t k = a; k < b; ++k) {
-            const double X = p->pulse.amplitude * source_fraction(p->pulse, k);
-            st = launch_step(p, segp(k - a), segp(k - a + 1), X, nullptr, flag, s);
+            const double X = p->pulse.amplitude * r.L[k].s;
+            st = launch_step(plan_of(k), segp(k - a), segp(k - a + 1), X, nullptr, flag, s);
             if (st != CRYO_OK) return st;
         }
         // adjoint step k: pass 1 reads lam^{k+1} (lam[cur]) and writes y^k,
@@ -201,19 +264,23 @@ static cryo_status grad_backward(GradRun &r) {
             d.lam_out = lam[c ^ 1];
             d.acc = acc;
             d.accg = accg;
-            d.s = source_fraction(p->pulse, k);
-            d.ds = source_fraction_dwidth(p->pulse, p->prob.dt, k);
-            d.cS = k >= 1 ? r.cS[k] : 0.0;
+            d.s = r.L[k].s;
+            d.ds = r.L[k].ds;
+            // the state before launch k is observed when launch k-1 ends a step
+            d.cS = k >= 1 && r.L[k - 1].obs > 0 ? r.cS[r.L[k - 1].obs] : 0.0;
             d.xs = p->eta * p->eta;
             return d;
         };
-        st = launch_adj(p, 1, args(b - 1, cur), flag, s);
+        // pass 1 (the line solves, with the capacity term) runs on the tables
+        // of its own launch; pass 2 (axial faces) needs no capacity law, so
+        // the fused launch takes those of its pass 1
+        st = launch_adj(plan_of(b - 1), 1, args(b - 1, cur), flag, s);
         for (int64_t k = b - 1; k > a && st == CRYO_OK; --k) {
             const AdjArgs d2 = args(k, cur), d1 = args(k - 1, cur ^ 1);
-            st = launch_adj(p, 21, d2, flag, s, &d1);
+            st = launch_adj(plan_of(k - 1), 21, d2, flag, s, &d1);
             cur ^= 1;
         }
-        if (st == CRYO_OK) st = launch_adj(p, 2, args(a, cur), flag, s);
+        if (st == CRYO_OK) st = launch_adj(plan_of(a), 2, args(a, cur), flag, s);
         if (st != CRYO_OK) return st;
         cur ^= 1;
     }

@@ -110,16 +110,13 @@ def test_turn_on_model_host_checks():
     plan.set_shape(4, 2, 1)                 # the sub-step tables follow
     plan.set_turn_on(False)
     plan.set_turn_on(True)
-    # the adjoint of the sub-steps is not built: refused before any device use
+    # the gradient's workspace counts the sub-steps among its kernel steps
+    plain = P.Plan(c)
     L = P.lib()
-    tgt = np.zeros(4)
-    J, g = ctypes.c_double(), np.zeros(2 + 2 * len(c["layers"]))
-    dp = ctypes.POINTER(ctypes.c_double)
-    st = L.cryo_gradient(plan._h, ctypes.c_void_p(256), 4, tgt.ctypes.data_as(dp), 0,
-                         ctypes.c_void_p(256), 1 << 40, ctypes.byref(J), g.ctypes.data_as(dp),
-                         None, None)
-    assert st == 6
-    assert "turn-on" in P.lib().cryo_last_error().decode()
+    b_on, b_off = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.cryo_gradient_workspace_bytes(plan._h, 40, 1, ctypes.byref(b_on)) == 0
+    assert L.cryo_gradient_workspace_bytes(plain._h, 40, 1, ctypes.byref(b_off)) == 0
+    assert b_on.value > b_off.value
 
 
 def test_polynomial_laws_host_checks():

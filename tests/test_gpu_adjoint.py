@@ -131,3 +131,28 @@ def test_gpu_gradient_general_power_laws(shape):
     e = _norm_err(gg, go, P.params_of(c))
     say("  normalised gradient error %.3e" % e)
     assert e < 1e-8, (gg, go)
+
+
+@pytest.mark.parametrize("seed,w_steps,ckpt,shape", [(0, 7.3, 7, None), (1, 0.374, 0, (4, 2, 1)),
+                                                     (2, 4.6, 60, (8, 1, 2))])
+def test_gpu_gradient_turn_on_matches_oracle_adjoint(seed, w_steps, ckpt, shape):
+    # the turn-on model's sub-steps (eq. (22)) inside the checkpointed sweep:
+    # pulse ends inside a regular step and inside a sub-step, fused passes
+    # with one and with two lines per group, segments cut inside sub-steps
+    import paper_1408_5853_amd as P
+    c = cellgen.tiny(seed, nr=40, nz=7, n_layers=3, nsteps=30, z_active=True, dt=2e-6,
+                     amplitude=4e9, heater=2)
+    dt = c["dt"]
+    c.update(t_on=3 * dt, period=20 * dt, width=w_steps * dt, turn_on=True)
+    tgt = _target(c, 30)
+    say("case adjoint turn-on width=%g dt ckpt=%d shape=%s" % (w_steps, ckpt, shape))
+    Jo, go, So = oracle.gradient(c, tgt)
+    plan = P.Plan(c)
+    if shape:
+        plan.set_shape(*shape)
+    Jg, gg, Sg = plan.gradient(tgt, ckpt=ckpt)
+    assert Jg == pytest.approx(Jo, rel=1e-9)
+    assert np.max(np.abs(Sg - So) / So) < 1e-10
+    e = _norm_err(gg, go, P.params_of(c))
+    say("  normalised gradient error %.3e" % e)
+    assert e < 1e-8, (gg, go)
