@@ -252,6 +252,9 @@ def main():
     ap.add_argument("--gradient-only", type=int, default=0, metavar="N",
                     help="profiling aid: time only a forward and a gradient of N steps on the "
                          "adjoint cell and print that result")
+    ap.add_argument("--batch-only", type=int, default=0, metavar="N",
+                    help="profiling aid: time only the batched sweep (and the same cells one "
+                         "at a time) over N steps and print that result")
     ap.add_argument("--poly-only", type=int, default=0, metavar="N",
                     help="profiling aid: time only N steps of the polynomial-law path on the "
                          "device cell and print that result")
@@ -270,6 +273,9 @@ def main():
     if args.gradient_only:
         gradient_extra(P, 50, stream)                       # warm
         print(json.dumps({"gradient": gradient_extra(P, args.gradient_only, stream)}), flush=True)
+        return
+    if args.batch_only:
+        print(json.dumps({"batch": batch_extra(P, args.batch_only, stream)}), flush=True)
         return
     if args.poly_only:
         print(json.dumps({"poly_laws": poly_extra(P, args.poly_only, stream)}), flush=True)

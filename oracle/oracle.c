@@ -396,6 +396,15 @@ static void z_boundaries(const ocell *c, double *T)
     else for (int i = 0; i < nr; i++) top[i] = c->bc_value[3];
 }
 
+/* weight of line j in the surface mean: trapezoid over lines 0..J (J the
+ * last line of the layered section), normalised to 1 */
+static double surface_weight(const ocell *c, int j)
+{
+    int J = c->z_full > 0 ? c->z_full : c->nz - 1;
+    if (j > J) return 0.0;
+    return ((j == 0 || j == J) ? 0.5 : 1.0) / J;
+}
+
 /* trapezoid weights along the outer surface r = r_max (lines 0..J, J the
  * last line of the layered section), normalised to 1 */
 static double surface_mean(const ocell *c, const double *T)
@@ -538,7 +547,8 @@ static void adjoint_line(const adj_ctx *x, const double *T, const double *Tn,
     const double *X = Tn + (size_t)j * nr;   /* new values of line j */
     double *lj = lamn + (size_t)j * nr, *ln_ = lj + nr, *ls_ = lj - nr;
     const double *r = g->r, *h = g->h;
-    for (int i = 1; i < nr - 1; i++) {
+    int n = line_len(c, j);
+    for (int i = 1; i < n - 1; i++) {
         double yi = y[i];
         if (yi == 0.0) continue;
         double Dw = X[i] - X[i - 1], De = X[i] - X[i + 1];
@@ -555,6 +565,8 @@ static void adjoint_line(const adj_ctx *x, const double *T, const double *Tn,
             double Tzn = 0.5 * (Tj[i] + Tnn[i]), Tzs = 0.5 * (Tj[i] + Tss[i]);
             double lzn = lam(c, m, Tzn), lzs = lam(c, m, Tzs);
             double dlzn = dlam(c, m, Tzn), dlzs = dlam(c, m, Tzs);
+            if (c->z_full > 0 && j == c->z_full && i >= c->nr_top - 1)
+                lzn = dlzn = 0.0;                                    /* the step face */
             double gn = Tnn[i] - Tj[i], gs = Tj[i] - Tss[i];
             double Lz = (lzn * gn - lzs * gs) / e2;
             double dLn = (0.5 * dlzn * gn + lzn) / e2;               /* dLz/dT_{j+1} */
@@ -634,7 +646,7 @@ int oc_gradient(const ocell *c, const double *T0, long N, const double *target,
 {
     geom g;
     if (check_cell(c) || N < 1 || c->poly_a || c->poly_b || c->joule_tref > 0 ||
-        c->z_full > 0 || geom_build(c, &g))
+        geom_build(c, &g))
         return 1;
     if (c->turn_on && c->width > 0 && pulse_start(c, 0) < 0) { geom_free(&g); return 1; }
     int nr = c->nr, nz = c->nz, L = c->n_layers, ng = 2 + 2 * L;
@@ -675,10 +687,8 @@ int oc_gradient(const ocell *c, const double *T0, long N, const double *target,
     for (int q = 0; q < ng; q++) grad[q] = 0.0;
 
     /* lam^M = dJ_N / dT^M (the last launch observes step N) */
-    for (int j = 0; j < nz; j++) {
-        double w = ((j == 0 || j == nz - 1) ? 0.5 : 1.0) / (nz - 1);
-        lam_[(size_t)j * nr + nr - 1] = 2.0 * (S[N] - target[N - 1]) * w;
-    }
+    for (int j = 0; j < nz; j++)
+        lam_[(size_t)j * nr + nr - 1] = 2.0 * (S[N] - target[N - 1]) * surface_weight(c, j);
     adj_ctx ax = { c, &g, L, ng };
     for (long sg = nseg - 1; sg >= 0; sg--) {
         long a = sg * K, b = (a + K < M) ? a + K : M;
@@ -699,24 +709,25 @@ int oc_gradient(const ocell *c, const double *T0, long N, const double *target,
 #pragma omp parallel for num_threads(nth) schedule(static)
             for (int j = 1; j < nz - 1; j++) {
                 rows_t *w = &scr[thread_id()];
+                int ln = line_len(c, j);
                 line_rows(c, &g, T, tau, s, j, w->A, w->B, w->C, w->F);
                 /* A^T: sub-diagonal C_{i-1}, diagonal B_i, super-diagonal A_{i+1} */
                 double *sub = w->F, *sup = w->al;
                 sub[0] = 0.0;
-                for (int i = 1; i < nr; i++) sub[i] = w->C[i - 1];
-                for (int i = 0; i < nr - 1; i++) sup[i] = w->A[i + 1];
-                sup[nr - 1] = 0.0;
-                thomas(nr, sub, w->B, sup, mu + (size_t)j * nr, w->wa, w->wb,
+                for (int i = 1; i < ln; i++) sub[i] = w->C[i - 1];
+                for (int i = 0; i < ln - 1; i++) sup[i] = w->A[i + 1];
+                sup[ln - 1] = 0.0;
+                thomas(ln, sub, w->B, sup, mu + (size_t)j * nr, w->wa, w->wb,
                        Y + (size_t)j * nr);
+                /* nodes outside the domain keep their values: no equation */
+                for (int i = ln; i < nr; i++) Y[(size_t)j * nr + i] = 0.0;
             }
             /* the state before launch l is observed when launch l-1 ends a step */
             memset(lamn, 0, sizeof(double) * n);
             long o = l >= 1 ? lh[l - 1].obs : 0;
             if (o > 0)
-                for (int j = 0; j < nz; j++) {
-                    double w = ((j == 0 || j == nz - 1) ? 0.5 : 1.0) / (nz - 1);
-                    lamn[(size_t)j * nr + nr - 1] = 2.0 * (S[o] - target[o - 1]) * w;
-                }
+                for (int j = 0; j < nz; j++)
+                    lamn[(size_t)j * nr + nr - 1] = 2.0 * (S[o] - target[o - 1]) * surface_weight(c, j);
             memset(gl, 0, sizeof(double) * nz * ng);
             /* lines three apart touch disjoint rows of lamn */
             for (int phase = 0; phase < 3; phase++) {

@@ -169,3 +169,16 @@ def test_turn_on_checkpointing_over_sub_steps_bitwise():
     for K in (1, 7, 60, 217):                 # 23 steps + 2 x 99 sub-steps = 221 launches
         J1, g1, S1 = oracle.gradient(c, target, ckpt=K)
         assert J1 == J0 and np.array_equal(g1, g0) and np.array_equal(S1, S0)
+
+
+@pytest.mark.parametrize("seed,nr_top", [(0, 9), (1, 6)])
+def test_stepped_gradient_matches_central_differences(seed, nr_top):
+    # the stepped domain (eq. (9)): shorter terminal lines, the closed step
+    # face, the surface mean over the layered section; a random start field
+    # so that the terminal and the step face carry heat
+    c = cellgen.tiny(20 + seed, nr=14, nz=8, n_layers=3, nsteps=24, z_active=True,
+                     dt=2e-6, amplitude=4e9, heater=2)
+    c["stepped"] = dict(z_full=4, nr_top=nr_top)
+    rng = np.random.default_rng(seed)
+    T0 = 28.0 + rng.uniform(0, 3, size=(c["nz"], c["nr"]))
+    _fd_check(c, seed, 1e-6, T0=T0)
