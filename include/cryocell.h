@@ -196,7 +196,9 @@ cryo_status cryo_forward(const cryo_plan *plan, void *T, int64_t k0,
  * T on r = r_max over z in [0, z_0] (lines 0..z_full).  1 <= z_full <= nz-2,
  * 3 <= nr_top <= nr (CRYO_ERR_ARG otherwise); must precede the plan's first
  * device call; FP64 and FP32; combines with the polynomial laws and the
- * turn-on model.  Gradients refuse such a plan (CRYO_ERR_UNSUPPORTED). */
+ * turn-on model.  Gradients follow the stepped domain (the surface mean over
+ * the layered section); a shape whose adjoint tables would not fit a
+ * workgroup's LDS is refused there (CRYO_ERR_UNSUPPORTED). */
 cryo_status cryo_plan_set_stepped(cryo_plan *plan, int32_t z_full, int32_t nr_top);
 
 /* Polynomial material laws of eqs. (23) and (24) in place of the power laws,
@@ -262,8 +264,9 @@ cryo_status cryo_autotune(const cryo_problem *prob, cryo_dtype dtype, int32_t st
  * once per step.  States are checkpointed every ckpt kernel steps (0: the
  * square root of their count, rounded up) and each segment is recomputed.
  * FP64 plans with one of the gradient's shapes only (CRYO_ERR_UNSUPPORTED
- * otherwise, see cryo_plan_set_shape); polynomial laws and stepped domains
- * are refused (CRYO_ERR_UNSUPPORTED).  T0 is a device field; target, J, grad and surf (nullable, N
+ * otherwise, see cryo_plan_set_shape); polynomial laws are refused
+ * (CRYO_ERR_UNSUPPORTED); a stepped domain (cryo_plan_set_stepped) is
+ * followed.  T0 is a device field; target, J, grad and surf (nullable, N
  * values) are host arrays.  Synchronous on `stream`. */
 cryo_status cryo_gradient_workspace_bytes(const cryo_plan *plan, int64_t nsteps, int64_t ckpt,
                                           size_t *bytes);

@@ -58,30 +58,54 @@ __device__ inline void nb_exchange(double v_last, double v_first, double &from_p
 }
 
 // Row tables and laws in LDS (dynamic shared memory); all threads call it.
+// STEPPED (eq. (9)): the terminal lines' tables too, after the row sums
+// (sgw2, sge2, sinf2; the full lines' tables otherwise).
 struct AdjLds {
     const double *sgw, *sge;
     const uint32_t *sinf;
+    const double *sgw2, *sge2;
+    const uint32_t *sinf2;
     LawLds<double> law;
 };
-__device__ inline AdjLds adj_stage(const StepArgs<double> &a, unsigned char *smem) {
+template <bool STEPPED>
+__device__ inline AdjLds adj_stage(const StepArgs<double> &a, unsigned char *smem, int rpl) {
     double *sgw = (double *)(smem + ((law_lds_bytes<double>(a.laws.L) + 15) & ~(size_t)15));
     double *sge = sgw + a.np;
     uint32_t *sinf = (uint32_t *)(sge + a.np);
+    double *sgw2 = (double *)(smem + adj_lds_bytes(a.laws.L, a.np, rpl));
+    double *sge2 = sgw2 + a.np;
+    uint32_t *sinf2 = (uint32_t *)(sge2 + a.np);
     for (int i = threadIdx.x; i < a.np; i += blockDim.x) {
         sgw[i] = a.gw[i];
         sge[i] = a.ge[i];
         sinf[i] = a.info[i];
+        if constexpr (STEPPED) {
+            sgw2[i] = a.gw2[i];
+            sge2[i] = a.ge2[i];
+            sinf2[i] = a.info2[i];
+        }
     }
     AdjLds t;
     t.sgw = sgw;
     t.sge = sge;
     t.sinf = sinf;
+    t.sgw2 = STEPPED ? sgw2 : sgw;
+    t.sge2 = STEPPED ? sge2 : sge;
+    t.sinf2 = STEPPED ? sinf2 : sinf;
     t.law = stage_laws<double>(a, smem);      // ends with a barrier
     return t;
 }
 
+// weight of interior line j's outer node in the surface mean (lines
+// 0..z_full of a stepped domain)
+template <bool STEPPED>
+__device__ inline double surf_weight(const StepArgs<double> &a, int j) {
+    if constexpr (STEPPED) return j < a.z_full ? a.wz_mid : j == a.z_full ? a.wz_end : 0.0;
+    else return a.wz_mid;
+}
+
 // Pass 1 of one step over this workgroup's line groups (tables staged).
-template <int RPL, int G, bool CUBE>
+template <int RPL, int G, bool CUBE, bool STEPPED = false>
 // (keep: lam^{n+1} of the group's single line comes in lamR, not from memory)
 __device__ inline void adj1_body(const StepArgs<double> &a, const AdjArgs &d,
                                  unsigned char *smem, const AdjLds &tb,
@@ -89,7 +113,7 @@ __device__ inline void adj1_body(const StepArgs<double> &a, const AdjArgs &d,
     constexpr int NL = WAVE * G, NG = ADJ_WAVES / G;
     __shared__ double xchg[NG][9 * G];
     __shared__ double xb[NG][2 * G];
-    const double *sgw = tb.sgw, *sge = tb.sge;
+    const double *sgw = tb.sgw, *sge = tb.sge;       // this line's tables
     const uint32_t *sinf = tb.sinf;
     const LawLds<double> &law = tb.law;
     const int lane = threadIdx.x & (WAVE - 1), wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -111,6 +135,12 @@ __device__ inline void adj1_body(const StepArgs<double> &a, const AdjArgs &d,
         const bool active = jr < j1;
         const int j = min(jr, a.nz - 2);
         const size_t base = (size_t)j * LS;
+        if constexpr (STEPPED) {                      // the terminal's lines
+            const bool up = j > a.z_full;
+            sgw = up ? tb.sgw2 : tb.sgw;
+            sge = up ? tb.sge2 : tb.sge;
+            sinf = up ? tb.sinf2 : tb.sinf;
+        }
         double T[RPL], MU[RPL], fw[RPL], fe[RPL];
         // the line's loads up front (latency overlaps the row work)
 #pragma unroll
@@ -265,7 +295,7 @@ __device__ inline void adj1_body(const StepArgs<double> &a, const AdjArgs &d,
                 const double ow = cap ? y[r] * fwT * Dw : 0.0;       // into row r-1
                 const double oe = cap ? y[r] * feT * De : 0.0;       // into row r+1
                 double lp = -(y[r] * self + oe_prev);
-                if (lg == a.surf_lane && r == a.surf_reg) lp += d.cS * a.wz_mid;
+                if (lg == a.surf_lane && r == a.surf_reg) lp += d.cS * surf_weight<STEPPED>(a, j);
                 if (r > 0) d.lpart[base + q - NL] = lp_prev - ow;
                 d.Y[base + q] = y[r];
                 oe_prev = oe;
@@ -310,25 +340,25 @@ __device__ inline void adj1_body(const StepArgs<double> &a, const AdjArgs &d,
     }
 }
 
-template <int RPL, int G, bool CUBE>
+template <int RPL, int G, bool CUBE, bool STEPPED>
 __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj1(StepArgs<double> a, AdjArgs d) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const AdjLds tb = adj_stage(a, smem);
+    const AdjLds tb = adj_stage<STEPPED>(a, smem, RPL);
     const double none[RPL] = {};
-    adj1_body<RPL, G, CUBE>(a, d, smem, tb, none, false);
+    adj1_body<RPL, G, CUBE, STEPPED>(a, d, smem, tb, none, false);
 }
 
 // Pass 2: axial faces.  Each interior line j adds the terms of its two
 // axial faces (capacity rows), and the lines next to the z-boundaries write
 // the boundary lines' lam^n.
-template <int RPL, int G>
+template <int RPL, int G, bool STEPPED = false>
 // (keep: lam^n of the group's single line goes to lamR, not to memory; the
 // boundary lines' lam^n is always written)
 __device__ inline void adj2_body(const StepArgs<double> &a, const AdjArgs &d,
                                  unsigned char *smem, const AdjLds &tb, double (&lamR)[RPL],
                                  bool keep) {
     constexpr int NL = WAVE * G, NG = ADJ_WAVES / G;
-    const uint32_t *sinf = tb.sinf;
+    const uint32_t *sinf = tb.sinf;                      // this line's table
     const LawLds<double> &law = tb.law;
     const int lane = threadIdx.x & (WAVE - 1), wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int grp = wv / G, wig = wv % G, lg = wig * WAVE + lane;
@@ -343,6 +373,7 @@ __device__ inline void adj2_body(const StepArgs<double> &a, const AdjArgs &d,
     // groups past the last line read line nz-2 and do no line
     const int jb = min(j0, a.nz - 2);
     const size_t bb = (size_t)jb * LS;
+    if constexpr (STEPPED) sinf = jb > a.z_full ? tb.sinf2 : tb.sinf;
     // start-up: the south faces (jb-1, jb) of the group's first line, and for
     // line 1 the lower boundary line's lam^n (that face's dF/dT_0)
 #pragma unroll
@@ -372,6 +403,7 @@ __device__ inline void adj2_body(const StepArgs<double> &a, const AdjArgs &d,
     }
     for (int j = j0; j < j1; ++j) {
         const size_t base = (size_t)j * LS;
+        if constexpr (STEPPED) sinf = j > a.z_full ? tb.sinf2 : tb.sinf;
         // the line above and this line's partial lam^n, up front
         double Tn[RPL], Yn[RPL], LP[RPL];
 #pragma unroll
@@ -385,7 +417,11 @@ __device__ inline void adj2_body(const StepArgs<double> &a, const AdjArgs &d,
         for (int r = 0; r < RPL; ++r) {
             const int q = r * NL + lg;
             const uint32_t inf_r = sinf[q];
-            const bool cap = (inf_r & 7) == K_CAP;
+            bool cap = (inf_r & 7) == K_CAP;
+            // the step face (eq. (9)): closed where the terminal's row above
+            // is not a capacity row
+            if constexpr (STEPPED)
+                if (j == a.z_full && (tb.sinf2[q] & 7) != K_CAP) cap = false;
             // non-capacity rows take the zero law: every face term vanishes
             const int lz = cap ? (inf_r >> 12) & 63 : law_zero(a.laws.L);
             const double t = Tc[r], tn = Tn[r];
@@ -404,7 +440,8 @@ __device__ inline void adj2_body(const StepArgs<double> &a, const AdjArgs &d,
             if (j == a.nz - 2) {
                 // the upper boundary line: its face with line nz-2
                 double le_ = cdF[r] * (y - 0.0);                    // d F_N / d T_{nz-1}
-                if (lg == a.surf_lane && r == a.surf_reg) le_ += d.cS * a.wz_end;
+                // (on a stepped domain the top line is not on the surface)
+                if (!STEPPED && lg == a.surf_lane && r == a.surf_reg) le_ += d.cS * a.wz_end;
                 d.lam_out[(size_t)(a.nz - 1) * LS + q] = le_;
             }
             if (keep) lamR[r] = lam;
@@ -434,12 +471,12 @@ __device__ inline void adj2_body(const StepArgs<double> &a, const AdjArgs &d,
     }
 }
 
-template <int RPL, int G>
+template <int RPL, int G, bool STEPPED>
 __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj2(StepArgs<double> a, AdjArgs d) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const AdjLds tb = adj_stage(a, smem);
+    const AdjLds tb = adj_stage<STEPPED>(a, smem, RPL);
     double lamR[RPL];
-    adj2_body<RPL, G>(a, d, smem, tb, lamR, false);
+    adj2_body<RPL, G, STEPPED>(a, d, smem, tb, lamR, false);
 }
 
 // Pass 2 of step k and pass 1 of step k - 1 in one launch: each line group
@@ -448,28 +485,29 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj2(StepArgs<double> a, Ad
 // step's line solves on it.  Every value that
 // crosses line groups (y^k of the neighbouring lines) is read in the first
 // phase and written only to the other buffer in the second.
-template <int RPL, int G, bool CUBE, bool KEEP>
+template <int RPL, int G, bool CUBE, bool KEEP, bool STEPPED>
 __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj21(StepArgs<double> a, AdjArgs d2,
                                                            AdjArgs d1) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const AdjLds tb = adj_stage(a, smem);
+    const AdjLds tb = adj_stage<STEPPED>(a, smem, RPL);
     // one line per group: lam^k stays in registers between the phases (no
     // other group reads it)
     double lamR[RPL] = {};
-    adj2_body<RPL, G>(a, d2, smem, tb, lamR, KEEP);
+    adj2_body<RPL, G, STEPPED>(a, d2, smem, tb, lamR, KEEP);
     __syncthreads();           // the LDS row sums area passes to the next phase
-    adj1_body<RPL, G, CUBE>(a, d1, smem, tb, lamR, KEEP);
+    adj1_body<RPL, G, CUBE, STEPPED>(a, d1, smem, tb, lamR, KEEP);
 }
 
 // lam^N = dJ_N / dT^N: the surface weights on the outer row
 __global__ void k_adj_init(double *lam, int nz, int np, int q_surf, double cS, double wz_end,
-                           double wz_mid) {
+                           double wz_mid, int J) {
     size_t n = (size_t)nz * np;
     for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < n;
          idx += (size_t)gridDim.x * blockDim.x) {
         const int j = (int)(idx / np), q = (int)(idx % np);
         double v = 0.0;
-        if (q == q_surf) v = cS * ((j == 0 || j == nz - 1) ? wz_end : wz_mid);
+        // the surface mean's lines 0..J (nz - 1, or a stepped domain's z_full)
+        if (q == q_surf && j <= J) v = cS * ((j == 0 || j == J) ? wz_end : wz_mid);
         lam[idx] = v;
     }
 }
@@ -495,7 +533,31 @@ int adj_grid(const cryo_plan *p) {
 // row-sum slots: one per workgroup of the adjoint passes
 int adj_slots(const cryo_plan *p) { return adj_grid(p); }
 
+// dynamic LDS of the adjoint passes (a stepped domain adds the terminal's
+// tables)
+size_t adj_lds(const cryo_plan *p) {
+    return adj_lds_bytes(p->L, p->np, p->rpl) + (p->stepped ? step_tables_bytes<double>(p->np) : 0);
+}
+
 StepArgs<double> step_args_f64(const cryo_plan *p, int *flag);
+
+// one pass (1, 2, or 21: pass 2 of step k with d, pass 1 of step k-1 with
+// d1) of one adjoint shape
+template <int R_, int G_, bool ST>
+static void adj_launch(int pass, bool cube, bool keep, dim3 g, dim3 b, size_t lds, hipStream_t s,
+                       const StepArgs<double> &a, const AdjArgs &d, const AdjArgs *d1) {
+    if (pass == 2) hipLaunchKernelGGL((k_adj2<R_, G_, ST>), g, b, lds, s, a, d);
+    else if (pass == 21 && cube && keep)
+        hipLaunchKernelGGL((k_adj21<R_, G_, true, true, ST>), g, b, lds, s, a, d, *d1);
+    else if (pass == 21 && cube)
+        hipLaunchKernelGGL((k_adj21<R_, G_, true, false, ST>), g, b, lds, s, a, d, *d1);
+    else if (pass == 21 && keep)
+        hipLaunchKernelGGL((k_adj21<R_, G_, false, true, ST>), g, b, lds, s, a, d, *d1);
+    else if (pass == 21)
+        hipLaunchKernelGGL((k_adj21<R_, G_, false, false, ST>), g, b, lds, s, a, d, *d1);
+    else if (cube) hipLaunchKernelGGL((k_adj1<R_, G_, true, ST>), g, b, lds, s, a, d);
+    else hipLaunchKernelGGL((k_adj1<R_, G_, false, ST>), g, b, lds, s, a, d);
+}
 
 // pass 1, pass 2, or (pass 21) pass 2 of step k with d and pass 1 of step k-1
 // with d1
@@ -503,25 +565,14 @@ cryo_status launch_adj(const cryo_plan *p, int pass, const AdjArgs &d, int *flag
                        const AdjArgs *d1) {
     StepArgs<double> a = step_args_f64(p, flag);
     dim3 g(adj_grid(p)), b(ADJ_WAVES * WAVE);
-    const size_t lds = adj_lds_bytes(p->L, p->np, p->rpl);
+    const size_t lds = adj_lds(p);
     const int key = p->rpl * 10 + p->wpl;
     if (pass == 21 && !d1) return fail(CRYO_ERR_ARG, "fused adjoint passes need two steps");
-#define ADJ_CASE(R_, G_)                                                                  \
-    case R_ * 10 + G_:                                                                    \
-        if (pass == 2)                                                                    \
-            hipLaunchKernelGGL((k_adj2<R_, G_>), g, b, lds, s, a, d);                     \
-        else if (pass == 21 && a.laws.cube && a.lpw == 1)                                 \
-            hipLaunchKernelGGL((k_adj21<R_, G_, true, true>), g, b, lds, s, a, d, *d1);   \
-        else if (pass == 21 && a.laws.cube)                                               \
-            hipLaunchKernelGGL((k_adj21<R_, G_, true, false>), g, b, lds, s, a, d, *d1);  \
-        else if (pass == 21 && a.lpw == 1)                                                \
-            hipLaunchKernelGGL((k_adj21<R_, G_, false, true>), g, b, lds, s, a, d, *d1);  \
-        else if (pass == 21)                                                              \
-            hipLaunchKernelGGL((k_adj21<R_, G_, false, false>), g, b, lds, s, a, d, *d1); \
-        else if (a.laws.cube)                                                             \
-            hipLaunchKernelGGL((k_adj1<R_, G_, true>), g, b, lds, s, a, d);               \
-        else                                                                              \
-            hipLaunchKernelGGL((k_adj1<R_, G_, false>), g, b, lds, s, a, d);              \
+    const bool cube = a.laws.cube, keep = a.lpw == 1;
+#define ADJ_CASE(R_, G_)                                                                    \
+    case R_ * 10 + G_:                                                                      \
+        if (p->stepped) adj_launch<R_, G_, true>(pass, cube, keep, g, b, lds, s, a, d, d1);   \
+        else adj_launch<R_, G_, false>(pass, cube, keep, g, b, lds, s, a, d, d1);             \
         break;
     switch (key) {
         ADJ_CASE(2, 1)
@@ -542,8 +593,9 @@ cryo_status launch_adj_init(const cryo_plan *p, double *lam, double cS, hipStrea
     const int q = p->surf_reg * (WAVE * p->wpl) + p->surf_lane;
     size_t n = (size_t)p->nz * p->np;
     int blocks = (int)std::min<size_t>((n + 255) / 256, 65536);
+    const int J = p->stepped ? p->z_full : p->nz - 1;
     hipLaunchKernelGGL(k_adj_init, dim3(blocks), dim3(256), 0, s, lam, p->nz, p->np, q, cS,
-                       0.5 / (p->nz - 1), 1.0 / (p->nz - 1));
+                       0.5 / J, 1.0 / J, J);
     return check_launch("adjoint init");
 }
 

@@ -17,6 +17,7 @@ cryo_status launch_adj(const cryo_plan *p, int pass, const AdjArgs &d, int *flag
 cryo_status launch_adj_init(const cryo_plan *p, double *lam, double cS, hipStream_t s);
 cryo_status launch_zero(double *ptr, size_t n, hipStream_t s);
 int adj_slots(const cryo_plan *p);
+size_t adj_lds(const cryo_plan *p);
 
 static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
@@ -149,7 +150,9 @@ static cryo_status grad_check(const cryo_plan *p, int64_t N, const double *targe
     if (!p || !T0 || N < 1 || !target || ckpt < 0) return fail(CRYO_ERR_ARG, "bad argument");
     if (p->dtype != CRYO_F64) return fail(CRYO_ERR_UNSUPPORTED, "the adjoint needs an FP64 plan");
     if (p->poly) return fail(CRYO_ERR_UNSUPPORTED, "no adjoint of the polynomial laws");
-    if (p->stepped) return fail(CRYO_ERR_UNSUPPORTED, "no adjoint of the stepped domain");
+    if (adj_lds(p) > MAX_STEP_LDS)
+        return fail(CRYO_ERR_UNSUPPORTED, "the adjoint's tables exceed a workgroup's LDS for this "
+                                          "shape; choose fewer rows per line");
     const int key = p->rpl * 10 + p->wpl;
     if (!(key == 21 || key == 41 || key == 81 || key == 42 || key == 82 || key == 44 || key == 84))
         return fail(CRYO_ERR_UNSUPPORTED, "the adjoint kernels take 2, 4 or 8 rows per lane; set "

@@ -162,8 +162,12 @@ def test_stepped_domain_host_checks():
     tgt = np.zeros(4)
     J, g = ctypes.c_double(), np.zeros(2 + 2 * len(c["layers"]))
     dp = ctypes.POINTER(ctypes.c_double)
-    plan.set_turn_on(False)
-    st = L.cryo_gradient(plan._h, ctypes.c_void_p(256), 4, tgt.ctypes.data_as(dp), 0,
+    # the adjoint's extra tables must fit a workgroup's LDS: refused up front
+    big = cellgen.tiny(3, nr=1500, nz=6, n_layers=5, nsteps=10, z_active=True, dt=2e-7,
+                       amplitude=5e9)
+    bp = P.Plan(dict(big, stepped=dict(z_full=3, nr_top=500)))
+    assert bp.shape()[:2] == (8, 4)
+    st = L.cryo_gradient(bp._h, ctypes.c_void_p(256), 4, tgt.ctypes.data_as(dp), 0,
                          ctypes.c_void_p(256), 1 << 40, ctypes.byref(J), g.ctypes.data_as(dp),
                          None, None)
-    assert st == 6 and "stepped" in P.lib().cryo_last_error().decode()
+    assert st == 6 and "LDS" in P.lib().cryo_last_error().decode()

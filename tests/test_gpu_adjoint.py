@@ -156,3 +156,37 @@ def test_gpu_gradient_turn_on_matches_oracle_adjoint(seed, w_steps, ckpt, shape)
     e = _norm_err(gg, go, P.params_of(c))
     say("  normalised gradient error %.3e" % e)
     assert e < 1e-8, (gg, go)
+
+
+@pytest.mark.parametrize("seed,nr,nz,z_full,nr_top,shape,ckpt,turn_on", [
+    (0, 14, 8, 4, 9, None, 7, False), (1, 14, 8, 4, 6, (4, 2, 1), 0, False),
+    (2, 40, 9, 5, 30, (8, 1, 2), 5, False), (3, 40, 9, 3, 22, None, 0, True)])
+def test_gpu_gradient_stepped_matches_oracle_adjoint(seed, nr, nz, z_full, nr_top, shape, ckpt,
+                                                     turn_on):
+    # the stepped domain (eq. (9)) in the adjoint passes: the terminal's
+    # tables, the closed step face, the surface over the layered section;
+    # one and two waves per line, one and two lines per group, with the
+    # turn-on model's sub-steps; random start fields
+    import paper_1408_5853_amd as P
+    c = cellgen.tiny(20 + seed, nr=nr, nz=nz, n_layers=3, nsteps=24, z_active=True, dt=2e-6,
+                     amplitude=4e9, heater=2)
+    c["stepped"] = dict(z_full=z_full, nr_top=nr_top)
+    if turn_on:
+        dt = c["dt"]
+        c.update(t_on=3 * dt, period=20 * dt, width=4.6 * dt, turn_on=True)
+    rng = np.random.default_rng(seed)
+    T0 = 28.0 + rng.uniform(0, 3, size=(nz, nr))
+    _, S = oracle.forward(c, T0, nsteps=24, surf=True)
+    tgt = S + rng.normal(scale=0.05, size=24) + 0.02
+    say("case adjoint stepped nr=%d nz=%d z_full=%d nr_top=%d shape=%s turn_on=%s" %
+        (nr, nz, z_full, nr_top, shape, turn_on))
+    Jo, go, So = oracle.gradient(c, tgt, T0=T0)
+    plan = P.Plan(c)
+    if shape:
+        plan.set_shape(*shape)
+    Jg, gg, Sg = plan.gradient(tgt, T0=T0, ckpt=ckpt)
+    assert Jg == pytest.approx(Jo, rel=1e-9)
+    assert np.max(np.abs(Sg - So) / So) < 1e-10
+    e = _norm_err(gg, go, P.params_of(c))
+    say("  normalised gradient error %.3e" % e)
+    assert e < 1e-8, (gg, go)
