@@ -30,8 +30,15 @@ def cases():
     c2 = cellgen.with_nz(cellgen.small_cell(2), 4)
     dt = c2["dt"]
     c2.update(t_on=3 * dt, width=5 * dt, period=20 * dt, turn_on=True)
+    c3 = cellgen.poly_variant(cellgen.with_nz(cellgen.small_cell(3, z_active=True), 10), 3,
+                              joule_tref=30.0)
+    c4 = cellgen.with_nz(cellgen.small_cell(4, z_active=True), 12)
+    c4["stepped"] = dict(z_full=6, nr_top=30)
     return [
         ("small_cell0_nz4", "eqs. (8)-(20), as-written cell (z-invariant)", c0, 3000),
+        ("small_cell3_poly_joule", "eqs. (8)-(20) with the polynomial laws of eqs. (23), (24) "
+                                   "and the Joule source of eq. (25)", c3, 1500),
+        ("small_cell4_stepped", "eqs. (8)-(20) on the stepped domain of eq. (9)", c4, 1500),
         ("small_cell1_z_active_nz12", "eqs. (8)-(20) with the explicit z half (eq. (11)) active",
          c1, 3000),
         ("small_cell2_turn_on", "eqs. (8)-(20) with the turn-on model of eq. (22), "
