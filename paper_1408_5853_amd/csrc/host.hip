@@ -575,7 +575,17 @@ cryo_status cryo_plan_set_poly_laws(cryo_plan *p, const double *a, const double 
     }
     B[(size_t)POLY_BLK * law_unit(L)] = 1.0;
     build_row_tables(p);
-    if (p->sub) return cryo_plan_set_poly_laws(p->sub, a, b, joule_tref);
+    if (p->sub) {
+        // the turn-on model's sub-step tables take the same laws, or neither does
+        const cryo_status st = cryo_plan_set_poly_laws(p->sub, a, b, joule_tref);
+        if (st != CRYO_OK) {
+            p->poly = false;
+            p->flaws.cube = p->laws.cube;
+            fill_pow_blob(p->flaws, p->fpow_blob);
+            build_row_tables(p);
+            return st;
+        }
+    }
     return CRYO_OK;
 }
 
@@ -592,7 +602,15 @@ cryo_status cryo_plan_set_stepped(cryo_plan *p, int32_t z_full, int32_t nr_top) 
         return fail(CRYO_ERR_UNSUPPORTED, "the terminal's tables exceed a workgroup's LDS");
     }
     build_row_tables(p);
-    if (p->sub) return cryo_plan_set_stepped(p->sub, z_full, nr_top);
+    if (p->sub) {
+        // the turn-on model's sub-step tables take the same domain, or neither does
+        const cryo_status st = cryo_plan_set_stepped(p->sub, z_full, nr_top);
+        if (st != CRYO_OK) {
+            p->stepped = false;
+            build_row_tables(p);
+            return st;
+        }
+    }
     return CRYO_OK;
 }
 
