@@ -96,3 +96,28 @@ def test_design_adam_first_step_descends():
         assert hist[1, i] < hist[0, i]
         ratio = design_params(new[i]) / design_params(cells[i])
         assert np.all(np.abs(np.log(ratio)) <= 0.0101)   # Adam steps at most lr
+
+
+def test_gradient_many_with_turn_on_and_stepped_plans_bitwise():
+    # designs with the turn-on model's sub-steps and with a stepped domain
+    # in one call: each run keeps its own kernel-step list and tables
+    import paper_1408_5853_amd as P
+    cells = []
+    for i in range(4):
+        c = cellgen.tiny(30 + i, nr=24, nz=8, n_layers=3, nsteps=24, z_active=True, dt=2e-6,
+                         amplitude=4e9, heater=2)
+        dt = c["dt"]
+        if i % 2 == 0:
+            c.update(t_on=3 * dt, period=20 * dt, width=4.6 * dt, turn_on=True)
+        if i >= 2:
+            c["stepped"] = dict(z_full=4, nr_top=15)
+        cells.append(c)
+    tg = _targets(cells, 24)
+    say("case gradient_many, turn-on and stepped designs")
+    J, grads, surfs = P.gradient_many(cells, tg, ckpt=6, streams=2)
+    for i, c in enumerate(cells):
+        Ji, gi, Si = P.gradient(c, tg[i], ckpt=6)
+        assert J[i] == Ji and np.array_equal(grads[i], gi) and np.array_equal(surfs[i], Si)
+    Jo, go, _ = oracle.gradient(cells[3], tg[3])
+    assert J[3] == pytest.approx(Jo, rel=1e-9)
+    assert _norm_err(grads[3], go, P.params_of(cells[3])) < 1e-8
