@@ -39,7 +39,7 @@ BYTES_PER_CELL_STEP = 16          # read T, write T^ (FP64; an FP32 pair is also
 # (0.6 changed only the adjoint kernels: its k_step is the code measured on 0.5.)
 MEASURED_TRAFFIC = {("cryocell 0.5 (gfx950)", (16, 1, 2)): 84.65e6,
                     ("cryocell 0.6 (gfx950)", (16, 1, 2)): 84.65e6,
-                    ("cryocell 0.7 (gfx950)", (16, 1, 2)): 75.23e6}
+                    ("cryocell 0.7 (gfx950)", (16, 1, 2)): 75.26e6}
 
 
 def log(*a):
