@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_TFLOPS = 78.6
 BYTES_PER_CELL_STEP = 16          # read T, write T^ (FP64; an FP32 pair is also 8 B/node)
+GRAD_BYTES_PER_CELL_STEP = 64     # forward 16 + recompute 16 + adjoint 32 (FP64)
 
 # HBM bytes per step launch measured with rocprofv3 (FETCH_SIZE x 2.000 +
 # WRITE_SIZE x 1.000, factors from a 256 MiB copy; profiles/k_step_f64_1024x4096.md),
@@ -118,6 +119,9 @@ def batch_extra(P, steps, stream):
     return {"workload": "design sweep: 256 cells, nr 128-512, nz 256-2048, 4-8 layers, FP32 pairs",
             "steps": steps, "cells": total,
             "batched_gcell_steps_s": round(total * steps / secs_b / 1e9, 2),
+            # FP32 pairs: read and write 8 B per node, as the single stepper
+            "batched_hbm_frac": round(total * steps / secs_b * BYTES_PER_CELL_STEP / 1e9
+                                      / HBM_PEAK_GBS, 4),
             "one_at_a_time_gcell_steps_s": round(total * steps / secs_1 / 1e9, 2),
             "speedup": round(secs_1 / secs_b, 2)}
 
@@ -138,10 +142,16 @@ def gradient_extra(P, steps, stream):
     t0 = time.perf_counter()
     J, g, _ = plan.gradient(tgt, nsteps=steps)
     t_grad = time.perf_counter() - t0
+    cells = c["nr"] * c["nz"]
     return {"workload": "adjoint: 512x2048, 6 layers, FP64, checkpoint stride ceil(sqrt(N))",
             "steps": steps, "forward_s": round(t_fwd, 3), "gradient_s": round(t_grad, 3),
             "gradient_over_forward": round(t_grad / t_fwd, 2), "J": J,
-            "grad_finite": bool(np.all(np.isfinite(g)))}
+            "grad_finite": bool(np.all(np.isfinite(g))),
+            "gradient_gcell_steps_s": round(cells * steps / t_grad / 1e9, 2),
+            # algorithmic bytes of a gradient step: forward and recompute 16 B
+            # each, the adjoint 32 B (read T^n, T^{n+1}, lam^{n+1}; write lam^n)
+            "gradient_hbm_frac": round(cells * steps / t_grad * GRAD_BYTES_PER_CELL_STEP / 1e9
+                                       / HBM_PEAK_GBS, 4)}
 
 
 def design_extra(P, steps, iters, stream):
