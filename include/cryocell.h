@@ -127,8 +127,11 @@ const char *cryo_version(void);
 
 /* Host-only check of a descriptor: geometry, layer counts, laws, pulse and
  * boundary kinds; T_init and held wall values must lie in the temperature
- * range of the FP64 law tables, [1/16 K, 2^20 K).  Does not test stability.
- * No device calls. */
+ * range of the FP64 law tables, [1/16 K, 2^20 K).  Law exponents (each
+ * layer's p and q, and p_m - p_{m+1} of neighbouring layers) must lie where
+ * the FP64 table powers' series truncation stays within 1e-14 relative,
+ * about -5.3 <= e <= 12.5 (CRYO_ERR_UNSUPPORTED otherwise).  Does not test
+ * stability.  No device calls. */
 cryo_status cryo_validate(const cryo_problem *prob);
 
 /* Largest dt allowed by the explicit z half, eq. (21):

@@ -9,9 +9,7 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# CRYOCELL_LIB names another build of the same library (A/B timing of kernel
-# variants); the in-tree build is the default
-LIB_PATH = os.environ.get("CRYOCELL_LIB") or os.path.join(HERE, "libcryocell.so")
+LIB_PATH = os.path.join(HERE, "libcryocell.so")
 
 CRYO_OK = 0
 STATUS = {0: "CRYO_OK", 1: "CRYO_ERR_ARG", 2: "CRYO_ERR_UNSTABLE", 3: "CRYO_ERR_DEVICE",

@@ -92,6 +92,35 @@ static void fill_pow_blob(const Laws &lw, std::vector<double> &blob) {
     }
 }
 
+// Relative truncation bound of the FP64 table power T^e (see POW_*): the
+// first term the binomial series of (1 + u)^e drops, |binom(e, POW_DEG + 1)|
+// |u|^(POW_DEG + 1) with |u| <= 2^-(POW_MBITS + 1).
+static double pow_trunc_bound(double e) {
+    double c = 1.0;
+    for (int k = 1; k <= POW_DEG + 1; ++k) c *= (e - (k - 1)) / k;
+    return fabs(c) * exp2(-(double)(POW_DEG + 1) * (POW_MBITS + 1));
+}
+
+// Every exponent a plan's power tables hold: the layers' p and q, and the
+// stepping kernel's interface ratio laws p_m - p_{m+1}.
+static cryo_status check_exponents(const cryo_geometry &g) {
+    for (int m = 0; m < g.n_layers; ++m) {
+        const cryo_material &mt = g.layers[m].mat;
+        const double ex[3] = {mt.p, mt.q,
+                              m + 1 < g.n_layers ? mt.p - g.layers[m + 1].mat.p : 0.0};
+        const char *what[3] = {"conductivity exponent p", "capacity exponent q",
+                               "conductivity ratio exponent p_m - p_{m+1}"};
+        for (int k = 0; k < 3; ++k)
+            if (pow_trunc_bound(ex[k]) > POW_TRUNC_MAX)
+                return fail(CRYO_ERR_UNSUPPORTED,
+                            std::string(what[k]) + " = " + std::to_string(ex[k]) +
+                                " of layer " + std::to_string(m) +
+                                " lies outside the range where the FP64 power series meets "
+                                "1e-14 (about -5.3 <= e <= 12.5)");
+    }
+    return CRYO_OK;
+}
+
 static cryo_status check_problem(const cryo_problem *pr) {
     if (!pr) return fail(CRYO_ERR_ARG, "null problem");
     const cryo_geometry &g = pr->geom;
@@ -116,6 +145,7 @@ static cryo_status check_problem(const cryo_problem *pr) {
         tot += l.intervals;
     }
     if (tot != g.nr - 1) return fail(CRYO_ERR_ARG, "sum of layer intervals must be nr - 1");
+    if (check_exponents(g) != CRYO_OK) return CRYO_ERR_UNSUPPORTED;
     const cryo_pulse &pu = pr->pulse;
     if (pu.layer < 0 || pu.layer >= g.n_layers)
         return fail(CRYO_ERR_ARG, "heater layer index out of range");

@@ -82,7 +82,10 @@ struct Laws {
 // FP64 powers T^e from tables: T = 2^x m, m in [1,2); m0 = 1 + (j + 1/2)/NM
 // for the top POW_MBITS mantissa bits j; u = m / m0 - 1 (|u| <= 1/(2 NM));
 // K T^e = [K 2^(x e)] m0^e (1 + u)^e, with (1 + u)^e summed as its binomial
-// series to degree 7; for |e| <= 4 the truncation stays below 1e-16 relative.
+// series to degree 7.  The first dropped term bounds the truncation:
+// |binom(e, 8)| u^8 <= |binom(e, 8)| 2^-56 relative, which is 0 for e = 0..7,
+// 1.4e-17 for e = -1, 2.3e-15 for e = -4 and 9e-14 for e = -8; the host
+// refuses exponents whose bound exceeds POW_TRUNC_MAX (about -5.3 <= e <= 12.5).
 // One block of doubles per law id:
 //   [0, 2 NM)            {m0^e, 2/m0} for j = 0..NM-1
 //   [2 NM, 2 NM + NE)    K 2^(x e) for binades x = EMIN..EMIN+NE-1
@@ -92,6 +95,7 @@ struct Laws {
 //   banks, so lanes reading different laws do not collide
 constexpr int POW_MBITS = 6, POW_NM = 1 << POW_MBITS, POW_NE = 24, POW_EMIN = -4;
 constexpr int POW_DEG = 7;
+constexpr double POW_TRUNC_MAX = 1e-14;
 constexpr double POW_TLO = 0.0625, POW_THI = 1048576.0;   // 2^EMIN, 2^(EMIN+NE)
 constexpr int POW_BX = 2 * POW_NM;                 // binade multipliers
 constexpr int POW_BE = POW_BX + POW_NE;            // exponent, then binomials from +2

@@ -67,6 +67,51 @@ def test_stability_bound_formula():
     assert P.stability_dt_max(c, 30.0) == pytest.approx(0.5 * eta * eta * want, rel=1e-14)
 
 
+def _binom8_bound(e):
+    # first term the degree-7 binomial series of (1 + u)^e drops, |u| <= 2^-7
+    c = 1.0
+    for k in range(1, 9):
+        c *= (e - (k - 1)) / k
+    return abs(c) * 2.0 ** -56
+
+
+def with_exponents(c, ps):
+    """Copy of `c` with conductivity exponents `ps`; k0 lowered where needed
+    so that eq. (21) still holds at the coldest temperature (28 K)."""
+    c = cellgen.scaled(c)
+    c["layers"] = [dict(l) for l in c["layers"]]
+    eta = c["height"] / (c["nz"] - 1)
+    for l, p in zip(c["layers"], ps):
+        l["p"] = float(p)
+        x = 28.0 / l["tref"]
+        cap = 0.5 * eta * eta * l["rho"] * l["c0"] * x ** l["q"] / (2 * c["dt"] * x ** p)
+        l["k0"] = min(l["k0"], cap)
+    return c
+
+
+def test_power_law_exponents_outside_series_range_refused():
+    # the FP64 table powers cut the binomial series of (1 + u)^e after degree
+    # 7: exponents whose first dropped term exceeds 1e-14 are refused, for
+    # the layers' own laws and for the interface ratio laws p_m - p_{m+1}
+    base = cellgen.small_cell(0)
+    assert _binom8_bound(-5.2) < 1e-14 < _binom8_bound(-5.5)
+    assert _binom8_bound(12.3) < 1e-14 < _binom8_bound(12.6)
+    P.validate(with_exponents(base, [1.0, -4.0, 1.2, 1.0]))       # ratios 5.0, -5.2
+    P.validate(with_exponents(base, [0.5, 2.0, 0.5, 2.0]))
+    for ps in ([1.0, -5.5, -5.5, 1.0],          # a layer's own exponent
+               [1.0, -4.0, 1.5, 1.0],           # ratio -5.5 between layers 1 and 2
+               [13.0, 13.0, 13.0, 13.0]):
+        with pytest.raises(P.CryoError) as e:
+            P.validate(with_exponents(base, ps))
+        assert e.value.status == 6 and "series" in P.lib().cryo_last_error().decode()
+    c = cellgen.scaled(base)
+    c["layers"] = [dict(l) for l in c["layers"]]
+    c["layers"][2]["q"] = -6.0                  # capacity exponent
+    with pytest.raises(P.CryoError) as e:
+        P.validate(c)
+    assert e.value.status == 6
+
+
 def test_nr_above_limit_unsupported():
     c = cellgen.small_cell(0)
     c = cellgen.scaled(c, nr=4097)

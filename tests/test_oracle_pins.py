@@ -723,6 +723,59 @@ def test_stepped_domain_heat_balance_exact():
         T = Tn
 
 
+@pytest.mark.parametrize("nt_from_outer", [0, 6])
+def test_stepped_domain_held_outer_wall_heat_balance(nt_from_outer):
+    # Outer wall held at T_w: on the layered lines (j <= z_full) heat enters
+    # through the wall face of the last capacity node (the r-operator is
+    # implicit, eq. (10): flux r_{i+1/2} lam (T_w - T^_{nr-2}) / h_{nr-1} with
+    # lam at the old face mean); the terminal's own outer wall is insulated
+    # (eq. (15)), also when the terminal spans every radial node, so its lines
+    # take no wall flux.  Insulated elsewhere, one layer (no interfaces), so
+    # the capacity-weighted content changes by exactly source + wall heat.
+    Ls = [layer(1e-3, 30, k0=3.0, p=1.3, c0=80.0, q=3.0, rho=4e3)]
+    Tw = 31.0
+    bc = [[0, 0.0], [1, Tw], [0, 0.0], [0, 0.0]]
+    c = cell(Ls, nz=11, height=5e-3, dt=2e-7, amplitude=3e8, width=4e-6,
+             period=1e-5, heater=0, bc=bc)
+    nr, nz = c["nr"], c["nz"]
+    j0, nt = 6, nr - nt_from_outer
+    c["stepped"] = dict(z_full=j0, nr_top=nt)
+    T = _random_field(c, 5, 28.0, 34.0)
+    T[:j0 + 1, -1] = Tw                          # held wall on the layered lines
+    T[j0 + 1:, nt - 1] = T[j0 + 1:, nt - 2]      # insulated terminal wall
+    T[0], T[-1] = T[1], T[-2]
+    r = oracle.radii(c)
+    h = np.diff(r)
+    eta = c["height"] / (nz - 1)
+    W = np.zeros_like(T)
+    W[:, 1:-1] = r[1:-1] * 0.5 * (h[:-1] + h[1:]) * eta
+    mask = np.zeros((nz, nr), bool)
+    mask[1:j0 + 1, 1:-1] = True
+    mask[j0 + 1:-1, 1:nt - 1] = True
+    l = Ls[0]
+    lam = lambda x: l["k_scale"] * l["k0"] * (x / l["tref"]) ** l["p"]
+    r_face = 0.5 * (r[-1] + r[-2])
+    wall_heat_seen = 0.0
+    for k in range(0, 36, 7):
+        Tn = oracle.forward(c, T, k0=k, nsteps=1)
+        rc = l["rho"] * l["c0"] * (T / l["tref"]) ** l["q"]
+        lhs = np.sum((W * rc * (Tn - T))[mask])
+        src = c["amplitude"] * oracle.source_fraction(c, k) * np.sum(W[mask])
+        jl = np.arange(1, j0 + 1)
+        flux = r_face * lam(0.5 * (T[jl, -2] + T[jl, -1])) * (Tw - Tn[jl, -2]) / h[-1]
+        wall = eta * np.sum(flux)
+        rhs = c["dt"] * (src + wall)
+        scale = np.sum((W * rc * np.abs(Tn - T))[mask])
+        assert abs(lhs - rhs) <= 1e-11 * max(abs(rhs), scale), (lhs, rhs)
+        # the held wall stays held on the layered lines only
+        assert np.all(Tn[:j0 + 1, -1] == Tw)
+        np.testing.assert_allclose(Tn[j0 + 1:-1, nt - 1], Tn[j0 + 1:-1, nt - 2],
+                                   rtol=1e-14, atol=0)
+        wall_heat_seen = max(wall_heat_seen, abs(c["dt"] * wall) / max(scale, 1e-300))
+        T = Tn
+    assert wall_heat_seen > 1e-3             # the wall term is not negligible
+
+
 def test_stepped_domain_rejects_bad_steps():
     c = cellgen.with_nz(cellgen.small_cell(0), 6)
     for bad in (dict(z_full=5, nr_top=10), dict(z_full=2, nr_top=2),
