@@ -31,20 +31,46 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_TFLOPS = 78.6
-BYTES_PER_CELL_STEP = 16          # read T, write T^ (FP64; an FP32 pair is also 8 B/node)
+BYTES_PER_CELL_STEP = 16          # FP64: read T, write T^
+F32_BYTES_PER_CELL_STEP = 8       # FP32: read T, write T^ (algorithmic)
+F32_PAIR_BYTES_PER_CELL_STEP = 16  # what the compensated pair storage moves
 GRAD_BYTES_PER_CELL_STEP = 64     # forward 16 + recompute 16 + adjoint 32 (FP64)
 
-# HBM bytes per step launch measured with rocprofv3 (FETCH_SIZE x 2.000 +
-# WRITE_SIZE x 1.000, factors from a 256 MiB copy; profiles/k_step_f64_1024x4096.md),
-# keyed by library version and kernel shape: any other build reports null.
-# (0.6 changed only the adjoint kernels: its k_step is the code measured on 0.5.)
-MEASURED_TRAFFIC = {("cryocell 0.5 (gfx950)", (16, 1, 2)): 84.65e6,
-                    ("cryocell 0.6 (gfx950)", (16, 1, 2)): 84.65e6,
-                    ("cryocell 0.7 (gfx950)", (16, 1, 2)): 75.26e6}
+# The headline kernel's HBM traffic comes from the committed rocprofv3
+# counter summary, and only when that summary was taken on the kernel
+# sources of this tree (their hash is written in it); otherwise null.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_step_f64_1024x4096.md")
+KERNEL_SOURCES = ["paper_1408_5853_amd/csrc/forward.hip", "paper_1408_5853_amd/csrc/device_common.h",
+                  "paper_1408_5853_amd/csrc/internal.h", "include/cryocell.h"]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    """sha256 (first 16 hex digits) of the stepping kernel's source files."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(path=TRAFFIC_PROFILE):
+    """HBM bytes per launch of the headline kernel from its counter summary,
+    if the summary names this tree's kernel source hash; else None."""
+    import re
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    m = re.search(r"kernel source sha256\[:16\]: `?([0-9a-f]{16})", text)
+    t = re.search(r"HBM bytes per launch: `?([0-9,]+)", text)
+    if not m or not t or m.group(1) != kernel_source_hash():
+        return None
+    return int(t.group(1).replace(",", ""))
 
 
 def timed(stream, fn):
@@ -59,38 +85,60 @@ def timed(stream, fn):
     return e0.elapsed_time(e1) * 1e-3
 
 
+def host_threads():
+    """Threads the host offers this process (its CPU affinity; at most 16,
+    one GPU's share of a GPU machine)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _oracle_rate(sample, lines, threads, seconds):
+    import oracle
+    n = 10
+    oracle.forward(sample, nsteps=2, nthreads=threads)         # warm
+    while True:
+        t0 = time.perf_counter()
+        oracle.forward(sample, nsteps=n, nthreads=threads)
+        dt = time.perf_counter() - t0
+        if dt > seconds / 3 or n > 10_000_000:
+            break
+        n *= 3
+    return sample["nr"] * lines * n / dt / 1e9, n, dt
+
+
 def cpu_baseline(cell, seconds):
-    """The oracle as it stands on the host cores, on a bounded sample: the
-    full radial grid, 16 interior lines, as many steps as fit in `seconds`."""
+    """The oracle as it stands on the host cores, on a bounded sample of the
+    workload: its full radial grid and 2 lines per host thread (interior
+    lines; the two z-boundary lines are copies and are not counted), as many
+    steps as fit in about `seconds`, on every thread and on one."""
     import cellgen
     import oracle
     oracle.build(force=False)
-    sample = cellgen.with_nz(cell, 18)
-    cores = os.cpu_count() or 1
-    n = 20
-    oracle.forward(sample, nsteps=2, nthreads=cores)         # warm
-    while True:
-        t0 = time.perf_counter()
-        oracle.forward(sample, nsteps=n, nthreads=cores)
-        dt = time.perf_counter() - t0
-        if dt > seconds / 4 or n > 10_000_000:
-            break
-        n *= 4
-    cells = sample["nr"] * sample["nz"] * n
-    return {"value": round(cells / dt / 1e9, 5), "unit": "Gcell-steps/s", "cores": cores,
+    cores = host_threads()
+    lines = 2 * cores
+    sample = cellgen.with_nz(cell, lines + 2)
+    v, n, dt = _oracle_rate(sample, lines, cores, 0.7 * seconds)
+    v1, n1, dt1 = _oracle_rate(sample, lines, 1, 0.3 * seconds)
+    return {"value": round(v, 5), "unit": "Gcell-steps/s", "cores": cores,
             "kind": "oracle",
-            "sample": "%d x %d nodes (the workload's full radial grid, 16 interior lines), "
-                      "%d steps, %.1f s on %d threads" % (sample["nr"], sample["nz"], n, dt, cores)}
+            "sample": "%d radial nodes x %d interior lines (the workload's radial grid; counted "
+                      "cells are the solved interior lines only), %d steps in %.1f s on %d "
+                      "threads" % (sample["nr"], lines, n, dt, cores),
+            "one_core": {"value": round(v1, 5), "steps": n1, "seconds": round(dt1, 2)}}
 
 
-def rate(plan_cls, cell, dtype, steps, warmup, stream):
-    plan = plan_cls(cell, dtype)
-    T = plan.init()
-    ws = plan.workspace(max(steps, warmup))
+def rate(P, cell, dtype, steps, warmup, stream):
+    """Seconds for `steps` steps of `cell` with the field resident in the
+    kernels' layout (cryo_state_*), after `warmup` untimed steps."""
+    plan = P.Plan(cell, dtype)
+    st = P.State(plan, plan.init())
     if warmup:
-        plan.forward(T, 0, warmup, ws=ws)
-    secs = timed(stream, lambda: plan.forward(T, warmup, steps, ws=ws))
-    plan.poll(ws)
+        st.forward(0, warmup)
+    secs = timed(stream, lambda: st.forward(warmup, steps))
+    st.poll()
     return secs, plan
 
 
@@ -104,24 +152,27 @@ def batch_extra(P, steps, stream):
     b.forward(T, 0, 64, ws)                                   # capture + warm
     secs_b = timed(stream, lambda: b.forward(T, 64, steps, ws))
     b.poll(ws)
-    # the same cells one at a time (each with its own launches)
+    # the same cells one at a time (each with its own launches, fields
+    # resident in the kernels' layout)
     plans = [P.Plan(c, "f32") for c in cells]
-    fields = [p.init() for p in plans]
-    wss = [p.workspace(steps) for p in plans]
-    for p, f, w in zip(plans, fields, wss):
-        p.forward(f, 0, 4, ws=w)
+    states = [P.State(p, p.init()) for p in plans]
+    for s in states:
+        s.forward(0, 4)
 
     def one_by_one():
-        for p, f, w in zip(plans, fields, wss):
-            p.forward(f, 4, steps, ws=w)
+        for s in states:
+            s.forward(4, steps)
 
     secs_1 = timed(stream, one_by_one)
+    rate_b = total * steps / secs_b
     return {"workload": "design sweep: 256 cells, nr 128-512, nz 256-2048, 4-8 layers, FP32 pairs",
             "steps": steps, "cells": total,
-            "batched_gcell_steps_s": round(total * steps / secs_b / 1e9, 2),
-            # FP32 pairs: read and write 8 B per node, as the single stepper
-            "batched_hbm_frac": round(total * steps / secs_b * BYTES_PER_CELL_STEP / 1e9
-                                      / HBM_PEAK_GBS, 4),
+            "batched_gcell_steps_s": round(rate_b / 1e9, 2),
+            # algorithmic FP32 traffic: read T, write T^ (8 B per node and step)
+            "batched_hbm_frac": round(rate_b * F32_BYTES_PER_CELL_STEP / 1e9 / HBM_PEAK_GBS, 4),
+            # what the compensated pairs move (16 B per node and step)
+            "batched_pair_storage_frac": round(rate_b * F32_PAIR_BYTES_PER_CELL_STEP / 1e9
+                                               / HBM_PEAK_GBS, 4),
             "one_at_a_time_gcell_steps_s": round(total * steps / secs_1 / 1e9, 2),
             "speedup": round(secs_1 / secs_b, 2)}
 
@@ -182,7 +233,7 @@ def paper_shape_extra(P, steps, stream):
     OpenCL code (context only: other hardware, other laws and domain)."""
     import cellgen
     c = cellgen.paper_shape(0)
-    secs, plan = rate(P.Plan, c, "f64", steps, 200, stream)
+    secs, plan = rate(P, c, "f64", steps, 200, stream)
     cells = c["nr"] * c["nz"]
     return {"workload": "paper-shape cell 631x1201, FP64", "steps": steps,
             "kernel_shape": list(plan.shape()),
@@ -223,7 +274,7 @@ def poly_extra(P, steps, stream):
     on the device cell (seeded coefficients around its power laws)."""
     import cellgen
     c = cellgen.poly_variant(cellgen.device_cell(0), 0, joule_tref=30.0)
-    secs, plan = rate(P.Plan, c, "f64", steps, 200, stream)
+    secs, plan = rate(P, c, "f64", steps, 200, stream)
     r = c["nr"] * c["nz"] * steps / secs / 1e9
     return {"workload": "device cell 1024x4096, FP64, polynomial laws + Joule source",
             "steps": steps, "kernel_shape": list(plan.shape()),
@@ -239,7 +290,7 @@ def stepped_extra(P, steps, stream):
     c = cellgen.device_cell(0)
     zf, nt = int(0.8 * (c["nz"] - 1)), 256
     c["stepped"] = dict(z_full=zf, nr_top=nt)
-    secs, plan = rate(P.Plan, c, "f64", steps, 200, stream)
+    secs, plan = rate(P, c, "f64", steps, 200, stream)
     nodes = c["nr"] * c["nz"]
     inside = c["nr"] * (zf + 1) + nt * (c["nz"] - 1 - zf)
     return {"workload": "device cell 1024x4096, FP64, terminal of 256 radial nodes above "
@@ -293,11 +344,13 @@ def main():
     cell = cellgen.device_cell(0)
     cells = cell["nr"] * cell["nz"]
     log("bench: device cell 1024x4096 FP64, %d steps after %d warmup" % (args.steps, args.warmup))
-    secs, plan = rate(P.Plan, cell, "f64", args.steps, args.warmup, stream)
+    secs, plan = rate(P, cell, "f64", args.steps, args.warmup, stream)
     value = cells * args.steps / secs / 1e9
     ms_step = 1e3 * secs / args.steps
-    # one k_step launch per step: the timed region / steps is its average
-    # duration plus the launch gap
+    # the timed region holds exactly one k_step launch per step on this
+    # stream (the field is resident: no layout conversion, no other kernel),
+    # so region / steps is the kernel's average launch duration plus the gap
+    # between launches
     achieved = BYTES_PER_CELL_STEP * cells / (secs / args.steps) / 1e9
     out = {
         "metric": "Gcell-steps/s & % HBM roofline (fwd, batched, adjoint) vs CPU oracle, 1 GPU",
@@ -317,13 +370,14 @@ def main():
                    "nr": cell["nr"], "nz": cell["nz"], "kernel_shape": list(plan.shape())},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": MEASURED_TRAFFIC.get((P.version(), tuple(plan.shape()))),
+                     "traffic": measured_traffic(),
                      "kernel": "k_step",
                      "bytes_per_launch": BYTES_PER_CELL_STEP * cells,
-                     "note": "algorithmic 16 B/cell-step; traffic = rocprofv3 FETCH_SIZE and "
-                             "WRITE_SIZE scaled by a 256 MiB copy; the 64 MiB ping-pong "
-                             "state stays in L2/MALL and the kernel is bound by FP64 VALU "
-                             "issue and LDS latency (46 % VALU busy), not by HBM"},
+                     "kernel_source_sha256_16": kernel_source_hash(),
+                     "note": "algorithmic 16 B/cell-step over the HIP-event time of the timed "
+                             "steps; traffic = rocprofv3 FETCH_SIZE and WRITE_SIZE per launch "
+                             "scaled by a plain copy, from the committed profile of these "
+                             "kernel sources (null if they changed since)"},
     }
     if args.copy_mib:
         n = args.copy_mib * (1 << 20) // 8
@@ -335,10 +389,14 @@ def main():
         out["copy_calibration_bytes"] = {"read": 8 * n, "written": 8 * n}
     if not args.no_extra:
         log("bench: FP32 pair rate")
-        s32, _ = rate(P.Plan, cell, "f32", 20_000, 500, stream)
+        s32, _ = rate(P, cell, "f32", 20_000, 500, stream)
         r32 = cells * 20_000 / s32 / 1e9
         out["extra"] = {"f32_pair_gcell_steps_s": round(r32, 3),
-                        "f32_pair_hbm_frac": round(r32 * BYTES_PER_CELL_STEP / HBM_PEAK_GBS, 4)}
+                        # algorithmic FP32 bytes (8 B per cell-step)
+                        "f32_hbm_frac": round(r32 * F32_BYTES_PER_CELL_STEP / HBM_PEAK_GBS, 4),
+                        # bytes the compensated pairs move (16 B per cell-step)
+                        "f32_pair_storage_frac": round(r32 * F32_PAIR_BYTES_PER_CELL_STEP
+                                                       / HBM_PEAK_GBS, 4)}
         log("bench: batched sweep")
         out["extra"]["batch"] = batch_extra(P, 2000, stream)
         log("bench: gradient")

@@ -240,6 +240,36 @@ cryo_status cryo_plan_set_turn_on(cryo_plan *plan, int32_t on);
  * CRYO_OK.  Synchronises `stream`. */
 cryo_status cryo_poll(const cryo_plan *plan, const void *ws, void *stream);
 
+/* ---- Resident state -----------------------------------------------------
+ * cryo_forward converts the field to the kernels' internal layout (radial
+ * rows lane-major per line, FP32 pairs interleaved per line) and back on
+ * every call: two extra passes over the field.  A resident state keeps the
+ * field in that layout in caller-owned device memory between calls, so that
+ * many short runs (restarts, design loops, step-by-step drivers) pay the
+ * conversion once.  The memory is a workspace of cryo_workspace_bytes
+ * bytes (256-aligned); the state object only records it and which of its two
+ * field buffers is current, so calls on one state must be ordered on one
+ * stream (or synchronised).  cryo_poll(plan, mem, stream) reports a
+ * non-finite temperature produced since the last cryo_state_load. */
+typedef struct cryo_state cryo_state;
+/* Record `mem` (bytes >= cryo_workspace_bytes) as a state of `plan`; makes
+ * the plan's device tables if this is the plan's first device use.  No
+ * other device work.  The plan must outlive the state. */
+cryo_status cryo_state_create(const cryo_plan *plan, void *mem, size_t bytes,
+                              cryo_state **out);
+void cryo_state_destroy(cryo_state *state);
+/* Load the field T (device, the Field layout above) into the state and clear
+ * its error word.  Asynchronous on `stream`. */
+cryo_status cryo_state_load(cryo_state *state, const void *T, void *stream);
+/* Advance the state by nsteps steps of eq. (8) from global step k0, exactly
+ * as cryo_forward does (same kernels, same results bit for bit); `surf` as
+ * there.  Asynchronous on `stream`. */
+cryo_status cryo_state_forward(cryo_state *state, int64_t k0, int64_t nsteps, double *surf,
+                               void *stream);
+/* Write the state's current field to T (device, the Field layout above);
+ * a non-finite value sets the error word.  Asynchronous on `stream`. */
+cryo_status cryo_state_store(const cryo_state *state, void *T, void *stream);
+
 /* ---- Autotuning ---------------------------------------------------------
  * Time every built kernel shape (rows per lane x waves per line covering nr)
  * and lines per wave 1, 2, 4, 8 on `prob` for `steps` steps and return the

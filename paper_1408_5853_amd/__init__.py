@@ -14,7 +14,7 @@ import numpy as np
 from . import _abi
 from ._abi import CryoError, check, lib
 
-__all__ = ["Plan", "Batch", "CryoError", "CryoSolve", "gradient", "with_params", "params_of",
+__all__ = ["Plan", "State", "Batch", "CryoError", "CryoSolve", "gradient", "with_params", "params_of",
            "autotune", "tune_batch",
            "validate", "stability_dt_max", "version"]
 
@@ -231,6 +231,60 @@ class Plan:
                                   _ptr(ws), ws.numel(), C.byref(J), g.ctypes.data_as(dp),
                                   S.ctypes.data_as(dp), _stream(stream)))
         return J.value, g, S
+
+
+class State:
+    """A plan's field kept in the kernels' internal layout in device memory
+    between calls (no layout conversion per call).  Calls on one State must
+    go to one stream in order."""
+
+    def __init__(self, plan, T=None, stream=None):
+        torch = _torch()
+        self.plan = plan
+        self.mem = torch.empty(plan.workspace_bytes(0), dtype=torch.uint8, device="cuda")
+        assert self.mem.data_ptr() % 256 == 0
+        h = C.c_void_p()
+        check(lib().cryo_state_create(plan._h, _ptr(self.mem), self.mem.numel(), C.byref(h)))
+        self._h = h
+        if T is not None:
+            self.load(T, stream)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().cryo_state_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load(self, T, stream=None):
+        self.plan._check_field(T)
+        check(lib().cryo_state_load(self._h, _ptr(T), _stream(stream)))
+
+    def forward(self, k0, nsteps, surf=None, stream=None):
+        """nsteps steps from global step k0 (as Plan.forward)."""
+        n = int(nsteps)
+        sp = None
+        if surf is not None:
+            torch = _torch()
+            if surf.dtype != torch.float64 or not surf.is_cuda or surf.numel() < n:
+                raise ValueError("surf must be a float64 CUDA tensor of length >= nsteps")
+            sp = _ptr(surf)
+        check(lib().cryo_state_forward(self._h, int(k0), n, sp, _stream(stream)))
+
+    def store(self, T=None, stream=None):
+        torch = _torch()
+        if T is None:
+            T = torch.empty(self.plan.field_shape, dtype=self.plan.torch_dtype, device="cuda")
+        self.plan._check_field(T)
+        check(lib().cryo_state_store(self._h, _ptr(T), _stream(stream)))
+        return T
+
+    def poll(self, stream=None):
+        self.plan.poll(self.mem, stream)
 
 
 class Batch:

@@ -26,6 +26,8 @@ SYMBOLS = [
     "cryo_batch_create", "cryo_batch_destroy", "cryo_batch_offsets", "cryo_batch_shape",
     "cryo_batch_workspace_bytes", "cryo_batch_init", "cryo_batch_forward", "cryo_batch_poll",
     "cryo_gradient_workspace_bytes", "cryo_gradient", "cryo_gradient_many", "cryo_autotune",
+    "cryo_state_create", "cryo_state_destroy", "cryo_state_load", "cryo_state_forward",
+    "cryo_state_store",
 ]
 
 
@@ -94,6 +96,12 @@ def lib():
         L.cryo_init.argtypes = [vp, vp, vp]
         L.cryo_forward.argtypes = [vp, vp, i64, i64, vp, C.c_size_t, vp, vp]
         L.cryo_poll.argtypes = [vp, vp, vp]
+        L.cryo_state_create.argtypes = [vp, vp, C.c_size_t, C.POINTER(vp)]
+        L.cryo_state_destroy.argtypes = [vp]
+        L.cryo_state_destroy.restype = None
+        L.cryo_state_load.argtypes = [vp, vp, vp]
+        L.cryo_state_forward.argtypes = [vp, i64, i64, vp, vp]
+        L.cryo_state_store.argtypes = [vp, vp, vp]
         i32p = C.POINTER(C.c_int32)
         L.cryo_plan_shape.argtypes = [vp, i32p, i32p, i32p]
         L.cryo_plan_set_shape.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
@@ -118,7 +126,7 @@ def lib():
                                          C.POINTER(dp)]
         for name in SYMBOLS:
             if name not in ("cryo_last_error", "cryo_version", "cryo_plan_destroy",
-                            "cryo_batch_destroy"):
+                            "cryo_batch_destroy", "cryo_state_destroy"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib

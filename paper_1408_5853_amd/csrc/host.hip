@@ -702,28 +702,37 @@ cryo_status cryo_init(const cryo_plan *p, void *T, void *stream) {
     return launch_fill(p, T, (hipStream_t)stream);
 }
 
-cryo_status cryo_forward(const cryo_plan *p, void *T, int64_t k0, int64_t nsteps, void *ws,
-                         size_t ws_bytes, double *surf, void *stream) {
-    if (!p || !T || nsteps < 0 || k0 < 0) return fail(CRYO_ERR_ARG, "bad argument");
+}  // extern "C"
+
+// Workspace (and resident state) layout: the error word, the two field
+// buffers of the kernels' internal layout (ping-pong), then the per-workgroup
+// surface partial sums of up to SURF_CHUNK steps.
+static cryo_status check_ws(const cryo_plan *p, const void *ws, size_t ws_bytes) {
     size_t need = 0;
-    cryo_workspace_bytes(p, nsteps, &need);
+    cryo_workspace_bytes(p, 0, &need);
     if (!ws || ws_bytes < need)
         return fail(CRYO_ERR_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes");
     if (((uintptr_t)ws & 255) != 0) return fail(CRYO_ERR_WORKSPACE, "workspace must be 256-aligned");
-    cryo_status st0 = ensure_device(const_cast<cryo_plan *>(p));
-    if (st0 == CRYO_OK && p->sub) st0 = ensure_device(p->sub);
-    if (st0 != CRYO_OK) return st0;
-    hipStream_t s = (hipStream_t)stream;
-    char *w = (char *)ws;
+    return CRYO_OK;
+}
+
+static cryo_status plan_on_device(const cryo_plan *p) {
+    cryo_status st = ensure_device(const_cast<cryo_plan *>(p));
+    if (st == CRYO_OK && p->sub) st = ensure_device(p->sub);
+    return st;
+}
+
+// nsteps steps from global step k0 on the internal fields of workspace w,
+// starting from buffer *cur; *cur names the buffer holding the result.
+static cryo_status run_steps(const cryo_plan *p, char *w, int *cur_io, int64_t k0,
+                             int64_t nsteps, double *surf, hipStream_t s) {
     int *flag = (int *)w;
     void *buf[2] = {w + 256, w + 256 + field_bytes(p)};
     double *part = (double *)(w + 256 + 2 * field_bytes(p));
-    // the conversion kernel also clears the non-finite flag
-    cryo_status st = launch_to_internal(p, T, buf[0], flag, s);
-    if (st != CRYO_OK) return st;
+    cryo_status st = CRYO_OK;
     int G = step_grid(p);
     int64_t done_surf = 0;
-    int cur = 0;
+    int cur = *cur_io;
     for (int64_t n = 0; n < nsteps; ++n) {
         double *pp = surf ? part + (size_t)(n % SURF_CHUNK) * G : nullptr;
         if (p->sub && pulse_start(p->pulse, k0 + n)) {
@@ -740,6 +749,7 @@ cryo_status cryo_forward(const cryo_plan *p, void *T, int64_t k0, int64_t nsteps
             cur ^= 1;
         }
         if (st != CRYO_OK) return st;
+        *cur_io = cur;
         if (surf && ((n + 1) % SURF_CHUNK == 0 || n + 1 == nsteps)) {
             int cnt = (int)(n + 1 - done_surf);
             st = launch_surf_reduce(p, part, cnt, surf + done_surf, s);
@@ -747,7 +757,70 @@ cryo_status cryo_forward(const cryo_plan *p, void *T, int64_t k0, int64_t nsteps
             done_surf = n + 1;
         }
     }
-    return launch_from_internal(p, buf[cur], T, flag, s);
+    return CRYO_OK;
+}
+
+// Resident state: the caller's workspace holding the field in the internal
+// layout between calls, and which of its two buffers is current.  Calls on
+// one state are ordered by the stream, so the host knows the current buffer.
+struct cryo_state {
+    const cryo_plan *plan;
+    char *mem;
+    int cur;
+};
+
+extern "C" {
+
+cryo_status cryo_forward(const cryo_plan *p, void *T, int64_t k0, int64_t nsteps, void *ws,
+                         size_t ws_bytes, double *surf, void *stream) {
+    if (!p || !T || nsteps < 0 || k0 < 0) return fail(CRYO_ERR_ARG, "bad argument");
+    cryo_status st = check_ws(p, ws, ws_bytes);
+    if (st == CRYO_OK) st = plan_on_device(p);
+    if (st != CRYO_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ws;
+    int *flag = (int *)w;
+    int cur = 0;
+    // the conversion kernel also clears the non-finite flag
+    st = launch_to_internal(p, T, w + 256, flag, s);
+    if (st == CRYO_OK) st = run_steps(p, w, &cur, k0, nsteps, surf, s);
+    if (st != CRYO_OK) return st;
+    return launch_from_internal(p, w + 256 + cur * field_bytes(p), T, flag, s);
+}
+
+cryo_status cryo_state_create(const cryo_plan *p, void *mem, size_t bytes, cryo_state **out) {
+    if (!p || !out) return fail(CRYO_ERR_ARG, "null argument");
+    *out = nullptr;
+    cryo_status st = check_ws(p, mem, bytes);
+    if (st == CRYO_OK) st = plan_on_device(p);
+    if (st != CRYO_OK) return st;
+    cryo_state *z = new cryo_state();
+    z->plan = p;
+    z->mem = (char *)mem;
+    z->cur = 0;
+    *out = z;
+    return CRYO_OK;
+}
+
+void cryo_state_destroy(cryo_state *z) { delete z; }
+
+cryo_status cryo_state_load(cryo_state *z, const void *T, void *stream) {
+    if (!z || !T) return fail(CRYO_ERR_ARG, "null argument");
+    z->cur = 0;
+    return launch_to_internal(z->plan, T, z->mem + 256, (int *)z->mem, (hipStream_t)stream);
+}
+
+cryo_status cryo_state_forward(cryo_state *z, int64_t k0, int64_t nsteps, double *surf,
+                               void *stream) {
+    if (!z || nsteps < 0 || k0 < 0) return fail(CRYO_ERR_ARG, "bad argument");
+    return run_steps(z->plan, z->mem, &z->cur, k0, nsteps, surf, (hipStream_t)stream);
+}
+
+cryo_status cryo_state_store(const cryo_state *z, void *T, void *stream) {
+    if (!z || !T) return fail(CRYO_ERR_ARG, "null argument");
+    const cryo_plan *p = z->plan;
+    return launch_from_internal(p, z->mem + 256 + z->cur * field_bytes(p), T, (int *)z->mem,
+                                (hipStream_t)stream);
 }
 
 cryo_status cryo_poll(const cryo_plan *p, const void *ws, void *stream) {
