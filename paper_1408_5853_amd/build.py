@@ -5,6 +5,7 @@ import glob
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -16,17 +17,29 @@ HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Wall", "-Wno-unused-result"]
 
 
+def _jobs():
+    try:
+        n = int(os.environ.get("MAX_JOBS", "0"))
+    except ValueError:
+        n = 0
+    return max(1, min(n or (os.cpu_count() or 1), 16))
+
+
 def build(verbose=False):
     srcs = sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
-    objs = []
-    for s in srcs:
+
+    def one(s):
         o = os.path.join(HERE, "csrc", os.path.basename(s) + ".o")
         cmd = ["hipcc", "-c", *HIP_FLAGS, "-I", os.path.join(ROOT, "include"),
                "-I", os.path.join(HERE, "csrc"), "-o", o, s]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
-        objs.append(o)
+        return o
+
+    # the sources compile independently; the largest dominates the wall time
+    with ThreadPoolExecutor(max_workers=_jobs()) as ex:
+        objs = list(ex.map(one, srcs))
     tmp = LIB + ".tmp"
     cmd = ["hipcc", "-shared", "--offload-arch=gfx950", "-o", tmp, *objs]
     subprocess.check_call(cmd)
