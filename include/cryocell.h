@@ -270,6 +270,34 @@ cryo_status cryo_state_forward(cryo_state *state, int64_t k0, int64_t nsteps, do
  * a non-finite value sets the error word.  Asynchronous on `stream`. */
 cryo_status cryo_state_store(const cryo_state *state, void *T, void *stream);
 
+/* ---- Forward without allocation ------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * cryo_forward_noalloc does exactly what cryo_forward does (same kernels,
+ * same results bit for bit) but keeps its workspace in a library-owned
+ * device array of CRYO_NOALLOC_MAX_BYTES bytes instead of caller memory; it
+ * calls no hipMalloc, hipFree or allocating library routine.  The caller
+ * still passes the field T (device, the Field layout above) and `surf`
+ * (device double[nsteps], nullable).  The array is part of the library's
+ * device code object: every GPU the library runs on holds its own copy
+ * until the process ends, and its address is looked up on the first call
+ * on each device.
+ *  - A plan whose workspace (cryo_workspace_bytes) exceeds the array is
+ *    refused with CRYO_ERR_WORKSPACE (72 MiB holds the 1024 x 4096 FP64 cell).
+ *  - The plan must already hold its device tables (made by its first
+ *    cryo_forward or by cryo_state_create); otherwise CRYO_ERR_ARG.  The
+ *    current device must be the plan's (CRYO_ERR_ARG).
+ *  - Every call on one GPU shares that GPU's array, which keeps the last
+ *    call's contents: calls that overlap on one GPU (other streams, other
+ *    host threads) race and must be ordered by the caller.
+ *  - The kernels' non-finite error word lives in the array and is not
+ *    reported (cryo_poll needs a workspace): callers that need that check
+ *    use cryo_forward.
+ * Asynchronous on `stream`. */
+#define CRYO_NOALLOC_MAX_BYTES (72u << 20)
+cryo_status cryo_forward_noalloc(const cryo_plan *plan, void *T, int64_t k0, int64_t nsteps,
+                                 double *surf, void *stream);
+
 /* ---- Autotuning ---------------------------------------------------------
  * Time every built kernel shape (rows per lane x waves per line covering nr)
  * and lines per wave 1, 2, 4, 8 on `prob` for `steps` steps and return the

@@ -196,6 +196,21 @@ class Plan:
                                  _stream(stream)))
         return T
 
+    def forward_noalloc(self, T, k0=0, nsteps=None, surf=None, stream=None):
+        """As forward, with the workspace in the library's own device array
+        (cryo_forward_noalloc: no allocation; the plan must have run once or
+        have a State, so that its device tables exist)."""
+        n = int(self.cell["nsteps"] if nsteps is None else nsteps)
+        self._check_field(T)
+        sp = None
+        if surf is not None:
+            torch = _torch()
+            if surf.dtype != torch.float64 or not surf.is_cuda or surf.numel() < n:
+                raise ValueError("surf must be a float64 CUDA tensor of length >= nsteps")
+            sp = _ptr(surf)
+        check(lib().cryo_forward_noalloc(self._h, _ptr(T), int(k0), n, sp, _stream(stream)))
+        return T
+
     def poll(self, ws, stream=None):
         check(lib().cryo_poll(self._h, _ptr(ws), _stream(stream)))
 

@@ -27,7 +27,7 @@ SYMBOLS = [
     "cryo_batch_workspace_bytes", "cryo_batch_init", "cryo_batch_forward", "cryo_batch_poll",
     "cryo_gradient_workspace_bytes", "cryo_gradient", "cryo_gradient_many", "cryo_autotune",
     "cryo_state_create", "cryo_state_destroy", "cryo_state_load", "cryo_state_forward",
-    "cryo_state_store",
+    "cryo_state_store", "cryo_forward_noalloc",
 ]
 
 
@@ -96,6 +96,7 @@ def lib():
         L.cryo_init.argtypes = [vp, vp, vp]
         L.cryo_forward.argtypes = [vp, vp, i64, i64, vp, C.c_size_t, vp, vp]
         L.cryo_poll.argtypes = [vp, vp, vp]
+        L.cryo_forward_noalloc.argtypes = [vp, vp, i64, i64, vp, vp]
         L.cryo_state_create.argtypes = [vp, vp, C.c_size_t, C.POINTER(vp)]
         L.cryo_state_destroy.argtypes = [vp]
         L.cryo_state_destroy.restype = None

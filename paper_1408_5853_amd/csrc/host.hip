@@ -760,6 +760,25 @@ static cryo_status run_steps(const cryo_plan *p, char *w, int *cur_io, int64_t k
     return CRYO_OK;
 }
 
+namespace cryo {
+// The forward of cryo_forward on a checked workspace `w` (error word, two
+// internal fields, surface partials) of a plan whose device tables exist.
+cryo_status forward_in(const cryo_plan *p, void *T, int64_t k0, int64_t nsteps, char *w,
+                       double *surf, hipStream_t s) {
+    int *flag = (int *)w;
+    int cur = 0;
+    // the conversion kernel also clears the non-finite flag
+    cryo_status st = launch_to_internal(p, T, w + 256, flag, s);
+    if (st == CRYO_OK) st = run_steps(p, w, &cur, k0, nsteps, surf, s);
+    if (st != CRYO_OK) return st;
+    return launch_from_internal(p, w + 256 + cur * field_bytes(p), T, flag, s);
+}
+
+bool plan_tables_on_device(const cryo_plan *p) {
+    return p->d_info != nullptr && (!p->sub || p->sub->d_info != nullptr);
+}
+}  // namespace cryo
+
 // Resident state: the caller's workspace holding the field in the internal
 // layout between calls, and which of its two buffers is current.  Calls on
 // one state are ordered by the stream, so the host knows the current buffer.
@@ -777,15 +796,7 @@ cryo_status cryo_forward(const cryo_plan *p, void *T, int64_t k0, int64_t nsteps
     cryo_status st = check_ws(p, ws, ws_bytes);
     if (st == CRYO_OK) st = plan_on_device(p);
     if (st != CRYO_OK) return st;
-    hipStream_t s = (hipStream_t)stream;
-    char *w = (char *)ws;
-    int *flag = (int *)w;
-    int cur = 0;
-    // the conversion kernel also clears the non-finite flag
-    st = launch_to_internal(p, T, w + 256, flag, s);
-    if (st == CRYO_OK) st = run_steps(p, w, &cur, k0, nsteps, surf, s);
-    if (st != CRYO_OK) return st;
-    return launch_from_internal(p, w + 256 + cur * field_bytes(p), T, flag, s);
+    return cryo::forward_in(p, T, k0, nsteps, (char *)ws, surf, (hipStream_t)stream);
 }
 
 cryo_status cryo_state_create(const cryo_plan *p, void *mem, size_t bytes, cryo_state **out) {

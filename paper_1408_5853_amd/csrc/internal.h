@@ -207,4 +207,9 @@ int step_grid(const cryo_plan *p);
 size_t step_lds(const cryo_plan *p);            // dynamic LDS of the stepping kernel
 constexpr size_t MAX_STEP_LDS = 160 * 1024 - 4096;   // leaves room for static LDS
 cryo_status ensure_device(cryo_plan *p);
+// host.hip: cryo_forward's device work on a checked workspace, and whether
+// a plan (and its turn-on sub-plan) has made its device tables
+cryo_status forward_in(const cryo_plan *p, void *T, int64_t k0, int64_t nsteps, char *w,
+                       double *surf, hipStream_t s);
+bool plan_tables_on_device(const cryo_plan *p);
 }  // namespace cryo
