@@ -245,6 +245,11 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
                 LnP[r] = LnQ[r];
             }
         }
+        // the held outer wall's row (uniform; -1 for none): its test below is
+        // a scalar branch per row, not a select kept in registers for every row
+        int hrow = (a.held[1] && !up) ? a.surf_reg : -1;
+        hrow = __builtin_amdgcn_readfirstlane(hrow);
+        const bool hlane = lg == a.surf_lane;
         // the rows' info words, one row ahead (they head each row's chain of
         // table lookups)
         uint32_t infn = tinf[lg];
@@ -307,8 +312,10 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
                 dd += (R)((inf_r >> 3) & 1) * X;                // heater capacity rows
             // held walls: rows 0 and nr - 1 are unit rows with dT = value - T
             if (r == 0 && a.held[0]) dd = lg == 0 ? dif<R>(a.val[0], (R)0, T, Tl) : dd;
-            if (r == a.surf_reg && a.held[1] && !up)
-                dd = lg == a.surf_lane ? dif<R>(a.val[1], (R)0, T, Tl) : dd;
+            if (r == hrow) {
+                asm volatile("" ::: "memory");               // keeps the branch
+                dd = hlane ? dif<R>(a.val[1], (R)0, T, Tl) : dd;
+            }
             fs_set(r, -Fo);
             lamW = lamE;
             const R aa = -fw, bb = fw + fe + rc, cc = -fe;
