@@ -154,8 +154,10 @@ void cryo_plan_destroy(cryo_plan *plan);
  * (the autotuner's hook) and must precede the plan's first device call.
  * Built shapes: one wave per line with 2, 3, 4, 5, 6, 7, 8, 10, 12 or 16
  * rows per lane, and (4,2) (8,2) (4,4) (8,4); 64 * waves * rows must cover
- * nr.  The gradient runs (2,1) (4,1) (8,1) (4,2) (8,2) (4,4) (8,4).  Results do not depend on lines_per_wave; different
- * chunk shapes change only rounding. */
+ * nr.  The gradient runs (2,1) (4,1) (8,1) (4,2) (8,2) (4,4) (8,4).  Other
+ * shapes, lines per wave included, change only rounding: the chunks of the
+ * line solve, and the order in which a line adds its two axial fluxes (its
+ * line block's march direction), depend on the shape. */
 cryo_status cryo_plan_shape(const cryo_plan *plan, int32_t *rows_per_lane,
                             int32_t *waves_per_line, int32_t *lines_per_wave);
 cryo_status cryo_plan_set_shape(cryo_plan *plan, int32_t rows_per_lane,
@@ -304,11 +306,29 @@ cryo_status cryo_forward_noalloc(const cryo_plan *plan, void *T, int64_t k0, int
  * fastest as shape[3] (for cryo_plan_set_shape or cryo_batch_create), with
  * its time per step (or -1 when taken from the cache).  The tuner allocates
  * and frees its own trial field and workspaces.  `cache_path` (nullable)
- * names a text file of earlier results keyed by dtype, nr, nz and layer
- * count; new results are appended.  Synchronous on `stream`. */
+ * names a text file of earlier results keyed by dtype, nr, nz, layer count
+ * and law family (every capacity exponent 3, or not); new results are
+ * appended.  Synchronous on `stream`. */
 cryo_status cryo_autotune(const cryo_problem *prob, cryo_dtype dtype, int32_t steps,
                           const char *cache_path, void *stream, int32_t *shape,
                           double *us_per_step);
+
+/* Launch shapes for a batch (cryo_batch_create's `shapes`, n x 3 values):
+ * the n instances are grouped as cryo_batch_create groups them with default
+ * shapes (rows per lane and waves per line covering nr, capacity-law family);
+ * for each group every built shape covering its largest radial size with
+ * fewer than twice as many rows (or at most 2 rows per lane), with lines per
+ * wave 1, 2, 4 and 8, is timed as a batch of up to 8 of the group's
+ * instances (spread over their sizes) for `steps` steps (rounded up to
+ * whole captured blocks of 32), and the shape with the least time per node
+ * and step is given to all of the group's instances (lines per wave capped
+ * at nz - 2).  `cache_path` (nullable) names a text file keyed by dtype, the
+ * group's default shape, law family and largest radial size; new results
+ * are appended.  The tuner allocates and frees its own trial fields and
+ * workspaces.  Synchronous on `stream`. */
+cryo_status cryo_batch_autotune(int32_t n, const cryo_problem *probs, cryo_dtype dtype,
+                                int32_t steps, const char *cache_path, void *stream,
+                                int32_t *shapes);
 
 /* ---- Gradient by the discrete adjoint -----------------------------------
  * J = sum_{n=1..N} (S_n - target_n)^2 with S_n the surface mean after step
@@ -352,9 +372,10 @@ cryo_status cryo_gradient_many(int32_t n, cryo_plan *const *plans, const void *c
 /* ---- Batched design sweeps ---------------------------------------------
  * Many independent cells (uneven grids, own dt, layers and pulse) stepped
  * together: instances are grouped by kernel shape; each step is one launch
- * per shape group over all of its instances, and blocks of steps are
- * captured once in a HIP graph (on a private capture stream) and replayed on
- * the caller's stream.  The fields of all instances are packed in one device
+ * per shape group over all of its instances, and blocks of 32 steps are
+ * captured once in a HIP graph (on private capture streams: one branch per
+ * shape group, so that groups may run side by side) and replayed on the
+ * caller's stream.  The fields of all instances are packed in one device
  * buffer: instance i's field (the plan's field layout) starts at element
  * offsets[i] of the batch dtype.  Every instance uses the same global step
  * range k0 .. k0 + nsteps. */

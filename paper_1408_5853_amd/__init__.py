@@ -390,21 +390,18 @@ def autotune(cell, dtype="f64", steps=20, cache=None, stream=None):
     return tuple(sh), us.value
 
 
-def tune_batch(cells, dtype="f32", steps=20, cache=None):
-    """Per-instance shapes for a Batch: instances are bucketed by radial
-    size and each bucket is tuned on its largest member."""
-    buckets = {}
-    for i, c in enumerate(cells):
-        key = int(c["nr"])
-        buckets.setdefault(key, []).append(i)
-    shapes = [None] * len(cells)
-    for key, idx in buckets.items():
-        rep = max(idx, key=lambda i: cells[i]["nz"])
-        sh, _ = autotune(cells[rep], dtype, steps, cache)
-        for i in idx:
-            lpw = min(sh[2], max(1, cells[i]["nz"] - 2))
-            shapes[i] = (sh[0], sh[1], lpw)
-    return shapes
+def tune_batch(cells, dtype="f32", steps=64, cache=None, stream=None):
+    """Per-instance launch shapes for Batch(cells, dtype, shapes=...), timed
+    on the GPU per shape group (cryo_batch_autotune); `cache` names an
+    optional text file of earlier results."""
+    n = len(cells)
+    ps = [_abi.ProblemStruct(c) for c in cells]
+    arr = (_abi.Problem * n)(*[p.s for p in ps])
+    out = (C.c_int32 * (3 * n))()
+    check(lib().cryo_batch_autotune(n, arr, _abi.F64 if dtype == "f64" else _abi.F32,
+                                    int(steps), cache.encode() if cache else None,
+                                    _stream(stream), out))
+    return [tuple(out[3 * i:3 * i + 3]) for i in range(n)]
 
 
 def params_of(cell):

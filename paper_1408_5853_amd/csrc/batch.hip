@@ -1,7 +1,7 @@
 // Batched stepping of many independent cells (design sweeps): instances
 // are grouped by kernel shape; each step is one launch per shape group over
 // all of its instances, and blocks of steps are captured once in a HIP graph
-// and replayed.  The global step index lives in device memory so a captured
+// (one branch per shape group) and replayed.  The global step index lives in device memory so a captured
 // block can be replayed for any step range.
 #include <string.h>
 
@@ -228,33 +228,59 @@ cryo_status cryo_batch_forward(cryo_batch *b, void *T, int64_t k0, int64_t nstep
     }
     cryo_status st = launch_set_i64(k0p, k0, s);
     if (st != CRYO_OK) return st;
-    auto launch_steps = [&](int64_t first, int64_t count, hipStream_t strm) -> cryo_status {
-        for (int64_t m = first; m < first + count; ++m)
-            for (const Bucket &bk : b->buckets) {
-                const cryo_plan *p0 = b->plans[bk.inst[0]];
-                size_t lds = 0;
-                for (int i : bk.inst) lds = std::max(lds, step_lds(b->plans[i]));
-                (void)p0;
-                cryo_status r = launch_step_batch(
-                    b->dtype, bk.rpl, bk.wpl, bk.cube, (const char *)b->d_block + bk.desc_off,
-                    (const int2 *)((const char *)b->d_block + bk.map_off), (int)bk.map.size(),
-                    lds, m, k0p, strm);
-                if (r != CRYO_OK) return r;
-            }
+    // the steps of one bucket (its instances only) on stream strm
+    auto launch_bucket = [&](const Bucket &bk, int64_t first, int64_t count,
+                             hipStream_t strm) -> cryo_status {
+        size_t lds = 0;
+        for (int i : bk.inst) lds = std::max(lds, step_lds(b->plans[i]));
+        for (int64_t m = first; m < first + count; ++m) {
+            cryo_status r = launch_step_batch(
+                b->dtype, bk.rpl, bk.wpl, bk.cube, (const char *)b->d_block + bk.desc_off,
+                (const int2 *)((const char *)b->d_block + bk.map_off), (int)bk.map.size(), lds,
+                m, k0p, strm);
+            if (r != CRYO_OK) return r;
+        }
         return CRYO_OK;
     };
     const int64_t blocks = nsteps / GRAPH_STEPS, rem = nsteps % GRAPH_STEPS;
     if (blocks > 0) {
         if (!b->exec) {
+            // One graph per block of GRAPH_STEPS steps: the buckets hold
+            // disjoint instances, so each bucket's chain of steps is a branch
+            // of its own (forked from and joined to the capture stream), and
+            // the branches may run side by side; the step counter advances
+            // after the join.
+            const size_t nb = b->buckets.size();
             hipStream_t cs;
-            if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
-                return fail(CRYO_ERR_DEVICE, "capture stream");
-            hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-            cryo_status r = e == hipSuccess ? launch_steps(0, GRAPH_STEPS, cs) : CRYO_ERR_DEVICE;
-            if (r == CRYO_OK) r = launch_add_i64(k0p, GRAPH_STEPS, cs);
+            std::vector<hipStream_t> bs(nb, nullptr);
+            std::vector<hipEvent_t> ev(nb + 1, nullptr);
+            bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
+            for (size_t q = 0; ok && q < nb; ++q)
+                ok = hipStreamCreateWithFlags(&bs[q], hipStreamNonBlocking) == hipSuccess;
+            for (size_t q = 0; ok && q <= nb; ++q)
+                ok = hipEventCreateWithFlags(&ev[q], hipEventDisableTiming) == hipSuccess;
+            cryo_status r = ok ? CRYO_OK : CRYO_ERR_DEVICE;
             hipGraph_t g = nullptr;
-            hipError_t e2 = hipStreamEndCapture(cs, &g);
-            (void)hipStreamDestroy(cs);
+            hipError_t e2 = hipErrorUnknown;
+            if (ok) {
+                hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+                if (e != hipSuccess) r = CRYO_ERR_DEVICE;
+                if (r == CRYO_OK && hipEventRecord(ev[nb], cs) != hipSuccess) r = CRYO_ERR_DEVICE;
+                for (size_t q = 0; r == CRYO_OK && q < nb; ++q) {
+                    if (hipStreamWaitEvent(bs[q], ev[nb], 0) != hipSuccess) r = CRYO_ERR_DEVICE;
+                    if (r == CRYO_OK) r = launch_bucket(b->buckets[q], 0, GRAPH_STEPS, bs[q]);
+                    if (r == CRYO_OK && (hipEventRecord(ev[q], bs[q]) != hipSuccess ||
+                                         hipStreamWaitEvent(cs, ev[q], 0) != hipSuccess))
+                        r = CRYO_ERR_DEVICE;
+                }
+                if (r == CRYO_OK) r = launch_add_i64(k0p, GRAPH_STEPS, cs);
+                e2 = hipStreamEndCapture(cs, &g);
+            }
+            for (size_t q = 0; q < nb; ++q)
+                if (bs[q]) (void)hipStreamDestroy(bs[q]);
+            for (size_t q = 0; q <= nb; ++q)
+                if (ev[q]) (void)hipEventDestroy(ev[q]);
+            if (ok) (void)hipStreamDestroy(cs);
             if (r != CRYO_OK || e2 != hipSuccess || !g) {
                 if (g) (void)hipGraphDestroy(g);
                 return fail(CRYO_ERR_DEVICE, "graph capture of the step block failed");
@@ -271,8 +297,10 @@ cryo_status cryo_batch_forward(cryo_batch *b, void *T, int64_t k0, int64_t nstep
                 return fail(CRYO_ERR_DEVICE, "graph launch failed");
     }
     b->graph_ws = ws;
-    st = launch_steps(0, rem, s);
-    if (st != CRYO_OK) return st;
+    for (const Bucket &bk : b->buckets) {
+        st = launch_bucket(bk, 0, rem, s);
+        if (st != CRYO_OK) return st;
+    }
     for (int i = 0; i < n; ++i) {
         const cryo_plan *p = b->plans[i];
         char *f = w + b->ws_field[i];

@@ -1,11 +1,16 @@
-// Autotuner: times every built kernel shape (rows per lane, waves per line)
-// and lines-per-wave on a problem and returns the fastest.  The tuner owns
-// its trial field and workspace (device allocations of its own, outside any
-// stepping call).  An optional text cache keyed by (dtype, nr, nz, layers)
-// records results across runs.
+// Autotuners: cryo_autotune times every built kernel shape (rows per lane,
+// waves per line) and lines-per-wave on one problem and returns the fastest;
+// cryo_batch_autotune does the same per shape group of a batch, timing
+// batches of the group's instances.  The tuners own their trial fields and
+// workspaces (device allocations of their own, outside any stepping call).
+// An optional text cache records results across runs: keyed by dtype,
+// radial and axial node counts, layer count and law family (cube or general
+// capacity exponents) for one problem, and by dtype, default shape, law
+// family and largest radial size for a batch group.
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -15,10 +20,17 @@ using namespace cryo;
 
 namespace {
 
+// every capacity exponent 3 selects the kernels' cube path
+bool all_cube(const cryo_problem *p) {
+    for (int m = 0; m < p->geom.n_layers; ++m)
+        if (p->geom.layers[m].mat.q != 3.0) return false;
+    return true;
+}
+
 std::string cache_key(const cryo_problem *p, cryo_dtype dt) {
-    char b[128];
-    snprintf(b, sizeof b, "%s %d %d %d", dt == CRYO_F64 ? "f64" : "f32", p->geom.nr, p->geom.nz,
-             p->geom.n_layers);
+    char b[160];
+    snprintf(b, sizeof b, "%s %d %d %d %s", dt == CRYO_F64 ? "f64" : "f32", p->geom.nr,
+             p->geom.nz, p->geom.n_layers, all_cube(p) ? "cube" : "power");
     return b;
 }
 
@@ -135,6 +147,143 @@ cryo_status cryo_autotune(const cryo_problem *prob, cryo_dtype dtype, int32_t st
     if (us_per_step) *us_per_step = best;
     cache_store(cache_path, key, bs, best);
     return CRYO_OK;
+}
+
+cryo_status cryo_batch_autotune(int32_t n, const cryo_problem *probs, cryo_dtype dtype,
+                                int32_t steps, const char *cache_path, void *stream,
+                                int32_t *shapes) {
+    if (n < 1 || !probs || !shapes || steps < 1) return fail(CRYO_ERR_ARG, "bad argument");
+    hipStream_t s = (hipStream_t)stream;
+    // the groups cryo_batch_create forms with default shapes
+    struct Group {
+        int rpl, wpl;
+        bool cube;
+        int nr_max = 0, nz_min = 1 << 30;
+        std::vector<int> inst;
+    };
+    std::vector<Group> groups;
+    for (int i = 0; i < n; ++i) {
+        cryo_plan *p = nullptr;
+        cryo_status st = cryo_plan_create(&probs[i], dtype, &p);
+        if (st != CRYO_OK)
+            return fail(st, "instance " + std::to_string(i) + ": " + cryo_last_error());
+        int rpl = 0, wpl = 0, lpw = 0;
+        cryo_plan_shape(p, &rpl, &wpl, &lpw);
+        cryo_plan_destroy(p);
+        const bool cube = all_cube(&probs[i]);
+        Group *g = nullptr;
+        for (Group &q : groups)
+            if (q.rpl == rpl && q.wpl == wpl && q.cube == cube) g = &q;
+        if (!g) {
+            groups.push_back(Group());
+            g = &groups.back();
+            g->rpl = rpl;
+            g->wpl = wpl;
+            g->cube = cube;
+        }
+        g->inst.push_back(i);
+        g->nr_max = std::max(g->nr_max, probs[i].geom.nr);
+        g->nz_min = std::min(g->nz_min, probs[i].geom.nz);
+    }
+#define TUNE_SHAPE(RP, GW) {RP, GW},
+    const int built[][2] = {CRYO_FOR_SHAPES(TUNE_SHAPE)};
+#undef TUNE_SHAPE
+    const int lpws[] = {1, 2, 4, 8};
+    const int run_steps = ((steps + 31) / 32) * 32;         // whole captured blocks
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    cryo_status result = CRYO_OK;
+    for (const Group &g : groups) {
+        char kb[160];
+        snprintf(kb, sizeof kb, "batch %s %d %d %s %d", dtype == CRYO_F64 ? "f64" : "f32", g.rpl,
+                 g.wpl, g.cube ? "cube" : "power", g.nr_max);
+        int32_t best_shape[3] = {g.rpl, g.wpl, 4};
+        if (!cache_lookup(cache_path, kb, best_shape)) {
+            // up to 8 of the group's instances, spread over its sizes
+            std::vector<int> order(g.inst);
+            std::sort(order.begin(), order.end(), [&](int a, int b) {
+                return (int64_t)probs[a].geom.nr * probs[a].geom.nz <
+                       (int64_t)probs[b].geom.nr * probs[b].geom.nz;
+            });
+            std::vector<int> sub;
+            const int k = std::min<int>(8, (int)order.size());
+            for (int q = 0; q < k; ++q) sub.push_back(order[(size_t)q * order.size() / k]);
+            std::vector<cryo_problem> sp;
+            double nodes = 0;
+            for (int i : sub) {
+                sp.push_back(probs[i]);
+                nodes += (double)probs[i].geom.nr * probs[i].geom.nz;
+            }
+            double best = 1e300;
+            for (const auto &sh : built) {
+                const int rows = 64 * sh[0] * sh[1];
+                if (rows < g.nr_max || (rows >= 2 * g.nr_max && sh[0] * sh[1] > 2)) continue;
+                for (int lpw : lpws) {
+                    std::vector<int32_t> shp;
+                    for (int i : sub) {
+                        shp.push_back(sh[0]);
+                        shp.push_back(sh[1]);
+                        shp.push_back(std::min(lpw, probs[i].geom.nz - 2));
+                    }
+                    cryo_batch *b = nullptr;
+                    if (cryo_batch_create((int32_t)sub.size(), sp.data(), dtype, shp.data(), &b) !=
+                        CRYO_OK)
+                        continue;
+                    int64_t nel = 0;
+                    std::vector<int64_t> off(sub.size() + 1);
+                    cryo_batch_offsets(b, off.data());
+                    nel = off.back();
+                    size_t wsb = 0;
+                    cryo_batch_workspace_bytes(b, &wsb);
+                    void *T = nullptr, *ws = nullptr;
+                    if (hipMalloc(&T, nel * (dtype == CRYO_F64 ? 8 : 4)) != hipSuccess ||
+                        hipMalloc(&ws, wsb) != hipSuccess) {
+                        if (T) (void)hipFree(T);
+                        cryo_batch_destroy(b);
+                        result = fail(CRYO_ERR_DEVICE, "batch tuner buffers");
+                        break;
+                    }
+                    cryo_status st = cryo_batch_init(b, T, s);
+                    // the first block captures the graph; the timed run replays it
+                    if (st == CRYO_OK) st = cryo_batch_forward(b, T, 0, 32, ws, wsb, s);
+                    (void)hipEventRecord(e0, s);
+                    if (st == CRYO_OK) st = cryo_batch_forward(b, T, 32, run_steps, ws, wsb, s);
+                    (void)hipEventRecord(e1, s);
+                    (void)hipEventSynchronize(e1);
+                    float ms = 0;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    if (st == CRYO_OK && cryo_batch_poll(b, ws, s, nullptr) == CRYO_OK) {
+                        const double t = 1e-3 * ms / (nodes * run_steps);
+                        if (t < best) {
+                            best = t;
+                            best_shape[0] = sh[0];
+                            best_shape[1] = sh[1];
+                            best_shape[2] = lpw;
+                        }
+                    }
+                    (void)hipFree(ws);
+                    (void)hipFree(T);
+                    cryo_batch_destroy(b);
+                }
+                if (result != CRYO_OK) break;
+            }
+            if (result != CRYO_OK) break;
+            if (best == 1e300) {
+                result = fail(CRYO_ERR_UNSUPPORTED, "no kernel shape ran for a batch group");
+                break;
+            }
+            cache_store(cache_path, kb, best_shape, 1e6 * best * nodes);
+        }
+        for (int i : g.inst) {
+            shapes[3 * i] = best_shape[0];
+            shapes[3 * i + 1] = best_shape[1];
+            shapes[3 * i + 2] = std::max(1, std::min(best_shape[2], probs[i].geom.nz - 2));
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return result;
 }
 
 }  // extern "C"
