@@ -95,7 +95,8 @@ def test_autograd_function_returns_adjoint_gradient():
     assert np.allclose(theta.grad.numpy(), gr, rtol=1e-14, atol=0)
 
 
-def test_adjoint_workload_full_size_against_reduced_oracle():
+@pytest.fixture(scope="module")
+def adjoint_workload():
     # 512 x 2048 nodes, 6 layers, 50,000 steps; the cell is exactly
     # z-invariant, so J and its gradient equal those of the 4-line reduction
     import paper_1408_5853_amd as P
@@ -105,10 +106,79 @@ def test_adjoint_workload_full_size_against_reduced_oracle():
     say("case adjoint workload 512x2048, %d steps" % n)
     Jg, gg, _ = P.gradient(c, tgt)
     Jo, go, _ = oracle.gradient(cellgen.with_nz(c, 4), tgt, ckpt=250)
+    return c, tgt, Jg, gg, Jo, go
+
+
+def test_adjoint_workload_full_size_against_reduced_oracle(adjoint_workload):
+    import paper_1408_5853_amd as P
+    c, _, Jg, gg, Jo, go = adjoint_workload
     e = _norm_err(gg, go, P.params_of(c))
     say("  J gpu %.12e oracle %.12e, normalised gradient error %.3e" % (Jg, Jo, e))
     assert Jg == pytest.approx(Jo, rel=1e-9)
     assert e < 1e-6
+
+
+# components whose log-sensitivity |g theta| is at least this fraction of the
+# largest must match the oracle adjoint to 1e-6 relative, each on its own
+SENS_FLOOR = 1e-3
+
+
+def test_adjoint_workload_per_component(adjoint_workload):
+    """Per-component bounds: 1e-6 relative for every component whose
+    log-sensitivity is at least SENS_FLOOR of the largest; below the floor
+    (sensitivities the objective barely feels) the error, scaled as a
+    log-sensitivity, must stay below 1e-9 of the largest log-sensitivity,
+    which is a relative bound of 1e-9 / (its fraction of the largest)."""
+    import paper_1408_5853_amd as P
+    c, _, _, gg, _, go = adjoint_workload
+    th = np.abs(P.params_of(c))
+    ls = np.abs(go * th)
+    frac = ls / ls.max()
+    rel = np.abs(gg - go) / np.abs(go)
+    scaled = np.abs(gg - go) * th / ls.max()
+    for q in range(len(th)):
+        say("  theta[%d] log-sensitivity fraction %.2e, relative error %.2e" % (q, frac[q], rel[q]))
+    big = frac >= SENS_FLOOR
+    assert big.sum() >= 8
+    assert np.all(rel[big] < 1e-6), rel[big]
+    assert np.all(scaled[~big] < 1e-9), scaled[~big]
+
+
+def test_adjoint_workload_central_differences(adjoint_workload):
+    """Central differences of the GPU forward's J (h = 1e-6 relative, one
+    component at a time) on the components whose log-sensitivity is at
+    least 1e-2 of the largest: there the difference quotient is accurate to
+    about 1e-7 (the rounding of J over 50,000 steps against a 2e-6 change)."""
+    import torch
+
+    import paper_1408_5853_amd as P
+    c, tgt, _, gg, _, _ = adjoint_workload
+    n = c["nsteps"]
+    th = P.params_of(c)
+    ls = np.abs(gg * th)
+    sh = P._gradient_shape(c)
+
+    def J_of(theta):
+        cc = P.with_params(c, theta)
+        plan = P.Plan(cc, "f64")
+        plan.set_shape(*sh)
+        st = P.State(plan, plan.init())
+        S = torch.zeros(n, dtype=torch.float64, device="cuda")
+        st.forward(0, n, surf=S)
+        st.poll()
+        return float(np.sum((S.cpu().numpy() - tgt) ** 2))
+
+    picked = [q for q in range(len(th)) if ls[q] >= 1e-2 * ls.max()]
+    assert len(picked) >= 4
+    for q in picked:
+        h = 1e-6 * abs(th[q])
+        tp, tm = th.copy(), th.copy()
+        tp[q] += h
+        tm[q] -= h
+        fd = (J_of(tp) - J_of(tm)) / (2 * h)
+        e = abs(fd - gg[q]) / abs(gg[q])
+        say("  theta[%d] adjoint %.10e central difference %.10e, relative %.2e" % (q, gg[q], fd, e))
+        assert e < 1e-5
 
 
 @pytest.mark.parametrize("shape", [(4, 1, 1), (8, 1, 2), (4, 2, 1)])
