@@ -13,8 +13,9 @@ Extra measurements in the same JSON line (not part of `value`): the FP32
 uneven cells) against the same cells stepped one at a time, the cost of a
 gradient (forward + checkpointed adjoint) relative to a forward on the
 adjoint workload (512 x 2048, 50,000 steps), and gradients per second of the
-batched-adjoint design loop (64 designs of 512 x 1024, a bounded sample of
-500 steps and 2 Adam iterations).
+batched-adjoint design loop (64 designs of 512 x 1024, 20 Adam iterations
+over a prefix of 1,000 of the 100,000 steps, final J checked against the
+oracle on four designs).
 
 Prints one JSON line.  --gpus above 1 is refused: the stepper runs on one GPU.
 """
@@ -143,36 +144,60 @@ def rate(P, cell, dtype, steps, warmup, stream):
 
 
 def batch_extra(P, steps, stream):
+    """The design sweep (256 uneven cells, FP32 pairs) as one batch with the
+    batch autotuner's launch shapes, against the same cells stepped one at a
+    time with tuned launches (each shape group's representative tuned by
+    cryo_autotune, its shape given to the group)."""
+    import collections
+
     import cellgen
     cells = cellgen.sweep_cells(0)
     total = sum(c["nr"] * c["nz"] for c in cells)
-    b = P.Batch(cells, "f32")
+    t0 = time.perf_counter()
+    shapes = P.tune_batch(cells, "f32")
+    tune_s = time.perf_counter() - t0
+    b = P.Batch(cells, "f32", shapes=shapes)
     T = b.init()
     ws = b.workspace()
     b.forward(T, 0, 64, ws)                                   # capture + warm
     secs_b = timed(stream, lambda: b.forward(T, 64, steps, ws))
     b.poll(ws)
-    # the same cells one at a time (each with its own launches, fields
-    # resident in the kernels' layout)
-    plans = [P.Plan(c, "f32") for c in cells]
+    # one at a time: every cell its own launches, fields resident in the
+    # kernels' layout; shapes tuned per group of equal default shape
+    groups = collections.defaultdict(list)
+    for i, c in enumerate(cells):
+        groups[P.Plan(c, "f32").shape()[:2]].append(i)
+    single = [None] * len(cells)
+    for idx in groups.values():
+        rep = max(idx, key=lambda i: cells[i]["nr"] * cells[i]["nz"])
+        sh, _ = P.autotune(cells[rep], "f32", steps=20)
+        for i in idx:
+            single[i] = (sh[0], sh[1], max(1, min(sh[2], cells[i]["nz"] - 2)))
+    plans = []
+    for c, sh in zip(cells, single):
+        p = P.Plan(c, "f32")
+        p.set_shape(*sh)
+        plans.append(p)
     states = [P.State(p, p.init()) for p in plans]
-    for s in states:
-        s.forward(0, 4)
+    for st in states:
+        st.forward(0, 4)
 
     def one_by_one():
-        for s in states:
-            s.forward(4, steps)
+        for st in states:
+            st.forward(4, steps)
 
     secs_1 = timed(stream, one_by_one)
     rate_b = total * steps / secs_b
     return {"workload": "design sweep: 256 cells, nr 128-512, nz 256-2048, 4-8 layers, FP32 pairs",
             "steps": steps, "cells": total,
+            "batch_shapes": sorted(set(shapes)), "batch_tune_s": round(tune_s, 2),
             "batched_gcell_steps_s": round(rate_b / 1e9, 2),
             # algorithmic FP32 traffic: read T, write T^ (8 B per node and step)
             "batched_hbm_frac": round(rate_b * F32_BYTES_PER_CELL_STEP / 1e9 / HBM_PEAK_GBS, 4),
             # what the compensated pairs move (16 B per node and step)
             "batched_pair_storage_frac": round(rate_b * F32_PAIR_BYTES_PER_CELL_STEP / 1e9
                                                / HBM_PEAK_GBS, 4),
+            "one_at_a_time_shapes": sorted(set(single)),
             "one_at_a_time_gcell_steps_s": round(total * steps / secs_1 / 1e9, 2),
             "speedup": round(secs_1 / secs_b, 2)}
 
@@ -206,25 +231,38 @@ def gradient_extra(P, steps, stream):
 
 
 def design_extra(P, steps, iters, stream):
-    """The batched-adjoint design loop on a bounded sample: all 64 designs of
-    512 x 1024 nodes, `steps` steps each, `iters` Adam iterations (iters + 1
-    gradient_many calls of 64 gradients)."""
+    """The batched-adjoint design loop: all 64 designs of 512 x 1024 nodes,
+    `iters` Adam iterations (iters + 1 gradient_many calls of 64 gradients)
+    over a prefix of `steps` steps of their 100,000; the final J of four
+    designs is checked against the oracle on each design's exact
+    z-invariant reduction (4 axial nodes)."""
     import cellgen
+    import numpy as np
+    import oracle
     from paper_1408_5853_amd.design import design_adam
     cells = cellgen.design_cells(0, nsteps=steps)
     tg = [cellgen.tracking_target(c, steps) for c in cells]
     P.gradient_many(cells[:2], tg[:2], streams=2)                # warm
     t0 = time.perf_counter()
-    _, hist = design_adam(cells, tg, iters=iters, lr=0.05, streams=4)
+    final, hist = design_adam(cells, tg, iters=iters, lr=0.05, streams=4)
     secs = time.perf_counter() - t0
     ngrad = len(cells) * (iters + 1)
     cell_steps = sum(c["nr"] * c["nz"] for c in cells) * steps * (iters + 1)
+    check = []
+    for i in (0, 21, 42, 63):
+        _, S = oracle.forward(cellgen.with_nz(final[i], 4), nsteps=steps, surf=True)
+        Jo = float(np.sum((S - tg[i]) ** 2))
+        check.append({"design": i, "J_gpu": float(hist[-1][i]), "J_oracle": Jo,
+                      "rel_diff": abs(float(hist[-1][i]) - Jo) / abs(Jo)})
     return {"workload": "design loop: 64 designs of 512x1024, FP64 adjoint, Adam lr 0.05 in "
-                        "log(amplitude, width, thicknesses)",
+                        "log(amplitude, width, thicknesses), prefix of %d of 100,000 steps"
+                        % steps,
             "steps": steps, "adam_iterations": iters, "gradients": ngrad,
             "seconds": round(secs, 3), "gradients_per_s": round(ngrad / secs, 2),
             "forward_equivalent_gcell_steps_s": round(cell_steps / secs / 1e9, 2),
-            "mean_J_first": float(hist[0].mean()), "mean_J_last": float(hist[-1].mean())}
+            "mean_J_first": float(hist[0].mean()), "mean_J_last": float(hist[-1].mean()),
+            "designs_improved": int(np.sum(hist[-1] < hist[0])),
+            "final_J_vs_oracle": check}
 
 
 def paper_shape_extra(P, steps, stream):
@@ -316,6 +354,9 @@ def main():
     ap.add_argument("--batch-only", type=int, default=0, metavar="N",
                     help="profiling aid: time only the batched sweep (and the same cells one "
                          "at a time) over N steps and print that result")
+    ap.add_argument("--design-only", type=int, default=0, metavar="N",
+                    help="time only the design loop (20 Adam iterations over N steps) and print "
+                         "that result")
     ap.add_argument("--poly-only", type=int, default=0, metavar="N",
                     help="profiling aid: time only N steps of the polynomial-law path on the "
                          "device cell and print that result")
@@ -337,6 +378,10 @@ def main():
         return
     if args.batch_only:
         print(json.dumps({"batch": batch_extra(P, args.batch_only, stream)}), flush=True)
+        return
+    if args.design_only:
+        print(json.dumps({"design_loop": design_extra(P, args.design_only, 20, stream)}),
+              flush=True)
         return
     if args.poly_only:
         print(json.dumps({"poly_laws": poly_extra(P, args.poly_only, stream)}), flush=True)
@@ -410,7 +455,7 @@ def main():
         log("bench: stepped domain")
         out["extra"]["stepped_domain"] = stepped_extra(P, 5000, stream)
         log("bench: design loop")
-        out["extra"]["design_loop"] = design_extra(P, 500, 2, stream)
+        out["extra"]["design_loop"] = design_extra(P, 1000, 20, stream)
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(cell, args.cpu_seconds)
