@@ -42,7 +42,7 @@ GRAD_BYTES_PER_CELL_STEP = 64     # forward 16 + recompute 16 + adjoint 32 (FP64
 # sources of this tree (their hash is written in it); otherwise null.
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_step_f64_1024x4096.md")
 KERNEL_SOURCES = ["paper_1408_5853_amd/csrc/forward.hip", "paper_1408_5853_amd/csrc/device_common.h",
-                  "paper_1408_5853_amd/csrc/internal.h", "include/cryocell.h"]
+                  "paper_1408_5853_amd/csrc/internal.h"]
 
 
 def log(*a):
