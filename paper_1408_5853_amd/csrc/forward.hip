@@ -386,12 +386,17 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
                 }
             }
             if (partial && lg == a.surf_lane) {
-                int sreg = a.surf_reg;
-                asm volatile("" : "+v"(sreg));               // cold path: no hoisting
-                double v = (double)Hn[0] + (double)Lnw[0];
+                // the surface row's register is uniform: one scalar test per
+                // register, and only the matching register's value is read
+                int sreg = __builtin_amdgcn_readfirstlane(a.surf_reg);
+                asm volatile("" : "+s"(sreg));               // cold path: no hoisting
+                double v = 0.0;
 #pragma unroll
-                for (int r = 1; r < RPL; ++r)
-                    if (r == sreg) v = (double)Hn[r] + (double)Lnw[r];
+                for (int r = 0; r < RPL; ++r)
+                    if (r == sreg) {
+                        asm volatile("" ::: "memory");       // keeps the branch
+                        v = (double)Hn[r] + (double)Lnw[r];
+                    }
                 if constexpr (STEPPED) {                    // lines 0..z_full
                     sv += j < a.z_full ? a.wz_mid * v : j == a.z_full ? a.wz_end * v : 0.0;
                     if (j == 1) sv += a.wz_end * (a.held[2] ? (double)a.val[2] : v);
