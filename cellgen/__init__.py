@@ -260,3 +260,15 @@ def poly_variant(cell, seed=0, joule_tref=0.0):
     c["poly"] = True
     c["joule_tref"] = float(joule_tref)
     return c
+
+
+def frozen(name):
+    """The problem dictionaries of a frozen workload (cellgen/frozen/NAME.json,
+    written by cellgen/freeze.py): small_cell, small_cell_z_active,
+    device_cell, device_cell_z_active, sweep_cells, adjoint_cell,
+    design_cells, paper_shape."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "frozen", name + ".json")
+    with open(path) as f:
+        return json.load(f)["problems"]

@@ -35,3 +35,15 @@ def test_tracking_target_shape_and_levels():
     t = cellgen.tracking_target(c, 60_000)
     assert t.shape == (60_000,) and set(np.unique(t)) == {28.0, 42.0}
     assert t[:4999].min() == 42.0 and t[5000:49_999].max() == 28.0
+
+
+def test_generator_reproduces_the_frozen_workloads():
+    # the frozen JSON files are the record of the measured inputs; the
+    # generator must still draw exactly them (a change to numpy's generator
+    # or to the draw order shows up here)
+    import json
+
+    from cellgen import freeze
+    for name, _, cells in freeze.workloads():
+        stored = cellgen.frozen(name)
+        assert json.loads(json.dumps(cells)) == stored, name
