@@ -9,13 +9,15 @@ its results over a 10,000-step prefix are stored rather than recomputed in
 the tests: the surface-mean trace every 10th step, and whole radial lines
 at the bottom, in the middle and in the layers below the held top line.
 Only the oracle (and the seeded input generator) is called here, with
-every host thread.  Each file records the sha256 of the oracle and the
-input generator it was made with; a CPU test checks that they are still
-the sources in the tree.  Run from the repository root:
+every host thread.  Each file records the sha256 of the oracle's sources
+and the problem dictionary it was run on; a CPU test checks that the oracle
+is unchanged and that the generator still draws that problem.  Run from the
+repository root:
 
     python tests/golden/make_twins.py
 """
 import hashlib
+import json
 import os
 import sys
 import time
@@ -31,7 +33,7 @@ import oracle  # noqa: E402
 
 STEPS = 10_000
 TRACE_EVERY = 10
-SOURCES = ["oracle/oracle.c", "oracle/__init__.py", "cellgen/__init__.py"]
+SOURCES = ["oracle/oracle.c", "oracle/__init__.py"]
 
 
 def sources_hash():
@@ -67,7 +69,8 @@ def main():
         steps = np.arange(TRACE_EVERY, STEPS + 1, TRACE_EVERY, dtype=np.int64)
         np.savez(path_of(name), steps=steps, surface=S[steps - 1], lines=lines,
                  field=T[lines], nsteps=np.int64(STEPS),
-                 sources_sha256=np.array(sources_hash()))
+                 sources_sha256=np.array(sources_hash()),
+                 problem_json=np.array(json.dumps(cell, sort_keys=True)))
         print("wrote %s (%.0f s)" % (path_of(name), time.time() - t0), flush=True)
 
 

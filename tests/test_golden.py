@@ -55,12 +55,13 @@ def test_gpu_matches_golden(name):
 
 def test_full_size_twin_fixtures_match_the_tree():
     # the stored full-size oracle runs (make_twins.py) were made by the
-    # oracle and input generator now in the tree; a change to either needs
-    # the fixtures rewritten
+    # oracle now in the tree, on the problems the generator still draws; a
+    # change to either needs the fixtures rewritten
     import make_twins
     for name, cell in make_twins.cases():
         with np.load(make_twins.path_of(name), allow_pickle=False) as z:
             assert str(z["sources_sha256"]) == make_twins.sources_hash(), name
+            assert json.loads(str(z["problem_json"])) == json.loads(json.dumps(cell)), name
             assert int(z["nsteps"]) == make_twins.STEPS
             assert list(z["lines"]) == make_twins.sample_lines(cell["nz"])
             assert z["field"].shape == (len(z["lines"]), cell["nr"])
