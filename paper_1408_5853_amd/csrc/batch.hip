@@ -103,6 +103,15 @@ static cryo_status batch_build_buckets(cryo_batch *b) {
         for (int w = 0; w < g; ++w) bk.map.push_back(make_int2((int)bk.inst.size(), w));
         bk.inst.push_back((int)i);
     }
+    // heaviest groups first: their branches are captured (and start) first,
+    // so the longest chains are not queued behind the short ones
+    auto work = [&](const Bucket &bk) {
+        double w = 0;
+        for (int i : bk.inst) w += (double)b->plans[i]->nr * b->plans[i]->nz;
+        return w;
+    };
+    std::stable_sort(b->buckets.begin(), b->buckets.end(),
+                     [&](const Bucket &x, const Bucket &y) { return work(x) > work(y); });
     const size_t ds = step_desc_bytes(b->dtype);
     size_t o = 0;
     for (Bucket &bk : b->buckets) {
