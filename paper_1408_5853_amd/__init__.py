@@ -309,6 +309,13 @@ class Batch:
         self.cells = list(cells)
         self.dtype = dtype
         n = len(self.cells)
+        for i, c in enumerate(self.cells):
+            # the batch steps the power-law cell of the problem structure; the
+            # plan options below have no batch form (a Plan per cell does)
+            for key in ("poly", "stepped", "turn_on"):
+                if c.get(key):
+                    raise ValueError("cell %d: batches do not offer the %r option; step such "
+                                     "cells with Plan" % (i, key))
         self._ps = [_abi.ProblemStruct(c) for c in self.cells]
         arr = (_abi.Problem * n)(*[p.s for p in self._ps])
         self._arr = arr
@@ -394,6 +401,10 @@ def tune_batch(cells, dtype="f32", steps=64, cache=None, stream=None):
     """Per-instance launch shapes for Batch(cells, dtype, shapes=...), timed
     on the GPU per shape group (cryo_batch_autotune); `cache` names an
     optional text file of earlier results."""
+    for i, c in enumerate(cells):
+        for key in ("poly", "stepped", "turn_on"):
+            if c.get(key):
+                raise ValueError("cell %d: batches do not offer the %r option" % (i, key))
     n = len(cells)
     ps = [_abi.ProblemStruct(c) for c in cells]
     arr = (_abi.Problem * n)(*[p.s for p in ps])

@@ -216,3 +216,17 @@ def test_stepped_domain_host_checks():
                          ctypes.c_void_p(256), 1 << 40, ctypes.byref(J), g.ctypes.data_as(dp),
                          None, None)
     assert st == 6 and "LDS" in P.lib().cryo_last_error().decode()
+
+
+def test_batch_refuses_plan_only_options():
+    # the turn-on model, the polynomial laws and the stepped domain are plan
+    # options without a batch form: a batch must refuse such cells rather
+    # than step their power-law problem (no device work happens)
+    base = cellgen.small_cell(0)
+    for extra in ({"turn_on": True}, {"stepped": {"z_full": 60, "nr_top": 30}},
+                  {"poly": True}):
+        c = dict(base, **extra)
+        with pytest.raises(ValueError):
+            P.Batch([base, c], "f64")
+        with pytest.raises(ValueError):
+            P.tune_batch([c], "f64")
