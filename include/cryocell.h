@@ -348,22 +348,39 @@ cryo_status cryo_batch_autotune(int32_t n, const cryo_problem *probs, cryo_dtype
  * otherwise, see cryo_plan_set_shape); polynomial laws are refused
  * (CRYO_ERR_UNSUPPORTED); a stepped domain (cryo_plan_set_stepped) is
  * followed.  T0 is a device field; target, J, grad and surf (nullable, N
- * values) are host arrays.  Synchronous on `stream`. */
+ * values) are host arrays.  Synchronous on `stream`; the same device work as
+ * cryo_gradient_async (results equal bit for bit). */
 cryo_status cryo_gradient_workspace_bytes(const cryo_plan *plan, int64_t nsteps, int64_t ckpt,
                                           size_t *bytes);
 cryo_status cryo_gradient(const cryo_plan *plan, const void *T0, int64_t nsteps,
                           const double *target, int64_t ckpt, void *ws, size_t ws_bytes,
                           double *J, double *grad, double *surf, void *stream);
 
+/* cryo_gradient on the caller's stream, with no host wait: target (N
+ * values), J (1), grad (2 + 2L) and surf (N values, nullable) are device
+ * arrays, and every phase (forward with checkpoints, J and the seeds dJ/dS_n,
+ * the backward sweep, the fixed-order parameter sums) is a launch or a
+ * device-to-device copy on `stream`, so a caller may capture it in a HIP
+ * graph once the plan holds its device tables (made by any earlier call on
+ * it; a capture must not be the plan's first device use).  Workspace as for
+ * cryo_gradient; the buffers must stay alive until the stream has finished.
+ * A non-finite temperature is not returned: cryo_poll(plan, ws, stream)
+ * reports it afterwards.  Argument errors as cryo_gradient. */
+cryo_status cryo_gradient_async(const cryo_plan *plan, const void *T0, int64_t nsteps,
+                                const double *target, int64_t ckpt, void *ws, size_t ws_bytes,
+                                double *J, double *grad, double *surf, void *stream);
+
 /* Gradients of n designs (the batched design loop): the same as n calls of
  * cryo_gradient, design i with plans[i], T0[i], targets[i] (nsteps values),
  * ws[i] of ws_bytes[i] bytes (cryo_gradient_workspace_bytes of plans[i]),
  * results J[i], grad[i] (2 + 2 L_i values) and surf_out[i] (nullable array,
- * nullable entries).  The designs run on n_streams library-created streams
- * of default priority: every forward is enqueued, then each design's trace is
- * read, then every backward sweep is enqueued, then the sums are reduced; the
- * results equal those of the single calls bit for bit.  Synchronous; errors
- * name the failing design. */
+ * nullable entries).  The designs run on n_streams streams of default
+ * priority that the library makes on first use and keeps per device (they do
+ * not wait for other streams: T0 must be ready when the call is made).
+ * Every target is copied in, then each design's whole gradient is enqueued
+ * on stream i mod n_streams, then the results are read; they equal those of
+ * the single calls bit for bit.  Synchronous; errors name the failing
+ * design. */
 cryo_status cryo_gradient_many(int32_t n, cryo_plan *const *plans, const void *const *T0,
                                int64_t nsteps, const double *const *targets, int64_t ckpt,
                                void *const *ws, const size_t *ws_bytes, int32_t n_streams,

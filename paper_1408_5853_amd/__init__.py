@@ -14,8 +14,8 @@ import numpy as np
 from . import _abi
 from ._abi import CryoError, check, lib
 
-__all__ = ["Plan", "State", "Batch", "CryoError", "CryoSolve", "gradient", "with_params", "params_of",
-           "autotune", "tune_batch",
+__all__ = ["Plan", "State", "Batch", "CryoError", "CryoSolve", "gradient", "gradient_plan",
+           "with_params", "params_of", "autotune", "tune_batch",
            "validate", "stability_dt_max", "version"]
 
 
@@ -214,11 +214,7 @@ class Plan:
     def poll(self, ws, stream=None):
         check(lib().cryo_poll(self._h, _ptr(ws), _stream(stream)))
 
-    def gradient(self, target, T0=None, nsteps=None, ckpt=0, stream=None):
-        """J = sum_n (S_n - target_n)^2 and dJ/d[amplitude, width, thickness_m,
-        k_scale_m] by the discrete adjoint (FP64 plans).  Returns (J, grad,
-        surface trace) as float, numpy, numpy.  Synchronous."""
-        torch = _torch()
+    def _gradient_ready(self):
         if self.shape()[:2] not in _ADJOINT_SHAPES:
             # the adjoint kernels take 2, 4 or 8 rows per lane: switch to the
             # gradient shape while the plan has not run yet (else the library
@@ -229,14 +225,24 @@ class Plan:
                     self.set_shape(*sh)
                 except CryoError:
                     pass
+
+    def gradient_workspace_bytes(self, nsteps, ckpt=0):
+        b = C.c_size_t()
+        check(lib().cryo_gradient_workspace_bytes(self._h, int(nsteps), int(ckpt), C.byref(b)))
+        return b.value
+
+    def gradient(self, target, T0=None, nsteps=None, ckpt=0, stream=None):
+        """J = sum_n (S_n - target_n)^2 and dJ/d[amplitude, width, thickness_m,
+        k_scale_m] by the discrete adjoint (FP64 plans).  Returns (J, grad,
+        surface trace) as float, numpy, numpy.  Synchronous."""
+        torch = _torch()
+        self._gradient_ready()
         n = int(self.cell["nsteps"] if nsteps is None else nsteps)
         tgt = np.ascontiguousarray(np.asarray(target, dtype=np.float64)[:n])
         if tgt.size < n:
             raise ValueError("target needs nsteps values")
         T = self.init() if T0 is None else self.field_from(T0)
-        b = C.c_size_t()
-        check(lib().cryo_gradient_workspace_bytes(self._h, n, int(ckpt), C.byref(b)))
-        ws = torch.empty(b.value, dtype=torch.uint8, device="cuda")
+        ws = torch.empty(self.gradient_workspace_bytes(n, ckpt), dtype=torch.uint8, device="cuda")
         J = C.c_double()
         L = len(self.cell["layers"])
         g = np.zeros(2 + 2 * L)
@@ -246,6 +252,32 @@ class Plan:
                                   _ptr(ws), ws.numel(), C.byref(J), g.ctypes.data_as(dp),
                                   S.ctypes.data_as(dp), _stream(stream)))
         return J.value, g, S
+
+    def gradient_async(self, target, T0, nsteps=None, ckpt=0, ws=None, stream=None):
+        """The gradient enqueued on the stream with no host wait
+        (cryo_gradient_async).  `target` (float64 CUDA tensor, nsteps values)
+        and the field T0 (this plan's Field layout) are read on the device.
+        Returns (J [1], grad [2 + 2L], surface trace [nsteps], ws), float64
+        CUDA tensors and the workspace (made here when None), which must stay
+        alive until the stream has finished; poll(ws) then reports a
+        non-finite temperature."""
+        torch = _torch()
+        self._gradient_ready()
+        n = int(self.cell["nsteps"] if nsteps is None else nsteps)
+        if (target.dtype != torch.float64 or not target.is_cuda or target.numel() < n
+                or not target.is_contiguous()):
+            raise ValueError("target must be a contiguous float64 CUDA tensor of length >= nsteps")
+        if ws is None:
+            ws = torch.empty(self.gradient_workspace_bytes(n, ckpt), dtype=torch.uint8,
+                             device="cuda")
+        L = len(self.cell["layers"])
+        J = torch.empty(1, dtype=torch.float64, device="cuda")
+        g = torch.empty(2 + 2 * L, dtype=torch.float64, device="cuda")
+        S = torch.empty(n, dtype=torch.float64, device="cuda")
+        check(lib().cryo_gradient_async(self._h, _ptr(T0), n, _ptr(target),
+                                        int(ckpt), _ptr(ws), ws.numel(), _ptr(J), _ptr(g),
+                                        _ptr(S), _stream(stream)))
+        return J, g, S, ws
 
 
 class State:
@@ -456,13 +488,19 @@ def _gradient_shape(cell):
     return (rpl, w, lpw)
 
 
-def gradient(cell, target, T0=None, nsteps=None, ckpt=0):
-    """(J, dJ/dtheta, surface trace) of `cell` on the GPU (FP64)."""
+def gradient_plan(cell):
+    """An FP64 plan of `cell` with the gradient's launch shape (set before
+    the plan's first device use, as the library requires)."""
     plan = Plan(cell, "f64")
     sh = _gradient_shape(cell)
     if sh is not None:
         plan.set_shape(*sh)
-    return plan.gradient(target, T0=T0, nsteps=nsteps, ckpt=ckpt)
+    return plan
+
+
+def gradient(cell, target, T0=None, nsteps=None, ckpt=0):
+    """(J, dJ/dtheta, surface trace) of `cell` on the GPU (FP64)."""
+    return gradient_plan(cell).gradient(target, T0=T0, nsteps=nsteps, ckpt=ckpt)
 
 
 def gradient_many(cells, targets, nsteps=None, ckpt=0, streams=4, T0s=None):
@@ -474,10 +512,7 @@ def gradient_many(cells, targets, nsteps=None, ckpt=0, streams=4, T0s=None):
     N = int(cells[0]["nsteps"] if nsteps is None else nsteps)
     plans, fields, wss, tg = [], [], [], []
     for i, c in enumerate(cells):
-        plan = Plan(c, "f64")
-        sh = _gradient_shape(c)
-        if sh is not None:
-            plan.set_shape(*sh)
+        plan = gradient_plan(c)
         plans.append(plan)
         fields.append(plan.init() if T0s is None or T0s[i] is None else plan.field_from(T0s[i]))
         b = C.c_size_t()

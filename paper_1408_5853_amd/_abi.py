@@ -25,8 +25,8 @@ SYMBOLS = [
     "cryo_plan_set_stepped",
     "cryo_batch_create", "cryo_batch_destroy", "cryo_batch_offsets", "cryo_batch_shape",
     "cryo_batch_workspace_bytes", "cryo_batch_init", "cryo_batch_forward", "cryo_batch_poll",
-    "cryo_gradient_workspace_bytes", "cryo_gradient", "cryo_gradient_many", "cryo_autotune",
-    "cryo_batch_autotune",
+    "cryo_gradient_workspace_bytes", "cryo_gradient", "cryo_gradient_async", "cryo_gradient_many",
+    "cryo_autotune", "cryo_batch_autotune",
     "cryo_state_create", "cryo_state_destroy", "cryo_state_load", "cryo_state_forward",
     "cryo_state_store", "cryo_forward_noalloc",
 ]
@@ -124,6 +124,7 @@ def lib():
                                           i32p]
         L.cryo_gradient_workspace_bytes.argtypes = [vp, i64, i64, C.POINTER(C.c_size_t)]
         L.cryo_gradient.argtypes = [vp, vp, i64, dp, i64, vp, C.c_size_t, dp, dp, dp, vp]
+        L.cryo_gradient_async.argtypes = [vp, vp, i64, vp, i64, vp, C.c_size_t, vp, vp, vp, vp]
         L.cryo_gradient_many.argtypes = [C.c_int32, C.POINTER(vp), C.POINTER(vp), i64,
                                          C.POINTER(dp), i64, C.POINTER(vp),
                                          C.POINTER(C.c_size_t), C.c_int32, dp, C.POINTER(dp),

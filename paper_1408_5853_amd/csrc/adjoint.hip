@@ -124,6 +124,7 @@ __device__ inline void adj1_body(const StepArgs<double> &a, const AdjArgs &d,
     const size_t LS = a.np;
     const int qW = lg > 0 ? (RPL - 1) * NL + lg - 1 : 0;
     const int qE = lg < NL - 1 ? lg + 1 : (RPL - 1) * NL + lg;
+    const double cS = d.cS ? *d.cS : 0.0;                    // dJ/dS of this state
     // per-row sums over the group's lines, in LDS (registers): [wave][row][lane]
     double *accW = (double *)(smem + adj_acc_offset(a.laws.L, a.np)) + (size_t)wv * RPL * WAVE + lane;
     double *accE = accW + (size_t)ADJ_WAVES * RPL * WAVE;
@@ -295,7 +296,7 @@ __device__ inline void adj1_body(const StepArgs<double> &a, const AdjArgs &d,
                 const double ow = cap ? y[r] * fwT * Dw : 0.0;       // into row r-1
                 const double oe = cap ? y[r] * feT * De : 0.0;       // into row r+1
                 double lp = -(y[r] * self + oe_prev);
-                if (lg == a.surf_lane && r == a.surf_reg) lp += d.cS * surf_weight<STEPPED>(a, j);
+                if (lg == a.surf_lane && r == a.surf_reg) lp += cS * surf_weight<STEPPED>(a, j);
                 if (r > 0) d.lpart[base + q - NL] = lp_prev - ow;
                 d.Y[base + q] = y[r];
                 oe_prev = oe;
@@ -366,6 +367,7 @@ __device__ inline void adj2_body(const StepArgs<double> &a, const AdjArgs &d,
     const int j0 = 1 + gidx * a.lpw;
     const int j1 = min(j0 + a.lpw, a.nz - 1);
     const size_t LS = a.np;
+    const double cS = d.cS ? *d.cS : 0.0;                    // dJ/dS of this state
     double accZ[RPL];
     // carried from the previous line of the group: the face (j-1, j) flux
     // F = lam (T_j - T_{j-1}) and dF/dT_j; and the lines j, j-1 (T, Y)
@@ -396,7 +398,7 @@ __device__ inline void adj2_body(const StepArgs<double> &a, const AdjArgs &d,
         Ys[r] = jb - 1 >= 1 ? d.Y[bb - LS + q] : 0.0;
         if (j0 == 1 && j0 < j1) {
             double l0 = (gs * ds - ls) * (0.0 - y);            // d F_S / d T_0
-            if (lg == a.surf_lane && r == a.surf_reg) l0 += d.cS * a.wz_end;
+            if (lg == a.surf_lane && r == a.surf_reg) l0 += cS * a.wz_end;
             d.lam_out[q] = l0;
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -441,7 +443,7 @@ __device__ inline void adj2_body(const StepArgs<double> &a, const AdjArgs &d,
                 // the upper boundary line: its face with line nz-2
                 double le_ = cdF[r] * (y - 0.0);                    // d F_N / d T_{nz-1}
                 // (on a stepped domain the top line is not on the surface)
-                if (!STEPPED && lg == a.surf_lane && r == a.surf_reg) le_ += d.cS * a.wz_end;
+                if (!STEPPED && lg == a.surf_lane && r == a.surf_reg) le_ += cS * a.wz_end;
                 d.lam_out[(size_t)(a.nz - 1) * LS + q] = le_;
             }
             if (keep) lamR[r] = lam;
@@ -499,8 +501,9 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj21(StepArgs<double> a, A
 }
 
 // lam^N = dJ_N / dT^N: the surface weights on the outer row
-__global__ void k_adj_init(double *lam, int nz, int np, int q_surf, double cS, double wz_end,
-                           double wz_mid, int J) {
+__global__ void k_adj_init(double *lam, int nz, int np, int q_surf, const double *cSp,
+                           double wz_end, double wz_mid, int J) {
+    const double cS = *cSp;
     size_t n = (size_t)nz * np;
     for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < n;
          idx += (size_t)gridDim.x * blockDim.x) {
@@ -589,7 +592,7 @@ cryo_status launch_adj(const cryo_plan *p, int pass, const AdjArgs &d, int *flag
                                                                   : "adjoint passes 2+1");
 }
 
-cryo_status launch_adj_init(const cryo_plan *p, double *lam, double cS, hipStream_t s) {
+cryo_status launch_adj_init(const cryo_plan *p, double *lam, const double *cS, hipStream_t s) {
     const int q = p->surf_reg * (WAVE * p->wpl) + p->surf_lane;
     size_t n = (size_t)p->nz * p->np;
     int blocks = (int)std::min<size_t>((n + 255) / 256, 65536);

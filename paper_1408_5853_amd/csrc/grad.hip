@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -14,7 +15,7 @@ namespace cryo {
 
 cryo_status launch_adj(const cryo_plan *p, int pass, const AdjArgs &d, int *flag, hipStream_t s,
                        const AdjArgs *d1 = nullptr);
-cryo_status launch_adj_init(const cryo_plan *p, double *lam, double cS, hipStream_t s);
+cryo_status launch_adj_init(const cryo_plan *p, double *lam, const double *cS, hipStream_t s);
 cryo_status launch_zero(double *ptr, size_t n, hipStream_t s);
 int adj_slots(const cryo_plan *p);
 size_t adj_lds(const cryo_plan *p);
@@ -90,7 +91,8 @@ static int64_t launch_count(const cryo_plan *p, int64_t N) {
 }
 
 struct GradLayout {
-    size_t flag, fwd_buf[2], part, ck, seg, lam[2], Y[2], lpart[2], acc, accg, surf, total;
+    size_t flag, fwd_buf[2], part, ck, seg, lam[2], Y[2], lpart[2], acc, accg, surf, tgt, seed,
+        rs, out, total;
     int64_t nck, K;
 };
 
@@ -121,27 +123,164 @@ static GradLayout grad_layout(const cryo_plan *p, int64_t N, int64_t ckpt) {
     g.acc = o; o += al256(sizeof(double) * 3 * (size_t)p->np * adj_slots(p));
     g.accg = o; o += al256(sizeof(double) * 2 * (size_t)adj_slots(p));
     g.surf = o; o += al256(sizeof(double) * (size_t)std::max<int64_t>(N, 1));
+    // a host target's copy, the seeds dJ/dS_n (n = 0..N), the per-row face
+    // sums, and J and grad for a host caller
+    g.tgt = o; o += al256(sizeof(double) * (size_t)std::max<int64_t>(N, 1));
+    g.seed = o; o += al256(sizeof(double) * (size_t)(N + 1));
+    g.rs = o; o += al256(sizeof(double) * 3 * (size_t)p->nr);
+    g.out = o; o += al256(sizeof(double) * (3 + 2 * (size_t)p->L));
     g.total = o;
     return g;
+}
+
+// The weights of the parameter gradient, from the geometry: h_i = thick_m /
+// n_m on the intervals of layer m and r_i = r_inner + the h up to i, so each
+// capacity row's faces (eq. (13)) and each interface row's two one-sided
+// fluxes (eq. (18)) move with every thickness, and every face law is
+// k_scale_m times the layer's law.  Layout (doubles): W[nr][L] and E[nr][L],
+// the thickness weights of a row's west and east face sums; per row {class
+// (0 none, 1 capacity, 2 interface), inner layer, outer layer}; k_scale[L].
+std::vector<double> grad_param_table(const cryo_plan *p) {
+    const int nr = p->nr, L = p->L;
+    std::vector<double> t(grad_param_doubles(nr, L), 0.0);
+    double *W = t.data(), *E = W + (size_t)nr * L, *rowc = E + (size_t)nr * L;
+    double *ks = rowc + 3 * (size_t)nr;
+    std::vector<double> dr((size_t)nr * L, 0.0), dh((size_t)(nr + 1) * L, 0.0);
+    for (int i = 1; i < nr; ++i) {
+        const int m = p->lay[i];
+        dh[(size_t)i * L + m] = 1.0 / p->layers[m].intervals;
+        for (int l = 0; l < L; ++l) dr[(size_t)i * L + l] = dr[(size_t)(i - 1) * L + l] + dh[(size_t)i * L + l];
+    }
+    const std::vector<double> &r = p->r, &h = p->h;
+    for (int i = 1; i < nr - 1; ++i) {
+        if (p->kind[i] == K_CAP) {
+            const int m = p->lay[i];
+            rowc[3 * i] = 1.0;
+            rowc[3 * i + 1] = rowc[3 * i + 2] = m;
+            const double rw = 0.5 * (r[i] + r[i - 1]), re = 0.5 * (r[i] + r[i + 1]);
+            const double hb = 0.5 * (h[i] + h[i + 1]);
+            for (int l = 0; l < L; ++l) {
+                const double dri = dr[(size_t)i * L + l];
+                const double drw = 0.5 * (dri + dr[(size_t)(i - 1) * L + l]);
+                const double dre = 0.5 * (dri + dr[(size_t)(i + 1) * L + l]);
+                const double dhi = dh[(size_t)i * L + l], dhe = dh[(size_t)(i + 1) * L + l];
+                const double dhb = 0.5 * (dhi + dhe);
+                W[(size_t)i * L + l] = drw / rw - dri / r[i] - dhb / hb - dhi / h[i];
+                E[(size_t)i * L + l] = dre / re - dri / r[i] - dhb / hb - dhe / h[i + 1];
+            }
+        } else if (p->kind[i] == K_IFACE) {
+            rowc[3 * i] = 2.0;
+            rowc[3 * i + 1] = p->lay[i];
+            rowc[3 * i + 2] = p->lay[i + 1];
+            for (int l = 0; l < L; ++l) {
+                W[(size_t)i * L + l] = dh[(size_t)(i + 1) * L + l] / h[i + 1];
+                E[(size_t)i * L + l] = dh[(size_t)i * L + l] / h[i];
+            }
+        }
+    }
+    for (int m = 0; m < L; ++m) ks[m] = p->layers[m].mat.k_scale;
+    return t;
+}
+
+// J = sum_n (S_n - target_n)^2 and the seeds seed[n] = dJ/dS_n = 2 (S_n -
+// target_n), seed[0] = 0 (the initial state is not observed).  One
+// workgroup: each thread sums its strided terms in order, then a fixed tree.
+constexpr int OBJ_THREADS = 1024;
+__global__ __launch_bounds__(OBJ_THREADS) void k_objective(const double *S, const double *tgt,
+                                                           int64_t N, double *seed, double *J) {
+    __shared__ double part[OBJ_THREADS];
+    const int t = threadIdx.x;
+    double a = 0.0;
+    for (int64_t n = t; n < N; n += OBJ_THREADS) {
+        const double dv = S[n] - tgt[n];
+        seed[n + 1] = 2.0 * dv;
+        a += dv * dv;
+    }
+    if (t == 0) seed[0] = 0.0;
+    part[t] = a;
+    __syncthreads();
+    for (int w = OBJ_THREADS / 2; w > 0; w >>= 1) {
+        if (t < w) part[t] += part[t + w];
+        __syncthreads();
+    }
+    if (t == 0) *J = part[0];
+}
+
+// The adjoint's per-row face sums over its workgroup slots, in slot order:
+// rs[c * nr + i] for c = west, east, axial and row i (lane-major position q).
+__global__ void k_grad_rows(const double *acc, int ngrp, int nr, int np, int rpl, double *rs) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= 3 * nr) return;
+    const int c = idx / nr, i = idx % nr;
+    const int q = (i % rpl) * (np / rpl) + i / rpl;
+    double v = 0.0;
+    for (int gi = 0; gi < ngrp; ++gi) v += acc[(size_t)gi * 3 * np + (size_t)c * np + q];
+    rs[idx] = v;
+}
+
+// grad = [amplitude, width, thickness_0..L-1, k_scale_0..L-1], one
+// workgroup per parameter: each thread sums its strided terms (the slots'
+// source sums, or the rows' face sums times their weights) in order, then a
+// fixed tree
+constexpr int PAR_THREADS = 256;
+__global__ __launch_bounds__(PAR_THREADS) void k_grad_params(const double *rs, const double *accg,
+                                                             int ngrp, int nr, int L,
+                                                             const double *tab, double *grad) {
+    __shared__ double part[PAR_THREADS];
+    const double *W = tab, *E = tab + (size_t)nr * L, *rowc = tab + 2 * (size_t)nr * L;
+    const double *ks = rowc + 3 * (size_t)nr;
+    const double *SW = rs, *SE = rs + nr, *SZ = rs + 2 * (size_t)nr;
+    const int t = threadIdx.x, par = blockIdx.x;
+    double g = 0.0;
+    if (par < 2) {
+        for (int gi = t; gi < ngrp; gi += PAR_THREADS) g += accg[2 * gi + par];
+    } else if (par < 2 + L) {
+        const int l = par - 2;
+        for (int i = 1 + t; i < nr - 1; i += PAR_THREADS)
+            g -= SW[i] * W[(size_t)i * L + l] + SE[i] * E[(size_t)i * L + l];
+    } else {
+        const int m = par - 2 - L;
+        for (int i = 1 + t; i < nr - 1; i += PAR_THREADS) {
+            const double cls = rowc[3 * i];
+            const int a = (int)rowc[3 * i + 1], b = (int)rowc[3 * i + 2];
+            if (cls == 1.0) {
+                if (a == m) g -= (SW[i] + SE[i] - SZ[i]) / ks[m];
+            } else if (cls == 2.0) {
+                if (a == m) g -= SW[i] / ks[a];
+                if (b == m) g -= SE[i] / ks[b];
+            }
+        }
+    }
+    part[t] = g;
+    __syncthreads();
+    for (int w = PAR_THREADS / 2; w > 0; w >>= 1) {
+        if (t < w) part[t] += part[t + w];
+        __syncthreads();
+    }
+    if (t == 0) grad[par] = part[0];
+}
+
+static cryo_status launched(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(CRYO_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return CRYO_OK;
 }
 
 }  // namespace cryo
 
 namespace cryo {
 
-// One gradient in phases, so that many can be in flight on several streams:
-// enqueue the forward with checkpoints, read the surface trace (J and the
-// adjoint seeds), enqueue the backward sweep, reduce the sums on the host.
+// One gradient, every phase on one stream with no host wait: the forward
+// with checkpoints, J and the seeds, the backward sweep, the parameter sums.
 struct GradRun {
     cryo_plan *p;
     const void *T0;
     int64_t N;
-    const double *target;
+    const double *target;     // device, N values
+    double *J, *grad;         // device results
     char *w;
     GradLayout g;
     hipStream_t s;
-    std::vector<double> S, cS;
-    double J;
     std::vector<Launch> L;    // the run's kernel steps
 };
 
@@ -167,7 +306,21 @@ static cryo_status grad_check(const cryo_plan *p, int64_t N, const double *targe
 
 static size_t field_f64(const cryo_plan *p) { return al256(8 * (size_t)p->nz * p->np); }
 
-// forward with checkpoints and the surface trace (enqueued on r.s)
+static GradRun grad_run(const cryo_plan *p, const void *T0, int64_t N, int64_t ckpt, void *ws,
+                        hipStream_t s) {
+    GradRun r;
+    r.p = const_cast<cryo_plan *>(p);
+    r.T0 = T0;
+    r.N = N;
+    r.w = (char *)ws;
+    r.g = grad_layout(p, N, ckpt);
+    r.s = s;
+    r.target = nullptr;
+    r.J = r.grad = nullptr;
+    return r;
+}
+
+// forward with checkpoints and the surface trace
 static cryo_status grad_forward(GradRun &r) {
     cryo_plan *p = r.p;
     cryo_status st = ensure_device(p);
@@ -207,21 +360,12 @@ static cryo_status grad_forward(GradRun &r) {
     return CRYO_OK;
 }
 
-// wait for the forward, read the trace: J and the seeds dJ/dS_n
+// J and the seeds dJ/dS_n, from the trace on the device
 static cryo_status grad_objective(GradRun &r) {
-    r.S.assign(r.N, 0.0);
-    if (hipMemcpyAsync(r.S.data(), r.w + r.g.surf, sizeof(double) * r.N, hipMemcpyDeviceToHost,
-                       r.s) != hipSuccess ||
-        hipStreamSynchronize(r.s) != hipSuccess)
-        return fail(CRYO_ERR_DEVICE, "surface trace copy");
-    r.J = 0.0;
-    r.cS.assign(r.N + 1, 0.0);
-    for (int64_t n = 1; n <= r.N; ++n) {
-        const double dv = r.S[n - 1] - r.target[n - 1];
-        r.J += dv * dv;
-        r.cS[n] = 2.0 * dv;
-    }
-    return CRYO_OK;
+    hipLaunchKernelGGL(k_objective, dim3(1), dim3(OBJ_THREADS), 0, r.s,
+                       (const double *)(r.w + r.g.surf), r.target, r.N,
+                       (double *)(r.w + r.g.seed), r.J);
+    return launched("objective");
 }
 
 // segments backwards: restore the checkpoint, recompute, adjoint steps
@@ -234,12 +378,13 @@ static cryo_status grad_backward(GradRun &r) {
     const size_t F = field_f64(p);
     auto ckp = [&](int64_t i) { return (double *)(w + g.ck + F * i); };
     auto segp = [&](int64_t i) { return (double *)(w + g.seg + F * i); };
+    const double *seed = (const double *)(w + g.seed);
     const int ngrp = adj_slots(p);
     double *acc = (double *)(w + g.acc), *accg = (double *)(w + g.accg);
     cryo_status st = launch_zero(acc, 3 * (size_t)p->np * ngrp, s);
     if (st == CRYO_OK) st = launch_zero(accg, 2 * (size_t)ngrp, s);
     double *lam[2] = {(double *)(w + g.lam[0]), (double *)(w + g.lam[1])};
-    if (st == CRYO_OK) st = launch_adj_init(p, lam[0], r.cS[r.N], s);
+    if (st == CRYO_OK) st = launch_adj_init(p, lam[0], seed + r.N, s);
     if (st != CRYO_OK) return st;
     int cur = 0;
     const int64_t M = (int64_t)r.L.size();
@@ -270,7 +415,7 @@ static cryo_status grad_backward(GradRun &r) {
             d.s = r.L[k].s;
             d.ds = r.L[k].ds;
             // the state before launch k is observed when launch k-1 ends a step
-            d.cS = k >= 1 && r.L[k - 1].obs > 0 ? r.cS[r.L[k - 1].obs] : 0.0;
+            d.cS = k >= 1 && r.L[k - 1].obs > 0 ? seed + r.L[k - 1].obs : nullptr;
             d.xs = p->eta * p->eta;
             return d;
         };
@@ -290,82 +435,79 @@ static cryo_status grad_backward(GradRun &r) {
     return CRYO_OK;
 }
 
-// wait for the backward; row sums over workgroup slots (fixed order), then the
-// parameter gradient
-static cryo_status grad_finish(GradRun &run, double *grad) {
-    cryo_plan *p = run.p;
-    const GradLayout &g = run.g;
-    char *w = run.w;
-    hipStream_t s = run.s;
+// row sums over the workgroup slots (fixed order), then the parameters
+static cryo_status grad_finish(GradRun &r) {
+    cryo_plan *p = r.p;
+    const GradLayout &g = r.g;
+    double *rs = (double *)(r.w + g.rs);
     const int ngrp = adj_slots(p);
-    const double *acc = (const double *)(w + g.acc), *accg = (const double *)(w + g.accg);
-    std::vector<double> hacc(3 * (size_t)p->np * ngrp), hg(2 * (size_t)ngrp);
+    hipLaunchKernelGGL(k_grad_rows, dim3((3 * p->nr + 255) / 256), dim3(256), 0, r.s,
+                       (const double *)(r.w + g.acc), ngrp, p->nr, p->np, p->rpl, rs);
+    cryo_status st = launched("gradient row sums");
+    if (st != CRYO_OK) return st;
+    if (!p->d_grad) return fail(CRYO_ERR_ARG, "the plan has no gradient tables");
+    hipLaunchKernelGGL(k_grad_params, dim3(2 + 2 * p->L), dim3(PAR_THREADS), 0, r.s,
+                       (const double *)rs, (const double *)(r.w + g.accg), ngrp, p->nr, p->L,
+                       (const double *)p->d_grad, r.grad);
+    return launched("gradient parameters");
+}
+
+static cryo_status grad_enqueue(GradRun &r) {
+    cryo_status st = grad_forward(r);
+    if (st == CRYO_OK) st = grad_objective(r);
+    if (st == CRYO_OK) st = grad_backward(r);
+    if (st == CRYO_OK) st = grad_finish(r);
+    return st;
+}
+
+// a host caller's target goes to the workspace, J and grad come from it
+static cryo_status grad_stage_host(GradRun &r, const double *target) {
+    double *t = (double *)(r.w + r.g.tgt);
+    if (hipMemcpyAsync(t, target, sizeof(double) * r.N, hipMemcpyHostToDevice, r.s) != hipSuccess)
+        return fail(CRYO_ERR_DEVICE, "target copy");
+    r.target = t;
+    r.J = (double *)(r.w + r.g.out);
+    r.grad = r.J + 1;
+    return CRYO_OK;
+}
+
+// wait for a host caller's run; results and the error word to the host
+static cryo_status grad_collect(GradRun &r, double *J, double *grad, double *surf_out) {
+    const int ng = 2 + 2 * r.p->L;
+    std::vector<double> out(1 + ng);
     int hflag = 0;
-    if (hipMemcpyAsync(hacc.data(), acc, sizeof(double) * hacc.size(), hipMemcpyDeviceToHost, s) !=
+    if (hipMemcpyAsync(out.data(), r.J, sizeof(double) * out.size(), hipMemcpyDeviceToHost,
+                       r.s) != hipSuccess ||
+        (surf_out && hipMemcpyAsync(surf_out, r.w + r.g.surf, sizeof(double) * r.N,
+                                    hipMemcpyDeviceToHost, r.s) != hipSuccess) ||
+        hipMemcpyAsync(&hflag, r.w + r.g.flag, sizeof(int), hipMemcpyDeviceToHost, r.s) !=
             hipSuccess ||
-        hipMemcpyAsync(hg.data(), accg, sizeof(double) * hg.size(), hipMemcpyDeviceToHost, s) !=
-            hipSuccess ||
-        hipMemcpyAsync(&hflag, w + g.flag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-        return fail(CRYO_ERR_DEVICE, "gradient sums copy");
+        hipStreamSynchronize(r.s) != hipSuccess)
+        return fail(CRYO_ERR_DEVICE, "gradient results copy");
     if (hflag) return fail(CRYO_ERR_NONFINITE, "non-finite or out-of-range temperature produced");
-    const int nr = p->nr, L = p->L, np = p->np, rpl = p->rpl, NL = np / rpl;
-    std::vector<double> SW(nr, 0.0), SE(nr, 0.0), SZ(nr, 0.0);
-    for (int i = 0; i < nr; ++i) {
-        const int q = (i % rpl) * NL + i / rpl;
-        for (int gi = 0; gi < ngrp; ++gi) {
-            const double *A = hacc.data() + (size_t)gi * 3 * np;
-            SW[i] += A[q];
-            SE[i] += A[np + q];
-            SZ[i] += A[2 * np + q];
-        }
+    *J = out[0];
+    memcpy(grad, out.data() + 1, sizeof(double) * ng);
+    return CRYO_OK;
+}
+
+// streams of cryo_gradient_many: made once per device, kept until the
+// process ends (default priority, not synchronising with the null stream)
+static std::mutex g_pool_mu;
+static std::vector<hipStream_t> g_pool[64];
+
+static cryo_status pool_streams(int n, std::vector<hipStream_t> &out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return fail(CRYO_ERR_DEVICE, "current device");
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    std::vector<hipStream_t> &v = g_pool[dev];
+    while ((int)v.size() < n) {
+        hipStream_t x = nullptr;
+        if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess)
+            return fail(CRYO_ERR_DEVICE, "stream creation");
+        v.push_back(x);
     }
-    double gQ = 0.0, gW = 0.0;
-    for (int gi = 0; gi < ngrp; ++gi) {
-        gQ += hg[2 * gi];
-        gW += hg[2 * gi + 1];
-    }
-    // geometry derivatives: h_i = thick_m / n_m for intervals of layer m,
-    // r_i = r_inner + sum of h up to i
-    std::vector<double> dr((size_t)nr * L, 0.0), dh((size_t)(nr + 1) * L, 0.0);
-    for (int i = 1; i < nr; ++i) {
-        const int m = p->lay[i];
-        dh[(size_t)i * L + m] = 1.0 / p->layers[m].intervals;
-        for (int l = 0; l < L; ++l) dr[(size_t)i * L + l] = dr[(size_t)(i - 1) * L + l] + dh[(size_t)i * L + l];
-    }
-    std::vector<double> gd(L, 0.0), gs(L, 0.0);
-    const std::vector<double> &r = p->r, &h = p->h;
-    for (int i = 1; i < nr - 1; ++i) {
-        if (p->kind[i] == K_CAP) {
-            const int m = p->lay[i];
-            gs[m] -= (SW[i] + SE[i] - SZ[i]) / p->layers[m].mat.k_scale;
-            const double rw = 0.5 * (r[i] + r[i - 1]), re = 0.5 * (r[i] + r[i + 1]);
-            const double hb = 0.5 * (h[i] + h[i + 1]);
-            for (int l = 0; l < L; ++l) {
-                const double dri = dr[(size_t)i * L + l];
-                const double drw = 0.5 * (dri + dr[(size_t)(i - 1) * L + l]);
-                const double dre = 0.5 * (dri + dr[(size_t)(i + 1) * L + l]);
-                const double dhi = dh[(size_t)i * L + l], dhe = dh[(size_t)(i + 1) * L + l];
-                const double dhb = 0.5 * (dhi + dhe);
-                const double wW = drw / rw - dri / r[i] - dhb / hb - dhi / h[i];
-                const double wE = dre / re - dri / r[i] - dhb / hb - dhe / h[i + 1];
-                gd[l] -= SW[i] * wW + SE[i] * wE;
-            }
-        } else if (p->kind[i] == K_IFACE) {
-            const int a = p->lay[i], b = p->lay[i + 1];
-            gs[a] -= SW[i] / p->layers[a].mat.k_scale;
-            gs[b] -= SE[i] / p->layers[b].mat.k_scale;
-            for (int l = 0; l < L; ++l)
-                gd[l] -= SW[i] * dh[(size_t)(i + 1) * L + l] / h[i + 1] +
-                         SE[i] * dh[(size_t)i * L + l] / h[i];
-        }
-    }
-    grad[0] = gQ;
-    grad[1] = gW;
-    for (int l = 0; l < L; ++l) {
-        grad[2 + l] = gd[l];
-        grad[2 + L + l] = gs[l];
-    }
+    out.assign(v.begin(), v.begin() + n);
     return CRYO_OK;
 }
 
@@ -388,22 +530,29 @@ cryo_status cryo_gradient(const cryo_plan *pc, const void *T0, int64_t N, const 
     if (!J || !grad) return fail(CRYO_ERR_ARG, "bad argument");
     cryo_status st = grad_check(pc, N, target, ckpt, T0, ws, ws_bytes);
     if (st != CRYO_OK) return st;
-    GradRun r;
-    r.p = const_cast<cryo_plan *>(pc);
-    r.T0 = T0;
-    r.N = N;
-    r.target = target;
-    r.w = (char *)ws;
-    r.g = grad_layout(pc, N, ckpt);
-    r.s = (hipStream_t)stream;
-    st = grad_forward(r);
-    if (st == CRYO_OK) st = grad_objective(r);
-    if (st == CRYO_OK) st = grad_backward(r);
-    if (st == CRYO_OK) st = grad_finish(r, grad);
+    GradRun r = grad_run(pc, T0, N, ckpt, ws, (hipStream_t)stream);
+    st = grad_stage_host(r, target);
+    if (st == CRYO_OK) st = grad_enqueue(r);
+    if (st == CRYO_OK) st = grad_collect(r, J, grad, surf_out);
+    return st;
+}
+
+cryo_status cryo_gradient_async(const cryo_plan *pc, const void *T0, int64_t N,
+                                const double *target, int64_t ckpt, void *ws, size_t ws_bytes,
+                                double *J, double *grad, double *surf_out, void *stream) {
+    if (!J || !grad) return fail(CRYO_ERR_ARG, "bad argument");
+    cryo_status st = grad_check(pc, N, target, ckpt, T0, ws, ws_bytes);
     if (st != CRYO_OK) return st;
-    *J = r.J;
-    if (surf_out) memcpy(surf_out, r.S.data(), sizeof(double) * N);
-    return CRYO_OK;
+    GradRun r = grad_run(pc, T0, N, ckpt, ws, (hipStream_t)stream);
+    r.target = target;
+    r.J = J;
+    r.grad = grad;
+    st = grad_enqueue(r);
+    if (st == CRYO_OK && surf_out &&
+        hipMemcpyAsync(surf_out, r.w + r.g.surf, sizeof(double) * N, hipMemcpyDeviceToDevice,
+                       r.s) != hipSuccess)
+        st = fail(CRYO_ERR_DEVICE, "surface trace copy");
+    return st;
 }
 
 cryo_status cryo_gradient_many(int32_t n, cryo_plan *const *plans, const void *const *T0,
@@ -417,42 +566,25 @@ cryo_status cryo_gradient_many(int32_t n, cryo_plan *const *plans, const void *c
         if (st != CRYO_OK) return fail(st, "design " + std::to_string(i) + ": " + cryo_last_error());
         if (!grad[i]) return fail(CRYO_ERR_ARG, "design " + std::to_string(i) + ": null grad");
     }
-    const int ns = std::min<int>(n_streams, n);
-    std::vector<hipStream_t> streams(ns, nullptr);
-    cryo_status st = CRYO_OK;
-    for (int k = 0; k < ns && st == CRYO_OK; ++k)
-        if (hipStreamCreateWithFlags(&streams[k], hipStreamNonBlocking) != hipSuccess)
-            st = fail(CRYO_ERR_DEVICE, "stream creation");
-    std::vector<GradRun> runs(n);
+    std::vector<hipStream_t> streams;
+    cryo_status st = pool_streams(std::min<int>(n_streams, n), streams);
+    if (st != CRYO_OK) return st;
+    const int ns = (int)streams.size();
+    std::vector<GradRun> runs;
+    runs.reserve(n);
+    for (int i = 0; i < n; ++i) runs.push_back(grad_run(plans[i], T0[i], N, ckpt, ws[i], streams[i % ns]));
+    // every target first (the streams are idle), then each design's whole
+    // gradient in turn, then the results
+    for (int i = 0; i < n && st == CRYO_OK; ++i) st = grad_stage_host(runs[i], targets[i]);
     for (int i = 0; i < n && st == CRYO_OK; ++i) {
-        GradRun &r = runs[i];
-        r.p = plans[i];
-        r.T0 = T0[i];
-        r.N = N;
-        r.target = targets[i];
-        r.w = (char *)ws[i];
-        r.g = grad_layout(plans[i], N, ckpt);
-        r.s = streams[i % ns];
+        st = grad_enqueue(runs[i]);
+        if (st != CRYO_OK) st = fail(st, "design " + std::to_string(i) + ": " + cryo_last_error());
     }
-    // all forwards in flight, then each trace as it completes, then all
-    // backward sweeps, then the reductions
-    for (int i = 0; i < n && st == CRYO_OK; ++i) st = grad_forward(runs[i]);
-    for (int i = 0; i < n && st == CRYO_OK; ++i) st = grad_objective(runs[i]);
-    for (int i = 0; i < n && st == CRYO_OK; ++i) st = grad_backward(runs[i]);
     for (int i = 0; i < n && st == CRYO_OK; ++i) {
-        st = grad_finish(runs[i], grad[i]);
-        if (st == CRYO_OK) {
-            J[i] = runs[i].J;
-            if (surf_out && surf_out[i]) memcpy(surf_out[i], runs[i].S.data(), sizeof(double) * N);
-        } else {
-            st = fail(st, "design " + std::to_string(i) + ": " + cryo_last_error());
-        }
+        st = grad_collect(runs[i], J + i, grad[i], surf_out ? surf_out[i] : nullptr);
+        if (st != CRYO_OK) st = fail(st, "design " + std::to_string(i) + ": " + cryo_last_error());
     }
-    for (hipStream_t x : streams)
-        if (x) {
-            (void)hipStreamSynchronize(x);
-            (void)hipStreamDestroy(x);
-        }
+    for (hipStream_t x : streams) (void)hipStreamSynchronize(x);
     return st;
 }
 

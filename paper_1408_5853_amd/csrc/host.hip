@@ -255,16 +255,24 @@ cryo_status ensure_device(cryo_plan *p) {
             e = hipMemcpy(p->d_info2, p->tfinfo.data(), sizeof(uint32_t) * np,
                           hipMemcpyHostToDevice);
     }
+    if (e == hipSuccess && p->dtype == CRYO_F64) {
+        const std::vector<double> gt = grad_param_table(p);
+        e = hipMalloc((void **)&p->d_grad, sizeof(double) * gt.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(p->d_grad, gt.data(), sizeof(double) * gt.size(), hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) {
         if (p->d_rows) (void)hipFree(p->d_rows);
         if (info) (void)hipFree(info);
         if (p->d_pow) (void)hipFree(p->d_pow);
         if (p->d_rows2) (void)hipFree(p->d_rows2);
         if (p->d_info2) (void)hipFree(p->d_info2);
+        if (p->d_grad) (void)hipFree(p->d_grad);
         p->d_rows = nullptr;
         p->d_pow = nullptr;
         p->d_rows2 = nullptr;
         p->d_info2 = nullptr;
+        p->d_grad = nullptr;
         return fail(CRYO_ERR_DEVICE, std::string("device table upload: ") + hipGetErrorString(e));
     }
     p->d_info = info;
@@ -513,6 +521,7 @@ void cryo_plan_destroy(cryo_plan *p) {
     if (p->d_pow) (void)hipFree(p->d_pow);
     if (p->d_rows2) (void)hipFree(p->d_rows2);
     if (p->d_info2) (void)hipFree(p->d_info2);
+    if (p->d_grad) (void)hipFree(p->d_grad);
     delete p;
 }
 

@@ -122,7 +122,7 @@ struct AdjArgs {
     double *acc;            // per workgroup: [workgroups][3][np] row sums
     double *accg;           // per workgroup: [workgroups][2]  (y s, y Q ds/dw)
     double s, ds;           // pulse average of step n and its width derivative
-    double cS;              // dJ_n / dS_n (0 for n = 0)
+    const double *cS;       // dJ_n / dS_n in device memory (null: 0, as for n = 0)
     double xs;              // scale of the capacity rows (eta^2): the source's too
 };
 
@@ -183,6 +183,8 @@ struct cryo_plan {
     std::vector<uint32_t> tfinfo;
     void *d_rows2 = nullptr;          // [2][np]: tfgw, tfge
     uint32_t *d_info2 = nullptr;      // [np]: tfinfo
+    // FP64 plans: the parameter weights of the gradient (grad_param_table)
+    double *d_grad = nullptr;
 };
 
 namespace cryo {
@@ -212,4 +214,8 @@ cryo_status ensure_device(cryo_plan *p);
 cryo_status forward_in(const cryo_plan *p, void *T, int64_t k0, int64_t nsteps, char *w,
                        double *surf, hipStream_t s);
 bool plan_tables_on_device(const cryo_plan *p);
+// grad.hip: the weights that turn the adjoint's per-row face sums into the
+// thickness and conductivity-scale derivatives (size grad_param_doubles)
+std::vector<double> grad_param_table(const cryo_plan *p);
+inline size_t grad_param_doubles(int nr, int L) { return 2 * (size_t)nr * L + 3 * (size_t)nr + L; }
 }  // namespace cryo
