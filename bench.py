@@ -244,7 +244,7 @@ def design_extra(P, steps, iters, stream):
     tg = [cellgen.tracking_target(c, steps) for c in cells]
     P.gradient_many(cells[:2], tg[:2], streams=2)                # warm
     t0 = time.perf_counter()
-    final, hist = design_adam(cells, tg, iters=iters, lr=0.05, streams=4)
+    final, hist = design_adam(cells, tg, iters=iters, lr=0.05)
     secs = time.perf_counter() - t0
     ngrad = len(cells) * (iters + 1)
     cell_steps = sum(c["nr"] * c["nz"] for c in cells) * steps * (iters + 1)

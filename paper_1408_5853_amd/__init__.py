@@ -503,9 +503,10 @@ def gradient(cell, target, T0=None, nsteps=None, ckpt=0):
     return gradient_plan(cell).gradient(target, T0=T0, nsteps=nsteps, ckpt=ckpt)
 
 
-def gradient_many(cells, targets, nsteps=None, ckpt=0, streams=4, T0s=None):
+def gradient_many(cells, targets, nsteps=None, ckpt=0, streams=0, T0s=None):
     """Gradients of many designs in one call (FP64, the library's concurrent
-    design loop over `streams` HIP streams).  Returns (J [n], [grad_i],
+    design loop over `streams` HIP streams; 0 lets the library choose).
+    Returns (J [n], [grad_i],
     [surface trace_i]); equal bit for bit to gradient() per design."""
     torch = _torch()
     n = len(cells)

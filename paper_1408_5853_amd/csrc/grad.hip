@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <mutex>
+#include <thread>
 #include <string>
 #include <vector>
 
@@ -18,6 +19,7 @@ cryo_status launch_adj(const cryo_plan *p, int pass, const AdjArgs &d, int *flag
 cryo_status launch_adj_init(const cryo_plan *p, double *lam, const double *cS, hipStream_t s);
 cryo_status launch_zero(double *ptr, size_t n, hipStream_t s);
 int adj_slots(const cryo_plan *p);
+int adj_grid(const cryo_plan *p);
 size_t adj_lds(const cryo_plan *p);
 
 static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -511,6 +513,20 @@ static cryo_status pool_streams(int n, std::vector<hipStream_t> &out) {
     return CRYO_OK;
 }
 
+// Designs side by side: as many as it takes for their launches to cover the
+// compute units (a launch of the gradient's kernels has adj_grid workgroups
+// of 8 waves, which at the adjoint's register use fill one unit each), at
+// most 4 (the hardware queues a process gets by default: streams beyond
+// them share queues and run one after another).
+static int auto_streams(int n, cryo_plan *const *plans) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    int grid = 1;
+    for (int i = 0; i < n; ++i) grid = std::max(grid, adj_grid(plans[i]));
+    return std::max(1, std::min(4, (cus + grid - 1) / grid));
+}
+
 }  // namespace cryo
 
 using namespace cryo;
@@ -559,26 +575,66 @@ cryo_status cryo_gradient_many(int32_t n, cryo_plan *const *plans, const void *c
                                int64_t N, const double *const *targets, int64_t ckpt,
                                void *const *ws, const size_t *ws_bytes, int32_t n_streams,
                                double *J, double *const *grad, double *const *surf_out) {
-    if (n < 1 || !plans || !T0 || !targets || !ws || !ws_bytes || !J || !grad || n_streams < 1)
+    if (n < 1 || !plans || !T0 || !targets || !ws || !ws_bytes || !J || !grad || n_streams < 0)
         return fail(CRYO_ERR_ARG, "bad argument");
     for (int i = 0; i < n; ++i) {
         cryo_status st = grad_check(plans[i], N, targets[i], ckpt, T0[i], ws[i], ws_bytes[i]);
         if (st != CRYO_OK) return fail(st, "design " + std::to_string(i) + ": " + cryo_last_error());
         if (!grad[i]) return fail(CRYO_ERR_ARG, "design " + std::to_string(i) + ": null grad");
     }
+    if (n_streams == 0) n_streams = auto_streams(n, plans);
     std::vector<hipStream_t> streams;
     cryo_status st = pool_streams(std::min<int>(n_streams, n), streams);
     if (st != CRYO_OK) return st;
     const int ns = (int)streams.size();
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    // device tables first, here: the enqueuing threads then only read plans
+    // (a plan may serve several designs)
+    for (int i = 0; i < n && st == CRYO_OK; ++i) {
+        st = ensure_device(plans[i]);
+        if (st == CRYO_OK && plans[i]->sub) st = ensure_device(plans[i]->sub);
+    }
+    if (st != CRYO_OK) return st;
     std::vector<GradRun> runs;
     runs.reserve(n);
     for (int i = 0; i < n; ++i) runs.push_back(grad_run(plans[i], T0[i], N, ckpt, ws[i], streams[i % ns]));
-    // every target first (the streams are idle), then each design's whole
-    // gradient in turn, then the results
+    // every target first (the streams are idle), then each stream's designs
+    // enqueued in turn by a host thread of its own (a single thread would
+    // wait on one stream's full queue while the others ran dry), then the
+    // results
     for (int i = 0; i < n && st == CRYO_OK; ++i) st = grad_stage_host(runs[i], targets[i]);
-    for (int i = 0; i < n && st == CRYO_OK; ++i) {
-        st = grad_enqueue(runs[i]);
-        if (st != CRYO_OK) st = fail(st, "design " + std::to_string(i) + ": " + cryo_last_error());
+    if (st != CRYO_OK) return st;
+    std::vector<cryo_status> tst(ns, CRYO_OK);
+    std::vector<int> tbad(ns, -1);
+    std::vector<std::string> terr(ns);
+    auto work = [&](int k) {
+        if (hipSetDevice(dev) != hipSuccess) {
+            tst[k] = CRYO_ERR_DEVICE;
+            tbad[k] = k;
+            terr[k] = "device selection in an enqueuing thread";
+            return;
+        }
+        for (int i = k; i < n; i += ns) {
+            const cryo_status e = grad_enqueue(runs[i]);
+            if (e != CRYO_OK) {
+                tst[k] = e;
+                tbad[k] = i;
+                terr[k] = cryo_last_error();
+                return;
+            }
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int k = 1; k < ns; ++k) pool.emplace_back(work, k);
+    work(0);
+    for (std::thread &x : pool) x.join();
+    int first = -1;
+    for (int k = 0; k < ns; ++k)
+        if (tst[k] != CRYO_OK && (first < 0 || tbad[k] < tbad[first])) first = k;
+    if (first >= 0) {
+        for (hipStream_t x : streams) (void)hipStreamSynchronize(x);
+        return fail(tst[first], "design " + std::to_string(tbad[first]) + ": " + terr[first]);
     }
     for (int i = 0; i < n && st == CRYO_OK; ++i) {
         st = grad_collect(runs[i], J + i, grad[i], surf_out ? surf_out[i] : nullptr);

@@ -18,7 +18,7 @@ def design_params(cell):
     return params_of(cell)[:2 + len(cell["layers"])]
 
 
-def design_adam(cells, targets, iters, lr=0.05, nsteps=None, ckpt=0, streams=4,
+def design_adam(cells, targets, iters, lr=0.05, nsteps=None, ckpt=0, streams=0,
                 betas=(0.9, 0.999), eps=1e-8):
     """Adam in log-parameter space over design_params of every design, with
     one gradient_many call per iteration.  Returns (final cells, J history

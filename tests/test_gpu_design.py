@@ -48,7 +48,7 @@ def test_gradient_many_equals_single_calls_bitwise():
         assert np.array_equal(surfs[i], Si)
 
 
-@pytest.mark.parametrize("streams", [1, 4])
+@pytest.mark.parametrize("streams", [0, 1, 4])
 def test_gradient_many_matches_oracle_adjoint(streams):
     import paper_1408_5853_amd as P
     cells = _small_designs(3, 20)
