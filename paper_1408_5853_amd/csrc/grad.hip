@@ -626,8 +626,16 @@ cryo_status cryo_gradient_many(int32_t n, cryo_plan *const *plans, const void *c
         }
     };
     std::vector<std::thread> pool;
-    for (int k = 1; k < ns; ++k) pool.emplace_back(work, k);
+    std::vector<int> inline_work;
+    for (int k = 1; k < ns; ++k) {
+        try {
+            pool.emplace_back(work, k);
+        } catch (...) {            // no thread: this thread enqueues those designs too
+            inline_work.push_back(k);
+        }
+    }
     work(0);
+    for (int k : inline_work) work(k);
     for (std::thread &x : pool) x.join();
     int first = -1;
     for (int k = 0; k < ns; ++k)
