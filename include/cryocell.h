@@ -322,10 +322,15 @@ cryo_status cryo_autotune(const cryo_problem *prob, cryo_dtype dtype, int32_t st
  * instances (spread over their sizes) for `steps` steps (rounded up to
  * whole captured blocks of 32), and the shape with the least time per node
  * and step is given to all of the group's instances (lines per wave capped
- * at nz - 2).  `cache_path` (nullable) names a text file keyed by dtype, the
- * group's default shape, law family and largest radial size; new results
- * are appended.  The tuner allocates and frees its own trial fields and
- * workspaces.  Synchronous on `stream`. */
+ * at nz - 2).  Then, with more than one group, the whole batch is timed:
+ * each group in turn (most nodes first) tries lines per wave 1, 2 and 4
+ * beside the others as picked and keeps a value that makes the batch at
+ * least 1 % faster (the groups' launches share the chip).  `cache_path`
+ * (nullable) names a text file keyed by dtype, the group's default shape,
+ * law family and largest radial size for the first pass, and by a hash of
+ * the instances' grids, layer counts and law families for the second; new
+ * results are appended.  The tuner allocates and frees its own trial fields
+ * and workspaces.  Synchronous on `stream`. */
 cryo_status cryo_batch_autotune(int32_t n, const cryo_problem *probs, cryo_dtype dtype,
                                 int32_t steps, const char *cache_path, void *stream,
                                 int32_t *shapes);

@@ -1,12 +1,14 @@
 // Autotuners: cryo_autotune times every built kernel shape (rows per lane,
 // waves per line) and lines-per-wave on one problem and returns the fastest;
 // cryo_batch_autotune does the same per shape group of a batch, timing
-// batches of the group's instances.  The tuners own their trial fields and
+// batches of the group's instances, then refines each group's lines per
+// wave on the whole batch.  The tuners own their trial fields and
 // workspaces (device allocations of their own, outside any stepping call).
 // An optional text cache records results across runs: keyed by dtype,
 // radial and axial node counts, layer count and law family (cube or general
 // capacity exponents) for one problem, and by dtype, default shape, law
-// family and largest radial size for a batch group.
+// family and largest radial size for a batch group, and by a hash of the
+// whole batch for the refinement.
 #include <stdio.h>
 #include <string.h>
 
@@ -64,6 +66,145 @@ void cache_store(const char *path, const std::string &key, const int32_t *shape,
     if (!f) return;
     fprintf(f, "%s | %d %d %d | %.3f us/step\n", key.c_str(), shape[0], shape[1], shape[2], us);
     fclose(f);
+}
+
+// An instance group of a batch (instances with one default shape and law
+// family), as cryo_batch_create forms them.
+struct Group {
+    int rpl, wpl;
+    bool cube;
+    int nr_max = 0, nz_min = 1 << 30;
+    std::vector<int> inst;
+};
+
+// Time per step of the whole batch with the given shapes (the best of two
+// timed runs of `run_steps` after the capture block).
+cryo_status time_batch(int32_t n, const cryo_problem *probs, cryo_dtype dtype,
+                       const std::vector<int32_t> &shp, int run_steps, hipStream_t s,
+                       hipEvent_t e0, hipEvent_t e1, double *us) {
+    cryo_batch *b = nullptr;
+    cryo_status st = cryo_batch_create(n, probs, dtype, shp.data(), &b);
+    if (st != CRYO_OK) return st;
+    std::vector<int64_t> off((size_t)n + 1);
+    cryo_batch_offsets(b, off.data());
+    size_t wsb = 0;
+    cryo_batch_workspace_bytes(b, &wsb);
+    void *T = nullptr, *ws = nullptr;
+    if (hipMalloc(&T, (size_t)off.back() * (dtype == CRYO_F64 ? 8 : 4)) != hipSuccess ||
+        hipMalloc(&ws, wsb) != hipSuccess) {
+        if (T) (void)hipFree(T);
+        cryo_batch_destroy(b);
+        return fail(CRYO_ERR_DEVICE, "batch tuner buffers");
+    }
+    st = cryo_batch_init(b, T, s);
+    if (st == CRYO_OK) st = cryo_batch_forward(b, T, 0, 32, ws, wsb, s);
+    double best = 1e300;
+    for (int rep = 0; rep < 2 && st == CRYO_OK; ++rep) {
+        (void)hipEventRecord(e0, s);
+        st = cryo_batch_forward(b, T, 32 + (int64_t)rep * run_steps, run_steps, ws, wsb, s);
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        best = std::min(best, 1e3 * ms / run_steps);
+    }
+    if (st == CRYO_OK) st = cryo_batch_poll(b, ws, s, nullptr);
+    (void)hipFree(ws);
+    (void)hipFree(T);
+    cryo_batch_destroy(b);
+    *us = best;
+    return st;
+}
+
+// FNV-1a over what decides a batch's grouping and work: per instance its
+// grid, layer count and law family.
+uint64_t batch_hash(int32_t n, const cryo_problem *probs, cryo_dtype dtype) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) {
+        for (int k = 0; k < 8; ++k) {
+            h ^= (v >> (8 * k)) & 0xff;
+            h *= 1099511628211ull;
+        }
+    };
+    mix((uint64_t)dtype);
+    mix((uint64_t)n);
+    for (int i = 0; i < n; ++i) {
+        mix((uint64_t)probs[i].geom.nr);
+        mix((uint64_t)probs[i].geom.nz);
+        mix((uint64_t)probs[i].geom.n_layers);
+        mix(all_cube(&probs[i]) ? 1 : 0);
+    }
+    return h;
+}
+
+// Second pass on the whole batch.  The groups' launches share the chip (one
+// graph branch per group), so the lines per wave that suit a group alone
+// need not suit it beside the others: each group in turn, most nodes first,
+// tries lines per wave 1, 2 and 4 with every other group as picked, and
+// keeps a value that makes the whole batch at least 1 % faster.  Cached per
+// batch (a hash of the instances' grids, layer counts and law families).
+cryo_status refine_lines_per_wave(int32_t n, const cryo_problem *probs, cryo_dtype dtype,
+                                  int run_steps, const char *cache_path, hipStream_t s,
+                                  hipEvent_t e0, hipEvent_t e1,
+                                  const std::vector<Group> &groups, int32_t *shapes) {
+    char hb[64];
+    snprintf(hb, sizeof hb, "batchset %016llx", (unsigned long long)batch_hash(n, probs, dtype));
+    auto gkey = [&](size_t gi) { return std::string(hb) + " g" + std::to_string(gi); };
+    auto apply = [&](const Group &g, int lpw, std::vector<int32_t> &shp) {
+        for (int i : g.inst) shp[3 * i + 2] = std::max(1, std::min(lpw, probs[i].geom.nz - 2));
+    };
+    std::vector<int32_t> shp(shapes, shapes + 3 * (size_t)n);
+    bool cached = cache_path != nullptr;
+    std::vector<int> lp(groups.size());
+    for (size_t gi = 0; gi < groups.size() && cached; ++gi) {
+        int32_t c[3];
+        if (!cache_lookup(cache_path, gkey(gi), c) || c[0] != groups[gi].rpl) cached = false;
+        else lp[gi] = c[2];
+    }
+    if (cached) {
+        for (size_t gi = 0; gi < groups.size(); ++gi) apply(groups[gi], lp[gi], shp);
+        std::copy(shp.begin(), shp.end(), shapes);
+        return CRYO_OK;
+    }
+    std::vector<size_t> order(groups.size());
+    std::vector<double> work(groups.size(), 0.0);
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        order[gi] = gi;
+        for (int i : groups[gi].inst) work[gi] += (double)probs[i].geom.nr * probs[i].geom.nz;
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t a, size_t b) { return work[a] > work[b]; });
+    double best = 0.0;
+    cryo_status st = time_batch(n, probs, dtype, shp, run_steps, s, e0, e1, &best);
+    if (st != CRYO_OK) return st;
+    for (size_t gi : order) {
+        const Group &g = groups[gi];
+        const int cur = shp[3 * g.inst[0] + 2];
+        int keep = cur;
+        for (int lpw : {1, 2, 4}) {
+            if (lpw == cur) continue;
+            std::vector<int32_t> trial(shp);
+            apply(g, lpw, trial);
+            if (trial == shp) continue;
+            double t = 0.0;
+            st = time_batch(n, probs, dtype, trial, run_steps, s, e0, e1, &t);
+            if (st != CRYO_OK) return st;
+            if (t < 0.99 * best) {
+                best = t;
+                keep = lpw;
+            }
+        }
+        apply(g, keep, shp);
+    }
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        int32_t c[3] = {shp[3 * groups[gi].inst[0]], shp[3 * groups[gi].inst[0] + 1], 0};
+        // the group's value before the cap at nz - 2
+        c[2] = 0;
+        for (int i : groups[gi].inst) c[2] = std::max<int32_t>(c[2], shp[3 * i + 2]);
+        cache_store(cache_path, gkey(gi), c, best);
+    }
+    std::copy(shp.begin(), shp.end(), shapes);
+    return CRYO_OK;
 }
 
 }  // namespace
@@ -155,12 +296,6 @@ cryo_status cryo_batch_autotune(int32_t n, const cryo_problem *probs, cryo_dtype
     if (n < 1 || !probs || !shapes || steps < 1) return fail(CRYO_ERR_ARG, "bad argument");
     hipStream_t s = (hipStream_t)stream;
     // the groups cryo_batch_create forms with default shapes
-    struct Group {
-        int rpl, wpl;
-        bool cube;
-        int nr_max = 0, nz_min = 1 << 30;
-        std::vector<int> inst;
-    };
     std::vector<Group> groups;
     for (int i = 0; i < n; ++i) {
         cryo_plan *p = nullptr;
@@ -281,6 +416,9 @@ cryo_status cryo_batch_autotune(int32_t n, const cryo_problem *probs, cryo_dtype
             shapes[3 * i + 2] = std::max(1, std::min(best_shape[2], probs[i].geom.nz - 2));
         }
     }
+    if (result == CRYO_OK && groups.size() > 1)
+        result = refine_lines_per_wave(n, probs, dtype, run_steps, cache_path, s, e0, e1, groups,
+                                       shapes);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return result;
