@@ -140,9 +140,20 @@ static double poly(const double *coef, int n, double T)
     return s;
 }
 
+/* d/dT of sum_{k<n} coef[k] T^k, term by term */
+static double dpoly(const double *coef, int n, double T)
+{
+    double s = 0.0, Tk = 1.0;
+    for (int k = 1; k < n; k++) {
+        s += k * coef[k] * Tk;
+        Tk *= T;
+    }
+    return s;
+}
+
 /* material laws: the workloads' power laws, or the polynomial fits of
- * eqs. (23) (c, cubic) and (24) (lambda, quartic) when given; and the
- * T-derivatives of the power laws (the adjoint takes power laws only) */
+ * eqs. (23) (c, cubic) and (24) (lambda, quartic) when given; and their
+ * T-derivatives (the adjoint's) */
 static double lam(const ocell *c, int m, double T)
 {
     if (c->poly_b) return c->kscale[m] * poly(c->poly_b + 5 * m, 5, T);
@@ -150,6 +161,7 @@ static double lam(const ocell *c, int m, double T)
 }
 static double dlam(const ocell *c, int m, double T)
 {
+    if (c->poly_b) return c->kscale[m] * dpoly(c->poly_b + 5 * m, 5, T);
     return c->p[m] * lam(c, m, T) / T;
 }
 static double cap(const ocell *c, int m, double T)
@@ -159,6 +171,7 @@ static double cap(const ocell *c, int m, double T)
 }
 static double dcap(const ocell *c, int m, double T)
 {
+    if (c->poly_a) return dpoly(c->poly_a + 4 * m, 4, T);
     return c->q[m] * cap(c, m, T) / T;
 }
 
@@ -572,7 +585,7 @@ static void adjoint_line(const adj_ctx *x, const double *T, const double *Tn,
             double dLn = (0.5 * dlzn * gn + lzn) / e2;               /* dLz/dT_{j+1} */
             double dLc = (0.5 * dlzn * gn - lzn - 0.5 * dlzs * gs - lzs) / e2;
             double dLs = (-0.5 * dlzs * gs + lzs) / e2;              /* dLz/dT_{j-1} */
-            /* residual r = aw lw Dw + ae le De + rc (X_i - T_i) - Lz - Q s */
+            /* residual r = aw lw Dw + ae le De + rc (X_i - T_i) - Lz - Q s chi */
             lj[i - 1] -= yi * aw * Dw * 0.5 * dlw;
             lj[i + 1] -= yi * ae * De * 0.5 * dle;
             lj[i] -= yi * (aw * Dw * 0.5 * dlw + ae * De * 0.5 * dle
@@ -580,8 +593,16 @@ static void adjoint_line(const adj_ctx *x, const double *T, const double *Tn,
             ln_[i] -= yi * (-dLn);
             ls_[i] -= yi * (-dLs);
             if (m == c->heater) {
-                gl[0] += yi * s;
-                gl[1] += yi * c->amplitude * sd;
+                /* the source Q s chi(T_i), chi = sqrt(tref / T_i) with the
+                 * Joule source of eq. (25), else 1; its T_i-derivative
+                 * -chi / (2 T_i) enters lam^n */
+                double chi = 1.0;
+                if (c->joule_tref > 0) {
+                    chi = sqrt(c->joule_tref / Tj[i]);
+                    lj[i] -= yi * 0.5 * c->amplitude * s * chi / Tj[i];
+                }
+                gl[0] += yi * s * chi;
+                gl[1] += yi * c->amplitude * sd * chi;
             }
             gl[2 + L + m] -= yi * (aw * lw * Dw + ae * le * De - Lz) / c->kscale[m];
             for (int l = 0; l < L; l++) {
@@ -645,8 +666,7 @@ int oc_gradient(const ocell *c, const double *T0, long N, const double *target,
                 int nthreads)
 {
     geom g;
-    if (check_cell(c) || N < 1 || c->poly_a || c->poly_b || c->joule_tref > 0 ||
-        geom_build(c, &g))
+    if (check_cell(c) || N < 1 || geom_build(c, &g))
         return 1;
     if (c->turn_on && c->width > 0 && pulse_start(c, 0) < 0) { geom_free(&g); return 1; }
     int nr = c->nr, nz = c->nz, L = c->n_layers, ng = 2 + 2 * L;

@@ -65,8 +65,9 @@ int oc_line_paper_sweep(const ocell *c, const double *T, long k, int j,
  * fall on step boundaries, else the call fails */
 int oc_forward(const ocell *c, double *T, long k0, long nsteps, double *surf,
                int nthreads);
-/* (fails when polynomial laws or the Joule source are set;
- * with the turn-on model the sub-steps are part of the sweep, and ckpt counts
+/* (with polynomial laws the adjoint takes their derivative polynomials, and
+ * with the Joule source the derivative of its sqrt(tref / T) factor; with
+ * the turn-on model the sub-steps are part of the sweep, and ckpt counts
  * kernel steps: sub-steps included)
  * J = sum_{n=1..N} (S_n - target_n)^2 and its gradient
  * grad = [dJ/dQ, dJ/dwidth, dJ/dthick[L], dJ/dkscale[L]] by the discrete

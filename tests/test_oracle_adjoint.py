@@ -182,3 +182,24 @@ def test_stepped_gradient_matches_central_differences(seed, nr_top):
     rng = np.random.default_rng(seed)
     T0 = 28.0 + rng.uniform(0, 3, size=(c["nz"], c["nr"]))
     _fd_check(c, seed, 1e-6, T0=T0)
+
+
+@pytest.mark.parametrize("seed,joule,z_active", [(0, 0.0, True), (1, 30.0, True), (2, 30.0, False)])
+def test_poly_gradient_matches_central_differences(seed, joule, z_active):
+    # the polynomial laws of eqs. (23), (24) (their derivative polynomials in
+    # the adjoint) and the Joule source of eq. (25), whose sqrt(tref / T)
+    # factor depends on the old temperature of each heater node
+    c = cellgen.poly_variant(
+        cellgen.tiny(30 + seed, nr=14, nz=6, n_layers=3, nsteps=30, z_active=z_active,
+                     dt=2e-6, amplitude=4e9, heater=2), seed, joule_tref=joule)
+    _fd_check(c, seed, 1e-6)
+
+
+def test_poly_gradient_checkpointing_bitwise():
+    c = cellgen.poly_variant(cellgen.tiny(33, nr=14, nz=6, n_layers=3, nsteps=25, z_active=True,
+                                          dt=2e-6, amplitude=4e9, heater=2), 3, joule_tref=30.0)
+    target = _target(c, np.random.default_rng(4))
+    J0, g0, S0 = oracle.gradient(c, target, ckpt=0)
+    for K in (1, 6):
+        J1, g1, S1 = oracle.gradient(c, target, ckpt=K)
+        assert J1 == J0 and np.array_equal(g1, g0) and np.array_equal(S1, S0)
