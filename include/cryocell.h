@@ -350,9 +350,10 @@ cryo_status cryo_batch_autotune(int32_t n, const cryo_problem *probs, cryo_dtype
  * once per step.  States are checkpointed every ckpt kernel steps (0: the
  * square root of their count, rounded up) and each segment is recomputed.
  * FP64 plans with one of the gradient's shapes only (CRYO_ERR_UNSUPPORTED
- * otherwise, see cryo_plan_set_shape); polynomial laws are refused
- * (CRYO_ERR_UNSUPPORTED); a stepped domain (cryo_plan_set_stepped) is
- * followed.  T0 is a device field; target, J, grad and surf (nullable, N
+ * otherwise, see cryo_plan_set_shape); polynomial laws and the Joule source
+ * (cryo_plan_set_poly_laws: the derivative polynomials, the interface row's
+ * quotient of two laws, the source's sqrt(tref / T) factor) and a stepped
+ * domain (cryo_plan_set_stepped) are followed.  T0 is a device field; target, J, grad and surf (nullable, N
  * values) are host arrays.  Synchronous on `stream`; the same device work as
  * cryo_gradient_async (results equal bit for bit). */
 cryo_status cryo_gradient_workspace_bytes(const cryo_plan *plan, int64_t nsteps, int64_t ckpt,

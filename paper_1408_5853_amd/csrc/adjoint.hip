@@ -26,6 +26,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <type_traits>
+
 #include "device_common.h"
 
 namespace cryo {
@@ -60,15 +62,18 @@ __device__ inline void nb_exchange(double v_last, double v_first, double &from_p
 // Row tables and laws in LDS (dynamic shared memory); all threads call it.
 // STEPPED (eq. (9)): the terminal lines' tables too, after the row sums
 // (sgw2, sge2, sinf2; the full lines' tables otherwise).
+// POLY: the polynomial laws of eqs. (23), (24) (the stepping kernel's
+// coefficient blob) instead of the power tables.
+template <bool POLY>
 struct AdjLds {
     const double *sgw, *sge;
     const uint32_t *sinf;
     const double *sgw2, *sge2;
     const uint32_t *sinf2;
-    LawLds<double> law;
+    std::conditional_t<POLY, LawPoly<double>, LawLds<double>> law;
 };
-template <bool STEPPED>
-__device__ inline AdjLds adj_stage(const StepArgs<double> &a, unsigned char *smem, int rpl) {
+template <bool STEPPED, bool POLY = false>
+__device__ inline AdjLds<POLY> adj_stage(const StepArgs<double> &a, unsigned char *smem, int rpl) {
     double *sgw = (double *)(smem + ((law_lds_bytes<double>(a.laws.L) + 15) & ~(size_t)15));
     double *sge = sgw + a.np;
     uint32_t *sinf = (uint32_t *)(sge + a.np);
@@ -85,15 +90,29 @@ __device__ inline AdjLds adj_stage(const StepArgs<double> &a, unsigned char *sme
             sinf2[i] = a.info2[i];
         }
     }
-    AdjLds t;
+    AdjLds<POLY> t;
     t.sgw = sgw;
     t.sge = sge;
     t.sinf = sinf;
     t.sgw2 = STEPPED ? sgw2 : sgw;
     t.sge2 = STEPPED ? sge2 : sge;
     t.sinf2 = STEPPED ? sinf2 : sinf;
-    t.law = stage_laws<double>(a, smem);      // ends with a barrier
+    if constexpr (POLY) t.law = stage_poly<double>(a, smem);   // ends with a barrier
+    else t.law = stage_laws<double>(a, smem);
     return t;
+}
+
+// Derivatives of the polynomial laws for the adjoint: the derivative
+// polynomial of sum_k c_k x^k (k <= 4), by Horner's rule.
+__device__ inline double poly_dlaw(const LawPoly<double> &l, int id, double x) {
+    const double *c = l.c + POLY_BLK * id;
+    return fma(fma(fma(4.0 * c[4], x, 3.0 * c[3]), x, 2.0 * c[2]), x, c[1]);
+}
+
+// lambda'(x) / lambda(x) of a polynomial law (0 for the zero law)
+__device__ inline double poly_dlog(const LawPoly<double> &l, int id, double x) {
+    const double v = l.lawc(id, x);
+    return v != 0.0 ? poly_dlaw(l, id, x) / v : 0.0;
 }
 
 // weight of interior line j's outer node in the surface mean (lines
@@ -105,17 +124,21 @@ __device__ inline double surf_weight(const StepArgs<double> &a, int j) {
 }
 
 // Pass 1 of one step over this workgroup's line groups (tables staged).
-template <int RPL, int G, bool CUBE, bool STEPPED = false>
+template <int RPL, int G, bool CUBE, bool STEPPED = false, bool POLY = false>
 // (keep: lam^{n+1} of the group's single line comes in lamR, not from memory)
+// POLY: the interface row's coefficient is the quotient of its inner (slot 2)
+// and outer (slot 3) layer laws, and with the Joule source (eq. (25)) a
+// heater row's source is X sqrt(tref / T) at the old T (a.X holds sqrt(tref)
+// in the adjoint's arguments, 1 without the Joule source).
 __device__ inline void adj1_body(const StepArgs<double> &a, const AdjArgs &d,
-                                 unsigned char *smem, const AdjLds &tb,
+                                 unsigned char *smem, const AdjLds<POLY> &tb,
                                  const double (&lamR)[RPL], bool keep) {
     constexpr int NL = WAVE * G, NG = ADJ_WAVES / G;
     __shared__ double xchg[NG][9 * G];
     __shared__ double xb[NG][2 * G];
     const double *sgw = tb.sgw, *sge = tb.sge;       // this line's tables
     const uint32_t *sinf = tb.sinf;
-    const LawLds<double> &law = tb.law;
+    const auto &law = tb.law;
     const int lane = threadIdx.x & (WAVE - 1), wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int grp = wv / G, wig = wv % G, lg = wig * WAVE + lane;
     const int gidx = blockIdx.x * NG + grp;                  // line group
@@ -181,7 +204,8 @@ __device__ inline void adj1_body(const StepArgs<double> &a, const AdjArgs &d,
             // ge (slot 2 is the unit law there, the zero law on padding)
             double l2v = l2 == law_unit(a.laws.L) ? 1.0 : 0.0;
             if (__any(ifc)) {
-                const double va = law.lawc(l2, t);
+                double va = law.lawc(l2, t);
+                if constexpr (POLY) va = va / law.lawc((inf_r >> 18) & 63, t);
                 if (ifc) l2v = va;
             }
             double rc;
@@ -241,16 +265,28 @@ __device__ inline void adj1_body(const StepArgs<double> &a, const AdjArgs &d,
             const uint32_t inf_r = sinf[q];
             const uint32_t kind = inf_r & 7;
             const double t = T[r], Te = (r < RPL - 1) ? T[r + 1] : TeL;
-            ieE = 0.5 * law.expo((inf_r >> 6) & 63) * rcp(0.5 * (t + Te));
-            const double it = rcp(t);
             const bool cap = kind == K_CAP, ifc = kind == K_IFACE;
-            fwT = cap ? fw[r] * ieW : ifc ? fw[r] * law.expo((inf_r >> 12) & 63) * it : 0.0;
-            feT = cap ? fe[r] * ieE : ifc ? fe[r] * law.expo((inf_r >> 18) & 63) * it : 0.0;
+            if constexpr (POLY) {
+                // the scaled interface row's west coefficient is the quotient
+                // lambda_a / lambda_b at the node; its east one is constant
+                ieE = 0.5 * poly_dlog(law, (inf_r >> 6) & 63, 0.5 * (t + Te));
+                const double dq = ifc ? poly_dlog(law, (inf_r >> 12) & 63, t) -
+                                            poly_dlog(law, (inf_r >> 18) & 63, t)
+                                      : 0.0;
+                fwT = cap ? fw[r] * ieW : ifc ? fw[r] * dq : 0.0;
+                feT = cap ? fe[r] * ieE : 0.0;
+            } else {
+                ieE = 0.5 * law.expo((inf_r >> 6) & 63) * rcp(0.5 * (t + Te));
+                const double it = rcp(t);
+                fwT = cap ? fw[r] * ieW : ifc ? fw[r] * law.expo((inf_r >> 12) & 63) * it : 0.0;
+                feT = cap ? fe[r] * ieE : ifc ? fe[r] * law.expo((inf_r >> 18) & 63) * it : 0.0;
+            }
         };
         double ieW0;               // 1/2 e_W / tf_W of row 0 (west face of the chunk)
         {
             const uint32_t iw = sinf[qW];
-            ieW0 = 0.5 * law.expo((iw >> 6) & 63) * rcp(0.5 * (TwF + T[0]));
+            if constexpr (POLY) ieW0 = 0.5 * poly_dlog(law, (iw >> 6) & 63, 0.5 * (TwF + T[0]));
+            else ieW0 = 0.5 * law.expo((iw >> 6) & 63) * rcp(0.5 * (TwF + T[0]));
         }
         // coupling terms leaving the chunk towards the neighbouring lanes'
         // rows (capacity rows: the face conductivity depends on both nodes)
@@ -261,8 +297,12 @@ __device__ inline void adj1_body(const StepArgs<double> &a, const AdjArgs &d,
             qwF = (sinf[lg] & 7) == K_CAP ? y[0] * fwT * Dw : 0.0;            // to row i0-1
             const uint32_t il = sinf[(RPL - 2) * NL + lg];
             const double TL = T[RPL - 2];
-            const double ieL = RPL >= 2 ? 0.5 * law.expo((il >> 6) & 63) * rcp(0.5 * (TL + T[RPL - 1]))
-                                        : ieW0;
+            double ieL = ieW0;
+            if constexpr (POLY) {
+                if (RPL >= 2) ieL = 0.5 * poly_dlog(law, (il >> 6) & 63, 0.5 * (TL + T[RPL - 1]));
+            } else {
+                if (RPL >= 2) ieL = 0.5 * law.expo((il >> 6) & 63) * rcp(0.5 * (TL + T[RPL - 1]));
+            }
             factors(RPL - 1, RPL >= 2 ? ieL : ieW0, Dw, De, fwT, feT, ie);
             qeL = (sinf[(RPL - 1) * NL + lg] & 7) == K_CAP ? y[RPL - 1] * feT * De : 0.0;
         }
@@ -284,7 +324,10 @@ __device__ inline void adj1_body(const StepArgs<double> &a, const AdjArgs &d,
                 const double t = T[r];
                 const int lc = (inf_r >> 24) & 63;
                 double rc, drc;
-                if constexpr (CUBE) {
+                if constexpr (POLY) {
+                    rc = law.lawc(lc, t);
+                    drc = poly_dlaw(law, lc, t);
+                } else if constexpr (CUBE) {
                     rc = law.cube(lc, t);
                     drc = 3.0 * law.cka[2 * lc] * t * t;
                 } else {
@@ -292,7 +335,15 @@ __device__ inline void adj1_body(const StepArgs<double> &a, const AdjArgs &d,
                     drc = law.expo(lc) * rc * rcp(t);
                 }
                 const bool cf = cap || ifc;
-                const double self = cf ? fwT * Dw + feT * De + drc * (X[r] - t) - rc : 0.0;
+                double self = cf ? fwT * Dw + feT * De + drc * (X[r] - t) - rc : 0.0;
+                // the Joule source X sqrt(tref / T): d(-source)/dT = source / (2 T)
+                double chi = 1.0;
+                if constexpr (POLY) {
+                    if (a.joule && ((inf_r >> 3) & 1)) {
+                        chi = a.X * rsqrt(t);
+                        self += 0.5 * a.pulse.amplitude * d.s * chi * rcp(t);
+                    }
+                }
                 const double ow = cap ? y[r] * fwT * Dw : 0.0;       // into row r-1
                 const double oe = cap ? y[r] * feT * De : 0.0;       // into row r+1
                 double lp = -(y[r] * self + oe_prev);
@@ -306,7 +357,7 @@ __device__ inline void adj1_body(const StepArgs<double> &a, const AdjArgs &d,
                 const double aw = accW[r * WAVE], ae = accE[r * WAVE];
                 accW[r * WAVE] = cf ? fma(y[r] * fw[r], Dw, aw) : aw;
                 accE[r * WAVE] = cf ? fma(y[r] * fe[r], De, ae) : ae;
-                gS += ((inf_r >> 3) & 1) ? y[r] : 0.0;
+                gS += ((inf_r >> 3) & 1) ? (POLY ? y[r] * chi : y[r]) : 0.0;
                 __builtin_amdgcn_sched_barrier(0);
             }
             d.lpart[base + (RPL - 1) * NL + lg] = lp_prev - qwNext;
@@ -341,26 +392,26 @@ __device__ inline void adj1_body(const StepArgs<double> &a, const AdjArgs &d,
     }
 }
 
-template <int RPL, int G, bool CUBE, bool STEPPED>
+template <int RPL, int G, bool CUBE, bool STEPPED, bool POLY = false>
 __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj1(StepArgs<double> a, AdjArgs d) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const AdjLds tb = adj_stage<STEPPED>(a, smem, RPL);
+    const AdjLds<POLY> tb = adj_stage<STEPPED, POLY>(a, smem, RPL);
     const double none[RPL] = {};
-    adj1_body<RPL, G, CUBE, STEPPED>(a, d, smem, tb, none, false);
+    adj1_body<RPL, G, CUBE, STEPPED, POLY>(a, d, smem, tb, none, false);
 }
 
 // Pass 2: axial faces.  Each interior line j adds the terms of its two
 // axial faces (capacity rows), and the lines next to the z-boundaries write
 // the boundary lines' lam^n.
-template <int RPL, int G, bool STEPPED = false>
+template <int RPL, int G, bool STEPPED = false, bool POLY = false>
 // (keep: lam^n of the group's single line goes to lamR, not to memory; the
 // boundary lines' lam^n is always written)
 __device__ inline void adj2_body(const StepArgs<double> &a, const AdjArgs &d,
-                                 unsigned char *smem, const AdjLds &tb, double (&lamR)[RPL],
-                                 bool keep) {
+                                 unsigned char *smem, const AdjLds<POLY> &tb,
+                                 double (&lamR)[RPL], bool keep) {
     constexpr int NL = WAVE * G, NG = ADJ_WAVES / G;
     const uint32_t *sinf = tb.sinf;                      // this line's table
-    const LawLds<double> &law = tb.law;
+    const auto &law = tb.law;
     const int lane = threadIdx.x & (WAVE - 1), wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int grp = wv / G, wig = wv % G, lg = wig * WAVE + lane;
     const int gidx = blockIdx.x * NG + grp;
@@ -386,10 +437,11 @@ __device__ inline void adj2_body(const StepArgs<double> &a, const AdjArgs &d,
         const int lz = cap ? (inf_r >> 12) & 63 : law_zero(a.laws.L);
         const double t = d.T[bb + q], ts = d.T[bb - LS + q];
         const double y = d.Y[bb + q];
-        const double e = law.expo(lz);
         const double fs = 0.5 * (t + ts);
         const double ls = law.lawc(lz, fs), ds = t - ts;
-        const double gs = 0.5 * e * ls * rcp(fs);
+        double gs;
+        if constexpr (POLY) gs = 0.5 * poly_dlaw(law, lz, fs);
+        else gs = 0.5 * law.expo(lz) * ls * rcp(fs);
         accZ[r] = 0.0;
         cF[r] = ls * ds;
         cdF[r] = gs * ds + ls;                                 // d F_S / d T_j
@@ -428,12 +480,13 @@ __device__ inline void adj2_body(const StepArgs<double> &a, const AdjArgs &d,
             const int lz = cap ? (inf_r >> 12) & 63 : law_zero(a.laws.L);
             const double t = Tc[r], tn = Tn[r];
             const double y = Yc[r], yn = Yn[r], ys = Ys[r];
-            const double e = law.expo(lz);
             // north face (j, j+1); the south face (j-1, j) is carried
             const double fn = 0.5 * (t + tn);
             const double ln = law.lawc(lz, fn);
             const double dn = tn - t;
-            const double gn = 0.5 * e * ln * rcp(fn);
+            double gn;
+            if constexpr (POLY) gn = 0.5 * poly_dlaw(law, lz, fn);
+            else gn = 0.5 * law.expo(lz) * ln * rcp(fn);
             const double dFlN = gn * dn - ln;                       // d F_N / d T_j
             const double lam = LP[r] + dFlN * (y - yn) + cdF[r] * (ys - y);
             accZ[r] += y * (ln * dn - cF[r]);
@@ -473,12 +526,12 @@ __device__ inline void adj2_body(const StepArgs<double> &a, const AdjArgs &d,
     }
 }
 
-template <int RPL, int G, bool STEPPED>
+template <int RPL, int G, bool STEPPED, bool POLY = false>
 __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj2(StepArgs<double> a, AdjArgs d) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const AdjLds tb = adj_stage<STEPPED>(a, smem, RPL);
+    const AdjLds<POLY> tb = adj_stage<STEPPED, POLY>(a, smem, RPL);
     double lamR[RPL];
-    adj2_body<RPL, G, STEPPED>(a, d, smem, tb, lamR, false);
+    adj2_body<RPL, G, STEPPED, POLY>(a, d, smem, tb, lamR, false);
 }
 
 // Pass 2 of step k and pass 1 of step k - 1 in one launch: each line group
@@ -487,17 +540,17 @@ __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj2(StepArgs<double> a, Ad
 // step's line solves on it.  Every value that
 // crosses line groups (y^k of the neighbouring lines) is read in the first
 // phase and written only to the other buffer in the second.
-template <int RPL, int G, bool CUBE, bool KEEP, bool STEPPED>
+template <int RPL, int G, bool CUBE, bool KEEP, bool STEPPED, bool POLY = false>
 __global__ __launch_bounds__(ADJ_WAVES *WAVE) void k_adj21(StepArgs<double> a, AdjArgs d2,
                                                            AdjArgs d1) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const AdjLds tb = adj_stage<STEPPED>(a, smem, RPL);
+    const AdjLds<POLY> tb = adj_stage<STEPPED, POLY>(a, smem, RPL);
     // one line per group: lam^k stays in registers between the phases (no
     // other group reads it)
     double lamR[RPL] = {};
-    adj2_body<RPL, G, STEPPED>(a, d2, smem, tb, lamR, KEEP);
+    adj2_body<RPL, G, STEPPED, POLY>(a, d2, smem, tb, lamR, KEEP);
     __syncthreads();           // the LDS row sums area passes to the next phase
-    adj1_body<RPL, G, CUBE, STEPPED>(a, d1, smem, tb, lamR, KEEP);
+    adj1_body<RPL, G, CUBE, STEPPED, POLY>(a, d1, smem, tb, lamR, KEEP);
 }
 
 // lam^N = dJ_N / dT^N: the surface weights on the outer row
@@ -547,6 +600,17 @@ StepArgs<double> step_args_f64(const cryo_plan *p, int *flag);
 // one pass (1, 2, or 21: pass 2 of step k with d, pass 1 of step k-1 with
 // d1) of one adjoint shape
 template <int R_, int G_, bool ST>
+static void adj_launch_poly(int pass, bool keep, dim3 g, dim3 b, size_t lds, hipStream_t s,
+                            const StepArgs<double> &a, const AdjArgs &d, const AdjArgs *d1) {
+    if (pass == 2) hipLaunchKernelGGL((k_adj2<R_, G_, ST, true>), g, b, lds, s, a, d);
+    else if (pass == 21 && keep)
+        hipLaunchKernelGGL((k_adj21<R_, G_, false, true, ST, true>), g, b, lds, s, a, d, *d1);
+    else if (pass == 21)
+        hipLaunchKernelGGL((k_adj21<R_, G_, false, false, ST, true>), g, b, lds, s, a, d, *d1);
+    else hipLaunchKernelGGL((k_adj1<R_, G_, false, ST, true>), g, b, lds, s, a, d);
+}
+
+template <int R_, int G_, bool ST>
 static void adj_launch(int pass, bool cube, bool keep, dim3 g, dim3 b, size_t lds, hipStream_t s,
                        const StepArgs<double> &a, const AdjArgs &d, const AdjArgs *d1) {
     if (pass == 2) hipLaunchKernelGGL((k_adj2<R_, G_, ST>), g, b, lds, s, a, d);
@@ -567,6 +631,8 @@ static void adj_launch(int pass, bool cube, bool keep, dim3 g, dim3 b, size_t ld
 cryo_status launch_adj(const cryo_plan *p, int pass, const AdjArgs &d, int *flag, hipStream_t s,
                        const AdjArgs *d1) {
     StepArgs<double> a = step_args_f64(p, flag);
+    // the Joule source's sqrt(tref) (the adjoint kernels read no other X)
+    a.X = a.joule ? sqrt(p->joule_tref) : 1.0;
     dim3 g(adj_grid(p)), b(ADJ_WAVES * WAVE);
     const size_t lds = adj_lds(p);
     const int key = p->rpl * 10 + p->wpl;
@@ -574,7 +640,10 @@ cryo_status launch_adj(const cryo_plan *p, int pass, const AdjArgs &d, int *flag
     const bool cube = a.laws.cube, keep = a.lpw == 1;
 #define ADJ_CASE(R_, G_)                                                                    \
     case R_ * 10 + G_:                                                                      \
-        if (p->stepped) adj_launch<R_, G_, true>(pass, cube, keep, g, b, lds, s, a, d, d1);   \
+        if (p->poly && p->stepped)                                                          \
+            adj_launch_poly<R_, G_, true>(pass, keep, g, b, lds, s, a, d, d1);              \
+        else if (p->poly) adj_launch_poly<R_, G_, false>(pass, keep, g, b, lds, s, a, d, d1); \
+        else if (p->stepped) adj_launch<R_, G_, true>(pass, cube, keep, g, b, lds, s, a, d, d1); \
         else adj_launch<R_, G_, false>(pass, cube, keep, g, b, lds, s, a, d, d1);             \
         break;
     switch (key) {

@@ -290,7 +290,6 @@ static cryo_status grad_check(const cryo_plan *p, int64_t N, const double *targe
                               const void *T0, void *ws, size_t ws_bytes) {
     if (!p || !T0 || N < 1 || !target || ckpt < 0) return fail(CRYO_ERR_ARG, "bad argument");
     if (p->dtype != CRYO_F64) return fail(CRYO_ERR_UNSUPPORTED, "the adjoint needs an FP64 plan");
-    if (p->poly) return fail(CRYO_ERR_UNSUPPORTED, "no adjoint of the polynomial laws");
     if (adj_lds(p) > MAX_STEP_LDS)
         return fail(CRYO_ERR_UNSUPPORTED, "the adjoint's tables exceed a workgroup's LDS for this "
                                           "shape; choose fewer rows per line");

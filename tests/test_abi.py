@@ -181,14 +181,17 @@ def test_polynomial_laws_host_checks():
     with pytest.raises(ValueError):
         plan.set_poly_laws(a[:-1], zero_b)
     P.Plan(dict(c, turn_on=True))                           # with the turn-on model
+    # the gradient takes the polynomial laws (FP64 plans; the host check
+    # refuses an FP32 plan before any device work)
     L = P.lib()
     tgt = np.zeros(4)
     J, g = ctypes.c_double(), np.zeros(2 + 2 * len(Ls))
     dp = ctypes.POINTER(ctypes.c_double)
-    st = L.cryo_gradient(plan._h, ctypes.c_void_p(256), 4, tgt.ctypes.data_as(dp), 0,
+    f32 = P.Plan(c, "f32")
+    st = L.cryo_gradient(f32._h, ctypes.c_void_p(256), 4, tgt.ctypes.data_as(dp), 0,
                          ctypes.c_void_p(256), 1 << 40, ctypes.byref(J), g.ctypes.data_as(dp),
                          None, None)
-    assert st == 6 and "polynomial" in P.lib().cryo_last_error().decode()
+    assert st == 6 and "FP64" in P.lib().cryo_last_error().decode()
 
 
 def test_stepped_domain_host_checks():

@@ -260,3 +260,35 @@ def test_gpu_gradient_stepped_matches_oracle_adjoint(seed, nr, nz, z_full, nr_to
     e = _norm_err(gg, go, P.params_of(c))
     say("  normalised gradient error %.3e" % e)
     assert e < 1e-8, (gg, go)
+
+
+@pytest.mark.parametrize("seed,nr,joule,shape,extra", [
+    (0, 40, 0.0, None, None), (1, 40, 30.0, (4, 2, 1), None), (2, 40, 30.0, (8, 1, 2), "stepped"),
+    (3, 40, 30.0, None, "turn_on"), (4, 300, 30.0, None, None), (5, 300, 0.0, (4, 4, 1), None)])
+def test_gpu_gradient_poly_matches_oracle_adjoint(seed, nr, joule, shape, extra):
+    # the polynomial laws of eqs. (23), (24) and the Joule source of eq. (25)
+    # in the adjoint passes: derivative polynomials, the interface row's
+    # quotient of two laws, the source's sqrt(tref / T) factor in lam^n and
+    # in the amplitude and width sums; with a stepped domain and with the
+    # turn-on model's sub-steps; one, two and four waves per line
+    import paper_1408_5853_amd as P
+    c = cellgen.poly_variant(cellgen.tiny(40 + seed, nr=nr, nz=9, n_layers=3, nsteps=30,
+                                          z_active=True, dt=2e-6, amplitude=4e9, heater=2),
+                             seed, joule_tref=joule)
+    if extra == "stepped":
+        c["stepped"] = dict(z_full=5, nr_top=30)
+    if extra == "turn_on":
+        dt = c["dt"]
+        c.update(t_on=3 * dt, period=20 * dt, width=4.6 * dt, turn_on=True)
+    tgt = _target(c, 30)
+    say("case adjoint poly nr=%d joule=%g shape=%s %s" % (nr, joule, shape, extra))
+    Jo, go, So = oracle.gradient(c, tgt)
+    plan = P.Plan(c)
+    if shape:
+        plan.set_shape(*shape)
+    Jg, gg, Sg = plan.gradient(tgt, ckpt=7)
+    assert Jg == pytest.approx(Jo, rel=1e-9)
+    assert np.max(np.abs(Sg - So) / So) < 1e-10
+    e = _norm_err(gg, go, P.params_of(c))
+    say("  normalised gradient error %.3e" % e)
+    assert e < 1e-8, (gg, go)
