@@ -128,7 +128,7 @@ int main(void) {
     c.poly_a = pa;
     c.poly_b = pb;
     c.joule_tref = 30.0;                   /* eq. (25) */
-    run_case("polynomial laws, Joule source", c, 0);
+    run_case("polynomial laws, Joule source", c, 1);
 
     if (failures) {
         fprintf(stderr, "%d checks failed\n", failures);
