@@ -593,22 +593,20 @@ cryo_status launch_fill(const cryo_plan *p, void *T, hipStream_t s) {
 }
 
 // Arguments of the stepping kernel (its row tables and laws: capacity rows
-// scaled by eta^2, so the source is too), or with `rows_as_written` the
-// tables of the rows as the equations write them (adjoint kernels).
+// scaled by eta^2, so the source is too); the adjoint kernels take the same.
 template <typename R>
 static StepArgs<R> step_args(const cryo_plan *p, const void *Tin, void *Tout, double X,
-                             double *partial, int *flag, bool rows_as_written = false) {
+                             double *partial, int *flag) {
     StepArgs<R> a;
-    const bool f = !rows_as_written;
-    const double xs = f ? p->eta * p->eta : 1.0;
+    const double xs = p->eta * p->eta;
     a.flag = flag;
     a.Tin = (const R *)Tin;
     a.Tout = (R *)Tout;
-    a.gw = (const R *)p->d_rows + (f ? 2 * (size_t)p->np : 0);
+    a.gw = (const R *)p->d_rows;
     a.ge = a.gw + p->np;
-    a.info = p->d_info + (f ? p->np : 0);
-    a.pow_blob = p->d_pow + (f ? p->pow_blob.size() : 0);
-    a.laws = f ? p->flaws : p->laws;
+    a.info = p->d_info;
+    a.pow_blob = p->d_pow;
+    a.laws = p->flaws;
     a.nz = p->nz;
     a.np = p->np;
     a.lpw = p->lpw;

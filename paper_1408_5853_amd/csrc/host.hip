@@ -212,28 +212,23 @@ cryo_status ensure_device(cryo_plan *p) {
     (void)hipGetDevice(&p->device);
     const int np = p->np;
     size_t es = p->dtype == CRYO_F64 ? sizeof(double) : sizeof(float);
-    // one array of four planes: gw, ge, fgw, fge
-    std::vector<double> rows(p->gw);
-    rows.insert(rows.end(), p->ge.begin(), p->ge.end());
-    rows.insert(rows.end(), p->fgw.begin(), p->fgw.end());
+    // one array of two planes: fgw, fge
+    std::vector<double> rows(p->fgw);
     rows.insert(rows.end(), p->fge.begin(), p->fge.end());
-    std::vector<uint32_t> infos(p->info);
-    infos.insert(infos.end(), p->finfo.begin(), p->finfo.end());
-    std::vector<double> blobs(p->pow_blob);
-    blobs.insert(blobs.end(), p->fpow_blob.begin(), p->fpow_blob.end());
-    hipError_t e = hipMalloc(&p->d_rows, es * 4 * np);
+    const std::vector<double> &blobs = p->fpow_blob;
+    hipError_t e = hipMalloc(&p->d_rows, es * 2 * np);
     uint32_t *info = nullptr;
-    if (e == hipSuccess) e = hipMalloc((void **)&info, sizeof(uint32_t) * 2 * np);
+    if (e == hipSuccess) e = hipMalloc((void **)&info, sizeof(uint32_t) * np);
     if (e == hipSuccess) {
         if (p->dtype == CRYO_F64) {
-            e = hipMemcpy(p->d_rows, rows.data(), es * 4 * np, hipMemcpyHostToDevice);
+            e = hipMemcpy(p->d_rows, rows.data(), es * 2 * np, hipMemcpyHostToDevice);
         } else {
             std::vector<float> a(rows.begin(), rows.end());
-            e = hipMemcpy(p->d_rows, a.data(), es * 4 * np, hipMemcpyHostToDevice);
+            e = hipMemcpy(p->d_rows, a.data(), es * 2 * np, hipMemcpyHostToDevice);
         }
     }
     if (e == hipSuccess)
-        e = hipMemcpy(info, infos.data(), sizeof(uint32_t) * 2 * np, hipMemcpyHostToDevice);
+        e = hipMemcpy(info, p->finfo.data(), sizeof(uint32_t) * np, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc((void **)&p->d_pow, sizeof(double) * blobs.size());
     if (e == hipSuccess)
         e = hipMemcpy(p->d_pow, blobs.data(), sizeof(double) * blobs.size(),
@@ -282,11 +277,11 @@ cryo_status ensure_device(cryo_plan *p) {
 // Lane-major per-row tables: row i = lg * rpl + reg of a line sits at
 // reg * (64 wpl) + lg, lg the lane within the line.
 // One line's rows: nodes 0..n-1 of the grid, row n-1 the outer wall
-// (insulated when `terminal`, else as the problem says).  Writes the rows as
-// written (gw, ge, info; may be null) and the stepping kernel's form (fgw,
-// fge, finfo) at the lane-major positions.
-static void fill_rows(cryo_plan *p, int n, bool terminal, double *gwo, double *geo,
-                      uint32_t *info, double *fgwo, double *fgeo, uint32_t *finfo) {
+// (insulated when `terminal`, else as the problem says).  Writes the rows in
+// the kernels' form (fgw, fge, finfo) at the lane-major positions; gw, ge and
+// the slot laws are first formed as the equations write the rows.
+static void fill_rows(cryo_plan *p, int n, bool terminal, double *fgwo, double *fgeo,
+                      uint32_t *finfo) {
     const cryo_problem *prob = &p->prob;
     const int nr = p->nr, L = p->L, rpl = p->rpl;
     const int ZERO = law_zero(L), UNIT = law_unit(L);
@@ -320,11 +315,6 @@ static void fill_rows(cryo_plan *p, int n, bool terminal, double *gwo, double *g
         } else {  // K_HI: eq. (15)/(17): T_{N} = T_{N-1}, or the held wall value
             if (bk[1] == CRYO_HELD && !terminal) { lawC = UNIT; held = 1; side = 1; }
             else { gw = 1.0; law2 = UNIT; side = 1; }
-        }
-        if (gwo) {
-            gwo[idx] = gw;
-            geo[idx] = ge;
-            info[idx] = info_pack(kind, heat, held, side, lawE, law2, law3, lawC);
         }
         // the stepping kernel's form: capacity rows times eta^2 (slot 2 then
         // takes the radial law), interface rows divided by the outer law
@@ -365,21 +355,16 @@ static void build_row_tables(cryo_plan *p) {
     // padding rows: identity; polynomial laws divide slot 2 by slot 3 on
     // every row, so slot 3 is the unit law there
     const uint32_t pad = info_pack(K_PAD, 0, 0, 0, ZERO, ZERO, p->poly ? UNIT : ZERO, UNIT);
-    p->gw.assign(np, 0.0);
-    p->ge.assign(np, 0.0);
-    p->info.assign(np, info_pack(K_PAD, 0, 0, 0, ZERO, ZERO, ZERO, UNIT));
     p->fgw.assign(np, 0.0);
     p->fge.assign(np, 0.0);
     p->finfo.assign(np, pad);
-    fill_rows(p, nr, false, p->gw.data(), p->ge.data(), p->info.data(), p->fgw.data(),
-              p->fge.data(), p->finfo.data());
+    fill_rows(p, nr, false, p->fgw.data(), p->fge.data(), p->finfo.data());
     // stepped domain (eq. (9)): the terminal's lines, nodes 0..nr_top-1
     p->tfgw.assign(np, 0.0);
     p->tfge.assign(np, 0.0);
     p->tfinfo.assign(np, pad);
     if (p->stepped)
-        fill_rows(p, p->nr_top, true, nullptr, nullptr, nullptr, p->tfgw.data(), p->tfge.data(),
-                  p->tfinfo.data());
+        fill_rows(p, p->nr_top, true, p->tfgw.data(), p->tfge.data(), p->tfinfo.data());
     p->surf_lane = (nr - 1) / p->rpl;
     p->surf_reg = (nr - 1) % p->rpl;
 }
@@ -473,8 +458,6 @@ cryo_status cryo_plan_create(const cryo_problem *prob, cryo_dtype dtype, cryo_pl
     lw.K[ZERO] = 0.0;
     lw.K[UNIT] = 1.0;
     for (int id = 0; id < nlaw; ++id) lw.lk[id] = lw.K[id] > 0 ? log2(lw.K[id]) : -2000.0;
-
-    fill_pow_blob(lw, p->pow_blob);
 
     // the stepping kernel's laws (see Laws): capacity rows scaled by eta^2,
     // interface rows by 1 / (outer law); FP32 takes log2 K - e, its laws being

@@ -147,13 +147,12 @@ struct cryo_plan {
     std::vector<double> r, h;         // node radii, interval widths (h[0] unused)
     std::vector<int> lay;             // layer of interval i
     std::vector<int> kind;            // row class per node
-    // host copies of the lane-major tables: rows of eqs. (13), (15), (18) as
-    // written (adjoint), and the stepping kernel's form of the same rows
-    // (capacity rows times eta^2, interface rows divided by the outer law)
-    std::vector<double> gw, ge;
-    std::vector<uint32_t> info;
+    // the laws as the equations write them (per layer: radial, axial,
+    // capacity; from these the kernels' laws are formed), and host copies of
+    // the lane-major row tables in the kernels' form of the rows of eqs.
+    // (13), (15), (18) (capacity rows times eta^2, interface rows divided by
+    // the outer law), which the stepping and the adjoint kernels share
     cryo::Laws laws;
-    std::vector<double> pow_blob;     // FP64 power tables (see POW_*)
     std::vector<double> fgw, fge;
     std::vector<uint32_t> finfo;
     cryo::Laws flaws;
@@ -161,9 +160,9 @@ struct cryo_plan {
     cryo::Pulse pulse;
     int surf_lane, surf_reg;          // owner of row nr-1
     // device tables (read-only, made at create time)
-    void *d_rows = nullptr;           // [4][np]: gw, ge, fgw, fge
-    uint32_t *d_info = nullptr;       // [2][np]: info, finfo
-    double *d_pow = nullptr;          // pow_blob, then fpow_blob
+    void *d_rows = nullptr;           // [2][np]: fgw, fge
+    uint32_t *d_info = nullptr;       // [np]: finfo
+    double *d_pow = nullptr;          // fpow_blob
     int device = 0;
     // transient turn-on model (eq. (22)): the same cell at dt / 100, whose
     // tables step the sub-steps of each pulse-start step (null when off)
