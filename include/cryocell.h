@@ -203,7 +203,8 @@ cryo_status cryo_forward(const cryo_plan *plan, void *T, int64_t k0,
  * device call; FP64 and FP32; combines with the polynomial laws and the
  * turn-on model.  Gradients follow the stepped domain (the surface mean over
  * the layered section); a shape whose adjoint tables would not fit a
- * workgroup's LDS is refused there (CRYO_ERR_UNSUPPORTED). */
+ * workgroup's LDS is refused there (CRYO_ERR_UNSUPPORTED).  Batches take the
+ * domain per instance (cryo_batch_create_with). */
 cryo_status cryo_plan_set_stepped(cryo_plan *plan, int32_t z_full, int32_t nr_top);
 
 /* Polynomial material laws of eqs. (23) and (24) in place of the power laws,
@@ -219,7 +220,8 @@ cryo_status cryo_plan_set_stepped(cryo_plan *plan, int32_t z_full, int32_t nr_to
  * temperature-independent.  Both laws must be positive, and dt within
  * eq. (21)'s bound, at the coldest prescribed temperature (checked there
  * only: CRYO_ERR_ARG, CRYO_ERR_UNSTABLE).  Arrays are copied.  Gradients
- * refuse such a plan (CRYO_ERR_UNSUPPORTED); batches do not offer it. */
+ * follow the laws and the source (see cryo_gradient); batches take them per
+ * instance (cryo_batch_create_with). */
 cryo_status cryo_plan_set_poly_laws(cryo_plan *plan, const double *a, const double *b,
                                     double joule_tref);
 
@@ -353,8 +355,8 @@ cryo_status cryo_batch_autotune(int32_t n, const cryo_problem *probs, cryo_dtype
  * otherwise, see cryo_plan_set_shape); polynomial laws and the Joule source
  * (cryo_plan_set_poly_laws: the derivative polynomials, the interface row's
  * quotient of two laws, the source's sqrt(tref / T) factor) and a stepped
- * domain (cryo_plan_set_stepped) are followed.  T0 is a device field; target, J, grad and surf (nullable, N
- * values) are host arrays.  Synchronous on `stream`; the same device work as
+ * domain (cryo_plan_set_stepped) are followed.  T0 is a device field;
+ * target, J, grad and surf (nullable, N values) are host arrays.  Synchronous on `stream`; the same device work as
  * cryo_gradient_async (results equal bit for bit). */
 cryo_status cryo_gradient_workspace_bytes(const cryo_plan *plan, int64_t nsteps, int64_t ckpt,
                                           size_t *bytes);
@@ -413,6 +415,28 @@ cryo_status cryo_gradient_many(int32_t n, cryo_plan *const *plans, const void *c
  * name the failing instance. */
 cryo_status cryo_batch_create(int32_t n, const cryo_problem *probs, cryo_dtype dtype,
                               const int32_t *shapes, cryo_batch **out);
+
+/* Plan options of one batch instance: what cryo_plan_set_poly_laws and
+ * cryo_plan_set_stepped set on a single plan (same arguments and checks). */
+typedef struct {
+    const double *poly_a;    /* NULL, or [n_layers][4]: c(T) of eq. (23) */
+    const double *poly_b;    /* NULL, or [n_layers][5]: lambda(T) / k_scale of
+                              * eq. (24); given with poly_a */
+    double joule_tref;       /* > 0 with the polynomial laws: the Joule source
+                              * of eq. (25); else 0 */
+    int32_t z_full, nr_top;  /* both 0: rectangular; else the stepped domain of
+                              * eq. (9) */
+} cryo_instance_options;
+/* cryo_batch_create with per-instance options (`opts`: n entries, nullable
+ * for none).  Instances are grouped by kernel shape, law family (cube
+ * capacity, general power laws, polynomial laws) and domain (rectangular or
+ * stepped), one launch per group and step as above; each instance steps
+ * exactly as a plan with the same shape and options (bit for bit).  The
+ * turn-on model has no batch form.  Option errors name the instance
+ * (CRYO_ERR_ARG, CRYO_ERR_UNSTABLE, as the plan setters). */
+cryo_status cryo_batch_create_with(int32_t n, const cryo_problem *probs, cryo_dtype dtype,
+                                   const int32_t *shapes, const cryo_instance_options *opts,
+                                   cryo_batch **out);
 void cryo_batch_destroy(cryo_batch *batch);
 /* Element offsets of the instances' fields in the packed buffer (n + 1). */
 cryo_status cryo_batch_offsets(const cryo_batch *batch, int64_t *offsets);

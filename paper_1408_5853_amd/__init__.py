@@ -342,12 +342,9 @@ class Batch:
         self.dtype = dtype
         n = len(self.cells)
         for i, c in enumerate(self.cells):
-            # the batch steps the power-law cell of the problem structure; the
-            # plan options below have no batch form (a Plan per cell does)
-            for key in ("poly", "stepped", "turn_on"):
-                if c.get(key):
-                    raise ValueError("cell %d: batches do not offer the %r option; step such "
-                                     "cells with Plan" % (i, key))
+            if c.get("turn_on"):
+                raise ValueError("cell %d: batches do not offer the turn-on model; step such "
+                                 "cells with Plan" % i)
         self._ps = [_abi.ProblemStruct(c) for c in self.cells]
         arr = (_abi.Problem * n)(*[p.s for p in self._ps])
         self._arr = arr
@@ -356,9 +353,26 @@ class Batch:
             flat = np.ascontiguousarray(np.asarray(shapes, dtype=np.int32).reshape(n, 3))
             self._shapes = flat
             sh = flat.ctypes.data_as(C.POINTER(C.c_int32))
+        # per-instance plan options: polynomial laws (eqs. (23)-(25)) and the
+        # stepped domain (eq. (9)), as Plan takes them from a cell
+        opts = (_abi.InstanceOptions * n)()
+        self._keep = []
+        dp = C.POINTER(C.c_double)
+        for i, c in enumerate(self.cells):
+            if c.get("poly"):
+                Ls = c["layers"]
+                a = np.ascontiguousarray([float(x) for l in Ls for x in l["poly_a"]])
+                b = np.ascontiguousarray([float(x) for l in Ls for x in l["poly_b"]])
+                self._keep += [a, b]
+                opts[i].poly_a = a.ctypes.data_as(dp)
+                opts[i].poly_b = b.ctypes.data_as(dp)
+                opts[i].joule_tref = float(c.get("joule_tref", 0.0))
+            if c.get("stepped"):
+                opts[i].z_full = int(c["stepped"]["z_full"])
+                opts[i].nr_top = int(c["stepped"]["nr_top"])
         h = C.c_void_p()
-        check(lib().cryo_batch_create(n, arr, _abi.F64 if dtype == "f64" else _abi.F32, sh,
-                                      C.byref(h)))
+        check(lib().cryo_batch_create_with(n, arr, _abi.F64 if dtype == "f64" else _abi.F32, sh,
+                                           opts, C.byref(h)))
         self._h = h
         off = (C.c_int64 * (n + 1))()
         check(lib().cryo_batch_offsets(self._h, off))

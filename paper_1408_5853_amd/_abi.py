@@ -23,7 +23,7 @@ SYMBOLS = [
     "cryo_workspace_bytes", "cryo_init", "cryo_forward", "cryo_poll",
     "cryo_plan_shape", "cryo_plan_set_shape", "cryo_plan_set_turn_on", "cryo_plan_set_poly_laws",
     "cryo_plan_set_stepped",
-    "cryo_batch_create", "cryo_batch_destroy", "cryo_batch_offsets", "cryo_batch_shape",
+    "cryo_batch_create", "cryo_batch_create_with", "cryo_batch_destroy", "cryo_batch_offsets", "cryo_batch_shape",
     "cryo_batch_workspace_bytes", "cryo_batch_init", "cryo_batch_forward", "cryo_batch_poll",
     "cryo_gradient_workspace_bytes", "cryo_gradient", "cryo_gradient_async", "cryo_gradient_many",
     "cryo_autotune", "cryo_batch_autotune",
@@ -65,6 +65,11 @@ class Boundary(C.Structure):
 class Problem(C.Structure):
     _fields_ = [("geom", Geometry), ("pulse", Pulse), ("bc", Boundary), ("dt", C.c_double),
                 ("T_init", C.c_double)]
+
+
+class InstanceOptions(C.Structure):
+    _fields_ = [("poly_a", C.POINTER(C.c_double)), ("poly_b", C.POINTER(C.c_double)),
+                ("joule_tref", C.c_double), ("z_full", C.c_int32), ("nr_top", C.c_int32)]
 
 
 _lib = None
@@ -111,6 +116,8 @@ def lib():
         L.cryo_plan_set_poly_laws.argtypes = [vp, dp, dp, C.c_double]
         L.cryo_plan_set_stepped.argtypes = [vp, C.c_int32, C.c_int32]
         L.cryo_batch_create.argtypes = [C.c_int32, pp, C.c_int, i32p, C.POINTER(vp)]
+        L.cryo_batch_create_with.argtypes = [C.c_int32, pp, C.c_int, i32p,
+                                             C.POINTER(InstanceOptions), C.POINTER(vp)]
         L.cryo_batch_destroy.argtypes = [vp]
         L.cryo_batch_destroy.restype = None
         L.cryo_batch_offsets.argtypes = [vp, C.POINTER(C.c_int64)]

@@ -128,8 +128,8 @@ template <int RPL, int G, bool CUBE, bool STEPPED = false, bool POLY = false>
 // (keep: lam^{n+1} of the group's single line comes in lamR, not from memory)
 // POLY: the interface row's coefficient is the quotient of its inner (slot 2)
 // and outer (slot 3) layer laws, and with the Joule source (eq. (25)) a
-// heater row's source is X sqrt(tref / T) at the old T (a.X holds sqrt(tref)
-// in the adjoint's arguments, 1 without the Joule source).
+// heater row's source is X sqrt(tref / T) at the old T (a.jsq holds
+// sqrt(tref)).
 __device__ inline void adj1_body(const StepArgs<double> &a, const AdjArgs &d,
                                  unsigned char *smem, const AdjLds<POLY> &tb,
                                  const double (&lamR)[RPL], bool keep) {
@@ -340,7 +340,7 @@ __device__ inline void adj1_body(const StepArgs<double> &a, const AdjArgs &d,
                 double chi = 1.0;
                 if constexpr (POLY) {
                     if (a.joule && ((inf_r >> 3) & 1)) {
-                        chi = a.X * rsqrt(t);
+                        chi = a.jsq * rsqrt(t);
                         self += 0.5 * a.pulse.amplitude * d.s * chi * rcp(t);
                     }
                 }
@@ -631,8 +631,6 @@ static void adj_launch(int pass, bool cube, bool keep, dim3 g, dim3 b, size_t ld
 cryo_status launch_adj(const cryo_plan *p, int pass, const AdjArgs &d, int *flag, hipStream_t s,
                        const AdjArgs *d1) {
     StepArgs<double> a = step_args_f64(p, flag);
-    // the Joule source's sqrt(tref) (the adjoint kernels read no other X)
-    a.X = a.joule ? sqrt(p->joule_tref) : 1.0;
     dim3 g(adj_grid(p)), b(ADJ_WAVES * WAVE);
     const size_t lds = adj_lds(p);
     const int key = p->rpl * 10 + p->wpl;

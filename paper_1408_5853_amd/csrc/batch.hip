@@ -19,6 +19,8 @@ constexpr int GRAPH_STEPS = 32;      // steps per captured graph block (even)
 struct Bucket {
     int rpl, wpl;
     bool cube;                       // every capacity exponent is 3
+    bool poly;                       // polynomial laws (eqs. (23)-(25))
+    bool stepped;                    // stepped domain (eq. (9))
     std::vector<int> inst;           // instance indices
     std::vector<int2> map;           // workgroup -> (instance, workgroup of instance)
     size_t desc_off = 0, map_off = 0;  // byte offsets in the device block
@@ -56,9 +58,9 @@ static int64_t abi_elems(const cryo_plan *p) {
 // descriptor builders live with the kernels (forward.hip)
 size_t step_desc_bytes(cryo_dtype dt);
 void step_desc_fill(const cryo_plan *p, void *out, void *buf0, void *buf1, int *flag);
-cryo_status launch_step_batch(cryo_dtype dt, int rpl, int wpl, bool cube, const void *desc,
-                              const int2 *map, int nwg, size_t lds, int64_t n,
-                              const int64_t *k0, hipStream_t s);
+cryo_status launch_step_batch(cryo_dtype dt, int rpl, int wpl, bool cube, bool poly,
+                              bool stepped, const void *desc, const int2 *map, int nwg,
+                              size_t lds, int64_t n, const int64_t *k0, hipStream_t s);
 cryo_status launch_set_i64(int64_t *ptr, int64_t v, hipStream_t s);
 cryo_status launch_add_i64(int64_t *ptr, int64_t v, hipStream_t s);
 
@@ -89,13 +91,18 @@ static cryo_status batch_build_buckets(cryo_batch *b) {
     std::map<int, int> idx;
     for (size_t i = 0; i < b->plans.size(); ++i) {
         const cryo_plan *p = b->plans[i];
-        int key = p->rpl * 10 + p->wpl + (p->laws.cube ? 1000 : 0);
+        // shape, law family (cube, power, polynomial) and domain
+        const bool cube = !p->poly && p->flaws.cube != 0;
+        int key = p->rpl * 10 + p->wpl + (cube ? 1000 : 0) + (p->poly ? 2000 : 0) +
+                  (p->stepped ? 4000 : 0);
         if (!idx.count(key)) {
             idx[key] = (int)b->buckets.size();
             Bucket bk;
             bk.rpl = p->rpl;
             bk.wpl = p->wpl;
-            bk.cube = p->laws.cube != 0;
+            bk.cube = cube;
+            bk.poly = p->poly;
+            bk.stepped = p->stepped;
             b->buckets.push_back(bk);
         }
         Bucket &bk = b->buckets[idx[key]];
@@ -135,6 +142,12 @@ extern "C" {
 
 cryo_status cryo_batch_create(int32_t n, const cryo_problem *probs, cryo_dtype dtype,
                               const int32_t *shapes, cryo_batch **out) {
+    return cryo_batch_create_with(n, probs, dtype, shapes, nullptr, out);
+}
+
+cryo_status cryo_batch_create_with(int32_t n, const cryo_problem *probs, cryo_dtype dtype,
+                                   const int32_t *shapes, const cryo_instance_options *opts,
+                                   cryo_batch **out) {
     if (!out || n < 1 || !probs) return fail(CRYO_ERR_ARG, "bad batch arguments");
     *out = nullptr;
     cryo_batch *b = new cryo_batch();
@@ -142,6 +155,19 @@ cryo_status cryo_batch_create(int32_t n, const cryo_problem *probs, cryo_dtype d
     for (int i = 0; i < n; ++i) {
         cryo_plan *p = nullptr;
         cryo_status st = cryo_plan_create(&probs[i], dtype, &p);
+        // the instance's plan options, as cryo_plan_set_poly_laws and
+        // cryo_plan_set_stepped set them on a single plan
+        if (st == CRYO_OK && opts) {
+            const cryo_instance_options &o = opts[i];
+            if ((o.poly_a != nullptr) != (o.poly_b != nullptr))
+                st = fail(CRYO_ERR_ARG, "polynomial laws need both poly_a and poly_b");
+            else if (!o.poly_a && o.joule_tref != 0.0)
+                st = fail(CRYO_ERR_ARG, "the Joule source needs the polynomial laws");
+            else if (o.poly_a)
+                st = cryo_plan_set_poly_laws(p, o.poly_a, o.poly_b, o.joule_tref);
+            if (st == CRYO_OK && (o.z_full != 0 || o.nr_top != 0))
+                st = cryo_plan_set_stepped(p, o.z_full, o.nr_top);
+        }
         if (st == CRYO_OK && shapes)
             st = cryo_plan_set_shape(p, shapes[3 * i], shapes[3 * i + 1], shapes[3 * i + 2]);
         else if (st == CRYO_OK)
@@ -244,7 +270,8 @@ cryo_status cryo_batch_forward(cryo_batch *b, void *T, int64_t k0, int64_t nstep
         for (int i : bk.inst) lds = std::max(lds, step_lds(b->plans[i]));
         for (int64_t m = first; m < first + count; ++m) {
             cryo_status r = launch_step_batch(
-                b->dtype, bk.rpl, bk.wpl, bk.cube, (const char *)b->d_block + bk.desc_off,
+                b->dtype, bk.rpl, bk.wpl, bk.cube, bk.poly, bk.stepped,
+                (const char *)b->d_block + bk.desc_off,
                 (const int2 *)((const char *)b->d_block + bk.map_off), (int)bk.map.size(), lds,
                 m, k0p, strm);
             if (r != CRYO_OK) return r;

@@ -155,6 +155,8 @@ struct StepArgs {
     int z_full;
     const R *gw2, *ge2;
     const uint32_t *info2;
+    double jsq;               // sqrt(T_J) with the Joule source, else 1 (batch
+                              // and adjoint kernels form their source with it)
 };
 
 constexpr int STEP_WAVES = STEP_WAVES_HOST;

@@ -471,15 +471,17 @@ __device__ inline double source_fraction_dev(const Pulse &p, int64_t k) {
 
 // One step of many instances: workgroup -> (instance, workgroup of that
 // instance); global step k = *k0 + n; buffers by the parity of n.
-template <typename R, int RPL, int G, bool CUBE>
+template <typename R, int RPL, int G, bool CUBE, bool POLY = false, bool STEPPED = false>
 __global__ __launch_bounds__(STEP_WAVES *WAVE) void k_step_batch(const StepArgs<R> *descs,
                                                                  const int2 *wg_map, int64_t n,
                                                                  const int64_t *k0) {
     const int2 m = wg_map[blockIdx.x];
     const StepArgs<R> &a = descs[m.x];
-    const double X = a.pulse.amplitude * source_fraction_dev(a.pulse, *k0 + n);
+    double X = a.pulse.amplitude * source_fraction_dev(a.pulse, *k0 + n);
+    if constexpr (POLY) X *= a.jsq;                 // the Joule source's sqrt(T_J)
     double *part = a.partial ? a.partial + (size_t)(n % SURF_CHUNK) * a.groups : nullptr;
-    step_body<R, RPL, G, CUBE>(a, m.y, a.buf[n & 1], a.buf[(n + 1) & 1], (R)X, part);
+    step_body<R, RPL, G, CUBE, POLY, STEPPED>(a, m.y, a.buf[n & 1], a.buf[(n + 1) & 1], (R)X,
+                                              part);
 }
 
 // ABI field -> internal lines.  FP32 fields are two planes [2][nz][nr]
@@ -611,7 +613,8 @@ static StepArgs<R> step_args(const cryo_plan *p, const void *Tin, void *Tout, do
     a.np = p->np;
     a.lpw = p->lpw;
     a.joule = p->poly && p->joule_tref > 0;
-    a.X = (R)(X * xs * (a.joule ? sqrt(p->joule_tref) : 1.0));
+    a.jsq = a.joule ? sqrt(p->joule_tref) : 1.0;
+    a.X = (R)(X * xs * a.jsq);
     for (int s = 0; s < 4; ++s) {
         a.held[s] = p->prob.bc.kind[s] == CRYO_HELD;
         a.val[s] = (R)p->prob.bc.value[s];
@@ -717,15 +720,26 @@ void step_desc_fill(const cryo_plan *p, void *out, void *buf0, void *buf1, int *
 }
 
 template <typename R>
-static cryo_status step_batch_t(int rpl, int wpl, bool cube, const void *desc, const int2 *map,
-                                int nwg, size_t lds, int64_t n, const int64_t *k0,
-                                hipStream_t s) {
+static cryo_status step_batch_t(int rpl, int wpl, bool cube, bool poly, bool stepped,
+                                const void *desc, const int2 *map, int nwg, size_t lds,
+                                int64_t n, const int64_t *k0, hipStream_t s) {
     const StepArgs<R> *d = (const StepArgs<R> *)desc;
     dim3 g(nwg), b(STEP_WAVES * WAVE);
     switch (rpl * 10 + wpl) {
 #define BATCH_CASE(RP, GW) \
     case RP * 10 + GW: \
-        if (cube) \
+        if (poly && stepped) \
+            hipLaunchKernelGGL((k_step_batch<R, RP, GW, false, true, true>), g, b, lds, s, d, map, \
+                               n, k0); \
+        else if (stepped && cube) \
+            hipLaunchKernelGGL((k_step_batch<R, RP, GW, true, false, true>), g, b, lds, s, d, map, \
+                               n, k0); \
+        else if (stepped) \
+            hipLaunchKernelGGL((k_step_batch<R, RP, GW, false, false, true>), g, b, lds, s, d, \
+                               map, n, k0); \
+        else if (poly) \
+            hipLaunchKernelGGL((k_step_batch<R, RP, GW, false, true>), g, b, lds, s, d, map, n, k0); \
+        else if (cube) \
             hipLaunchKernelGGL((k_step_batch<R, RP, GW, true>), g, b, lds, s, d, map, n, k0); \
         else \
             hipLaunchKernelGGL((k_step_batch<R, RP, GW, false>), g, b, lds, s, d, map, n, k0); \
@@ -737,11 +751,12 @@ static cryo_status step_batch_t(int rpl, int wpl, bool cube, const void *desc, c
     return launch_check("step_batch");
 }
 
-cryo_status launch_step_batch(cryo_dtype dt, int rpl, int wpl, bool cube, const void *desc,
-                              const int2 *map, int nwg, size_t lds, int64_t n, const int64_t *k0,
-                              hipStream_t s) {
-    return dt == CRYO_F64 ? step_batch_t<double>(rpl, wpl, cube, desc, map, nwg, lds, n, k0, s)
-                          : step_batch_t<float>(rpl, wpl, cube, desc, map, nwg, lds, n, k0, s);
+cryo_status launch_step_batch(cryo_dtype dt, int rpl, int wpl, bool cube, bool poly,
+                              bool stepped, const void *desc, const int2 *map, int nwg,
+                              size_t lds, int64_t n, const int64_t *k0, hipStream_t s) {
+    return dt == CRYO_F64
+               ? step_batch_t<double>(rpl, wpl, cube, poly, stepped, desc, map, nwg, lds, n, k0, s)
+               : step_batch_t<float>(rpl, wpl, cube, poly, stepped, desc, map, nwg, lds, n, k0, s);
 }
 
 __global__ void k_set_i64(int64_t *p, int64_t v) { *p = v; }

@@ -221,15 +221,24 @@ def test_stepped_domain_host_checks():
     assert st == 6 and "LDS" in P.lib().cryo_last_error().decode()
 
 
-def test_batch_refuses_plan_only_options():
-    # the turn-on model, the polynomial laws and the stepped domain are plan
-    # options without a batch form: a batch must refuse such cells rather
-    # than step their power-law problem (no device work happens)
+def test_batch_plan_options():
+    # polynomial laws and the stepped domain are per-instance batch options
+    # (cryo_batch_create_with, host-side checks only here); the turn-on model
+    # has no batch form, and the batch tuner times power-law rectangular
+    # cells only: both refuse rather than step another problem
     base = cellgen.small_cell(0)
-    for extra in ({"turn_on": True}, {"stepped": {"z_full": 60, "nr_top": 30}},
-                  {"poly": True}):
+    poly = cellgen.poly_variant(base, 0, joule_tref=30.0)
+    stepped = dict(base, stepped={"z_full": 60, "nr_top": 30})
+    b = P.Batch([base, poly, stepped, dict(poly, stepped={"z_full": 60, "nr_top": 30})], "f64")
+    assert len(b.offsets) == 5
+    b.close()
+    with pytest.raises(P.CryoError) as e:                          # nr_top > nr
+        P.Batch([base, dict(base, stepped={"z_full": 60, "nr_top": base["nr"] + 1})], "f64")
+    assert "instance 1" in str(e.value)
+    for extra in ({"turn_on": True}, {"stepped": {"z_full": 60, "nr_top": 30}}, {"poly": True}):
         c = dict(base, **extra)
-        with pytest.raises(ValueError):
-            P.Batch([base, c], "f64")
+        if "turn_on" in extra:
+            with pytest.raises(ValueError):
+                P.Batch([base, c], "f64")
         with pytest.raises(ValueError):
             P.tune_batch([c], "f64")

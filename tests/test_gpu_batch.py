@@ -58,3 +58,46 @@ def test_batch_extreme_instances_match_oracle(dtype, tol):
             assert rel_err(g[1], To[1]) < 1e-10
         else:
             assert np.max(np.abs(g - To[1][None, :])) < tol
+
+
+def _option_cells():
+    # plain, polynomial laws with and without the Joule source (eqs.
+    # (23)-(25)), the stepped domain (eq. (9)) and both, z-active, two
+    # radial sizes (two chunk shapes)
+    st = {"z_full": 80, "nr_top": 40}
+    c = [cellgen.small_cell(0, z_active=True),
+         cellgen.poly_variant(cellgen.small_cell(1, z_active=True), 1, joule_tref=30.0),
+         cellgen.poly_variant(cellgen.small_cell(2, z_active=True), 2),
+         dict(cellgen.small_cell(3, z_active=True), stepped=st),
+         dict(cellgen.poly_variant(cellgen.small_cell(4, z_active=True), 4, joule_tref=40.0),
+              stepped=st),
+         cellgen.poly_variant(cellgen.tiny(5, nr=200, nz=40, n_layers=3, z_active=True,
+                                           dt=2e-6, amplitude=4e9, heater=2), 5,
+                              joule_tref=30.0)]
+    return c
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batch_with_plan_options(dtype):
+    # each instance equals a single plan with the same launch shape and
+    # options, bit for bit (graph blocks and a remainder), and the oracle
+    # within the tolerances
+    import torch
+
+    import paper_1408_5853_amd as P
+    cells = _option_cells()
+    n = 70
+    say("case batch with plan options %s" % dtype)
+    got, b = _run_batch(cells, n, dtype)
+    for i, c in enumerate(cells):
+        plan = P.Plan(c, dtype)
+        plan.set_shape(*b.shape(i))
+        T = plan.init()
+        plan.forward(T, 0, n)
+        torch.cuda.synchronize()
+        assert np.array_equal(got[i], plan.field_values(T)), i
+        To = oracle.forward(c, nsteps=n)
+        if dtype == "f64":
+            assert rel_err(got[i], To) < 1e-10, i
+        else:
+            assert np.max(np.abs(got[i] - To)) < 1e-4, i
