@@ -143,18 +143,20 @@ def rate(P, cell, dtype, steps, warmup, stream):
     return secs, plan
 
 
-def batch_extra(P, steps, stream):
+def batch_extra(P, steps, stream, tune_cache=None):
     """The design sweep (256 uneven cells, FP32 pairs) as one batch with the
     batch autotuner's launch shapes, against the same cells stepped one at a
     time with tuned launches (each shape group's representative tuned by
-    cryo_autotune, its shape given to the group)."""
+    cryo_autotune, its shape given to the group).  `tune_cache` (a text file
+    of the tuner) lets a profiled run take the shapes an unprofiled run
+    picked."""
     import collections
 
     import cellgen
     cells = cellgen.sweep_cells(0)
     total = sum(c["nr"] * c["nz"] for c in cells)
     t0 = time.perf_counter()
-    shapes = P.tune_batch(cells, "f32")
+    shapes = P.tune_batch(cells, "f32", cache=tune_cache)
     tune_s = time.perf_counter() - t0
     b = P.Batch(cells, "f32", shapes=shapes)
     T = b.init()
@@ -354,6 +356,8 @@ def main():
     ap.add_argument("--batch-only", type=int, default=0, metavar="N",
                     help="profiling aid: time only the batched sweep (and the same cells one "
                          "at a time) over N steps and print that result")
+    ap.add_argument("--tune-cache", default=None, metavar="PATH",
+                    help="text cache of the batch autotuner (reused when it holds this batch)")
     ap.add_argument("--design-only", type=int, default=0, metavar="N",
                     help="time only the design loop (20 Adam iterations over N steps) and print "
                          "that result")
@@ -377,7 +381,8 @@ def main():
         print(json.dumps({"gradient": gradient_extra(P, args.gradient_only, stream)}), flush=True)
         return
     if args.batch_only:
-        print(json.dumps({"batch": batch_extra(P, args.batch_only, stream)}), flush=True)
+        print(json.dumps({"batch": batch_extra(P, args.batch_only, stream, args.tune_cache)}),
+              flush=True)
         return
     if args.design_only:
         print(json.dumps({"design_loop": design_extra(P, args.design_only, 20, stream)}),
@@ -443,7 +448,7 @@ def main():
                         "f32_pair_storage_frac": round(r32 * F32_PAIR_BYTES_PER_CELL_STEP
                                                        / HBM_PEAK_GBS, 4)}
         log("bench: batched sweep")
-        out["extra"]["batch"] = batch_extra(P, 2000, stream)
+        out["extra"]["batch"] = batch_extra(P, 2000, stream, args.tune_cache)
         log("bench: gradient")
         out["extra"]["gradient"] = gradient_extra(P, 50_000, stream)
         log("bench: paper shape")

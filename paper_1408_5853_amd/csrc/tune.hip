@@ -77,7 +77,7 @@ struct Group {
     std::vector<int> inst;
 };
 
-// Time per step of the whole batch with the given shapes (the best of two
+// Time per step of the whole batch with the given shapes (the best of three
 // timed runs of `run_steps` after the capture block).
 cryo_status time_batch(int32_t n, const cryo_problem *probs, cryo_dtype dtype,
                        const std::vector<int32_t> &shp, int run_steps, hipStream_t s,
@@ -99,7 +99,7 @@ cryo_status time_batch(int32_t n, const cryo_problem *probs, cryo_dtype dtype,
     st = cryo_batch_init(b, T, s);
     if (st == CRYO_OK) st = cryo_batch_forward(b, T, 0, 32, ws, wsb, s);
     double best = 1e300;
-    for (int rep = 0; rep < 2 && st == CRYO_OK; ++rep) {
+    for (int rep = 0; rep < 3 && st == CRYO_OK; ++rep) {
         (void)hipEventRecord(e0, s);
         st = cryo_batch_forward(b, T, 32 + (int64_t)rep * run_steps, run_steps, ws, wsb, s);
         (void)hipEventRecord(e1, s);
@@ -141,8 +141,10 @@ uint64_t batch_hash(int32_t n, const cryo_problem *probs, cryo_dtype dtype) {
 // graph branch per group), so the lines per wave that suit a group alone
 // need not suit it beside the others: each group in turn, most nodes first,
 // tries lines per wave 1, 2 and 4 with every other group as picked, and
-// keeps a value that makes the whole batch at least 1 % faster.  Cached per
-// batch (a hash of the instances' grids, layer counts and law families).
+// keeps a value that makes the whole batch at least 1 % faster; a second
+// round over the groups follows when the first changed any (the groups'
+// best values depend on each other).  Cached per batch (a hash of the
+// instances' grids, layer counts and law families).
 cryo_status refine_lines_per_wave(int32_t n, const cryo_problem *probs, cryo_dtype dtype,
                                   int run_steps, const char *cache_path, hipStream_t s,
                                   hipEvent_t e0, hipEvent_t e1,
@@ -177,24 +179,29 @@ cryo_status refine_lines_per_wave(int32_t n, const cryo_problem *probs, cryo_dty
     double best = 0.0;
     cryo_status st = time_batch(n, probs, dtype, shp, run_steps, s, e0, e1, &best);
     if (st != CRYO_OK) return st;
-    for (size_t gi : order) {
-        const Group &g = groups[gi];
-        const int cur = shp[3 * g.inst[0] + 2];
-        int keep = cur;
-        for (int lpw : {1, 2, 4}) {
-            if (lpw == cur) continue;
-            std::vector<int32_t> trial(shp);
-            apply(g, lpw, trial);
-            if (trial == shp) continue;
-            double t = 0.0;
-            st = time_batch(n, probs, dtype, trial, run_steps, s, e0, e1, &t);
-            if (st != CRYO_OK) return st;
-            if (t < 0.99 * best) {
-                best = t;
-                keep = lpw;
+    for (int round = 0; round < 2; ++round) {
+        bool changed = false;
+        for (size_t gi : order) {
+            const Group &g = groups[gi];
+            const int cur = shp[3 * g.inst[0] + 2];
+            int keep = cur;
+            for (int lpw : {1, 2, 4}) {
+                if (lpw == cur) continue;
+                std::vector<int32_t> trial(shp);
+                apply(g, lpw, trial);
+                if (trial == shp) continue;
+                double t = 0.0;
+                st = time_batch(n, probs, dtype, trial, run_steps, s, e0, e1, &t);
+                if (st != CRYO_OK) return st;
+                if (t < 0.99 * best) {
+                    best = t;
+                    keep = lpw;
+                }
             }
+            if (keep != cur) changed = true;
+            apply(g, keep, shp);
         }
-        apply(g, keep, shp);
+        if (!changed) break;
     }
     for (size_t gi = 0; gi < groups.size(); ++gi) {
         int32_t c[3] = {shp[3 * groups[gi].inst[0]], shp[3 * groups[gi].inst[0] + 1], 0};
