@@ -327,7 +327,7 @@ cryo_status cryo_autotune(const cryo_problem *prob, cryo_dtype dtype, int32_t st
  * at nz - 2).  Then, with more than one group, the whole batch is timed:
  * each group in turn (most nodes first) tries lines per wave 1, 2 and 4
  * beside the others as picked and keeps a value that makes the batch at
- * least 1 % faster (the groups' launches share the chip), in a second round
+ * least 1 % faster (the groups' launches share the chip), in a second sweep
  * too when the first changed any group.  `cache_path`
  * (nullable) names a text file keyed by dtype, the group's default shape,
  * law family and largest radial size for the first pass, and by a hash of

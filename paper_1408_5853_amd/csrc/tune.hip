@@ -142,7 +142,7 @@ uint64_t batch_hash(int32_t n, const cryo_problem *probs, cryo_dtype dtype) {
 // need not suit it beside the others: each group in turn, most nodes first,
 // tries lines per wave 1, 2 and 4 with every other group as picked, and
 // keeps a value that makes the whole batch at least 1 % faster; a second
-// round over the groups follows when the first changed any (the groups'
+// sweep over the groups follows when the first changed any (the groups'
 // best values depend on each other).  Cached per batch (a hash of the
 // instances' grids, layer counts and law families).
 cryo_status refine_lines_per_wave(int32_t n, const cryo_problem *probs, cryo_dtype dtype,
@@ -179,7 +179,7 @@ cryo_status refine_lines_per_wave(int32_t n, const cryo_problem *probs, cryo_dty
     double best = 0.0;
     cryo_status st = time_batch(n, probs, dtype, shp, run_steps, s, e0, e1, &best);
     if (st != CRYO_OK) return st;
-    for (int round = 0; round < 2; ++round) {
+    for (int sweep = 0; sweep < 2; ++sweep) {
         bool changed = false;
         for (size_t gi : order) {
             const Group &g = groups[gi];
