@@ -12,7 +12,9 @@ Extra measurements in the same JSON line (not part of `value`): the FP32
 (compensated pair) rate on the same cell, the batched design sweep (256
 uneven cells) against the same cells stepped one at a time, the cost of a
 gradient (forward + checkpointed adjoint) relative to a forward on the
-adjoint workload (512 x 2048, 50,000 steps), and gradients per second of the
+adjoint workload (512 x 2048, 50,000 steps), with checkpoints only and with
+the states of the last steps kept in up to 200 GiB of HBM, and gradients per
+second of the
 batched-adjoint design loop (64 designs of 512 x 1024, 20 Adam iterations
 over a prefix of 1,000 of the 100,000 steps, final J checked against the
 oracle on four designs).
@@ -36,6 +38,7 @@ BYTES_PER_CELL_STEP = 16          # FP64: read T, write T^
 F32_BYTES_PER_CELL_STEP = 8       # FP32: read T, write T^ (algorithmic)
 F32_PAIR_BYTES_PER_CELL_STEP = 16  # what the compensated pair storage moves
 GRAD_BYTES_PER_CELL_STEP = 64     # forward 16 + recompute 16 + adjoint 32 (FP64)
+GRAD_STORE_GIB = 200              # device memory the stored-tail gradient may take
 
 # The headline kernel's HBM traffic comes from the committed rocprofv3
 # counter summary, and only when that summary was taken on the kernel
@@ -219,11 +222,18 @@ def batch_extra(P, steps, stream, tune_cache=None):
             "speedup": round(secs_1 / secs_b, 2)}
 
 
-def gradient_extra(P, steps, stream):
+def gradient_extra(P, steps, stream, store_gib=GRAD_STORE_GIB):
+    """A forward and a gradient of `steps` steps on the adjoint workload,
+    both timed with HIP events on the stream (the gradient enqueued with
+    cryo_gradient_async, its workspace made beforehand): first with
+    checkpoints only, then with a gradient store that fits in `store_gib`
+    GiB (at most 85 % of the free device memory) and its bitwise check."""
     import cellgen
     import numpy as np
+    import torch
     c = cellgen.adjoint_cell(0)
     tgt = cellgen.tracking_target(c, steps)
+    td = torch.tensor(tgt, dtype=torch.float64, device="cuda")
     plan = P.Plan(c, "f64")
     sh = P._gradient_shape(c)
     plan.set_shape(*sh)
@@ -232,19 +242,53 @@ def gradient_extra(P, steps, stream):
     plan.forward(T, 0, 10, ws=ws)
     T = plan.init()
     t_fwd = timed(stream, lambda: plan.forward(T, 0, steps, ws=ws))
-    t0 = time.perf_counter()
-    J, g, _ = plan.gradient(tgt, nsteps=steps)
-    t_grad = time.perf_counter() - t0
+    T0 = plan.init()
+    torch.cuda.synchronize()
+    gws = torch.empty(plan.gradient_workspace_bytes(steps), dtype=torch.uint8, device="cuda")
+    res = {}
+    t_grad = timed(stream, lambda: res.update(
+        out=plan.gradient_async(td, T0, nsteps=steps, ws=gws)))
+    plan.poll(gws)
+    J = float(res["out"][0].item())
+    g = res["out"][1].cpu().numpy()
     cells = c["nr"] * c["nz"]
-    return {"workload": "adjoint: 512x2048, 6 layers, FP64, checkpoint stride ceil(sqrt(N))",
-            "steps": steps, "forward_s": round(t_fwd, 3), "gradient_s": round(t_grad, 3),
-            "gradient_over_forward": round(t_grad / t_fwd, 2), "J": J,
-            "grad_finite": bool(np.all(np.isfinite(g))),
-            "gradient_gcell_steps_s": round(cells * steps / t_grad / 1e9, 2),
-            # algorithmic bytes of a gradient step: forward and recompute 16 B
-            # each, the adjoint 32 B (read T^n, T^{n+1}, lam^{n+1}; write lam^n)
-            "gradient_hbm_frac": round(cells * steps / t_grad * GRAD_BYTES_PER_CELL_STEP / 1e9
+    out = {"workload": "adjoint: 512x2048, 6 layers, FP64, checkpoint stride ceil(sqrt(N))",
+           "steps": steps, "forward_s": round(t_fwd, 3), "gradient_s": round(t_grad, 3),
+           "gradient_over_forward": round(t_grad / t_fwd, 2), "J": J,
+           "grad_finite": bool(np.all(np.isfinite(g))),
+           "workspace_gib": round(gws.numel() / 2**30, 2),
+           "gradient_gcell_steps_s": round(cells * steps / t_grad / 1e9, 2),
+           # algorithmic bytes of a gradient step: forward and recompute 16 B
+           # each, the adjoint 32 B (read T^n, T^{n+1}, lam^{n+1}; write lam^n)
+           "gradient_hbm_frac": round(cells * steps / t_grad * GRAD_BYTES_PER_CELL_STEP / 1e9
+                                      / HBM_PEAK_GBS, 4)}
+    del res, gws
+    torch.cuda.empty_cache()
+    if store_gib > 0:
+        free, _ = torch.cuda.mem_get_info()
+        budget = int(min(store_gib * 2**30, 0.85 * free))
+        d = plan.gradient_store_for(steps, budget)
+        plan.set_gradient_store(d)
+        gws = torch.empty(plan.gradient_workspace_bytes(steps), dtype=torch.uint8, device="cuda")
+        res = {}
+        t_st = timed(stream, lambda: res.update(
+            out=plan.gradient_async(td, T0, nsteps=steps, ws=gws)))
+        plan.poll(gws)
+        Js = float(res["out"][0].item())
+        gs = res["out"][1].cpu().numpy()
+        recomputed = (steps - d) / steps
+        out["store"] = {
+            "stored_steps": d, "workspace_gib": round(gws.numel() / 2**30, 2),
+            "gradient_s": round(t_st, 3), "gradient_over_forward": round(t_st / t_fwd, 2),
+            "equal_bitwise": bool(Js == J and np.array_equal(gs, g)),
+            # forward 16 B, the recompute's 16 B only for the steps not stored,
+            # the adjoint 32 B
+            "gradient_hbm_frac": round(cells * steps / t_st * (48 + 16 * recomputed) / 1e9
                                        / HBM_PEAK_GBS, 4)}
+        plan.set_gradient_store(0)
+        del res, gws
+        torch.cuda.empty_cache()
+    return out
 
 
 def design_extra(P, steps, iters, stream):
@@ -368,6 +412,8 @@ def main():
     ap.add_argument("--gradient-only", type=int, default=0, metavar="N",
                     help="profiling aid: time only a forward and a gradient of N steps on the "
                          "adjoint cell and print that result")
+    ap.add_argument("--grad-store-gib", type=float, default=GRAD_STORE_GIB, metavar="GIB",
+                    help="device memory the stored-tail gradient may take (0: skip it)")
     ap.add_argument("--batch-only", type=int, default=0, metavar="N",
                     help="profiling aid: time only the batched sweep (and the same cells one "
                          "at a time) over N steps and print that result")
@@ -392,8 +438,9 @@ def main():
 
     stream = torch.cuda.current_stream()
     if args.gradient_only:
-        gradient_extra(P, 50, stream)                       # warm
-        print(json.dumps({"gradient": gradient_extra(P, args.gradient_only, stream)}), flush=True)
+        gradient_extra(P, 50, stream, args.grad_store_gib)  # warm
+        print(json.dumps({"gradient": gradient_extra(P, args.gradient_only, stream,
+                                                     args.grad_store_gib)}), flush=True)
         return
     if args.batch_only:
         print(json.dumps({"batch": batch_extra(P, args.batch_only, stream, args.tune_cache)}),
@@ -466,7 +513,7 @@ def main():
         log("bench: batched sweep")
         extra["batch"] = batch_extra(P, 2000, stream, args.tune_cache)
         log("bench: gradient")
-        extra["gradient"] = gradient_extra(P, 50_000, stream)
+        extra["gradient"] = gradient_extra(P, 50_000, stream, args.grad_store_gib)
         log("bench: paper shape")
         extra["paper_shape"] = paper_shape_extra(P, 10_000, stream)
         log("bench: turn-on model")

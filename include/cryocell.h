@@ -350,8 +350,11 @@ cryo_status cryo_batch_autotune(int32_t n, const cryo_problem *probs, cryo_dtype
  * (cryo_plan_set_turn_on) the sweep runs over kernel steps, the 100
  * sub-steps of each pulse-start step included, whose source factors carry
  * p^2 and a width derivative of their own; the surface is still observed
- * once per step.  States are checkpointed every ckpt kernel steps (0: the
- * square root of their count, rounded up) and each segment is recomputed.
+ * once per step.  The states of the last kernel steps are kept from the
+ * forward as far as the plan's gradient store reaches
+ * (cryo_plan_set_gradient_store; none by default); the steps before them
+ * are checkpointed every ckpt kernel steps (0: the square root of their
+ * count, rounded up) and each segment is recomputed.
  * FP64 plans with one of the gradient's shapes only (CRYO_ERR_UNSUPPORTED
  * otherwise, see cryo_plan_set_shape); polynomial laws and the Joule source
  * (cryo_plan_set_poly_laws: the derivative polynomials, the interface row's
@@ -361,6 +364,25 @@ cryo_status cryo_batch_autotune(int32_t n, const cryo_problem *probs, cryo_dtype
  * cryo_gradient_async (results equal bit for bit). */
 cryo_status cryo_gradient_workspace_bytes(const cryo_plan *plan, int64_t nsteps, int64_t ckpt,
                                           size_t *bytes);
+/* The gradient store of a plan: the last `steps` kernel steps of a gradient's
+ * run (all of them if the run has fewer) keep their states from its forward
+ * (one field of 8 nz np bytes, rounded up to 256, per step, plus one for the
+ * final state), so their adjoint steps need no recompute; only the steps
+ * before them are checkpointed and recomputed.  This trades device memory
+ * for time: each stored step saves one recomputed step.  The workspace
+ * (cryo_gradient_workspace_bytes) grows accordingly; results are the same
+ * bit for bit for every store.  0 (the default) stores none.  The setting is
+ * read by the later workspace queries and gradient calls on the plan.
+ * CRYO_ERR_ARG for steps < 0.  (The paper's scheme has no adjoint; this is
+ * the memory/recompute split of the discrete adjoint of Sec. 3's steps.) */
+cryo_status cryo_plan_set_gradient_store(cryo_plan *plan, int64_t steps);
+/* The largest gradient store (at most the run's kernel steps) for which the
+ * workspace of a run of nsteps steps with checkpoint interval ckpt fits in
+ * budget_bytes, into *steps; 0 when no store fits (the workspace without one
+ * may still not).  Host-only; the plan's own setting is neither read nor
+ * changed.  CRYO_ERR_ARG for a null pointer, nsteps < 1 or ckpt < 0. */
+cryo_status cryo_gradient_store_steps(const cryo_plan *plan, int64_t nsteps, int64_t ckpt,
+                                      size_t budget_bytes, int64_t *steps);
 cryo_status cryo_gradient(const cryo_plan *plan, const void *T0, int64_t nsteps,
                           const double *target, int64_t ckpt, void *ws, size_t ws_bytes,
                           double *J, double *grad, double *surf, void *stream);

@@ -231,12 +231,31 @@ class Plan:
         check(lib().cryo_gradient_workspace_bytes(self._h, int(nsteps), int(ckpt), C.byref(b)))
         return b.value
 
-    def gradient(self, target, T0=None, nsteps=None, ckpt=0, stream=None):
+    def set_gradient_store(self, steps):
+        """Keep the states of the run's last `steps` kernel steps from the
+        gradient's forward (cryo_plan_set_gradient_store): no recompute for
+        them, one field of device memory each.  0: checkpoints only."""
+        check(lib().cryo_plan_set_gradient_store(self._h, int(steps)))
+
+    def gradient_store_for(self, nsteps, budget_bytes, ckpt=0):
+        """The largest gradient store whose workspace for nsteps steps fits
+        in budget_bytes (cryo_gradient_store_steps; 0 when none fits).  The
+        plan's own setting is left as it is."""
+        self._gradient_ready()
+        d = C.c_int64()
+        check(lib().cryo_gradient_store_steps(self._h, int(nsteps), int(ckpt),
+                                              int(budget_bytes), C.byref(d)))
+        return d.value
+
+    def gradient(self, target, T0=None, nsteps=None, ckpt=0, stream=None, store=None):
         """J = sum_n (S_n - target_n)^2 and dJ/d[amplitude, width, thickness_m,
         k_scale_m] by the discrete adjoint (FP64 plans).  Returns (J, grad,
-        surface trace) as float, numpy, numpy.  Synchronous."""
+        surface trace) as float, numpy, numpy.  Synchronous.  `store` (when
+        given) sets the plan's gradient store first."""
         torch = _torch()
         self._gradient_ready()
+        if store is not None:
+            self.set_gradient_store(store)
         n = int(self.cell["nsteps"] if nsteps is None else nsteps)
         tgt = np.ascontiguousarray(np.asarray(target, dtype=np.float64)[:n])
         if tgt.size < n:
@@ -253,16 +272,18 @@ class Plan:
                                   S.ctypes.data_as(dp), _stream(stream)))
         return J.value, g, S
 
-    def gradient_async(self, target, T0, nsteps=None, ckpt=0, ws=None, stream=None):
+    def gradient_async(self, target, T0, nsteps=None, ckpt=0, ws=None, stream=None, store=None):
         """The gradient enqueued on the stream with no host wait
         (cryo_gradient_async).  `target` (float64 CUDA tensor, nsteps values)
         and the field T0 (this plan's Field layout) are read on the device.
         Returns (J [1], grad [2 + 2L], surface trace [nsteps], ws), float64
         CUDA tensors and the workspace (made here when None), which must stay
         alive until the stream has finished; poll(ws) then reports a
-        non-finite temperature."""
+        non-finite temperature.  `store` as for gradient."""
         torch = _torch()
         self._gradient_ready()
+        if store is not None:
+            self.set_gradient_store(store)
         n = int(self.cell["nsteps"] if nsteps is None else nsteps)
         if (target.dtype != torch.float64 or not target.is_cuda or target.numel() < n
                 or not target.is_contiguous()):
@@ -512,22 +533,25 @@ def gradient_plan(cell):
     return plan
 
 
-def gradient(cell, target, T0=None, nsteps=None, ckpt=0):
-    """(J, dJ/dtheta, surface trace) of `cell` on the GPU (FP64)."""
-    return gradient_plan(cell).gradient(target, T0=T0, nsteps=nsteps, ckpt=ckpt)
+def gradient(cell, target, T0=None, nsteps=None, ckpt=0, store=0):
+    """(J, dJ/dtheta, surface trace) of `cell` on the GPU (FP64); `store`
+    kernel steps at the end keep their states (Plan.set_gradient_store)."""
+    return gradient_plan(cell).gradient(target, T0=T0, nsteps=nsteps, ckpt=ckpt, store=store)
 
 
-def gradient_many(cells, targets, nsteps=None, ckpt=0, streams=0, T0s=None):
+def gradient_many(cells, targets, nsteps=None, ckpt=0, streams=0, T0s=None, store=0):
     """Gradients of many designs in one call (FP64, the library's concurrent
     design loop over `streams` HIP streams; 0 lets the library choose).
     Returns (J [n], [grad_i],
-    [surface trace_i]); equal bit for bit to gradient() per design."""
+    [surface trace_i]); equal bit for bit to gradient() per design.  `store`:
+    the gradient store of every design's plan (a number, or one per design)."""
     torch = _torch()
     n = len(cells)
     N = int(cells[0]["nsteps"] if nsteps is None else nsteps)
     plans, fields, wss, tg = [], [], [], []
     for i, c in enumerate(cells):
         plan = gradient_plan(c)
+        plan.set_gradient_store(store[i] if isinstance(store, (list, tuple)) else store)
         plans.append(plan)
         fields.append(plan.init() if T0s is None or T0s[i] is None else plan.field_from(T0s[i]))
         b = C.c_size_t()

@@ -22,7 +22,7 @@ SYMBOLS = [
     "cryo_plan_create", "cryo_plan_destroy", "cryo_grid_radii", "cryo_source_fraction",
     "cryo_workspace_bytes", "cryo_init", "cryo_forward", "cryo_poll",
     "cryo_plan_shape", "cryo_plan_set_shape", "cryo_plan_set_turn_on", "cryo_plan_set_poly_laws",
-    "cryo_plan_set_stepped",
+    "cryo_plan_set_stepped", "cryo_plan_set_gradient_store", "cryo_gradient_store_steps",
     "cryo_batch_create", "cryo_batch_create_with", "cryo_batch_destroy", "cryo_batch_offsets", "cryo_batch_shape",
     "cryo_batch_workspace_bytes", "cryo_batch_init", "cryo_batch_forward", "cryo_batch_poll",
     "cryo_gradient_workspace_bytes", "cryo_gradient", "cryo_gradient_async", "cryo_gradient_many",
@@ -115,6 +115,8 @@ def lib():
         L.cryo_plan_set_turn_on.argtypes = [vp, C.c_int32]
         L.cryo_plan_set_poly_laws.argtypes = [vp, dp, dp, C.c_double]
         L.cryo_plan_set_stepped.argtypes = [vp, C.c_int32, C.c_int32]
+        L.cryo_plan_set_gradient_store.argtypes = [vp, i64]
+        L.cryo_gradient_store_steps.argtypes = [vp, i64, i64, C.c_size_t, C.POINTER(C.c_int64)]
         L.cryo_batch_create.argtypes = [C.c_int32, pp, C.c_int, i32p, C.POINTER(vp)]
         L.cryo_batch_create_with.argtypes = [C.c_int32, pp, C.c_int, i32p,
                                              C.POINTER(InstanceOptions), C.POINTER(vp)]

@@ -1,6 +1,8 @@
 // Gradient driver: J = sum_{n=1..N} (S_n - target_n)^2 of the surface mean S
 // and dJ/d[amplitude, width, thickness_m, k_scale_m] by the discrete
-// adjoint, with checkpoints every K steps and recompute of each segment.
+// adjoint: the states of the last steps kept from the forward as far as the
+// plan's store reaches, checkpoints every K steps before them and recompute
+// of each segment.
 #include <math.h>
 #include <string.h>
 
@@ -93,27 +95,35 @@ static int64_t launch_count(const cryo_plan *p, int64_t N) {
 }
 
 struct GradLayout {
-    size_t flag, fwd_buf[2], part, ck, seg, lam[2], Y[2], lpart[2], acc, accg, surf, tgt, seed,
-        rs, out, total;
+    size_t flag, fwd_buf[2], part, ck, seg, store, lam[2], Y[2], lpart[2], acc, accg, surf, tgt,
+        seed, rs, out, total;
     int64_t nck, K;
+    int64_t H, D;    // head kernel steps (checkpointed, recomputed), stored tail steps
 };
 
-// checkpoints every K kernel steps (sub-steps of the turn-on model count)
-static GradLayout grad_layout(const cryo_plan *p, int64_t N, int64_t ckpt) {
+// The last D kernel steps (the plan's gradient store, at most all of them)
+// keep their states from the forward: T^H .. T^M in D + 1 fields.  The H
+// steps before them are checkpointed every K steps and each segment is
+// recomputed into a buffer of K fields.
+static GradLayout grad_layout_store(const cryo_plan *p, int64_t N, int64_t ckpt, int64_t store,
+                                    int64_t M) {
     GradLayout g;
     const size_t F = al256(8 * (size_t)p->nz * p->np);
-    const int64_t M = launch_count(p, N);
-    int64_t K = ckpt > 0 ? ckpt : (int64_t)ceil(sqrt((double)std::max<int64_t>(M, 1)));
-    K = std::max<int64_t>(1, std::min<int64_t>(K, std::max<int64_t>(M, 1)));
+    g.D = std::min<int64_t>(std::max<int64_t>(store, 0), M);
+    g.H = M - g.D;
+    int64_t K = ckpt > 0 ? ckpt : (int64_t)ceil(sqrt((double)std::max<int64_t>(g.H, 1)));
+    K = std::max<int64_t>(1, std::min<int64_t>(K, std::max<int64_t>(g.H, 1)));
     g.K = K;
-    g.nck = (M + K - 1) / K;
+    g.nck = (g.H + K - 1) / K;
     size_t o = 0;
     g.flag = o; o += 256;
     g.fwd_buf[0] = o; o += F;
     g.fwd_buf[1] = o; o += F;
     g.part = o; o += al256(sizeof(double) * (size_t)SURF_CHUNK * step_grid(p));
-    g.ck = o; o += F * (size_t)std::max<int64_t>(g.nck, 1);
-    g.seg = o; o += F * (size_t)(K + 1);
+    g.ck = o; o += F * (size_t)g.nck;
+    // segment states a+1 .. b (state a is read from its checkpoint)
+    g.seg = o; o += g.H > 0 ? F * (size_t)K : 0;
+    g.store = o; o += g.D > 0 ? F * (size_t)(g.D + 1) : 0;
     g.lam[0] = o; o += F;
     g.lam[1] = o; o += F;
     // y and the radial part of lam, by step parity (the fused passes read
@@ -133,6 +143,27 @@ static GradLayout grad_layout(const cryo_plan *p, int64_t N, int64_t ckpt) {
     g.out = o; o += al256(sizeof(double) * (3 + 2 * (size_t)p->L));
     g.total = o;
     return g;
+}
+
+static GradLayout grad_layout(const cryo_plan *p, int64_t N, int64_t ckpt) {
+    return grad_layout_store(p, N, ckpt, p->grad_store, launch_count(p, N));
+}
+
+// The largest store (at most all M kernel steps) whose workspace fits in
+// `budget`.  Every store d costs at least the fields of d + 9 states (the
+// stored ones and the final one, two forward buffers, six adjoint fields)
+// beyond the parts that do not depend on it, and at most 2 sqrt(M - d) + 2
+// more (checkpoints and segment), so the scan down from that bound is short.
+static int64_t store_for_budget(const cryo_plan *p, int64_t N, int64_t ckpt, size_t budget) {
+    const int64_t M = launch_count(p, N);
+    const size_t F = al256(8 * (size_t)p->nz * p->np);
+    const GradLayout all = grad_layout_store(p, N, ckpt, M, M);
+    const size_t fixed = all.total - F * (size_t)(M + 9);
+    if (budget < fixed + 9 * F) return 0;
+    int64_t d = std::min<int64_t>(M, (int64_t)((budget - fixed) / F) - 9);
+    for (; d > 0; --d)
+        if (grad_layout_store(p, N, ckpt, d, M).total <= budget) return d;
+    return 0;
 }
 
 // The weights of the parameter gradient, from the geometry: h_i = thick_m /
@@ -321,7 +352,7 @@ static GradRun grad_run(const cryo_plan *p, const void *T0, int64_t N, int64_t c
     return r;
 }
 
-// forward with checkpoints and the surface trace
+// forward with checkpoints (head) or kept states (tail) and the surface trace
 static cryo_status grad_forward(GradRun &r) {
     cryo_plan *p = r.p;
     cryo_status st = ensure_device(p);
@@ -336,15 +367,21 @@ static cryo_status grad_forward(GradRun &r) {
     double *surf = (double *)(w + g.surf);
     double *part = (double *)(w + g.part);
     const int G = step_grid(p);
-    st = launch_to_internal(p, r.T0, w + g.fwd_buf[0], flag, s);
+    // state k: in the stored tail, or one of two buffers (the checkpoints
+    // are copies)
+    auto state = [&](int64_t k) -> void * {
+        return g.D > 0 && k >= g.H ? w + g.store + F * (size_t)(k - g.H) : w + g.fwd_buf[k & 1];
+    };
+    st = launch_to_internal(p, r.T0, state(0), flag, s);
     if (st != CRYO_OK) return st;
     int64_t done = 0;
     const int64_t M = (int64_t)r.L.size();
     for (int64_t l = 0; l < M; ++l) {
         const Launch &ln = r.L[l];
-        void *cur = w + g.fwd_buf[l & 1], *nxt = w + g.fwd_buf[(l + 1) & 1];
-        if (l % g.K == 0 && hipMemcpyAsync(w + g.ck + F * (l / g.K), cur, F,
-                                           hipMemcpyDeviceToDevice, s) != hipSuccess)
+        void *cur = state(l), *nxt = state(l + 1);
+        if (l < g.H && l % g.K == 0 &&
+            hipMemcpyAsync(w + g.ck + F * (l / g.K), cur, F, hipMemcpyDeviceToDevice, s) !=
+                hipSuccess)
             return fail(CRYO_ERR_DEVICE, "checkpoint copy");
         const double X = p->pulse.amplitude * ln.s;
         double *pp = ln.obs > 0 ? part + (size_t)((ln.obs - 1) % SURF_CHUNK) * G : nullptr;
@@ -356,8 +393,8 @@ static cryo_status grad_forward(GradRun &r) {
             done = ln.obs;
         }
     }
-    // the final state sits in fwd_buf[M & 1]: the surface trace is all the
-    // backward sweep needs from it
+    // the backward sweep needs the final state only when the tail is stored
+    // (the last segment's recompute makes it otherwise)
     return CRYO_OK;
 }
 
@@ -369,7 +406,8 @@ static cryo_status grad_objective(GradRun &r) {
     return launched("objective");
 }
 
-// segments backwards: restore the checkpoint, recompute, adjoint steps
+// the adjoint steps backwards: the stored tail first, then each head
+// segment (recompute from its checkpoint, adjoint steps)
 static cryo_status grad_backward(GradRun &r) {
     cryo_plan *p = r.p;
     const GradLayout &g = r.g;
@@ -391,22 +429,14 @@ static cryo_status grad_backward(GradRun &r) {
     const int64_t M = (int64_t)r.L.size();
     // the plan whose tables step launch k (the turn-on sub-steps: dt / 100)
     auto plan_of = [&](int64_t k) { return r.L[k].sub ? p->sub : p; };
-    for (int64_t sg = g.nck - 1; sg >= 0; --sg) {
-        const int64_t a = sg * g.K, b = std::min<int64_t>(M, a + g.K);
-        if (hipMemcpyAsync(segp(0), ckp(sg), F, hipMemcpyDeviceToDevice, s) != hipSuccess)
-            return fail(CRYO_ERR_DEVICE, "checkpoint restore");
-        for (int64_t k = a; k < b; ++k) {
-            const double X = p->pulse.amplitude * r.L[k].s;
-            st = launch_step(plan_of(k), segp(k - a), segp(k - a + 1), X, nullptr, flag, s);
-            if (st != CRYO_OK) return st;
-        }
-        // adjoint step k: pass 1 reads lam^{k+1} (lam[cur]) and writes y^k,
-        // pass 2 writes lam^k (lam[cur ^ 1]); pass 2 of step k and pass 1 of
-        // step k-1 run as one launch inside the segment
+    // adjoint steps b-1 down to a, with state k at T(k): pass 1 reads
+    // lam^{k+1} (lam[cur]) and writes y^k, pass 2 writes lam^k (lam[cur ^ 1]);
+    // pass 2 of step k and pass 1 of step k-1 run as one launch
+    auto sweep = [&](int64_t a, int64_t b, auto T) -> cryo_status {
         auto args = [&](int64_t k, int c) {
             AdjArgs d;
-            d.T = segp(k - a);
-            d.X = segp(k - a + 1);
+            d.T = T(k);
+            d.X = T(k + 1);
             d.lam_in = lam[c];
             d.Y = (double *)(w + g.Y[k & 1]);
             d.lpart = (double *)(w + g.lpart[k & 1]);
@@ -423,15 +453,33 @@ static cryo_status grad_backward(GradRun &r) {
         // pass 1 (the line solves, with the capacity term) runs on the tables
         // of its own launch; pass 2 (axial faces) needs no capacity law, so
         // the fused launch takes those of its pass 1
-        st = launch_adj(plan_of(b - 1), 1, args(b - 1, cur), flag, s);
-        for (int64_t k = b - 1; k > a && st == CRYO_OK; --k) {
+        cryo_status e = launch_adj(plan_of(b - 1), 1, args(b - 1, cur), flag, s);
+        for (int64_t k = b - 1; k > a && e == CRYO_OK; --k) {
             const AdjArgs d2 = args(k, cur), d1 = args(k - 1, cur ^ 1);
-            st = launch_adj(plan_of(k - 1), 21, d2, flag, s, &d1);
+            e = launch_adj(plan_of(k - 1), 21, d2, flag, s, &d1);
             cur ^= 1;
         }
-        if (st == CRYO_OK) st = launch_adj(plan_of(a), 2, args(a, cur), flag, s);
-        if (st != CRYO_OK) return st;
+        if (e == CRYO_OK) e = launch_adj(plan_of(a), 2, args(a, cur), flag, s);
         cur ^= 1;
+        return e;
+    };
+    // the stored tail: its states are where the forward left them
+    if (g.D > 0) {
+        st = sweep(g.H, M, [&](int64_t k) { return (double *)(w + g.store) + (F / 8) * (k - g.H); });
+        if (st != CRYO_OK) return st;
+    }
+    // then the head's segments backwards: recompute states a+1 .. b from the
+    // checkpoint of state a, then the adjoint steps
+    for (int64_t sg = g.nck - 1; sg >= 0; --sg) {
+        const int64_t a = sg * g.K, b = std::min<int64_t>(g.H, a + g.K);
+        auto T = [&](int64_t k) { return k == a ? ckp(sg) : segp(k - a - 1); };
+        for (int64_t k = a; k < b; ++k) {
+            const double X = p->pulse.amplitude * r.L[k].s;
+            st = launch_step(plan_of(k), T(k), T(k + 1), X, nullptr, flag, s);
+            if (st != CRYO_OK) return st;
+        }
+        st = sweep(a, b, T);
+        if (st != CRYO_OK) return st;
     }
     return CRYO_OK;
 }
@@ -531,6 +579,19 @@ static int auto_streams(int n, cryo_plan *const *plans) {
 using namespace cryo;
 
 extern "C" {
+
+cryo_status cryo_plan_set_gradient_store(cryo_plan *p, int64_t steps) {
+    if (!p || steps < 0) return fail(CRYO_ERR_ARG, "bad argument");
+    p->grad_store = steps;
+    return CRYO_OK;
+}
+
+cryo_status cryo_gradient_store_steps(const cryo_plan *p, int64_t nsteps, int64_t ckpt,
+                                     size_t budget_bytes, int64_t *steps) {
+    if (!p || !steps || nsteps < 1 || ckpt < 0) return fail(CRYO_ERR_ARG, "bad argument");
+    *steps = store_for_budget(p, nsteps, ckpt, budget_bytes);
+    return CRYO_OK;
+}
 
 cryo_status cryo_gradient_workspace_bytes(const cryo_plan *p, int64_t nsteps, int64_t ckpt,
                                           size_t *bytes) {

@@ -184,6 +184,9 @@ struct cryo_plan {
     uint32_t *d_info2 = nullptr;      // [np]: tfinfo
     // FP64 plans: the parameter weights of the gradient (grad_param_table)
     double *d_grad = nullptr;
+    // kernel steps at the end of a gradient's run whose states its forward
+    // keeps (no recompute for their adjoint steps); 0: none
+    int64_t grad_store = 0;
 };
 
 namespace cryo {

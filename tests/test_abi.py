@@ -242,3 +242,34 @@ def test_batch_plan_options():
                 P.Batch([base, c], "f64")
         with pytest.raises(ValueError):
             P.tune_batch([c], "f64")
+
+def test_gradient_store_host_checks():
+    # the stored tail replaces checkpoints and the segment buffer: the
+    # workspace changes by whole fields, and a store beyond the run's kernel
+    # steps is the same as storing all of them
+    plan = P.Plan(cellgen.with_nz(cellgen.adjoint_cell(0), 64))
+    plan._gradient_ready()
+    rpl, wpl, _ = plan.shape()
+    F = (8 * 64 * 64 * wpl * rpl + 255) // 256 * 256
+    N = 100
+
+    def ws(store):
+        plan.set_gradient_store(store)
+        return plan.gradient_workspace_bytes(N)
+
+    base = ws(0)          # 2 forward buffers, 10 checkpoints, 10 segment states, 6 adjoint fields
+    assert ws(40) - base == ((2 + 8 + 8 + 41 + 6) - (2 + 10 + 10 + 6)) * F    # head 60: K = nck = 8
+    assert ws(N) - base == ((2 + N + 1 + 6) - (2 + 10 + 10 + 6)) * F          # no head at all
+    assert ws(10 ** 9) == ws(N)
+    # the budget query is the largest fitting store, by brute force (the
+    # workspace is not monotone in the store: the head's checkpoints and
+    # segment shrink in steps)
+    sizes = [ws(d) for d in range(N + 1)]
+    for budget in [base - 1, base, base + 37 * F, base + 37 * F + 1, sizes[N] - 1, sizes[N],
+                   sizes[N] + 10 * F]:
+        want = max([d for d in range(N + 1) if sizes[d] <= budget], default=0)
+        assert plan.gradient_store_for(N, budget) == want, budget
+    plan.set_gradient_store(0)
+    with pytest.raises(P.CryoError) as e:
+        plan.set_gradient_store(-1)
+    assert e.value.status == 1
