@@ -292,3 +292,25 @@ def test_gpu_gradient_poly_matches_oracle_adjoint(seed, nr, joule, shape, extra)
     e = _norm_err(gg, go, P.params_of(c))
     say("  normalised gradient error %.3e" % e)
     assert e < 1e-8, (gg, go)
+
+
+def test_adjoint_workload_with_the_bench_store(adjoint_workload):
+    """The full workload as the bench times its stored-tail variant (the
+    states of the last steps kept in up to 200 GiB, at most 85 % of the free
+    device memory): J and the gradient equal the checkpoints-only sweep's
+    bit for bit, so the oracle comparison above covers it."""
+    import torch
+
+    import paper_1408_5853_amd as P
+    c, tgt, Jg, gg, _, _ = adjoint_workload
+    n = c["nsteps"]
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    plan = P.gradient_plan(c)
+    d = plan.gradient_store_for(n, int(min(200 * 2**30, 0.85 * free)))
+    say("case adjoint workload with a store of %d steps" % d)
+    assert d > 0
+    Js, gs, _ = plan.gradient(tgt, store=d)
+    assert Js == Jg and np.array_equal(gs, gg)
+    plan.set_gradient_store(0)
+    torch.cuda.empty_cache()
