@@ -273,3 +273,18 @@ def test_gradient_store_host_checks():
     with pytest.raises(P.CryoError) as e:
         plan.set_gradient_store(-1)
     assert e.value.status == 1
+
+
+def test_gradient_store_counts_turn_on_sub_steps():
+    # the store counts kernel steps: with the turn-on model (eq. (22)) the
+    # pulse start at step 0 adds 99 sub-steps, so storing everything of a
+    # 100-step run means 199 states
+    c = dict(cellgen.with_nz(cellgen.adjoint_cell(0), 64), turn_on=True)
+    plan = P.Plan(c)
+    assert plan.gradient_store_for(100, 1 << 50) == 199
+    plan.set_gradient_store(199)
+    all_stored = plan.gradient_workspace_bytes(100)
+    plan.set_gradient_store(10 ** 6)
+    assert plan.gradient_workspace_bytes(100) == all_stored
+    plain = P.Plan(cellgen.with_nz(cellgen.adjoint_cell(0), 64))
+    assert plain.gradient_store_for(100, 1 << 50) == 100

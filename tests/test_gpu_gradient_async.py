@@ -53,15 +53,18 @@ def test_async_gradient_equals_host_call_and_oracle(kind):
     assert e < 1e-8, (g, go)
 
 
-def test_async_gradient_replays_from_a_graph():
+@pytest.mark.parametrize("store", [0, 17, 40])
+def test_async_gradient_replays_from_a_graph(store):
     # the whole gradient captured once and replayed three times, with other
     # device work and host synchronisation between the replays; every replay
-    # against the eager call, bit for bit
+    # against the eager call, bit for bit; with checkpoints only, with part
+    # of the run's states stored and with all of them
     import torch
 
     import paper_1408_5853_amd as P
     c, tgt = _case("plain")
     plan = P.gradient_plan(c)
+    plan.set_gradient_store(store)
     T0 = plan.init()
     td = torch.tensor(tgt, dtype=torch.float64, device="cuda")
     ws = torch.empty(plan.gradient_workspace_bytes(40, 6), dtype=torch.uint8, device="cuda")
@@ -71,7 +74,7 @@ def test_async_gradient_replays_from_a_graph():
     other = P.gradient_plan(_case("stepped")[0])
     To = other.init()
     wo = other.workspace(50)
-    say("case gradient_async graph capture")
+    say("case gradient_async graph capture, store %d" % store)
     gr = torch.cuda.CUDAGraph()
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
