@@ -460,6 +460,17 @@ typedef struct {
 cryo_status cryo_batch_create_with(int32_t n, const cryo_problem *probs, cryo_dtype dtype,
                                    const int32_t *shapes, const cryo_instance_options *opts,
                                    cryo_batch **out);
+/* cryo_batch_autotune for instances with plan options (`opts`: n entries,
+ * nullable for none, as cryo_batch_create_with takes them): instances are
+ * grouped as cryo_batch_create_with groups them (shape, law family, domain),
+ * each trial batch is made with the instances' options, and the cache keys
+ * add the law family "poly" and the word "stepped" for such groups and the
+ * options to the batch hash (a batch without options keeps the keys of
+ * cryo_batch_autotune, which is this call with opts NULL).  Shapes the
+ * options' tables do not fit are skipped. */
+cryo_status cryo_batch_autotune_with(int32_t n, const cryo_problem *probs, cryo_dtype dtype,
+                                     const cryo_instance_options *opts, int32_t steps,
+                                     const char *cache_path, void *stream, int32_t *shapes);
 void cryo_batch_destroy(cryo_batch *batch);
 /* Element offsets of the instances' fields in the packed buffer (n + 1). */
 cryo_status cryo_batch_offsets(const cryo_batch *batch, int64_t *offsets);

@@ -355,6 +355,30 @@ class State:
         self.plan.poll(self.mem, stream)
 
 
+def _instance_options(cells):
+    """Per-instance plan options of a batch: the polynomial laws (eqs.
+    (23)-(25)) and the stepped domain (eq. (9)), as Plan takes them from a
+    cell.  Returns the ctypes array and the arrays it points into (to be
+    kept alive with it)."""
+    n = len(cells)
+    opts = (_abi.InstanceOptions * n)()
+    keep = []
+    dp = C.POINTER(C.c_double)
+    for i, c in enumerate(cells):
+        if c.get("poly"):
+            Ls = c["layers"]
+            a = np.ascontiguousarray([float(x) for l in Ls for x in l["poly_a"]])
+            b = np.ascontiguousarray([float(x) for l in Ls for x in l["poly_b"]])
+            keep += [a, b]
+            opts[i].poly_a = a.ctypes.data_as(dp)
+            opts[i].poly_b = b.ctypes.data_as(dp)
+            opts[i].joule_tref = float(c.get("joule_tref", 0.0))
+        if c.get("stepped"):
+            opts[i].z_full = int(c["stepped"]["z_full"])
+            opts[i].nr_top = int(c["stepped"]["nr_top"])
+    return opts, keep
+
+
 class Batch:
     """Many independent cells stepped together (design sweeps)."""
 
@@ -374,23 +398,7 @@ class Batch:
             flat = np.ascontiguousarray(np.asarray(shapes, dtype=np.int32).reshape(n, 3))
             self._shapes = flat
             sh = flat.ctypes.data_as(C.POINTER(C.c_int32))
-        # per-instance plan options: polynomial laws (eqs. (23)-(25)) and the
-        # stepped domain (eq. (9)), as Plan takes them from a cell
-        opts = (_abi.InstanceOptions * n)()
-        self._keep = []
-        dp = C.POINTER(C.c_double)
-        for i, c in enumerate(self.cells):
-            if c.get("poly"):
-                Ls = c["layers"]
-                a = np.ascontiguousarray([float(x) for l in Ls for x in l["poly_a"]])
-                b = np.ascontiguousarray([float(x) for l in Ls for x in l["poly_b"]])
-                self._keep += [a, b]
-                opts[i].poly_a = a.ctypes.data_as(dp)
-                opts[i].poly_b = b.ctypes.data_as(dp)
-                opts[i].joule_tref = float(c.get("joule_tref", 0.0))
-            if c.get("stepped"):
-                opts[i].z_full = int(c["stepped"]["z_full"])
-                opts[i].nr_top = int(c["stepped"]["nr_top"])
+        opts, self._keep = _instance_options(self.cells)
         h = C.c_void_p()
         check(lib().cryo_batch_create_with(n, arr, _abi.F64 if dtype == "f64" else _abi.F32, sh,
                                            opts, C.byref(h)))
@@ -466,19 +474,21 @@ def autotune(cell, dtype="f64", steps=20, cache=None, stream=None):
 
 def tune_batch(cells, dtype="f32", steps=64, cache=None, stream=None):
     """Per-instance launch shapes for Batch(cells, dtype, shapes=...), timed
-    on the GPU per shape group (cryo_batch_autotune); `cache` names an
-    optional text file of earlier results."""
+    on the GPU per shape group (cryo_batch_autotune_with: cells may carry the
+    polynomial laws or the stepped domain, as Batch takes them); `cache`
+    names an optional text file of earlier results."""
     for i, c in enumerate(cells):
-        for key in ("poly", "stepped", "turn_on"):
-            if c.get(key):
-                raise ValueError("cell %d: batches do not offer the %r option" % (i, key))
+        if c.get("turn_on"):
+            raise ValueError("cell %d: batches do not offer the turn-on model" % i)
     n = len(cells)
     ps = [_abi.ProblemStruct(c) for c in cells]
     arr = (_abi.Problem * n)(*[p.s for p in ps])
+    opts, keep = _instance_options(cells)
     out = (C.c_int32 * (3 * n))()
-    check(lib().cryo_batch_autotune(n, arr, _abi.F64 if dtype == "f64" else _abi.F32,
-                                    int(steps), cache.encode() if cache else None,
-                                    _stream(stream), out))
+    check(lib().cryo_batch_autotune_with(n, arr, _abi.F64 if dtype == "f64" else _abi.F32,
+                                         opts, int(steps), cache.encode() if cache else None,
+                                         _stream(stream), out))
+    del keep
     return [tuple(out[3 * i:3 * i + 3]) for i in range(n)]
 
 

@@ -26,7 +26,7 @@ SYMBOLS = [
     "cryo_batch_create", "cryo_batch_create_with", "cryo_batch_destroy", "cryo_batch_offsets", "cryo_batch_shape",
     "cryo_batch_workspace_bytes", "cryo_batch_init", "cryo_batch_forward", "cryo_batch_poll",
     "cryo_gradient_workspace_bytes", "cryo_gradient", "cryo_gradient_async", "cryo_gradient_many",
-    "cryo_autotune", "cryo_batch_autotune",
+    "cryo_autotune", "cryo_batch_autotune", "cryo_batch_autotune_with",
     "cryo_state_create", "cryo_state_destroy", "cryo_state_load", "cryo_state_forward",
     "cryo_state_store", "cryo_forward_noalloc",
 ]
@@ -131,6 +131,9 @@ def lib():
         L.cryo_autotune.argtypes = [pp, C.c_int, C.c_int32, C.c_char_p, vp, i32p, dp]
         L.cryo_batch_autotune.argtypes = [C.c_int32, pp, C.c_int, C.c_int32, C.c_char_p, vp,
                                           i32p]
+        L.cryo_batch_autotune_with.argtypes = [C.c_int32, pp, C.c_int,
+                                               C.POINTER(InstanceOptions), C.c_int32,
+                                               C.c_char_p, vp, i32p]
         L.cryo_gradient_workspace_bytes.argtypes = [vp, i64, i64, C.POINTER(C.c_size_t)]
         L.cryo_gradient.argtypes = [vp, vp, i64, dp, i64, vp, C.c_size_t, dp, dp, dp, vp]
         L.cryo_gradient_async.argtypes = [vp, vp, i64, vp, i64, vp, C.c_size_t, vp, vp, vp, vp]

@@ -7,8 +7,10 @@
 // An optional text cache records results across runs: keyed by dtype,
 // radial and axial node counts, layer count and law family (cube or general
 // capacity exponents) for one problem, and by dtype, default shape, law
-// family and largest radial size for a batch group, and by a hash of the
-// whole batch for the refinement.
+// family, domain and largest radial size for a batch group, and by a hash of
+// the whole batch for the refinement.  Batch instances may carry plan
+// options (polynomial laws, stepped domain); they are grouped and timed as
+// cryo_batch_create_with groups and steps them.
 #include <stdio.h>
 #include <string.h>
 
@@ -27,6 +29,12 @@ bool all_cube(const cryo_problem *p) {
     for (int m = 0; m < p->geom.n_layers; ++m)
         if (p->geom.layers[m].mat.q != 3.0) return false;
     return true;
+}
+
+// an instance's options: polynomial laws, stepped domain
+bool opt_poly(const cryo_instance_options *o, int i) { return o && o[i].poly_a; }
+bool opt_stepped(const cryo_instance_options *o, int i) {
+    return o && (o[i].z_full != 0 || o[i].nr_top != 0);
 }
 
 std::string cache_key(const cryo_problem *p, cryo_dtype dt) {
@@ -68,22 +76,22 @@ void cache_store(const char *path, const std::string &key, const int32_t *shape,
     fclose(f);
 }
 
-// An instance group of a batch (instances with one default shape and law
-// family), as cryo_batch_create forms them.
+// An instance group of a batch (instances with one default shape, law
+// family and domain), as cryo_batch_create_with forms them.
 struct Group {
     int rpl, wpl;
-    bool cube;
+    bool cube, poly, stepped;
     int nr_max = 0, nz_min = 1 << 30;
     std::vector<int> inst;
 };
 
 // Time per step of the whole batch with the given shapes (the best of three
 // timed runs of `run_steps` after the capture block).
-cryo_status time_batch(int32_t n, const cryo_problem *probs, cryo_dtype dtype,
-                       const std::vector<int32_t> &shp, int run_steps, hipStream_t s,
-                       hipEvent_t e0, hipEvent_t e1, double *us) {
+cryo_status time_batch(int32_t n, const cryo_problem *probs, const cryo_instance_options *opts,
+                       cryo_dtype dtype, const std::vector<int32_t> &shp, int run_steps,
+                       hipStream_t s, hipEvent_t e0, hipEvent_t e1, double *us) {
     cryo_batch *b = nullptr;
-    cryo_status st = cryo_batch_create(n, probs, dtype, shp.data(), &b);
+    cryo_status st = cryo_batch_create_with(n, probs, dtype, shp.data(), opts, &b);
     if (st != CRYO_OK) return st;
     std::vector<int64_t> off((size_t)n + 1);
     cryo_batch_offsets(b, off.data());
@@ -117,8 +125,9 @@ cryo_status time_batch(int32_t n, const cryo_problem *probs, cryo_dtype dtype,
 }
 
 // FNV-1a over what decides a batch's grouping and work: per instance its
-// grid, layer count and law family.
-uint64_t batch_hash(int32_t n, const cryo_problem *probs, cryo_dtype dtype) {
+// grid, layer count, law family and domain.
+uint64_t batch_hash(int32_t n, const cryo_problem *probs, const cryo_instance_options *opts,
+                    cryo_dtype dtype) {
     uint64_t h = 1469598103934665603ull;
     auto mix = [&](uint64_t v) {
         for (int k = 0; k < 8; ++k) {
@@ -133,6 +142,14 @@ uint64_t batch_hash(int32_t n, const cryo_problem *probs, cryo_dtype dtype) {
         mix((uint64_t)probs[i].geom.nz);
         mix((uint64_t)probs[i].geom.n_layers);
         mix(all_cube(&probs[i]) ? 1 : 0);
+        // options change the hash only where they are set, so a batch
+        // without any keeps its key
+        if (opt_poly(opts, i)) mix(0x706f6c79);
+        if (opt_stepped(opts, i)) {
+            mix(0x73746570);
+            mix((uint64_t)opts[i].z_full);
+            mix((uint64_t)opts[i].nr_top);
+        }
     }
     return h;
 }
@@ -145,12 +162,14 @@ uint64_t batch_hash(int32_t n, const cryo_problem *probs, cryo_dtype dtype) {
 // sweep over the groups follows when the first changed any (the groups'
 // best values depend on each other).  Cached per batch (a hash of the
 // instances' grids, layer counts and law families).
-cryo_status refine_lines_per_wave(int32_t n, const cryo_problem *probs, cryo_dtype dtype,
+cryo_status refine_lines_per_wave(int32_t n, const cryo_problem *probs,
+                                  const cryo_instance_options *opts, cryo_dtype dtype,
                                   int run_steps, const char *cache_path, hipStream_t s,
                                   hipEvent_t e0, hipEvent_t e1,
                                   const std::vector<Group> &groups, int32_t *shapes) {
     char hb[64];
-    snprintf(hb, sizeof hb, "batchset %016llx", (unsigned long long)batch_hash(n, probs, dtype));
+    snprintf(hb, sizeof hb, "batchset %016llx",
+             (unsigned long long)batch_hash(n, probs, opts, dtype));
     auto gkey = [&](size_t gi) { return std::string(hb) + " g" + std::to_string(gi); };
     auto apply = [&](const Group &g, int lpw, std::vector<int32_t> &shp) {
         for (int i : g.inst) shp[3 * i + 2] = std::max(1, std::min(lpw, probs[i].geom.nz - 2));
@@ -177,7 +196,7 @@ cryo_status refine_lines_per_wave(int32_t n, const cryo_problem *probs, cryo_dty
     std::stable_sort(order.begin(), order.end(),
                      [&](size_t a, size_t b) { return work[a] > work[b]; });
     double best = 0.0;
-    cryo_status st = time_batch(n, probs, dtype, shp, run_steps, s, e0, e1, &best);
+    cryo_status st = time_batch(n, probs, opts, dtype, shp, run_steps, s, e0, e1, &best);
     if (st != CRYO_OK) return st;
     for (int sweep = 0; sweep < 2; ++sweep) {
         bool changed = false;
@@ -191,7 +210,7 @@ cryo_status refine_lines_per_wave(int32_t n, const cryo_problem *probs, cryo_dty
                 apply(g, lpw, trial);
                 if (trial == shp) continue;
                 double t = 0.0;
-                st = time_batch(n, probs, dtype, trial, run_steps, s, e0, e1, &t);
+                st = time_batch(n, probs, opts, dtype, trial, run_steps, s, e0, e1, &t);
                 if (st != CRYO_OK) return st;
                 if (t < 0.99 * best) {
                     best = t;
@@ -297,9 +316,9 @@ cryo_status cryo_autotune(const cryo_problem *prob, cryo_dtype dtype, int32_t st
     return CRYO_OK;
 }
 
-cryo_status cryo_batch_autotune(int32_t n, const cryo_problem *probs, cryo_dtype dtype,
-                                int32_t steps, const char *cache_path, void *stream,
-                                int32_t *shapes) {
+cryo_status cryo_batch_autotune_with(int32_t n, const cryo_problem *probs, cryo_dtype dtype,
+                                     const cryo_instance_options *opts, int32_t steps,
+                                     const char *cache_path, void *stream, int32_t *shapes) {
     if (n < 1 || !probs || !shapes || steps < 1) return fail(CRYO_ERR_ARG, "bad argument");
     hipStream_t s = (hipStream_t)stream;
     // the groups cryo_batch_create forms with default shapes
@@ -312,16 +331,22 @@ cryo_status cryo_batch_autotune(int32_t n, const cryo_problem *probs, cryo_dtype
         int rpl = 0, wpl = 0, lpw = 0;
         cryo_plan_shape(p, &rpl, &wpl, &lpw);
         cryo_plan_destroy(p);
-        const bool cube = all_cube(&probs[i]);
+        // the grouping of cryo_batch_create_with: shape, law family, domain
+        const bool poly = opt_poly(opts, i), stepped = opt_stepped(opts, i);
+        const bool cube = !poly && all_cube(&probs[i]);
         Group *g = nullptr;
         for (Group &q : groups)
-            if (q.rpl == rpl && q.wpl == wpl && q.cube == cube) g = &q;
+            if (q.rpl == rpl && q.wpl == wpl && q.cube == cube && q.poly == poly &&
+                q.stepped == stepped)
+                g = &q;
         if (!g) {
             groups.push_back(Group());
             g = &groups.back();
             g->rpl = rpl;
             g->wpl = wpl;
             g->cube = cube;
+            g->poly = poly;
+            g->stepped = stepped;
         }
         g->inst.push_back(i);
         g->nr_max = std::max(g->nr_max, probs[i].geom.nr);
@@ -338,8 +363,11 @@ cryo_status cryo_batch_autotune(int32_t n, const cryo_problem *probs, cryo_dtype
     cryo_status result = CRYO_OK;
     for (const Group &g : groups) {
         char kb[160];
-        snprintf(kb, sizeof kb, "batch %s %d %d %s %d", dtype == CRYO_F64 ? "f64" : "f32", g.rpl,
-                 g.wpl, g.cube ? "cube" : "power", g.nr_max);
+        // (rectangular power-law groups keep the key they had before the
+        // options existed)
+        snprintf(kb, sizeof kb, "batch %s %d %d %s%s %d", dtype == CRYO_F64 ? "f64" : "f32", g.rpl,
+                 g.wpl, g.poly ? "poly" : g.cube ? "cube" : "power",
+                 g.stepped ? " stepped" : "", g.nr_max);
         int32_t best_shape[3] = {g.rpl, g.wpl, 4};
         if (!cache_lookup(cache_path, kb, best_shape)) {
             // up to 8 of the group's instances, spread over its sizes
@@ -352,9 +380,11 @@ cryo_status cryo_batch_autotune(int32_t n, const cryo_problem *probs, cryo_dtype
             const int k = std::min<int>(8, (int)order.size());
             for (int q = 0; q < k; ++q) sub.push_back(order[(size_t)q * order.size() / k]);
             std::vector<cryo_problem> sp;
+            std::vector<cryo_instance_options> so;
             double nodes = 0;
             for (int i : sub) {
                 sp.push_back(probs[i]);
+                if (opts) so.push_back(opts[i]);
                 nodes += (double)probs[i].geom.nr * probs[i].geom.nz;
             }
             double best = 1e300;
@@ -369,8 +399,8 @@ cryo_status cryo_batch_autotune(int32_t n, const cryo_problem *probs, cryo_dtype
                         shp.push_back(std::min(lpw, probs[i].geom.nz - 2));
                     }
                     cryo_batch *b = nullptr;
-                    if (cryo_batch_create((int32_t)sub.size(), sp.data(), dtype, shp.data(), &b) !=
-                        CRYO_OK)
+                    if (cryo_batch_create_with((int32_t)sub.size(), sp.data(), dtype, shp.data(),
+                                               opts ? so.data() : nullptr, &b) != CRYO_OK)
                         continue;
                     int64_t nel = 0;
                     std::vector<int64_t> off(sub.size() + 1);
@@ -424,11 +454,17 @@ cryo_status cryo_batch_autotune(int32_t n, const cryo_problem *probs, cryo_dtype
         }
     }
     if (result == CRYO_OK && groups.size() > 1)
-        result = refine_lines_per_wave(n, probs, dtype, run_steps, cache_path, s, e0, e1, groups,
-                                       shapes);
+        result = refine_lines_per_wave(n, probs, opts, dtype, run_steps, cache_path, s, e0, e1,
+                                       groups, shapes);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return result;
+}
+
+cryo_status cryo_batch_autotune(int32_t n, const cryo_problem *probs, cryo_dtype dtype,
+                                int32_t steps, const char *cache_path, void *stream,
+                                int32_t *shapes) {
+    return cryo_batch_autotune_with(n, probs, dtype, nullptr, steps, cache_path, stream, shapes);
 }
 
 }  // extern "C"

@@ -223,9 +223,9 @@ def test_stepped_domain_host_checks():
 
 def test_batch_plan_options():
     # polynomial laws and the stepped domain are per-instance batch options
-    # (cryo_batch_create_with, host-side checks only here); the turn-on model
-    # has no batch form, and the batch tuner times power-law rectangular
-    # cells only: both refuse rather than step another problem
+    # (cryo_batch_create_with, host-side checks only here; the batch tuner
+    # takes them too, on the GPU); the turn-on model has no batch form: the
+    # batch and its tuner refuse it rather than step another problem
     base = cellgen.small_cell(0)
     poly = cellgen.poly_variant(base, 0, joule_tref=30.0)
     stepped = dict(base, stepped={"z_full": 60, "nr_top": 30})
@@ -235,13 +235,12 @@ def test_batch_plan_options():
     with pytest.raises(P.CryoError) as e:                          # nr_top > nr
         P.Batch([base, dict(base, stepped={"z_full": 60, "nr_top": base["nr"] + 1})], "f64")
     assert "instance 1" in str(e.value)
-    for extra in ({"turn_on": True}, {"stepped": {"z_full": 60, "nr_top": 30}}, {"poly": True}):
-        c = dict(base, **extra)
-        if "turn_on" in extra:
-            with pytest.raises(ValueError):
-                P.Batch([base, c], "f64")
-        with pytest.raises(ValueError):
-            P.tune_batch([c], "f64")
+    c = dict(base, turn_on=True)
+    with pytest.raises(ValueError):
+        P.Batch([base, c], "f64")
+    with pytest.raises(ValueError):
+        P.tune_batch([base, c], "f64")
+
 
 def test_gradient_store_host_checks():
     # the stored tail replaces checkpoints and the segment buffer: the

@@ -12,11 +12,11 @@ from gpu_util import rel_err, run_gpu, say
 pytestmark = pytest.mark.gpu
 
 
-def _run_batch(cells, n, dtype, k0=0):
+def _run_batch(cells, n, dtype, k0=0, shapes=None):
     import torch
 
     import paper_1408_5853_amd as P
-    b = P.Batch(cells, dtype)
+    b = P.Batch(cells, dtype, shapes=shapes)
     T = b.init()
     ws = b.workspace()
     b.forward(T, k0, n, ws)
@@ -92,6 +92,39 @@ def test_batch_with_plan_options(dtype):
     for i, c in enumerate(cells):
         plan = P.Plan(c, dtype)
         plan.set_shape(*b.shape(i))
+        T = plan.init()
+        plan.forward(T, 0, n)
+        torch.cuda.synchronize()
+        assert np.array_equal(got[i], plan.field_values(T)), i
+        To = oracle.forward(c, nsteps=n)
+        if dtype == "f64":
+            assert rel_err(got[i], To) < 1e-10, i
+        else:
+            assert np.max(np.abs(got[i] - To)) < 1e-4, i
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_tuned_batch_with_plan_options(dtype, tmp_path):
+    # the batch tuner on instances with the polynomial laws and the stepped
+    # domain: it groups them as the batch does, its shapes build, each
+    # instance still equals a single plan of that shape bit for bit and the
+    # oracle within the tolerances, and a second call reads the cache
+    import torch
+
+    import paper_1408_5853_amd as P
+    cells = _option_cells()
+    cache = str(tmp_path / "tune.txt")
+    say("case tuned batch with plan options %s" % dtype)
+    shapes = P.tune_batch(cells, dtype, steps=32, cache=cache)
+    text = open(cache).read()
+    assert " poly" in text and " stepped" in text
+    assert P.tune_batch(cells, dtype, steps=32, cache=cache) == shapes
+    n = 70
+    got, b = _run_batch(cells, n, dtype, shapes=shapes)
+    for i, c in enumerate(cells):
+        assert tuple(b.shape(i)) == tuple(shapes[i]), i
+        plan = P.Plan(c, dtype)
+        plan.set_shape(*shapes[i])
         T = plan.init()
         plan.forward(T, 0, n)
         torch.cuda.synchronize()
