@@ -236,7 +236,8 @@ cryo_status cryo_plan_set_poly_laws(cryo_plan *plan, const double *a, const doub
  * otherwise).  The plan builds host tables for dt/100 here (device tables at
  * its next forward call), follows later cryo_plan_set_shape calls, and frees
  * them with on = 0 or cryo_plan_destroy.  Gradients include the sub-steps
- * in their sweep (see cryo_gradient); batches do not offer the model. */
+ * in their sweep (see cryo_gradient); batch instances take the model
+ * through cryo_instance_options (see cryo_batch_create_with). */
 cryo_status cryo_plan_set_turn_on(cryo_plan *plan, int32_t on);
 
 /* After the stream has finished a cryo_forward that used `ws`: returns
@@ -439,8 +440,9 @@ cryo_status cryo_gradient_many(int32_t n, cryo_plan *const *plans, const void *c
 cryo_status cryo_batch_create(int32_t n, const cryo_problem *probs, cryo_dtype dtype,
                               const int32_t *shapes, cryo_batch **out);
 
-/* Plan options of one batch instance: what cryo_plan_set_poly_laws and
- * cryo_plan_set_stepped set on a single plan (same arguments and checks). */
+/* Plan options of one batch instance: what cryo_plan_set_poly_laws,
+ * cryo_plan_set_stepped and cryo_plan_set_turn_on set on a single plan
+ * (same arguments and checks). */
 typedef struct {
     const double *poly_a;    /* NULL, or [n_layers][4]: c(T) of eq. (23) */
     const double *poly_b;    /* NULL, or [n_layers][5]: lambda(T) / k_scale of
@@ -449,14 +451,22 @@ typedef struct {
                               * of eq. (25); else 0 */
     int32_t z_full, nr_top;  /* both 0: rectangular; else the stepped domain of
                               * eq. (9) */
+    int32_t turn_on;         /* nonzero: the turn-on model of eq. (22) (pulse
+                              * starts on whole steps, CRYO_ERR_UNSUPPORTED
+                              * otherwise) */
 } cryo_instance_options;
 /* cryo_batch_create with per-instance options (`opts`: n entries, nullable
  * for none).  Instances are grouped by kernel shape, law family (cube
  * capacity, general power laws, polynomial laws) and domain (rectangular or
  * stepped), one launch per group and step as above; each instance steps
- * exactly as a plan with the same shape and options (bit for bit).  The
- * turn-on model has no batch form.  Option errors name the instance
- * (CRYO_ERR_ARG, CRYO_ERR_UNSTABLE, as the plan setters). */
+ * exactly as a plan with the same shape and options (bit for bit).  With
+ * the turn-on model on some instances, cryo_batch_forward splits its step
+ * range at every step where one of them starts a pulse: that step runs
+ * eagerly, those instances through their 100 sub-steps of dt/100 and the
+ * others through one step each (single-plan launches of the same kernels),
+ * and the steps between such steps run as above.  Option errors name the
+ * instance (CRYO_ERR_ARG, CRYO_ERR_UNSTABLE, CRYO_ERR_UNSUPPORTED, as the
+ * plan setters). */
 cryo_status cryo_batch_create_with(int32_t n, const cryo_problem *probs, cryo_dtype dtype,
                                    const int32_t *shapes, const cryo_instance_options *opts,
                                    cryo_batch **out);
@@ -467,7 +477,9 @@ cryo_status cryo_batch_create_with(int32_t n, const cryo_problem *probs, cryo_dt
  * add the law family "poly" and the word "stepped" for such groups and the
  * options to the batch hash (a batch without options keeps the keys of
  * cryo_batch_autotune, which is this call with opts NULL).  Shapes the
- * options' tables do not fit are skipped. */
+ * options' tables do not fit are skipped.  The turn-on model is not timed
+ * (its sub-steps are rare and run on the instance's shape): trial batches
+ * step without it. */
 cryo_status cryo_batch_autotune_with(int32_t n, const cryo_problem *probs, cryo_dtype dtype,
                                      const cryo_instance_options *opts, int32_t steps,
                                      const char *cache_path, void *stream, int32_t *shapes);

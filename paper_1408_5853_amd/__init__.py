@@ -376,6 +376,7 @@ def _instance_options(cells):
         if c.get("stepped"):
             opts[i].z_full = int(c["stepped"]["z_full"])
             opts[i].nr_top = int(c["stepped"]["nr_top"])
+        opts[i].turn_on = int(bool(c.get("turn_on")))
     return opts, keep
 
 
@@ -386,10 +387,6 @@ class Batch:
         self.cells = list(cells)
         self.dtype = dtype
         n = len(self.cells)
-        for i, c in enumerate(self.cells):
-            if c.get("turn_on"):
-                raise ValueError("cell %d: batches do not offer the turn-on model; step such "
-                                 "cells with Plan" % i)
         self._ps = [_abi.ProblemStruct(c) for c in self.cells]
         arr = (_abi.Problem * n)(*[p.s for p in self._ps])
         self._arr = arr
@@ -475,11 +472,8 @@ def autotune(cell, dtype="f64", steps=20, cache=None, stream=None):
 def tune_batch(cells, dtype="f32", steps=64, cache=None, stream=None):
     """Per-instance launch shapes for Batch(cells, dtype, shapes=...), timed
     on the GPU per shape group (cryo_batch_autotune_with: cells may carry the
-    polynomial laws or the stepped domain, as Batch takes them); `cache`
-    names an optional text file of earlier results."""
-    for i, c in enumerate(cells):
-        if c.get("turn_on"):
-            raise ValueError("cell %d: batches do not offer the turn-on model" % i)
+    polynomial laws, the stepped domain or the turn-on model, as Batch takes
+    them); `cache` names an optional text file of earlier results."""
     n = len(cells)
     ps = [_abi.ProblemStruct(c) for c in cells]
     arr = (_abi.Problem * n)(*[p.s for p in ps])

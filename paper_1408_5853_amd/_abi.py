@@ -69,7 +69,8 @@ class Problem(C.Structure):
 
 class InstanceOptions(C.Structure):
     _fields_ = [("poly_a", C.POINTER(C.c_double)), ("poly_b", C.POINTER(C.c_double)),
-                ("joule_tref", C.c_double), ("z_full", C.c_int32), ("nr_top", C.c_int32)]
+                ("joule_tref", C.c_double), ("z_full", C.c_int32), ("nr_top", C.c_int32),
+                ("turn_on", C.c_int32)]
 
 
 _lib = None

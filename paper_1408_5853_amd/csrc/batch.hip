@@ -1,8 +1,10 @@
 // Batched stepping of many independent cells (design sweeps): instances
 // are grouped by kernel shape; each step is one launch per shape group over
 // all of its instances, and blocks of steps are captured once in a HIP graph
-// (one branch per shape group) and replayed.  The global step index lives in device memory so a captured
-// block can be replayed for any step range.
+// (one branch per shape group) and replayed.  The global step index lives
+// in device memory so a captured block can be replayed for any step range.
+// Steps where an instance with the turn-on model starts a pulse run eagerly,
+// instance by instance.
 #include <string.h>
 
 #include <algorithm>
@@ -167,6 +169,9 @@ cryo_status cryo_batch_create_with(int32_t n, const cryo_problem *probs, cryo_dt
                 st = cryo_plan_set_poly_laws(p, o.poly_a, o.poly_b, o.joule_tref);
             if (st == CRYO_OK && (o.z_full != 0 || o.nr_top != 0))
                 st = cryo_plan_set_stepped(p, o.z_full, o.nr_top);
+            // the sub-step tables take the laws and domain set above, and
+            // the shape set below
+            if (st == CRYO_OK && o.turn_on) st = cryo_plan_set_turn_on(p, 1);
         }
         if (st == CRYO_OK && shapes)
             st = cryo_plan_set_shape(p, shapes[3 * i], shapes[3 * i + 1], shapes[3 * i + 2]);
@@ -233,6 +238,7 @@ cryo_status cryo_batch_forward(cryo_batch *b, void *T, int64_t k0, int64_t nstep
     const int n = (int)b->plans.size();
     for (cryo_plan *p : b->plans) {
         cryo_status st = ensure_device(p);
+        if (st == CRYO_OK && p->sub) st = ensure_device(p->sub);
         if (st != CRYO_OK) return st;
     }
     if (!b->d_block) {
@@ -261,9 +267,9 @@ cryo_status cryo_batch_forward(cryo_batch *b, void *T, int64_t k0, int64_t nstep
                                             w + b->ws_field[i], (int *)w + i, s);
         if (st != CRYO_OK) return st;
     }
-    cryo_status st = launch_set_i64(k0p, k0, s);
-    if (st != CRYO_OK) return st;
-    // the steps of one bucket (its instances only) on stream strm
+    cryo_status st = CRYO_OK;
+    // the steps of one bucket (its instances only) on stream strm: step
+    // offsets first .. first + count - 1 from the device step counter
     auto launch_bucket = [&](const Bucket &bk, int64_t first, int64_t count,
                              hipStream_t strm) -> cryo_status {
         size_t lds = 0;
@@ -278,69 +284,141 @@ cryo_status cryo_batch_forward(cryo_batch *b, void *T, int64_t k0, int64_t nstep
         }
         return CRYO_OK;
     };
-    const int64_t blocks = nsteps / GRAPH_STEPS, rem = nsteps % GRAPH_STEPS;
-    if (blocks > 0) {
-        if (!b->exec) {
-            // One graph per block of GRAPH_STEPS steps: the buckets hold
-            // disjoint instances, so each bucket's chain of steps is a branch
-            // of its own (forked from and joined to the capture stream), and
-            // the branches may run side by side; the step counter advances
-            // after the join.
-            const size_t nb = b->buckets.size();
-            hipStream_t cs;
-            std::vector<hipStream_t> bs(nb, nullptr);
-            std::vector<hipEvent_t> ev(nb + 1, nullptr);
-            bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
-            for (size_t q = 0; ok && q < nb; ++q)
-                ok = hipStreamCreateWithFlags(&bs[q], hipStreamNonBlocking) == hipSuccess;
-            for (size_t q = 0; ok && q <= nb; ++q)
-                ok = hipEventCreateWithFlags(&ev[q], hipEventDisableTiming) == hipSuccess;
-            cryo_status r = ok ? CRYO_OK : CRYO_ERR_DEVICE;
-            hipGraph_t g = nullptr;
-            hipError_t e2 = hipErrorUnknown;
-            if (ok) {
-                hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-                if (e != hipSuccess) r = CRYO_ERR_DEVICE;
-                if (r == CRYO_OK && hipEventRecord(ev[nb], cs) != hipSuccess) r = CRYO_ERR_DEVICE;
-                for (size_t q = 0; r == CRYO_OK && q < nb; ++q) {
-                    if (hipStreamWaitEvent(bs[q], ev[nb], 0) != hipSuccess) r = CRYO_ERR_DEVICE;
-                    if (r == CRYO_OK) r = launch_bucket(b->buckets[q], 0, GRAPH_STEPS, bs[q]);
-                    if (r == CRYO_OK && (hipEventRecord(ev[q], bs[q]) != hipSuccess ||
-                                         hipStreamWaitEvent(cs, ev[q], 0) != hipSuccess))
-                        r = CRYO_ERR_DEVICE;
-                }
-                if (r == CRYO_OK) r = launch_add_i64(k0p, GRAPH_STEPS, cs);
-                e2 = hipStreamEndCapture(cs, &g);
+    auto ensure_graph = [&]() -> cryo_status {
+        if (b->exec) return CRYO_OK;
+        // One graph per block of GRAPH_STEPS steps: the buckets hold
+        // disjoint instances, so each bucket's chain of steps is a branch
+        // of its own (forked from and joined to the capture stream), and
+        // the branches may run side by side; the step counter advances
+        // after the join.
+        const size_t nb = b->buckets.size();
+        hipStream_t cs;
+        std::vector<hipStream_t> bs(nb, nullptr);
+        std::vector<hipEvent_t> ev(nb + 1, nullptr);
+        bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
+        for (size_t q = 0; ok && q < nb; ++q)
+            ok = hipStreamCreateWithFlags(&bs[q], hipStreamNonBlocking) == hipSuccess;
+        for (size_t q = 0; ok && q <= nb; ++q)
+            ok = hipEventCreateWithFlags(&ev[q], hipEventDisableTiming) == hipSuccess;
+        cryo_status r = ok ? CRYO_OK : CRYO_ERR_DEVICE;
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipErrorUnknown;
+        if (ok) {
+            hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) r = CRYO_ERR_DEVICE;
+            if (r == CRYO_OK && hipEventRecord(ev[nb], cs) != hipSuccess) r = CRYO_ERR_DEVICE;
+            for (size_t q = 0; r == CRYO_OK && q < nb; ++q) {
+                if (hipStreamWaitEvent(bs[q], ev[nb], 0) != hipSuccess) r = CRYO_ERR_DEVICE;
+                if (r == CRYO_OK) r = launch_bucket(b->buckets[q], 0, GRAPH_STEPS, bs[q]);
+                if (r == CRYO_OK && (hipEventRecord(ev[q], bs[q]) != hipSuccess ||
+                                     hipStreamWaitEvent(cs, ev[q], 0) != hipSuccess))
+                    r = CRYO_ERR_DEVICE;
             }
-            for (size_t q = 0; q < nb; ++q)
-                if (bs[q]) (void)hipStreamDestroy(bs[q]);
-            for (size_t q = 0; q <= nb; ++q)
-                if (ev[q]) (void)hipEventDestroy(ev[q]);
-            if (ok) (void)hipStreamDestroy(cs);
-            if (r != CRYO_OK || e2 != hipSuccess || !g) {
-                if (g) (void)hipGraphDestroy(g);
-                return fail(CRYO_ERR_DEVICE, "graph capture of the step block failed");
-            }
-            if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
-                (void)hipGraphDestroy(g);
-                return fail(CRYO_ERR_DEVICE, "graph instantiation failed");
-            }
-            b->graph = g;
-            b->graph_ws = ws;
+            if (r == CRYO_OK) r = launch_add_i64(k0p, GRAPH_STEPS, cs);
+            e2 = hipStreamEndCapture(cs, &g);
         }
-        for (int64_t q = 0; q < blocks; ++q)
-            if (hipGraphLaunch(b->exec, s) != hipSuccess)
-                return fail(CRYO_ERR_DEVICE, "graph launch failed");
+        for (size_t q = 0; q < nb; ++q)
+            if (bs[q]) (void)hipStreamDestroy(bs[q]);
+        for (size_t q = 0; q <= nb; ++q)
+            if (ev[q]) (void)hipEventDestroy(ev[q]);
+        if (ok) (void)hipStreamDestroy(cs);
+        if (r != CRYO_OK || e2 != hipSuccess || !g) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(CRYO_ERR_DEVICE, "graph capture of the step block failed");
+        }
+        if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return fail(CRYO_ERR_DEVICE, "graph instantiation failed");
+        }
+        b->graph = g;
+        b->graph_ws = ws;
+        return CRYO_OK;
+    };
+    // The fields of all instances sit in buffer `par` before global step k.
+    int64_t k = k0;
+    int par = 0;
+    // regular steps k .. k + count - 1 of every instance: captured blocks of
+    // GRAPH_STEPS steps (they start from buffer 0) and single launches
+    auto regular = [&](int64_t count) -> cryo_status {
+        cryo_status r = CRYO_OK;
+        if (count > 0 && par == 1) {
+            // one step from buffer 1: step offset 1 from counter k - 1
+            r = launch_set_i64(k0p, k - 1, s);
+            for (const Bucket &bk : b->buckets)
+                if (r == CRYO_OK) r = launch_bucket(bk, 1, 1, s);
+            if (r != CRYO_OK) return r;
+            ++k;
+            --count;
+            par = 0;
+        }
+        if (count == 0) return CRYO_OK;
+        r = launch_set_i64(k0p, k, s);
+        const int64_t blocks = count / GRAPH_STEPS, rem = count % GRAPH_STEPS;
+        if (r == CRYO_OK && blocks > 0) r = ensure_graph();
+        for (int64_t q = 0; q < blocks && r == CRYO_OK; ++q)
+            if (hipGraphLaunch(b->exec, s) != hipSuccess) r = fail(CRYO_ERR_DEVICE, "graph launch failed");
+        // (each block advanced the counter by GRAPH_STEPS)
+        for (const Bucket &bk : b->buckets)
+            if (r == CRYO_OK) r = launch_bucket(bk, 0, rem, s);
+        k += count;
+        par = (int)(rem & 1);
+        return r;
+    };
+    // Step kk, where an instance of the turn-on model starts a pulse: single-
+    // plan launches of the same kernels, that instance's step as the 100
+    // sub-steps of dt / 100 of eq. (22) (an even number of buffer swaps, so
+    // its field is then copied to the buffer the other instances' steps write).
+    auto special = [&](int64_t kk) -> cryo_status {
+        for (int i = 0; i < n; ++i) {
+            const cryo_plan *p = b->plans[i];
+            char *f = w + b->ws_field[i];
+            void *buf[2] = {f, f + field_bytes_internal(p)};
+            int *flag = (int *)w + i;
+            cryo_status r = CRYO_OK;
+            if (p->sub && pulse_start(p->pulse, kk)) {
+                int c = par;
+                for (int q = 0; q < 100 && r == CRYO_OK; ++q) {
+                    const double X = p->pulse.amplitude * turn_on_source(p->pulse, kk, q);
+                    r = launch_step(p->sub, buf[c], buf[c ^ 1], X, nullptr, flag, s);
+                    c ^= 1;
+                }
+                if (r == CRYO_OK && hipMemcpyAsync(buf[par ^ 1], buf[par], field_bytes_internal(p),
+                                                   hipMemcpyDeviceToDevice, s) != hipSuccess)
+                    r = fail(CRYO_ERR_DEVICE, "sub-step field copy");
+            } else {
+                const double X = p->pulse.amplitude * source_fraction(p->pulse, kk);
+                r = launch_step(p, buf[par], buf[par ^ 1], X, nullptr, flag, s);
+            }
+            if (r != CRYO_OK) return r;
+        }
+        ++k;
+        par ^= 1;
+        return CRYO_OK;
+    };
+    // the steps of the range where a turn-on instance starts a pulse
+    std::vector<int64_t> starts;
+    for (const cryo_plan *p : b->plans) {
+        if (!p->sub || !(p->pulse.W > 0) || !pulse_starts_on_steps(p->pulse)) continue;
+        const int64_t kb = (int64_t)p->pulse.b0, kp = (int64_t)p->pulse.P;
+        int64_t kk = kb;
+        if (k0 > kb) kk = kb + (k0 - kb + kp - 1) / kp * kp;
+        for (; kk < k0 + nsteps; kk += kp)
+            if (pulse_start(p->pulse, kk)) starts.push_back(kk);
     }
-    b->graph_ws = ws;
-    for (const Bucket &bk : b->buckets) {
-        st = launch_bucket(bk, 0, rem, s);
+    std::sort(starts.begin(), starts.end());
+    starts.erase(std::unique(starts.begin(), starts.end()), starts.end());
+    for (int64_t ks : starts) {
+        st = regular(ks - k);
+        if (st == CRYO_OK) st = special(ks);
         if (st != CRYO_OK) return st;
     }
+    st = regular(k0 + nsteps - k);
+    if (st != CRYO_OK) return st;
+    b->graph_ws = ws;
     for (int i = 0; i < n; ++i) {
         const cryo_plan *p = b->plans[i];
         char *f = w + b->ws_field[i];
-        st = launch_from_internal(p, f + (nsteps & 1) * field_bytes_internal(p),
+        st = launch_from_internal(p, f + par * field_bytes_internal(p),
                                   (char *)T + es * b->off[i], (int *)w + i, s);
         if (st != CRYO_OK) return st;
     }

@@ -321,6 +321,14 @@ cryo_status cryo_batch_autotune_with(int32_t n, const cryo_problem *probs, cryo_
                                      const char *cache_path, void *stream, int32_t *shapes) {
     if (n < 1 || !probs || !shapes || steps < 1) return fail(CRYO_ERR_ARG, "bad argument");
     hipStream_t s = (hipStream_t)stream;
+    // the turn-on model's rare sub-steps run on the instance's own shape and
+    // are not timed: trial batches step without it
+    std::vector<cryo_instance_options> plain;
+    if (opts) {
+        plain.assign(opts, opts + n);
+        for (cryo_instance_options &o : plain) o.turn_on = 0;
+        opts = plain.data();
+    }
     // the groups cryo_batch_create forms with default shapes
     std::vector<Group> groups;
     for (int i = 0; i < n; ++i) {

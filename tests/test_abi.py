@@ -222,10 +222,9 @@ def test_stepped_domain_host_checks():
 
 
 def test_batch_plan_options():
-    # polynomial laws and the stepped domain are per-instance batch options
-    # (cryo_batch_create_with, host-side checks only here; the batch tuner
-    # takes them too, on the GPU); the turn-on model has no batch form: the
-    # batch and its tuner refuse it rather than step another problem
+    # polynomial laws, the stepped domain and the turn-on model are
+    # per-instance batch options (cryo_batch_create_with, host-side checks
+    # only here; the batch tuner takes them too, on the GPU)
     base = cellgen.small_cell(0)
     poly = cellgen.poly_variant(base, 0, joule_tref=30.0)
     stepped = dict(base, stepped={"z_full": 60, "nr_top": 30})
@@ -235,11 +234,14 @@ def test_batch_plan_options():
     with pytest.raises(P.CryoError) as e:                          # nr_top > nr
         P.Batch([base, dict(base, stepped={"z_full": 60, "nr_top": base["nr"] + 1})], "f64")
     assert "instance 1" in str(e.value)
-    c = dict(base, turn_on=True)
-    with pytest.raises(ValueError):
-        P.Batch([base, c], "f64")
-    with pytest.raises(ValueError):
-        P.tune_batch([base, c], "f64")
+    b = P.Batch([base, dict(base, turn_on=True), dict(poly, turn_on=True, stepped={"z_full": 60,
+                                                                                 "nr_top": 30})],
+                "f32")
+    assert len(b.offsets) == 4
+    b.close()
+    with pytest.raises(P.CryoError) as e:     # the turn-on model needs pulse starts on steps
+        P.Batch([base, dict(base, turn_on=True, t_on=2.5 * base["dt"])], "f64")
+    assert e.value.status == 6 and "instance 1" in str(e.value)
 
 
 def test_gradient_store_host_checks():

@@ -90,3 +90,59 @@ def test_turn_on_fig3_cold_start(mult):
     To, So = oracle.forward(c, nsteps=n, surf=True)
     assert rel_err(Tg, To) < F64_TOL and rel_err(Sg, So) < F64_TOL
     assert np.all(np.diff(Sg) >= 0)         # heating without the start jump
+
+
+def _batch_cells():
+    # instances with their own dt and pulse: turn-on model with starts at
+    # steps 3, 73, 143 and at 40, on a plain cell; the model with the
+    # polynomial laws and a stepped domain; one instance without it (its
+    # pulse still starts at step 3); two radial sizes (two launch groups)
+    def pulsed(c, t_on, period, width, on=True):
+        dt = c["dt"]
+        c = dict(c, t_on=t_on * dt, period=period * dt, width=width * dt,
+                 amplitude=3 * c["amplitude"])
+        if on:
+            c["turn_on"] = True
+        return c
+    a = pulsed(cellgen.with_nz(cellgen.small_cell(0, z_active=True), 24), 3, 70, 5.0)
+    b = pulsed(cellgen.with_nz(cellgen.small_cell(1, z_active=True), 20), 40, 1000, 0.37)
+    p = pulsed(cellgen.poly_variant(cellgen.with_nz(cellgen.small_cell(2, z_active=True), 30), 2,
+                                    joule_tref=30.0), 3, 70, 4.6)
+    p["stepped"] = {"z_full": 18, "nr_top": 40}
+    plain = pulsed(cellgen.with_nz(cellgen.small_cell(3, z_active=True), 16), 3, 70, 5.0, on=False)
+    big = pulsed(cellgen.tiny(4, nr=200, nz=12, n_layers=3, z_active=True, dt=2e-6,
+                              amplitude=4e9, heater=2), 40, 1000, 2.5)
+    return [a, b, p, plain, big]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("k0,n", [(2, 150), (0, 75)])
+def test_batch_with_turn_on_instances(dtype, k0, n):
+    # the batch splits its step range at the pulse starts of its turn-on
+    # instances (captured blocks and single steps between them, from either
+    # buffer): every instance equals a single plan with the same shape and
+    # options bit for bit, and the oracle within the tolerances
+    import torch
+
+    import paper_1408_5853_amd as P
+    cells = _batch_cells()
+    say("case batch with turn-on instances %s k0=%d steps=%d" % (dtype, k0, n))
+    b = P.Batch(cells, dtype)
+    T = b.init()
+    ws = b.workspace()
+    b.forward(T, k0, n, ws)
+    b.poll(ws)
+    torch.cuda.synchronize()
+    for i, c in enumerate(cells):
+        got = P.Plan.field_values(b.field(T, i))
+        plan = P.Plan(c, dtype)
+        plan.set_shape(*b.shape(i))
+        Ts = plan.init()
+        plan.forward(Ts, k0, n)
+        torch.cuda.synchronize()
+        assert np.array_equal(got, plan.field_values(Ts)), i
+        To = oracle.forward(c, k0=k0, nsteps=n)
+        if dtype == "f64":
+            assert rel_err(got, To) < F64_TOL, i
+        else:
+            assert np.max(np.abs(got - To)) < F32_TOL_K, i
