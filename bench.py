@@ -91,7 +91,7 @@ def timed(stream, fn):
 
 def host_threads():
     """Threads the host offers this process (its CPU affinity; at most 16,
-    one GPU's share of a GPU machine)."""
+    one GPU's share of the host's cores on an eight-GPU node)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
