@@ -237,7 +237,7 @@ cryo_status cryo_plan_set_poly_laws(cryo_plan *plan, const double *a, const doub
  * its next forward call), follows later cryo_plan_set_shape calls, and frees
  * them with on = 0 or cryo_plan_destroy.  Gradients include the sub-steps
  * in their sweep (see cryo_gradient); batch instances take the model
- * through cryo_instance_options (see cryo_batch_create_with). */
+ * through the turn_on field of their options, see cryo_batch_create_with. */
 cryo_status cryo_plan_set_turn_on(cryo_plan *plan, int32_t on);
 
 /* After the stream has finished a cryo_forward that used `ws`: returns
