@@ -406,17 +406,23 @@ cryo_status cryo_gradient_async(const cryo_plan *plan, const void *T0, int64_t n
  * cryo_gradient, design i with plans[i], T0[i], targets[i] (nsteps values),
  * ws[i] of ws_bytes[i] bytes (cryo_gradient_workspace_bytes of plans[i]),
  * results J[i], grad[i] (2 + 2 L_i values) and surf_out[i] (nullable array,
- * nullable entries).  The designs run on n_streams streams (0: enough for
+ * nullable entries).  Designs may share a workspace (the same ws[i]
+ * pointer, large enough for each of them): those run one after another on
+ * one stream, so k workspaces with a gradient store each can serve any
+ * number of designs.  The designs run on n_streams streams (0: enough for
  * the launches of designs running side by side to cover the compute units,
- * at most 4, the hardware queues a process gets by default) of default
- * priority that the library makes on first use and keeps per device (they do
- * not wait for other streams: T0 must be ready when the call is made).
- * Every target is copied in, then each design's whole gradient is enqueued
- * on stream i mod n_streams (one host thread per stream enqueues its
- * designs in order), then the results are read; they equal those of the
- * single calls bit for bit.  The plans' device tables are made first, on the
- * calling thread.  Synchronous; errors name the failing design (the lowest
- * index among the threads' first failures). */
+ * at most 4, the hardware queues a process gets by default; never more than
+ * the distinct workspaces) of default priority that the library makes on
+ * first use and keeps per device (they do not wait for other streams: T0
+ * must be ready when the call is made).  The targets are copied in at once
+ * to a device block the call allocates (with room for each design's J,
+ * gradient, trace and error word, copied there from its workspace when the
+ * design ends); then each workspace's designs are enqueued in order on
+ * stream q mod n_streams for the q-th distinct workspace (one host thread
+ * per stream), then the block is read back and freed.  Results equal those
+ * of the single calls bit for bit.  The plans' device tables are made first,
+ * on the calling thread.  Synchronous; errors name the failing design (the
+ * lowest index among the threads' first failures). */
 cryo_status cryo_gradient_many(int32_t n, cryo_plan *const *plans, const void *const *T0,
                                int64_t nsteps, const double *const *targets, int64_t ckpt,
                                void *const *ws, const size_t *ws_bytes, int32_t n_streams,

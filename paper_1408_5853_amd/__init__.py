@@ -543,16 +543,18 @@ def gradient(cell, target, T0=None, nsteps=None, ckpt=0, store=0):
     return gradient_plan(cell).gradient(target, T0=T0, nsteps=nsteps, ckpt=ckpt, store=store)
 
 
-def gradient_many(cells, targets, nsteps=None, ckpt=0, streams=0, T0s=None, store=0):
+def gradient_many(cells, targets, nsteps=None, ckpt=0, streams=0, T0s=None, store=0, shared=0):
     """Gradients of many designs in one call (FP64, the library's concurrent
     design loop over `streams` HIP streams; 0 lets the library choose).
     Returns (J [n], [grad_i],
     [surface trace_i]); equal bit for bit to gradient() per design.  `store`:
-    the gradient store of every design's plan (a number, or one per design)."""
+    the gradient store of every design's plan (a number, or one per design).
+    `shared` k > 0: k workspaces, design i on workspace i mod k (designs on
+    one workspace run one after another), instead of one per design."""
     torch = _torch()
     n = len(cells)
     N = int(cells[0]["nsteps"] if nsteps is None else nsteps)
-    plans, fields, wss, tg = [], [], [], []
+    plans, fields, sizes, tg = [], [], [], []
     for i, c in enumerate(cells):
         plan = gradient_plan(c)
         plan.set_gradient_store(store[i] if isinstance(store, (list, tuple)) else store)
@@ -560,11 +562,18 @@ def gradient_many(cells, targets, nsteps=None, ckpt=0, streams=0, T0s=None, stor
         fields.append(plan.init() if T0s is None or T0s[i] is None else plan.field_from(T0s[i]))
         b = C.c_size_t()
         check(lib().cryo_gradient_workspace_bytes(plan._h, N, int(ckpt), C.byref(b)))
-        wss.append(torch.empty(b.value, dtype=torch.uint8, device="cuda"))
+        sizes.append(b.value)
         t = np.ascontiguousarray(np.asarray(targets[i], dtype=np.float64)[:N])
         if t.size < N:
             raise ValueError("target %d needs nsteps values" % i)
         tg.append(t)
+    k = int(shared)
+    if k > 0:
+        pool = [torch.empty(max(sizes[i::k]), dtype=torch.uint8, device="cuda")
+                for i in range(min(k, n))]
+        wss = [pool[i % k] for i in range(n)]
+    else:
+        wss = [torch.empty(sz, dtype=torch.uint8, device="cuda") for sz in sizes]
     vp, dp = C.c_void_p, C.POINTER(C.c_double)
     grads = [np.zeros(2 + 2 * len(c["layers"])) for c in cells]
     surfs = [np.zeros(N) for _ in cells]

@@ -642,9 +642,19 @@ cryo_status cryo_gradient_many(int32_t n, cryo_plan *const *plans, const void *c
         if (st != CRYO_OK) return fail(st, "design " + std::to_string(i) + ": " + cryo_last_error());
         if (!grad[i]) return fail(CRYO_ERR_ARG, "design " + std::to_string(i) + ": null grad");
     }
+    // designs that share a workspace run one after another on one stream:
+    // workspace groups in order of first use, group q on stream q mod ns
+    std::vector<int> grp(n);
+    std::vector<void *> wsg;
+    for (int i = 0; i < n; ++i) {
+        int q = 0;
+        while (q < (int)wsg.size() && wsg[q] != ws[i]) ++q;
+        if (q == (int)wsg.size()) wsg.push_back(ws[i]);
+        grp[i] = q;
+    }
     if (n_streams == 0) n_streams = auto_streams(n, plans);
     std::vector<hipStream_t> streams;
-    cryo_status st = pool_streams(std::min<int>(n_streams, n), streams);
+    cryo_status st = pool_streams(std::min<int>(n_streams, (int)wsg.size()), streams);
     if (st != CRYO_OK) return st;
     const int ns = (int)streams.size();
     int dev = 0;
@@ -656,15 +666,38 @@ cryo_status cryo_gradient_many(int32_t n, cryo_plan *const *plans, const void *c
         if (st == CRYO_OK && plans[i]->sub) st = ensure_device(plans[i]->sub);
     }
     if (st != CRYO_OK) return st;
+    // Per design, outside the (possibly shared) workspaces: its target, then
+    // J, grad, the surface trace and the error word, which each design's
+    // work on its stream copies there before the next design may reuse its
+    // workspace.  One device block (allocated here, freed on return), filled
+    // from the host at once and read back at once.
+    std::vector<size_t> ro(n + 1, 0);
+    for (int i = 0; i < n; ++i) ro[i + 1] = ro[i] + (size_t)(2 * N + 4 + 2 * plans[i]->L);
+    std::vector<double> hres(ro[n], 0.0);
+    for (int i = 0; i < n; ++i) memcpy(hres.data() + ro[i], targets[i], sizeof(double) * N);
+    double *dres = nullptr;
+    if (hipMalloc((void **)&dres, sizeof(double) * ro[n]) != hipSuccess)
+        return fail(CRYO_ERR_DEVICE, "gradient results block");
+    struct Free {
+        double *p;
+        ~Free() { (void)hipFree(p); }
+    } free_res{dres};
+    if (hipMemcpy(dres, hres.data(), sizeof(double) * ro[n], hipMemcpyHostToDevice) != hipSuccess)
+        return fail(CRYO_ERR_DEVICE, "target copy");
+    auto rJ = [&](int i) { return dres + ro[i] + N; };
+    auto rS = [&](int i) { return dres + ro[i] + N + 1 + 2 + 2 * plans[i]->L; };
+    auto rF = [&](int i) { return rS(i) + N; };
     std::vector<GradRun> runs;
     runs.reserve(n);
-    for (int i = 0; i < n; ++i) runs.push_back(grad_run(plans[i], T0[i], N, ckpt, ws[i], streams[i % ns]));
-    // every target first (the streams are idle), then each stream's designs
-    // enqueued in turn by a host thread of its own (a single thread would
-    // wait on one stream's full queue while the others ran dry), then the
-    // results
-    for (int i = 0; i < n && st == CRYO_OK; ++i) st = grad_stage_host(runs[i], targets[i]);
-    if (st != CRYO_OK) return st;
+    for (int i = 0; i < n; ++i) {
+        runs.push_back(grad_run(plans[i], T0[i], N, ckpt, ws[i], streams[grp[i] % ns]));
+        runs[i].target = dres + ro[i];
+        runs[i].J = rJ(i);
+        runs[i].grad = rJ(i) + 1;
+    }
+    // each stream's designs enqueued in order by a host thread of its own
+    // (a single thread would wait on one stream's full queue while the
+    // others ran dry), then the results
     std::vector<cryo_status> tst(ns, CRYO_OK);
     std::vector<int> tbad(ns, -1);
     std::vector<std::string> terr(ns);
@@ -675,8 +708,17 @@ cryo_status cryo_gradient_many(int32_t n, cryo_plan *const *plans, const void *c
             terr[k] = "device selection in an enqueuing thread";
             return;
         }
-        for (int i = k; i < n; i += ns) {
-            const cryo_status e = grad_enqueue(runs[i]);
+        for (int i = 0; i < n; ++i) {
+            if (grp[i] % ns != k) continue;
+            GradRun &r = runs[i];
+            cryo_status e = grad_enqueue(r);
+            // the trace and the error word leave the workspace with the design
+            if (e == CRYO_OK &&
+                (hipMemcpyAsync(rS(i), r.w + r.g.surf, sizeof(double) * N,
+                                hipMemcpyDeviceToDevice, r.s) != hipSuccess ||
+                 hipMemcpyAsync(rF(i), r.w + r.g.flag, sizeof(int), hipMemcpyDeviceToDevice,
+                                r.s) != hipSuccess))
+                e = fail(CRYO_ERR_DEVICE, "gradient results copy");
             if (e != CRYO_OK) {
                 tst[k] = e;
                 tbad[k] = i;
@@ -697,19 +739,26 @@ cryo_status cryo_gradient_many(int32_t n, cryo_plan *const *plans, const void *c
     work(0);
     for (int k : inline_work) work(k);
     for (std::thread &x : pool) x.join();
+    for (hipStream_t x : streams) (void)hipStreamSynchronize(x);
     int first = -1;
     for (int k = 0; k < ns; ++k)
         if (tst[k] != CRYO_OK && (first < 0 || tbad[k] < tbad[first])) first = k;
-    if (first >= 0) {
-        for (hipStream_t x : streams) (void)hipStreamSynchronize(x);
+    if (first >= 0)
         return fail(tst[first], "design " + std::to_string(tbad[first]) + ": " + terr[first]);
+    if (hipMemcpy(hres.data(), dres, sizeof(double) * ro[n], hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(CRYO_ERR_DEVICE, "gradient results copy");
+    for (int i = 0; i < n; ++i) {
+        int flag = 0;
+        memcpy(&flag, hres.data() + (rF(i) - dres), sizeof(int));
+        if (flag)
+            return fail(CRYO_ERR_NONFINITE, "design " + std::to_string(i) +
+                                                ": non-finite or out-of-range temperature produced");
+        J[i] = hres[ro[i] + N];
+        memcpy(grad[i], hres.data() + ro[i] + N + 1, sizeof(double) * (2 + 2 * plans[i]->L));
+        if (surf_out && surf_out[i])
+            memcpy(surf_out[i], hres.data() + (rS(i) - dres), sizeof(double) * N);
     }
-    for (int i = 0; i < n && st == CRYO_OK; ++i) {
-        st = grad_collect(runs[i], J + i, grad[i], surf_out ? surf_out[i] : nullptr);
-        if (st != CRYO_OK) st = fail(st, "design " + std::to_string(i) + ": " + cryo_last_error());
-    }
-    for (hipStream_t x : streams) (void)hipStreamSynchronize(x);
-    return st;
+    return CRYO_OK;
 }
 
 }  // extern "C"

@@ -19,18 +19,20 @@ def design_params(cell):
 
 
 def design_adam(cells, targets, iters, lr=0.05, nsteps=None, ckpt=0, streams=0,
-                betas=(0.9, 0.999), eps=1e-8):
+                betas=(0.9, 0.999), eps=1e-8, store=0, shared=0):
     """Adam in log-parameter space over design_params of every design, with
-    one gradient_many call per iteration.  Returns (final cells, J history
-    [iters + 1][n]): the last row is J at the final designs.  The pulse width
-    is kept below its period."""
+    one gradient_many call per iteration (`store` and `shared` as there: k
+    shared workspaces with a gradient store each trade recompute for
+    memory).  Returns (final cells, J history [iters + 1][n]): the last row
+    is J at the final designs.  The pulse width is kept below its period."""
     cells = [copy.deepcopy(c) for c in cells]
     n = len(cells)
     m = [None] * n
     v = [None] * n
     hist = []
     for it in range(iters + 1):
-        J, grads, _ = gradient_many(cells, targets, nsteps=nsteps, ckpt=ckpt, streams=streams)
+        J, grads, _ = gradient_many(cells, targets, nsteps=nsteps, ckpt=ckpt, streams=streams,
+                                    store=store, shared=shared)
         hist.append(J.copy())
         if it == iters:
             break

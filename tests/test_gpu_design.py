@@ -48,6 +48,25 @@ def test_gradient_many_equals_single_calls_bitwise():
         assert np.array_equal(surfs[i], Si)
 
 
+@pytest.mark.parametrize("shared,store,streams", [(1, 0, 0), (2, 24, 0), (2, [24, 0, 7, 24, 3], 4),
+                                                  (3, 10, 2)])
+def test_gradient_many_shared_workspaces_bitwise(shared, store, streams):
+    # designs sharing a workspace run one after another on one stream (with
+    # or without gradient stores, mixed per design); every result equals the
+    # single call's bit for bit
+    import paper_1408_5853_amd as P
+    cells = _small_designs(5, 24)
+    tg = _targets(cells, 24)
+    say("case gradient_many shared=%d store=%s streams=%d" % (shared, store, streams))
+    J, grads, surfs = P.gradient_many(cells, tg, ckpt=5, streams=streams, store=store,
+                                      shared=shared)
+    for i, c in enumerate(cells):
+        Ji, gi, Si = P.gradient(c, tg[i], ckpt=5)
+        assert J[i] == Ji, i
+        assert np.array_equal(grads[i], gi), i
+        assert np.array_equal(surfs[i], Si), i
+
+
 @pytest.mark.parametrize("streams", [0, 1, 4])
 def test_gradient_many_matches_oracle_adjoint(streams):
     import paper_1408_5853_amd as P
