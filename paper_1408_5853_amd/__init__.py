@@ -594,21 +594,24 @@ def _make_solve():
     class CryoSolve(torch.autograd.Function):
         """J(theta) for theta = [amplitude, width, thickness_m, k_scale_m] of a
         cell, differentiable by the hand-written discrete adjoint (one forward
-        with checkpoints, recompute and adjoint sweep per call).
+        with checkpoints, recompute and adjoint sweep per call; `store` kernel
+        steps at the end keep their states instead, see
+        Plan.set_gradient_store).
 
-        CryoSolve.apply(theta, cell, target, nsteps, ckpt) -> J (0-d tensor)."""
+        CryoSolve.apply(theta, cell, target, nsteps, ckpt[, store]) -> J (0-d
+        tensor)."""
 
         @staticmethod
-        def forward(ctx, theta, cell, target, nsteps, ckpt):
+        def forward(ctx, theta, cell, target, nsteps, ckpt, store=0):
             c = with_params(cell, theta.detach().cpu().numpy())
-            J, g, _ = gradient(c, target, nsteps=nsteps, ckpt=ckpt)
+            J, g, _ = gradient(c, target, nsteps=nsteps, ckpt=ckpt, store=store)
             ctx.save_for_backward(torch.as_tensor(g, dtype=theta.dtype, device=theta.device))
             return torch.as_tensor(J, dtype=theta.dtype, device=theta.device)
 
         @staticmethod
         def backward(ctx, gJ):
             (g,) = ctx.saved_tensors
-            return gJ * g, None, None, None, None
+            return gJ * g, None, None, None, None, None
 
     return CryoSolve
 

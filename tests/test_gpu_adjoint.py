@@ -93,6 +93,11 @@ def test_autograd_function_returns_adjoint_gradient():
     Jr, gr, _ = P.gradient(c, tgt)
     assert float(J) == pytest.approx(Jr, rel=1e-14)
     assert np.allclose(theta.grad.numpy(), gr, rtol=1e-14, atol=0)
+    # with every state stored: the same J and gradient bit for bit
+    th2 = torch.tensor(P.params_of(c), dtype=torch.float64, requires_grad=True)
+    J2 = P.CryoSolve.apply(th2, c, tgt, 20, 0, 20)
+    J2.backward()
+    assert float(J2) == float(J) and torch.equal(th2.grad, theta.grad)
 
 
 @pytest.fixture(scope="module")
