@@ -140,3 +140,18 @@ def test_gradient_many_with_turn_on_and_stepped_plans_bitwise():
     Jo, go, _ = oracle.gradient(cells[3], tg[3])
     assert J[3] == pytest.approx(Jo, rel=1e-9)
     assert _norm_err(grads[3], go, P.params_of(cells[3])) < 1e-8
+
+
+def test_gradient_many_names_the_design_with_a_nonfinite_field():
+    # three designs on one shared workspace, the middle one started from a
+    # field with a NaN: the error names it, although the design after it
+    # reuses (and clears) the workspace's error word
+    import paper_1408_5853_amd as P
+    cells = _small_designs(3, 12)
+    tg = _targets(cells, 12)
+    bad = np.full((cells[1]["nz"], cells[1]["nr"]), 28.0)
+    bad[1, 3] = np.nan
+    say("case gradient_many shared workspace, design 1 non-finite")
+    with pytest.raises(P.CryoError) as e:
+        P.gradient_many(cells, tg, ckpt=4, shared=1, T0s=[None, bad, None])
+    assert e.value.status == 4 and "design 1" in str(e.value)
