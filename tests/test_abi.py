@@ -289,3 +289,20 @@ def test_gradient_store_counts_turn_on_sub_steps():
     assert plan.gradient_workspace_bytes(100) == all_stored
     plain = P.Plan(cellgen.with_nz(cellgen.adjoint_cell(0), 64))
     assert plain.gradient_store_for(100, 1 << 50) == 100
+
+
+def test_new_entry_points_refuse_bad_arguments():
+    # host-side argument checks of the gradient store calls and the batch
+    # tuner with options (no device work happens before them)
+    L = P.lib()
+    plan = P.Plan(cellgen.with_nz(cellgen.adjoint_cell(0), 64))
+    d = ctypes.c_int64()
+    assert L.cryo_plan_set_gradient_store(None, 5) == 1
+    assert L.cryo_gradient_store_steps(None, 10, 0, 1 << 30, ctypes.byref(d)) == 1
+    assert L.cryo_gradient_store_steps(plan._h, 0, 0, 1 << 30, ctypes.byref(d)) == 1
+    assert L.cryo_gradient_store_steps(plan._h, 10, -1, 1 << 30, ctypes.byref(d)) == 1
+    assert L.cryo_gradient_store_steps(plan._h, 10, 0, 1 << 30, None) == 1
+    assert L.cryo_gradient_store_steps(plan._h, 10, 0, 0, ctypes.byref(d)) == 0 and d.value == 0
+    shapes = (ctypes.c_int32 * 3)()
+    assert L.cryo_batch_autotune_with(0, None, 0, None, 32, None, None, shapes) == 1
+    assert L.cryo_batch_autotune_with(1, plan._ps.ref(), 0, None, 0, None, None, shapes) == 1
