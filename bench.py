@@ -225,9 +225,11 @@ def batch_extra(P, steps, stream, tune_cache=None):
 def gradient_extra(P, steps, stream, store_gib=GRAD_STORE_GIB):
     """A forward and a gradient of `steps` steps on the adjoint workload,
     both timed with HIP events on the stream (the gradient enqueued with
-    cryo_gradient_async, its workspace made beforehand): first with
-    checkpoints only, then with a gradient store that fits in `store_gib`
-    GiB (at most 85 % of the free device memory) and its bitwise check."""
+    cryo_gradient_async, its workspace made beforehand): with checkpoints
+    only (reported under "checkpoints_only"), then with a gradient store that
+    fits in `store_gib` GiB (at most 85 % of the free device memory), whose
+    figures are the top-level ones, with its bitwise check against the
+    first."""
     import cellgen
     import numpy as np
     import torch
@@ -252,22 +254,27 @@ def gradient_extra(P, steps, stream, store_gib=GRAD_STORE_GIB):
     J = float(res["out"][0].item())
     g = res["out"][1].cpu().numpy()
     cells = c["nr"] * c["nz"]
-    out = {"workload": "adjoint: 512x2048, 6 layers, FP64, checkpoint stride ceil(sqrt(N))",
-           "steps": steps, "forward_s": round(t_fwd, 3), "gradient_s": round(t_grad, 3),
-           "gradient_over_forward": round(t_grad / t_fwd, 2), "J": J,
-           "grad_finite": bool(np.all(np.isfinite(g))),
-           "workspace_gib": round(gws.numel() / 2**30, 2),
-           "gradient_gcell_steps_s": round(cells * steps / t_grad / 1e9, 2),
-           # algorithmic bytes of a gradient step: forward and recompute 16 B
-           # each, the adjoint 32 B (read T^n, T^{n+1}, lam^{n+1}; write lam^n)
-           "gradient_hbm_frac": round(cells * steps / t_grad * GRAD_BYTES_PER_CELL_STEP / 1e9
-                                      / HBM_PEAK_GBS, 4)}
+    # checkpoints only: algorithmic bytes of a gradient step are forward and
+    # recompute 16 B each, the adjoint 32 B (read T^n, T^{n+1}, lam^{n+1};
+    # write lam^n)
+    ck = {"workload": "adjoint: 512x2048, 6 layers, FP64, checkpoint stride ceil(sqrt(N))",
+          "workspace_gib": round(gws.numel() / 2**30, 2), "gradient_s": round(t_grad, 3),
+          "gradient_over_forward": round(t_grad / t_fwd, 2),
+          "gradient_gcell_steps_s": round(cells * steps / t_grad / 1e9, 2),
+          "gradient_hbm_frac": round(cells * steps / t_grad * GRAD_BYTES_PER_CELL_STEP / 1e9
+                                     / HBM_PEAK_GBS, 4)}
+    out = {"steps": steps, "forward_s": round(t_fwd, 3), "J": J,
+           "grad_finite": bool(np.all(np.isfinite(g)))}
     del res, gws
     torch.cuda.empty_cache()
+    d = 0
     if store_gib > 0:
         free, _ = torch.cuda.mem_get_info()
         budget = int(min(store_gib * 2**30, 0.85 * free))
         d = plan.gradient_store_for(steps, budget)
+    if d > 0:
+        # the states of the last d steps kept from the forward (no recompute
+        # for them): the recompute's 16 B only for the other steps
         plan.set_gradient_store(d)
         gws = torch.empty(plan.gradient_workspace_bytes(steps), dtype=torch.uint8, device="cuda")
         res = {}
@@ -277,17 +284,22 @@ def gradient_extra(P, steps, stream, store_gib=GRAD_STORE_GIB):
         Js = float(res["out"][0].item())
         gs = res["out"][1].cpu().numpy()
         recomputed = (steps - d) / steps
-        out["store"] = {
+        out.update({
+            "workload": "adjoint: 512x2048, 6 layers, FP64, the last %d of %d steps' states kept "
+                        "from the forward (gradient store), checkpoints every "
+                        "ceil(sqrt(%d)) steps before them" % (d, steps, steps - d),
             "stored_steps": d, "workspace_gib": round(gws.numel() / 2**30, 2),
             "gradient_s": round(t_st, 3), "gradient_over_forward": round(t_st / t_fwd, 2),
-            "equal_bitwise": bool(Js == J and np.array_equal(gs, g)),
-            # forward 16 B, the recompute's 16 B only for the steps not stored,
-            # the adjoint 32 B
+            "gradient_gcell_steps_s": round(cells * steps / t_st / 1e9, 2),
             "gradient_hbm_frac": round(cells * steps / t_st * (48 + 16 * recomputed) / 1e9
-                                       / HBM_PEAK_GBS, 4)}
+                                       / HBM_PEAK_GBS, 4),
+            "equal_bitwise_to_checkpoints_only": bool(Js == J and np.array_equal(gs, g))})
         plan.set_gradient_store(0)
         del res, gws
         torch.cuda.empty_cache()
+    else:
+        out.update(ck)
+    out["checkpoints_only"] = ck
     return out
 
 
