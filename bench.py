@@ -78,10 +78,17 @@ def measured_traffic(path=TRAFFIC_PROFILE):
 
 
 def timed(stream, fn):
+    """Seconds between two HIP events on `stream` around the work `fn`
+    enqueues.  A spin kernel (about a millisecond) goes first, before the
+    start event, so that the host has enqueued the first launches by the
+    time the start event is reached: a short timed region then measures the
+    kernels, not the host's latency to its first launch."""
     import torch
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        torch.cuda._sleep(2_000_000)
     e0.record(stream)
     fn()
     e1.record(stream)
