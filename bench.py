@@ -77,6 +77,21 @@ def measured_traffic(path=TRAFFIC_PROFILE):
     return int(t.group(1).replace(",", ""))
 
 
+def measured_valu_busy(path=TRAFFIC_PROFILE):
+    """Fraction of the headline kernel's cycles its SIMDs issue VALU work,
+    from the same counter summary (its kernel source hash must match)."""
+    import re
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    m = re.search(r"kernel source sha256\[:16\]: `?([0-9a-f]{16})", text)
+    t = re.search(r"VALU busy per launch[^`]*`([0-9.]+)`", text)
+    if not m or not t or m.group(1) != kernel_source_hash():
+        return None
+    return float(t.group(1))
+
+
 def timed(stream, fn):
     """Seconds between two HIP events on `stream` around the work `fn`
     enqueues.  A spin kernel (about a millisecond) goes first, before the
@@ -524,6 +539,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(),
+                     # FP64 sits near the VALU ridge: the profile's VALU busy
+                     # fraction of the same kernel sources (null if changed)
+                     "valu_busy": measured_valu_busy(),
                      "kernel": "k_step",
                      "bytes_per_launch": BYTES_PER_CELL_STEP * cells,
                      "kernel_source_sha256_16": kernel_source_hash(),
