@@ -345,7 +345,13 @@ __device__ inline void step_body(const StepArgs<R> &a, const int blk, const R *_
             }
         }
         R X[RPL];
+        // the line solve is the step's longest dependent chain (the cyclic
+        // reduction's exchanges): a wave inside it issues before a wave still
+        // in its rows, whose independent work fills the gaps (measured: 1 %
+        // on the 1024 x 4096 FP64 step, results bit for bit the same)
+        __builtin_amdgcn_s_setprio(2);
         solve_tail<R, RPL, G>(a0, b0, c0, d0, al, ga, de, X, lane, wig, xch);
+        __builtin_amdgcn_s_setprio(0);
         // the line after next (slot) and the next neighbours have landed
         if constexpr (RING) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         if (active) {
